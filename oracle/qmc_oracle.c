@@ -1,0 +1,451 @@
+/*
+ * qmc_oracle.c -- plain FP64 CPU oracle for the rank-1 lattice multi-summation
+ * and its MDI-LR tensor-product form (Zhong & Feng, arXiv 2404.08867).
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is the checker, not the product: only the
+ * test suite, the smoke check and the benchmark's CPU-baseline leg may load it.
+ * It shares no code, header, table or constant with the HIP library; it is
+ * deliberately slow and literal so that it can be read against the paper:
+ *   - every lattice index k = (i * z_j) mod n is recomputed from scratch with
+ *     exact 64-bit integer arithmetic (no incremental update);
+ *   - every coordinate is an IEEE double division k / n (plus the shift, wrapped
+ *     once into [0,1));
+ *   - every sum is a Neumaier-compensated FP64 sum taken in index order.
+ *
+ * Integrand families (the parameter vector layout is part of the contract):
+ *   0 EXP_SUM       f(x) = exp(sum_j c_j x_j)                      params c[d]
+ *   1 PRODUCT_PEAK  f(x) = prod_j 1 / (c_j^-2 + (x_j - w_j)^2)     params c[d], w[d]
+ *   2 GAUSSIAN      f(x) = exp(-sum_j c_j^2 (x_j - w_j)^2)         params c[d], w[d]
+ *   3 OSCILLATORY   f(x) = cos(2 pi u + sum_j c_j x_j)             params u, c[d]
+ * Oracle-only integrands used to pin the index map against the paper's tables:
+ *   100 TEST1_F     f(x) = x_2 exp(x_1 x_2) / (e - 2)   (Test 1, d = 2)
+ *   101 SIN_SQ      f(x) = sin(2 pi + sum_j x_j^2)       (Tests 1 and 2)
+ *
+ * Parity notes: nothing here is pinned by being retyped elsewhere; the pins live
+ * in the test suite (printed table values, closed forms, the dual-lattice
+ * character identity, brute force on tiny grids).
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define OR_EXP_SUM 0
+#define OR_PRODUCT_PEAK 1
+#define OR_GAUSSIAN 2
+#define OR_OSCILLATORY 3
+#define OR_TEST1_F 100
+#define OR_SIN_SQ 101
+
+#define OR_OK 0
+#define OR_BAD_ARG 1
+#define OR_TOO_BIG 2
+
+static const double OR_PI = 3.14159265358979323846264338327950288;
+
+/* ------------------------------------------------------------------------- */
+/* Neumaier (improved Kahan) compensated summation.                          */
+/* ------------------------------------------------------------------------- */
+typedef struct {
+    double s, c;
+} neu_t;
+
+static void neu_add(neu_t* a, double v) {
+    double t = a->s + v;
+    if (fabs(a->s) >= fabs(v))
+        a->c += (a->s - t) + v;
+    else
+        a->c += (v - t) + a->s;
+    a->s = t;
+}
+
+static double neu_value(const neu_t* a) { return a->s + a->c; }
+
+/* ------------------------------------------------------------------------- */
+/* Korobov generating vector (Sec. 2.2, Korobov-lattice example):            */
+/*   z(a) = (1, a, a^2, ..., a^{d-1}) mod n.                                  */
+/* ------------------------------------------------------------------------- */
+int oracle_korobov(int d, int64_t n, int64_t a, int64_t* z) {
+    if (d < 1 || n < 1 || a < 0 || !z) return OR_BAD_ARG;
+    if (n >= ((int64_t)1 << 31)) return OR_BAD_ARG;
+    int64_t am = a % n;
+    int64_t p = 1 % n;
+    for (int j = 0; j < d; ++j) {
+        z[j] = p;
+        p = (p * am) % n; /* p, am < 2^31: the product fits in int64 */
+    }
+    return OR_OK;
+}
+
+/* Point indices of the rank-1 lattice (eq. 2.1): k_ij = (i z_j) mod n, for
+ * i = i0 .. i0+count-1, written row-major [count][d]. */
+int oracle_lattice_points(int d, int64_t n, const int64_t* z, int64_t i0, int64_t count,
+                          int64_t* k_out) {
+    if (d < 1 || n < 1 || !z || !k_out || i0 < 0 || count < 0) return OR_BAD_ARG;
+    for (int64_t r = 0; r < count; ++r) {
+        int64_t i = i0 + r;
+        for (int j = 0; j < d; ++j) k_out[r * d + j] = (i % n) * z[j] % n;
+    }
+    return OR_OK;
+}
+
+/* Number of FP64 parameters of a family at dimension d. */
+int oracle_param_count(int family, int d) {
+    switch (family) {
+        case OR_EXP_SUM: return d;
+        case OR_PRODUCT_PEAK: return 2 * d;
+        case OR_GAUSSIAN: return 2 * d;
+        case OR_OSCILLATORY: return d + 1;
+        case OR_TEST1_F: return 0;
+        case OR_SIN_SQ: return 0;
+        default: return -1;
+    }
+}
+
+/* The integrand itself, literally as defined above. */
+double oracle_eval(int family, int d, const double* p, const double* x) {
+    switch (family) {
+        case OR_EXP_SUM: {
+            double s = 0.0;
+            for (int j = 0; j < d; ++j) s += p[j] * x[j];
+            return exp(s);
+        }
+        case OR_PRODUCT_PEAK: {
+            double f = 1.0;
+            for (int j = 0; j < d; ++j) {
+                double c = p[j], w = p[d + j];
+                f *= 1.0 / (1.0 / (c * c) + (x[j] - w) * (x[j] - w));
+            }
+            return f;
+        }
+        case OR_GAUSSIAN: {
+            double s = 0.0;
+            for (int j = 0; j < d; ++j) {
+                double c = p[j], w = p[d + j];
+                s += c * c * (x[j] - w) * (x[j] - w);
+            }
+            return exp(-s);
+        }
+        case OR_OSCILLATORY: {
+            double t = 2.0 * OR_PI * p[0];
+            for (int j = 0; j < d; ++j) t += p[1 + j] * x[j];
+            return cos(t);
+        }
+        case OR_TEST1_F:
+            return x[1] * exp(x[0] * x[1]) / (exp(1.0) - 2.0);
+        case OR_SIN_SQ: {
+            double s = 2.0 * OR_PI;
+            for (int j = 0; j < d; ++j) s += x[j] * x[j];
+            return sin(s);
+        }
+        default:
+            return NAN;
+    }
+}
+
+/* Gradient of the integrand with respect to its parameter vector (same layout
+ * as params), accumulated as g += scale * df/dp.  Only the four families. */
+static void oracle_eval_grad(int family, int d, const double* p, const double* x, double scale,
+                             double* g) {
+    switch (family) {
+        case OR_EXP_SUM: {
+            double f = oracle_eval(family, d, p, x);
+            for (int j = 0; j < d; ++j) g[j] += scale * x[j] * f;
+            break;
+        }
+        case OR_PRODUCT_PEAK: {
+            double f = oracle_eval(family, d, p, x);
+            for (int j = 0; j < d; ++j) {
+                double c = p[j], w = p[d + j];
+                double q = 1.0 / (c * c) + (x[j] - w) * (x[j] - w);
+                /* d(1/q)/dc = 2 c^-3 / q^2 ; d(1/q)/dw = 2 (x - w) / q^2 */
+                g[j] += scale * f * (2.0 / (c * c * c)) / q;
+                g[d + j] += scale * f * 2.0 * (x[j] - w) / q;
+            }
+            break;
+        }
+        case OR_GAUSSIAN: {
+            double f = oracle_eval(family, d, p, x);
+            for (int j = 0; j < d; ++j) {
+                double c = p[j], w = p[d + j];
+                g[j] += scale * f * (-2.0 * c * (x[j] - w) * (x[j] - w));
+                g[d + j] += scale * f * (2.0 * c * c * (x[j] - w));
+            }
+            break;
+        }
+        case OR_OSCILLATORY: {
+            double t = 2.0 * OR_PI * p[0];
+            for (int j = 0; j < d; ++j) t += p[1 + j] * x[j];
+            double s = sin(t);
+            g[0] += scale * (-2.0 * OR_PI * s);
+            for (int j = 0; j < d; ++j) g[1 + j] += scale * (-x[j] * s);
+            break;
+        }
+        default:
+            break;
+    }
+}
+
+/* Coordinates of lattice point i: x_j = {k_ij / n + shift_j} (eq. 2.1 and the
+ * shifted lattice of Sec. 2.1), the fractional part taken by one subtraction. */
+static void lattice_point(int d, int64_t n, const int64_t* z, const double* shift, int64_t i,
+                          double* x) {
+    for (int j = 0; j < d; ++j) {
+        int64_t k = (i * z[j]) % n;
+        double t = (double)k / (double)n;
+        if (shift) {
+            t += shift[j];
+            if (t >= 1.0) t -= 1.0;
+        }
+        x[j] = t;
+    }
+}
+
+static int check_lattice_args(int d, int64_t n, const int64_t* z, const double* shift) {
+    if (d < 1 || d > 4096 || n < 1 || n >= ((int64_t)1 << 31) || !z) return OR_BAD_ARG;
+    for (int j = 0; j < d; ++j)
+        if (z[j] < 0 || z[j] >= n) return OR_BAD_ARG;
+    if (shift)
+        for (int j = 0; j < d; ++j)
+            if (!(shift[j] >= 0.0 && shift[j] < 1.0)) return OR_BAD_ARG;
+    return OR_OK;
+}
+
+/* Plain rank-1 lattice rule (eq. 1.2 with the points of eq. 2.1):
+ *   Q = (1/n) sum_{i=0}^{n-1} f(x_i).
+ * Also returns A = (1/n) sum |f(x_i)|, the scale used for relative errors of
+ * mixed-sign results. */
+int oracle_lattice_sum(int d, int64_t n, const int64_t* z, const double* shift, int family,
+                       const double* params, double* q_out, double* absq_out) {
+    if (check_lattice_args(d, n, z, shift) != OR_OK) return OR_BAD_ARG;
+    if (oracle_param_count(family, d) < 0) return OR_BAD_ARG;
+    double* x = (double*)malloc(sizeof(double) * (size_t)d);
+    if (!x) return OR_TOO_BIG;
+    neu_t acc = {0.0, 0.0}, aacc = {0.0, 0.0};
+    for (int64_t i = 0; i < n; ++i) {
+        lattice_point(d, n, z, shift, i, x);
+        double f = oracle_eval(family, d, params, x);
+        neu_add(&acc, f);
+        neu_add(&aacc, fabs(f));
+    }
+    free(x);
+    if (q_out) *q_out = neu_value(&acc) / (double)n;
+    if (absq_out) *absq_out = neu_value(&aacc) / (double)n;
+    return OR_OK;
+}
+
+/* Same sum restricted to the index range [i0, i0 + count): the partial sum
+ * (not divided by n).  Used to check sampled pieces of very large sums. */
+int oracle_lattice_partial(int d, int64_t n, const int64_t* z, const double* shift, int family,
+                           const double* params, int64_t i0, int64_t count, double* sum_out) {
+    if (check_lattice_args(d, n, z, shift) != OR_OK) return OR_BAD_ARG;
+    if (oracle_param_count(family, d) < 0 || i0 < 0 || count < 0 || i0 + count > n)
+        return OR_BAD_ARG;
+    double* x = (double*)malloc(sizeof(double) * (size_t)d);
+    if (!x) return OR_TOO_BIG;
+    neu_t acc = {0.0, 0.0};
+    for (int64_t i = i0; i < i0 + count; ++i) {
+        lattice_point(d, n, z, shift, i, x);
+        neu_add(&acc, oracle_eval(family, d, params, x));
+    }
+    free(x);
+    *sum_out = neu_value(&acc);
+    return OR_OK;
+}
+
+/* Value and parameter gradient of the plain rule:
+ *   q = (1/n) sum_i f(x_i),   grad_p = (1/n) sum_i df/dp (x_i).
+ * Each gradient component is its own Neumaier sum in index order. */
+int oracle_lattice_grad(int d, int64_t n, const int64_t* z, const double* shift, int family,
+                        const double* params, double* q_out, double* grad_out) {
+    if (check_lattice_args(d, n, z, shift) != OR_OK) return OR_BAD_ARG;
+    int P = oracle_param_count(family, d);
+    if (P < 0 || family >= 100) return OR_BAD_ARG;
+    double* x = (double*)malloc(sizeof(double) * (size_t)d);
+    double* g = (double*)malloc(sizeof(double) * (size_t)P);
+    neu_t* gacc = (neu_t*)calloc((size_t)P, sizeof(neu_t));
+    if (!x || !g || !gacc) {
+        free(x);
+        free(g);
+        free(gacc);
+        return OR_TOO_BIG;
+    }
+    neu_t acc = {0.0, 0.0};
+    for (int64_t i = 0; i < n; ++i) {
+        lattice_point(d, n, z, shift, i, x);
+        neu_add(&acc, oracle_eval(family, d, params, x));
+        memset(g, 0, sizeof(double) * (size_t)P);
+        oracle_eval_grad(family, d, params, x, 1.0, g);
+        for (int p = 0; p < P; ++p) neu_add(&gacc[p], g[p]);
+    }
+    if (q_out) *q_out = neu_value(&acc) / (double)n;
+    for (int p = 0; p < P; ++p) grad_out[p] = neu_value(&gacc[p]) / (double)n;
+    free(x);
+    free(g);
+    free(gacc);
+    return OR_OK;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Per-direction node counts of the transformed grid (eq. 3.5):              */
+/*   n_i = lcm(z_i, z_{i+1}) / min(z_i, z_{i+1}),  i < d;   n_d = ceil(n / z_d). */
+/* ------------------------------------------------------------------------- */
+static int64_t gcd64(int64_t a, int64_t b) {
+    while (b) {
+        int64_t t = a % b;
+        a = b;
+        b = t;
+    }
+    return a;
+}
+
+int oracle_mdi_dims(int d, const int64_t* z, int64_t n, int64_t* N_out) {
+    if (d < 1 || !z || !N_out || n < 1) return OR_BAD_ARG;
+    for (int i = 0; i + 1 < d; ++i) {
+        int64_t a = z[i], b = z[i + 1];
+        if (a < 1 || b < 1) return OR_BAD_ARG;
+        int64_t g = gcd64(a, b);
+        int64_t mn = a < b ? a : b;
+        /* lcm / min = (a / g) * b / min, computed without overflow for a, b < 2^31 */
+        int64_t l = (a / g) * b;
+        N_out[i] = l / mn;
+    }
+    if (z[d - 1] < 1) return OR_BAD_ARG;
+    N_out[d - 1] = (n + z[d - 1] - 1) / z[d - 1];
+    return OR_OK;
+}
+
+/* ------------------------------------------------------------------------- */
+/* MDI-LR value of the improved (tensor-product) rule.                       */
+/* Reading used throughout: the transformed grid has N_k nodes in direction  */
+/* k at the cell centres xi_{k,s} = (s + 1/2) / N_k, with the equal weight    */
+/* 1 / prod_k N_k, i.e.                                                       */
+/*   Qhat = (prod N_k)^-1 sum_{s in prod [0,N_k)} f(xi_{1,s_1}, ..., xi_{d,s_d}). */
+/* ------------------------------------------------------------------------- */
+
+/* Brute force over the whole grid (for tiny grids only). */
+int oracle_mdi_lr_brute(int d, const int64_t* N, int family, const double* params, double* q_out) {
+    if (d < 1 || !N || oracle_param_count(family, d) < 0) return OR_BAD_ARG;
+    double total = 1.0;
+    for (int k = 0; k < d; ++k) {
+        if (N[k] < 1) return OR_BAD_ARG;
+        total *= (double)N[k];
+    }
+    if (total > 67108864.0) return OR_TOO_BIG; /* 2^26 grid points */
+    int64_t* s = (int64_t*)calloc((size_t)d, sizeof(int64_t));
+    double* x = (double*)malloc(sizeof(double) * (size_t)d);
+    if (!s || !x) {
+        free(s);
+        free(x);
+        return OR_TOO_BIG;
+    }
+    neu_t acc = {0.0, 0.0};
+    int64_t count = (int64_t)total;
+    for (int64_t r = 0; r < count; ++r) {
+        for (int k = 0; k < d; ++k) x[k] = ((double)s[k] + 0.5) / (double)N[k];
+        neu_add(&acc, oracle_eval(family, d, params, x));
+        /* mixed-radix increment of the multi-index s */
+        for (int k = 0; k < d; ++k) {
+            if (++s[k] < N[k]) break;
+            s[k] = 0;
+        }
+    }
+    free(s);
+    free(x);
+    *q_out = neu_value(&acc) / total;
+    return OR_OK;
+}
+
+/* One factor phi_k(y) of a product-form integrand, as a complex number
+ * (re, im).  EXP_SUM: e^{c y}; GAUSSIAN: e^{-c^2 (y-w)^2};
+ * PRODUCT_PEAK: 1 / (c^-2 + (y-w)^2); OSCILLATORY: e^{i c y}. */
+static void factor(int family, int d, const double* p, int k, double y, double* re, double* im) {
+    *im = 0.0;
+    switch (family) {
+        case OR_EXP_SUM: *re = exp(p[k] * y); break;
+        case OR_GAUSSIAN: {
+            double c = p[k], w = p[d + k];
+            *re = exp(-c * c * (y - w) * (y - w));
+            break;
+        }
+        case OR_PRODUCT_PEAK: {
+            double c = p[k], w = p[d + k];
+            *re = 1.0 / (1.0 / (c * c) + (y - w) * (y - w));
+            break;
+        }
+        case OR_OSCILLATORY: {
+            double a = p[1 + k] * y;
+            *re = cos(a);
+            *im = sin(a);
+            break;
+        }
+        default: *re = NAN; break;
+    }
+}
+
+/* MDI with m = 1 (Algorithm 1 driven by Algorithm 2) for product-form
+ * integrands.  The "symbolic function" g_k that remains after the first
+ * d - k coordinates have been summed out is carried as a coefficient C times
+ * the product of the remaining factors; eq. 2.14c with m = 1 and weight 1/N_k
+ * then turns g_k into g_{k-1} by multiplying C with the one-dimensional
+ * weighted sum M = (1/N) sum_s phi(xi_s) of the coordinate being deleted.
+ * For OSCILLATORY the function is Re(e^{2 pi i u} prod_k e^{i c_k y_k}) and C
+ * is complex.  C is kept as a mantissa pair with a separate power-of-two
+ * exponent so that d in the thousands cannot overflow. */
+int oracle_mdi_lr_sweep(int d, const int64_t* N, int family, const double* params, double* q_out) {
+    if (d < 1 || !N || family < 0 || family > 3) return OR_BAD_ARG;
+    double cre = 1.0, cim = 0.0;
+    int cexp = 0;
+    if (family == OR_OSCILLATORY) {
+        cre = cos(2.0 * OR_PI * params[0]);
+        cim = sin(2.0 * OR_PI * params[0]);
+    }
+    for (int k = 0; k < d; ++k) { /* delete the first remaining coordinate */
+        if (N[k] < 1) return OR_BAD_ARG;
+        neu_t mre = {0.0, 0.0}, mim = {0.0, 0.0};
+        for (int64_t s = 0; s < N[k]; ++s) {
+            double y = ((double)s + 0.5) / (double)N[k];
+            double re, im;
+            factor(family, d, params, k, y, &re, &im);
+            neu_add(&mre, re);
+            neu_add(&mim, im);
+        }
+        double Mre = neu_value(&mre) / (double)N[k];
+        double Mim = neu_value(&mim) / (double)N[k];
+        double nre = cre * Mre - cim * Mim;
+        double nim = cre * Mim + cim * Mre;
+        double big = fabs(nre) > fabs(nim) ? fabs(nre) : fabs(nim);
+        int e = 0;
+        if (big > 0.0 && isfinite(big)) {
+            frexp(big, &e);
+            nre = ldexp(nre, -e);
+            nim = ldexp(nim, -e);
+            cexp += e;
+        }
+        cre = nre;
+        cim = nim;
+    }
+    *q_out = ldexp(cre, cexp);
+    return OR_OK;
+}
+
+/* The one-dimensional weighted sums M_k themselves (real part, imaginary part),
+ * for diagnostics of the sweep. */
+int oracle_mdi_lr_factors(int d, const int64_t* N, int family, const double* params, double* m_re,
+                          double* m_im) {
+    if (d < 1 || !N || family < 0 || family > 3) return OR_BAD_ARG;
+    for (int k = 0; k < d; ++k) {
+        if (N[k] < 1) return OR_BAD_ARG;
+        neu_t mre = {0.0, 0.0}, mim = {0.0, 0.0};
+        for (int64_t s = 0; s < N[k]; ++s) {
+            double y = ((double)s + 0.5) / (double)N[k];
+            double re, im;
+            factor(family, d, params, k, y, &re, &im);
+            neu_add(&mre, re);
+            neu_add(&mim, im);
+        }
+        m_re[k] = neu_value(&mre) / (double)N[k];
+        m_im[k] = neu_value(&mim) / (double)N[k];
+    }
+    return OR_OK;
+}

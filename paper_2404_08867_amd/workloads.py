@@ -1,0 +1,184 @@
+"""Seeded synthetic inputs for the lattice-sum workloads.
+
+This module draws random numbers and nothing else: it holds none of the
+method's arithmetic (no generating vector, no lattice index, no integrand
+value).  It is the only module shared by the HIP path's tests/benchmark and the
+CPU oracle's tests.
+
+The paper (Zhong & Feng, arXiv 2404.08867) uses no dataset; its experiments are
+closed-form integrands on Korobov lattices (Sec. 4-6).  The workloads below keep
+those shapes -- Korobov parameter a, dimension d, prime point counts n, product
+or additive integrands with per-direction parameters -- with parameters drawn
+from fixed seeds:
+
+  * generator: ``numpy.random.default_rng(seed)`` (PCG64);
+  * seed of workload k: ``2404088670 + k``;
+  * draw order: a, then c, then w, then u.
+
+Workloads (k = 0..4):
+  0 plain_d4_expsum      d=4,   n=1009,      exp-sum, c ~ U[0,1]
+  1 plain_d20_peak       d=20,  n=1048573,   product-peak, c ~ U[0.5,2], w ~ U[0,1]
+  2 mdi_d100_gauss       d=100, N=64 nodes per direction (a = N), Gaussian,
+                         c ~ U[0.1,1], w ~ U[0,1]; extra sets for throughput
+  3 batched_4096         4096 integrands, d ~ U{8..200}, n uniform over the primes
+                         in [2^12, 2^22], a ~ U{2..n-1}, family uniform over
+                         {exp-sum, product-peak, Gaussian} with the parameter laws above
+  4 adjoint_d50_osc      d=50, n=16777213, one a shared by 64 oscillatory sets,
+                         u ~ U[0,1], c ~ U[0,2]
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+
+SEED_BASE = 2404088670
+
+# Family ids (the same numbering as the C ABI and the oracle).
+EXP_SUM, PRODUCT_PEAK, GAUSSIAN, OSCILLATORY = 0, 1, 2, 3
+FAMILY_NAMES = {EXP_SUM: "exp_sum", PRODUCT_PEAK: "product_peak", GAUSSIAN: "gaussian",
+                OSCILLATORY: "oscillatory"}
+
+
+def param_count(family: int, d: int) -> int:
+    """Length of the FP64 parameter vector: c | c,w | c,w | u,c."""
+    return {EXP_SUM: d, PRODUCT_PEAK: 2 * d, GAUSSIAN: 2 * d, OSCILLATORY: d + 1}[family]
+
+
+def draw_params(rng: np.random.Generator, family: int, d: int) -> np.ndarray:
+    """One parameter vector with the paper-style laws used by the workloads."""
+    if family == EXP_SUM:
+        return rng.uniform(0.0, 1.0, d)
+    if family == PRODUCT_PEAK:
+        c = rng.uniform(0.5, 2.0, d)
+        w = rng.uniform(0.0, 1.0, d)
+        return np.concatenate([c, w])
+    if family == GAUSSIAN:
+        c = rng.uniform(0.1, 1.0, d)
+        w = rng.uniform(0.0, 1.0, d)
+        return np.concatenate([c, w])
+    if family == OSCILLATORY:
+        c = rng.uniform(0.0, 2.0, d)
+        u = rng.uniform(0.0, 1.0, 1)
+        return np.concatenate([u, c])
+    raise ValueError(f"unknown family {family}")
+
+
+def draw_coprime(rng: np.random.Generator, n: int) -> int:
+    """A Korobov parameter a in [2, n-1] with gcd(a, n) = 1 (a = 1 when n <= 2)."""
+    if n <= 2:
+        return 1
+    while True:
+        a = int(rng.integers(2, n))
+        if math.gcd(a, n) == 1:
+            return a
+
+
+def primes_between(lo: int, hi: int) -> np.ndarray:
+    """All primes p with lo <= p <= hi (sieve of Eratosthenes)."""
+    sieve = np.ones(hi + 1, dtype=bool)
+    sieve[:2] = False
+    for p in range(2, int(hi ** 0.5) + 1):
+        if sieve[p]:
+            sieve[p * p::p] = False
+    idx = np.nonzero(sieve)[0]
+    return idx[idx >= lo]
+
+
+@dataclass
+class Plain:
+    """One plain lattice-sum problem: Korobov parameter a, not the vector z."""
+    name: str
+    d: int
+    n: int
+    a: int
+    family: int
+    params: np.ndarray
+    shift: np.ndarray | None = None
+
+
+@dataclass
+class MdiSets:
+    """MDI-LR problem: node counts per direction and nsets parameter vectors."""
+    name: str
+    d: int
+    N: np.ndarray
+    family: int
+    params: np.ndarray  # [nsets, P]
+
+
+@dataclass
+class Batch:
+    name: str
+    problems: list = field(default_factory=list)
+
+
+@dataclass
+class AdjointSets:
+    name: str
+    d: int
+    n: int
+    a: int
+    family: int
+    params: np.ndarray  # [nsets, P]
+
+
+def plain_d4_expsum() -> Plain:
+    rng = np.random.default_rng(SEED_BASE + 0)
+    n, d = 1009, 4
+    a = int(rng.integers(2, n))
+    c = rng.uniform(0.0, 1.0, d)
+    return Plain("plain_d4_expsum", d, n, a, EXP_SUM, c)
+
+
+def plain_d20_peak() -> Plain:
+    rng = np.random.default_rng(SEED_BASE + 1)
+    n, d = 1048573, 20
+    a = int(rng.integers(2, n))
+    c = rng.uniform(0.5, 2.0, d)
+    w = rng.uniform(0.0, 1.0, d)
+    return Plain("plain_d20_peak", d, n, a, PRODUCT_PEAK, np.concatenate([c, w]))
+
+
+def mdi_d100_gauss(nsets: int = 1) -> MdiSets:
+    """Set 0 is the single seeded problem; set s does not depend on nsets."""
+    rng = np.random.default_rng(SEED_BASE + 2)
+    d, N = 100, 64
+    r = rng.random((nsets, 2 * d))  # row s holds set s's draws: c then w
+    c = 0.1 + 0.9 * r[:, :d]
+    w = r[:, d:]
+    return MdiSets("mdi_d100_gauss", d, np.full(d, N, dtype=np.int64), GAUSSIAN,
+                   np.concatenate([c, w], axis=1))
+
+
+def batched_4096(count: int = 4096, d_range=(8, 200), n_range=(1 << 12, 1 << 22)) -> Batch:
+    rng = np.random.default_rng(SEED_BASE + 3)
+    primes = primes_between(*n_range)
+    out = Batch("batched_4096")
+    for b in range(count):
+        d = int(rng.integers(d_range[0], d_range[1] + 1))
+        n = int(primes[rng.integers(0, primes.size)])
+        a = int(rng.integers(2, n))
+        fam = int(rng.integers(0, 3))  # exp-sum, product-peak, Gaussian
+        out.problems.append(Plain(f"b{b}", d, n, a, fam, draw_params(rng, fam, d)))
+    return out
+
+
+def adjoint_d50_osc(nsets: int = 64) -> AdjointSets:
+    rng = np.random.default_rng(SEED_BASE + 4)
+    n, d = 16777213, 50
+    a = int(rng.integers(2, n))
+    r = rng.random((nsets, d + 1))  # row s holds set s's draws: c then u
+    c = 2.0 * r[:, :d]
+    u = r[:, d:]
+    return AdjointSets("adjoint_d50_osc", d, n, a, OSCILLATORY, np.concatenate([u, c], axis=1))
+
+
+def random_plain(seed: int, family: int, d: int, n: int, shift: bool = False) -> Plain:
+    """A small seeded test problem (parity cases, edge cases)."""
+    rng = np.random.default_rng(seed)
+    a = draw_coprime(rng, n)
+    p = draw_params(rng, family, d)
+    s = rng.uniform(0.0, 1.0, d) if shift else None
+    return Plain(f"rand{seed}", d, n, a, family, p, s)
