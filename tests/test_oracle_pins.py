@@ -287,3 +287,29 @@ def test_oracle_rejects_bad_arguments():
         O.lattice_sum([1], 5, O.EXP_SUM, [1.0], shift=[1.0])  # shift in [0, 1)
     with pytest.raises(ValueError):
         O.mdi_lr([0], O.EXP_SUM, [1.0])
+
+
+# ---- the shifted lattice: wrap into [0, 1) -----------------------------------------
+@pytest.mark.parametrize("family", [0, 1, 2])
+def test_shift_by_own_point_permutes_lattice(family):
+    """Shifting a rank-1 lattice by one of its own points maps the point set onto
+    itself ({x_i + x_s} = x_{i+s}), so the rule is unchanged -- for integrands that
+    are not periodic this only holds if the shift wraps into [0, 1)."""
+    n, d = 1009, 4
+    z = O.korobov(d, n, 331)
+    rng = np.random.default_rng(7 + family)
+    p = W.draw_params(rng, family, d)
+    q0, _ = O.lattice_sum(z, n, family, p)
+    for s in (1, 500, 1008):
+        shift = O.lattice_points(z, n, s, 1)[0] / n
+        qs, _ = O.lattice_sum(z, n, family, p, shift)
+        assert qs == pytest.approx(q0, rel=1e-13)
+
+
+@pytest.mark.parametrize("m", [0, 137, 996])
+def test_rotated_midpoint_shift(m):
+    """d = 1, z = 1, Delta = (m + 1/2)/n: the shifted points are the midpoints in
+    rotated order, so the rule equals the midpoint rule for a non-periodic f."""
+    n = 997
+    q, _ = O.lattice_sum([1], n, O.EXP_SUM, [1.7], shift=[(m + 0.5) / n])
+    assert q == pytest.approx(O.mdi_lr([n], O.EXP_SUM, [1.7]), rel=1e-13)
