@@ -1,0 +1,252 @@
+#!/usr/bin/env python3
+"""Throughput of the rank-1 lattice-sum hot path on one MI355X.
+
+One step is one call of the plain lattice rule over the whole workload (index
+generation, coordinates, integrand, per-thread, wavefront, workgroup and
+cross-workgroup reductions -- a single fused launch).  The default workload is
+`plain_d20_peak`: d = 20, n = 1048573 (prime), seeded Korobov z, product-peak
+integrand, evaluated with QMC_FP32_COMPENSATED; the FP64 path is timed beside it.
+
+Timing: W eager warm-up steps, then K steps captured in one HIP graph and
+replayed once between two device synchronisations (the inputs are resident in
+HBM; the graph removes Python launch overhead from the measurement).  HIP events
+recorded on the launch stream around the replay give the average kernel
+duration used for the roofline.  The FP64 CPU oracle is timed on a bounded
+sample (the same workload, repeated for about 10 s) on one host core; its value
+also gives the relative error of each GPU result.
+
+Prints one JSON line.  Only one GPU is supported.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import statistics
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "lattice-point integrand evals/sec at rel err ≤1e-6 vs FP64 oracle (1 GPU)"
+
+# VALU issue peak of MI355X without packed FP32: 256 CUs x 64 lanes x 2.4 GHz.
+PEAK_LANE_OPS = 256 * 64 * 2.4e9
+
+# Algorithmic VALU lane-operations per lattice point (one d-dimensional
+# integrand evaluation): d * (3 index + 2 coordinate + c_fam) + T + 6, with
+# c_fam = 1 (exp-sum, oscillatory), 2 (Gaussian), 3 (product peak), one
+# transcendental T and 6 for accumulation and scaling.
+C_FAM = {0: 1, 1: 3, 2: 2, 3: 1}
+
+
+def work_per_point(d: int, family: int) -> int:
+    return d * (3 + 2 + C_FAM[family]) + 1 + 6
+
+
+def parse():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--workload", default="plain_d20_peak",
+                    choices=["plain_d20_peak", "plain_d4_expsum", "mdi_d100_gauss"])
+    ap.add_argument("--cpu-seconds", type=float, default=10.0,
+                    help="wall-clock budget of the oracle's CPU-baseline sample")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    return ap.parse_args()
+
+
+def oracle_baseline(prob, seconds):
+    """CPU-baseline leg: the FP64 oracle on the same workload, repeated for about
+    `seconds` (at least once).  Returns (points/s, reps, Q, A)."""
+    import oracle as O
+    z = O.korobov(prob.d, prob.n, prob.a)
+    t0 = time.perf_counter()
+    q, a = O.lattice_sum(z, prob.n, prob.family, prob.params, prob.shift)
+    reps = 1
+    while time.perf_counter() - t0 < seconds:
+        O.lattice_sum(z, prob.n, prob.family, prob.params, prob.shift)
+        reps += 1
+    dt = time.perf_counter() - t0
+    return prob.n * reps / dt, reps, q, a
+
+
+def oracle_mdi_baseline(w, nsets, seconds):
+    import numpy as np
+    import oracle as O
+    t0 = time.perf_counter()
+    vals = []
+    s = 0
+    while s < nsets and (s == 0 or time.perf_counter() - t0 < seconds):
+        vals.append(O.mdi_lr(w.N, w.family, w.params[s]))
+        s += 1
+    dt = time.perf_counter() - t0
+    return float(np.sum(w.N)) * s / dt, s, vals
+
+
+def time_graph(torch, launch, steps, warmup):
+    """Eager warm-up, capture `steps` launches in one graph, replay it once timed."""
+    for _ in range(warmup):
+        launch()
+    torch.cuda.synchronize()
+    # single-call eager latency (host launch + kernel), median of 20
+    lat = []
+    for _ in range(20):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        launch()
+        torch.cuda.synchronize()
+        lat.append(time.perf_counter() - t0)
+    g = torch.cuda.CUDAGraph()
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        launch()
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    with torch.cuda.graph(g):
+        for _ in range(steps):
+            launch()
+    g.replay()  # untimed replay
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e0.record()
+    g.replay()
+    e1.record()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    wall = t1 - t0
+    kern = e0.elapsed_time(e1) * 1e-3
+    return wall / steps, kern / steps, statistics.median(lat), g
+
+
+def bench_plain(args, torch, qmc, W):
+    prob = W.plain_d20_peak() if args.workload == "plain_d20_peak" else W.plain_d4_expsum()
+    z = torch.tensor(qmc.korobov(prob.d, prob.n, prob.a), device="cuda")
+    params = torch.tensor(prob.params, dtype=torch.float64, device="cuda")
+    ws = qmc.Workspace(qmc.workspace_size(prob.d, prob.n, 1))
+    results = {}
+    for prec, name in ((qmc.FP32_COMPENSATED, "fp32c"), (qmc.FP64, "fp64")):
+        out = torch.zeros(1, dtype=torch.float64, device="cuda")
+
+        def launch(prec=prec, out=out):
+            qmc.lattice_sum(z, prob.n, prob.family, params, prec, ws=ws, out=out)
+
+        step_s, kern_s, lat_s, g = time_graph(torch, launch, args.steps, args.warmup)
+        results[name] = dict(step_s=step_s, kern_s=kern_s, lat_s=lat_s, q=float(out.item()))
+        del g
+    units = prob.n
+    wpp = work_per_point(prob.d, prob.family)
+    config = {"workload": prob.name, "d": prob.d, "n": prob.n, "a": prob.a,
+              "family": W.FAMILY_NAMES[prob.family], "precision": "fp32_compensated",
+              "lattice": "korobov", "shift": None}
+    return prob, results, units, wpp, config
+
+
+def bench_mdi(args, torch, qmc, W):
+    nsets = 65536
+    w = W.mdi_d100_gauss(nsets=nsets)
+    N = torch.tensor(w.N.astype("int32"), device="cuda")
+    params = torch.tensor(w.params, dtype=torch.float64, device="cuda")
+    results = {}
+    for prec, name in ((qmc.FP32_COMPENSATED, "fp32c"), (qmc.FP64, "fp64")):
+        out = torch.zeros(nsets, dtype=torch.float64, device="cuda")
+
+        def launch(prec=prec, out=out):
+            qmc.mdi_lr(N, w.family, params, prec, out=out)
+
+        step_s, kern_s, lat_s, g = time_graph(torch, launch, args.steps, args.warmup)
+        results[name] = dict(step_s=step_s, kern_s=kern_s, lat_s=lat_s, q=out.cpu().numpy())
+        del g
+    units = int(w.N.sum()) * nsets  # one-dimensional factor evaluations per launch
+    wpp = 2 + 1 + 2  # per factor: FMA, square, transcendental, accumulate (Gaussian)
+    config = {"workload": w.name, "d": w.d, "N": int(w.N[0]), "nsets": nsets,
+              "family": W.FAMILY_NAMES[w.family], "precision": "fp32_compensated",
+              "unit_of_work": "one-dimensional factor evaluation"}
+    return w, results, units, wpp, config
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
+              "the multi-GPU sharding is described in DESIGN.md but not implemented.", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    from paper_2404_08867_amd import qmc
+    from paper_2404_08867_amd import workloads as W
+
+    if not torch.cuda.is_available():
+        print("bench.py: no GPU visible", file=sys.stderr)
+        sys.exit(1)
+    torch.cuda.set_device(0)
+    qmc.lib()  # fail loudly if the HIP library is missing
+
+    if args.workload == "mdi_d100_gauss":
+        prob, res, units, wpp, config = bench_mdi(args, torch, qmc, W)
+    else:
+        prob, res, units, wpp, config = bench_plain(args, torch, qmc, W)
+
+    line = {"metric": METRIC}
+    main_r = res["fp32c"]
+    value = units / main_r["step_s"]
+    achieved = wpp * units / main_r["kern_s"]
+    line.update({
+        "value": value,
+        "unit": "lattice-point evals/s" if args.workload != "mdi_d100_gauss" else "factor evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": main_r["step_s"] * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": config,
+        "roofline": {
+            "bound": "alu",
+            "achieved": achieved / 1e12,
+            "peak": PEAK_LANE_OPS / 1e12,
+            "unit": "T VALU lane-ops/s",
+            "frac": achieved / PEAK_LANE_OPS,
+            "traffic": None,
+            "work_per_unit": wpp,
+            "kernel_us": main_r["kern_s"] * 1e6,
+        },
+        "eager_latency_us": main_r["lat_s"] * 1e6,
+        "fp64": {"value": units / res["fp64"]["step_s"], "ms_per_step": res["fp64"]["step_s"] * 1e3,
+                 "kernel_us": res["fp64"]["kern_s"] * 1e6},
+    })
+
+    if not args.no_cpu_baseline:
+        if args.workload == "mdi_d100_gauss":
+            rate, reps, vals = oracle_mdi_baseline(prob, len(prob.params), args.cpu_seconds)
+            qs32, qs64 = res["fp32c"]["q"], res["fp64"]["q"]
+            e32 = max(abs(qs32[s] - v) / abs(v) for s, v in enumerate(vals))
+            e64 = max(abs(qs64[s] - v) / abs(v) for s, v in enumerate(vals))
+            sample = f"first {reps} of {len(qs32)} parameter sets, d=100, N=64"
+        else:
+            rate, reps, qo, ao = oracle_baseline(prob, args.cpu_seconds)
+            e32 = abs(res["fp32c"]["q"] - qo) / max(abs(qo), ao)
+            e64 = abs(res["fp64"]["q"] - qo) / max(abs(qo), ao)
+            sample = f"full workload (n={prob.n} points) repeated {reps} times"
+        line["cpu_baseline"] = {"value": rate, "unit": line["unit"], "cores": 1, "kind": "oracle",
+                                "sample": sample}
+        line["rel_err"] = e32
+        line["fp64"]["rel_err"] = e64
+        line["meets_1e-6"] = bool(e32 <= 1e-6)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

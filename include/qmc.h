@@ -1,0 +1,173 @@
+/*
+ * qmc.h -- C ABI of libqmc.so: rank-1 lattice multi-summation on MI355X (gfx950).
+ *
+ * The library evaluates the quasi-Monte Carlo lattice rule of Zhong & Feng,
+ * "An efficient implementation algorithm for quasi-Monte Carlo approximations of
+ * high-dimensional integrals" (arXiv 2404.08867):
+ *
+ *   plain form   Q = (1/n) sum_{i=0}^{n-1} f(x_i),  x_ij = { k_ij / n + Delta_j },
+ *                k_ij = (i z_j) mod n                      (eq. 1.2, eq. 2.1, Sec. 2.1 shifted lattice)
+ *   MDI-LR form  Qhat = (prod_k N_k)^-1 sum_{s} f((s_1 + 1/2)/N_1, ..., (s_d + 1/2)/N_d)
+ *                evaluated by dimension sweeps           (Sec. 3.2 improved rule, eq. iQMC,
+ *                                                          Algorithms 1 and 2 with m = 1)
+ *
+ * Integrand families (fixed parameter layout, FP64, device memory):
+ *   QMC_EXP_SUM       f(x) = exp(sum_j c_j x_j)                    params: c[d]
+ *   QMC_PRODUCT_PEAK  f(x) = prod_j 1 / (c_j^-2 + (x_j - w_j)^2)   params: c[d], w[d]
+ *   QMC_GAUSSIAN      f(x) = exp(-sum_j c_j^2 (x_j - w_j)^2)       params: c[d], w[d]
+ *   QMC_OSCILLATORY   f(x) = cos(2 pi u + sum_j c_j x_j)           params: u, c[d]
+ * (the families of the paper's Tests 3-7: Gaussian, exp of a signed sum,
+ *  product peak, cos of a sum -- with per-direction parameters).
+ *
+ * Conventions for every entry point:
+ *   - Every call returns a qmc_status; no C++ exception crosses the ABI.  On an
+ *     error nothing is launched and qmc_last_error() (thread-local) says why.
+ *   - "device" arrays are caller-owned HIP device allocations; "host" arrays are
+ *     ordinary host memory.  The library never frees caller memory.
+ *   - Launches are asynchronous on `stream` (a hipStream_t; NULL = the default
+ *     stream).  Results are valid once the stream has been synchronised.
+ *   - No entry point that launches work allocates memory.  Scratch space comes
+ *     from the caller's workspace `ws` (device, 256-byte aligned, at least the
+ *     size reported by the matching *_workspace_size query).  Its first 1 MiB
+ *     holds completion counters: a workspace must be zero-filled once before its
+ *     first use, and every call leaves the counters at zero again, so one
+ *     workspace serves any sequence of calls to any entry point without clearing.
+ *     Calls that run concurrently need distinct workspaces.
+ *   - Scalar arguments are validated before anything is launched:
+ *       1 <= d <= 1024, 1 <= n < 2^31, 1 <= nsets <= 4096 (qmc_mdi_lr: 2^24),
+ *       valid family and precision.  z_j in [0, n) and Delta_j in [0, 1) are the
+ *       caller's contract for device arrays (not read back on the host).
+ *   - Results are deterministic: every reduction runs in a fixed order, so a
+ *     given call on given inputs returns bit-identical values on every run.
+ */
+#ifndef QMC_H
+#define QMC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    QMC_OK = 0,
+    QMC_ERR_INVALID_ARG = 1,   /* a scalar or pointer argument is out of its documented range */
+    QMC_ERR_UNSUPPORTED = 2,   /* valid request the library does not implement */
+    QMC_ERR_WORKSPACE = 3,     /* workspace missing, misaligned or smaller than required */
+    QMC_ERR_OUT_OF_MEMORY = 4, /* a plan-creation allocation failed */
+    QMC_ERR_DEVICE = 5         /* the HIP runtime reported an error */
+} qmc_status;
+
+typedef enum {
+    QMC_EXP_SUM = 0,
+    QMC_PRODUCT_PEAK = 1,
+    QMC_GAUSSIAN = 2,
+    QMC_OSCILLATORY = 3
+} qmc_family;
+
+/* QMC_FP64: every arithmetic step in IEEE double precision.
+ * QMC_FP32_COMPENSATED: exact integer indices; the index-to-coordinate map, the
+ * argument sums and all accumulation in double; the per-point transcendental
+ * (exp2, cos, reciprocal) and the product-peak factors in single precision.
+ * Its relative error against the FP64 rule is reported by the tests and the
+ * benchmark for every workload (target <= 1e-6). */
+typedef enum { QMC_FP64 = 0, QMC_FP32_COMPENSATED = 1 } qmc_precision;
+
+/* How qmc_mdi_lr_dims obtains n for the Korobov lattice z(a) (Lemma 3.2, eq. 3.5). */
+typedef enum {
+    QMC_N_A_POW_D = 0,         /* n = a^d:      N_k = a for every k                     */
+    QMC_N_ONE_PLUS_A_POW_D = 1,/* n = 1 + a^d:  N_k = a (k < d), N_d = a + 1             */
+    QMC_N_EXPLICIT = 2         /* n given:      eq. 3.5 on z(a) = (1, a, ..) mod n        */
+} qmc_n_mode;
+
+/* ---- library information ------------------------------------------------- */
+const char* qmc_version(void);
+const char* qmc_status_string(qmc_status s);
+/* Message of the last failing call on this thread ("" if none). */
+const char* qmc_last_error(void);
+
+/* ---- host helpers ------------------------------------------------------ */
+
+/* Korobov generating vector (Sec. 2.2, Korobov-lattice example):
+ *   z_out[j] = a^j mod n, j = 0..d-1, computed with exact 64-bit modular products.
+ * z_out: host, d entries.  Requires 1 <= d <= 1024, 1 <= n < 2^31, 0 <= a.
+ * gcd(a, n) = 1 is not enforced (the rule is defined for any z). */
+qmc_status qmc_korobov(int32_t d, int64_t n, int64_t a, int64_t* z_out);
+
+/* Node counts of the transformed tensor grid for the Korobov lattice (eq. 3.5):
+ *   N_i = lcm(z_i, z_{i+1}) / min(z_i, z_{i+1}) for i < d,  N_d = ceil(n / z_d),
+ * with n chosen by n_mode (n_explicit is used only by QMC_N_EXPLICIT).
+ * N_out: host, d entries.  Fails with QMC_ERR_INVALID_ARG when a count would
+ * exceed 2^20. */
+qmc_status qmc_mdi_lr_dims(int32_t d, int64_t a, int32_t n_mode, int64_t n_explicit,
+                           int32_t* N_out);
+
+/* Number of FP64 parameters of `family` at dimension d (d, 2d, 2d or d + 1). */
+qmc_status qmc_param_count(int32_t family, int32_t d, int32_t* count);
+
+/* Workspace bytes sufficient for qmc_lattice_sum, qmc_lattice_sum_adjoint and
+ * qmc_mdi_lr on problems with d <= max_d, n <= max_n and nsets <= max_sets. */
+qmc_status qmc_workspace_size(int32_t max_d, int64_t max_n, int32_t max_sets, size_t* bytes);
+
+/* ---- the plain rule ----------------------------------------------------- */
+
+/* Plain rank-1 lattice rule, fused in one launch: exact integer point indices
+ * generated in registers, coordinates, integrand, per-thread accumulation,
+ * wavefront and workgroup reductions, and a fixed-order cross-workgroup sum.
+ *   Q_s = (1/n) sum_{i=0}^{n-1} f_s(x_i),   s = 0..nsets-1,
+ * with x_ij = {k_ij / n + shift_j}, k_ij = (i z_j) mod n (eq. 1.2, eq. 2.1; the
+ * shifted lattice of Sec. 2.1).  All nsets parameter sets share z and shift.
+ *   z       device int64[d], 0 <= z_j < n
+ *   shift   device double[d] in [0,1), or NULL for the unshifted lattice
+ *   params  device double[nsets][qmc_param_count(family, d)]
+ *   q_out   device double[nsets]
+ *   ws      device workspace of qmc_workspace_size(d, n, nsets) bytes */
+qmc_status qmc_lattice_sum(int32_t d, int64_t n, const int64_t* z, const double* shift,
+                           int32_t family, const double* params, int32_t nsets,
+                           int32_t precision, double* q_out, void* ws, size_t ws_bytes,
+                           void* stream);
+
+/* Launch configuration of the plain-sum kernel.  Zero fields mean "choose
+ * automatically".  points_per_thread must be 0, 4, 8 or 16 (the tile is
+ * 256 * points_per_thread consecutive points); max_blocks caps the persistent
+ * grid per parameter set (1 .. 2048, and never above the workspace bound). */
+typedef struct {
+    int32_t points_per_thread;
+    int32_t max_blocks;
+} qmc_launch_config;
+
+/* qmc_lattice_sum with an explicit launch configuration (cfg may be NULL).
+ * The result does not depend on the configuration beyond rounding order. */
+qmc_status qmc_lattice_sum_ex(int32_t d, int64_t n, const int64_t* z, const double* shift,
+                              int32_t family, const double* params, int32_t nsets,
+                              int32_t precision, double* q_out, void* ws, size_t ws_bytes,
+                              void* stream, const qmc_launch_config* cfg);
+
+/* Debug export of the point indices (eq. 2.1): k_out[r*d + j] = ((i0 + r) z_j) mod n
+ * for r = 0..count-1, computed by the same device index generator as the sums.
+ *   z      device int64[d];  k_out device int32[count*d];  0 <= i0, count <= 2^26. */
+qmc_status qmc_lattice_points(int32_t d, int64_t n, const int64_t* z, int64_t i0, int64_t count,
+                              int32_t* k_out, void* stream);
+
+/* ---- the MDI-LR form ---------------------------------------------------- */
+
+/* MDI-LR (Algorithm 2 driving Algorithm 1 with m = 1) for the improved rule:
+ *   Qhat_s = prod_k M_{s,k},  M_{s,k} = (1/N_k) sum_{t=0}^{N_k-1} phi_{s,k}((t + 1/2)/N_k),
+ * the dimension sweep of a product-form integrand (the oscillatory family is the
+ * real part of a complex product with the factor e^{2 pi i u}).  Each sweep step
+ * sums one direction out of the symbolic product, as eq. 2.14c does.
+ *   N       device int32[d], 1 <= N_k <= 2^20 (e.g. from qmc_mdi_lr_dims); values
+ *           outside that range are clamped into it on the device
+ *   nsets   1 .. 2^24 parameter sets (one launch; no workspace is used)
+ *   params  device double[nsets][qmc_param_count(family, d)]
+ *   q_out   device double[nsets] */
+qmc_status qmc_mdi_lr(int32_t d, const int32_t* N, int32_t family, const double* params,
+                      int32_t nsets, int32_t precision, double* q_out, void* ws,
+                      size_t ws_bytes, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* QMC_H */

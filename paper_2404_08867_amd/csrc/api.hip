@@ -1,0 +1,265 @@
+// C ABI of libqmc.so: argument validation, error reporting and dispatch to the
+// kernel launchers.  Nothing here allocates device memory; see include/qmc.h.
+#include <stdarg.h>
+#include <stdio.h>
+
+#include <string>
+
+#include "qmc.h"
+#include "kernels.hpp"
+
+namespace {
+
+thread_local std::string g_last_error;
+
+qmc_status fail(qmc_status s, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return s;
+}
+
+qmc_status ok() {
+    g_last_error.clear();
+    return QMC_OK;
+}
+
+qmc_status from_hip(hipError_t e, const char* where) {
+    if (e == hipSuccess) return ok();
+    return fail(QMC_ERR_DEVICE, "%s: HIP error %d (%s)", where, (int)e, hipGetErrorString(e));
+}
+
+constexpr int kMaxD = 1024;
+constexpr int64_t kMaxN = (int64_t)1 << 31;  // exclusive
+constexpr int kMaxSets = 4096;           // plain sums: one grid row and 33 counters per set
+constexpr int kMaxMdiSets = 1 << 24;     // MDI-LR: sets are spread over workgroups
+constexpr int64_t kMaxNodes = (int64_t)1 << 20;
+constexpr int64_t kMaxExport = (int64_t)1 << 26;
+
+int param_count(int family, int d) {
+    switch (family) {
+        case QMC_EXP_SUM: return d;
+        case QMC_PRODUCT_PEAK: return 2 * d;
+        case QMC_GAUSSIAN: return 2 * d;
+        case QMC_OSCILLATORY: return d + 1;
+        default: return -1;
+    }
+}
+
+qmc_status check_common(int32_t d, int32_t family, int32_t nsets, int32_t precision,
+                        int32_t max_sets = kMaxSets) {
+    if (d < 1 || d > kMaxD) return fail(QMC_ERR_INVALID_ARG, "d = %d outside [1, %d]", d, kMaxD);
+    if (param_count(family, d) < 0) return fail(QMC_ERR_INVALID_ARG, "unknown family %d", family);
+    if (nsets < 1 || nsets > max_sets)
+        return fail(QMC_ERR_INVALID_ARG, "nsets = %d outside [1, %d]", nsets, max_sets);
+    if (precision != QMC_FP64 && precision != QMC_FP32_COMPENSATED)
+        return fail(QMC_ERR_INVALID_ARG, "unknown precision %d", precision);
+    return QMC_OK;
+}
+
+qmc_status check_workspace(const void* ws, size_t ws_bytes, size_t need) {
+    if (!ws) return fail(QMC_ERR_WORKSPACE, "workspace pointer is NULL");
+    if (((uintptr_t)ws) % 256 != 0) return fail(QMC_ERR_WORKSPACE, "workspace not 256-byte aligned");
+    if (ws_bytes < need)
+        return fail(QMC_ERR_WORKSPACE, "workspace has %zu bytes, %zu needed", ws_bytes, need);
+    return QMC_OK;
+}
+
+int64_t gcd64(int64_t a, int64_t b) {
+    while (b) {
+        const int64_t t = a % b;
+        a = b;
+        b = t;
+    }
+    return a;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* qmc_version(void) { return "qmc-mi355x 0.1.0 (gfx950)"; }
+
+const char* qmc_status_string(qmc_status s) {
+    switch (s) {
+        case QMC_OK: return "ok";
+        case QMC_ERR_INVALID_ARG: return "invalid argument";
+        case QMC_ERR_UNSUPPORTED: return "unsupported";
+        case QMC_ERR_WORKSPACE: return "workspace too small or misaligned";
+        case QMC_ERR_OUT_OF_MEMORY: return "out of memory";
+        case QMC_ERR_DEVICE: return "device error";
+    }
+    return "unknown status";
+}
+
+const char* qmc_last_error(void) { return g_last_error.c_str(); }
+
+qmc_status qmc_korobov(int32_t d, int64_t n, int64_t a, int64_t* z_out) {
+    if (d < 1 || d > kMaxD) return fail(QMC_ERR_INVALID_ARG, "d = %d outside [1, %d]", d, kMaxD);
+    if (n < 1 || n >= kMaxN) return fail(QMC_ERR_INVALID_ARG, "n = %lld outside [1, 2^31)", (long long)n);
+    if (a < 0) return fail(QMC_ERR_INVALID_ARG, "a = %lld is negative", (long long)a);
+    if (!z_out) return fail(QMC_ERR_INVALID_ARG, "z_out is NULL");
+    // z_j = a^j mod n by repeated modular multiplication; residues < 2^31 so
+    // every product fits in 62 bits.
+    const int64_t am = a % n;
+    int64_t r = 1 % n;
+    for (int32_t j = 0; j < d; ++j) {
+        z_out[j] = r;
+        r = (r * am) % n;
+    }
+    return ok();
+}
+
+qmc_status qmc_mdi_lr_dims(int32_t d, int64_t a, int32_t n_mode, int64_t n_explicit,
+                           int32_t* N_out) {
+    if (d < 1 || d > kMaxD) return fail(QMC_ERR_INVALID_ARG, "d = %d outside [1, %d]", d, kMaxD);
+    if (!N_out) return fail(QMC_ERR_INVALID_ARG, "N_out is NULL");
+    if (a < 1 || a > kMaxNodes) return fail(QMC_ERR_INVALID_ARG, "a = %lld outside [1, 2^20]", (long long)a);
+    switch (n_mode) {
+        case QMC_N_A_POW_D:
+            // z = (1, a, ..., a^{d-1}) is not reduced (n = a^d > a^{d-1}), so eq. 3.5 gives
+            // N_i = lcm(a^{i-1}, a^i) / a^{i-1} = a and N_d = ceil(a^d / a^{d-1}) = a.
+            for (int32_t k = 0; k < d; ++k) N_out[k] = (int32_t)a;
+            return ok();
+        case QMC_N_ONE_PLUS_A_POW_D:
+            // Same z; N_d = ceil((1 + a^d) / a^{d-1}) = a + 1.
+            if (a + 1 > kMaxNodes) return fail(QMC_ERR_INVALID_ARG, "N_d = a + 1 exceeds 2^20");
+            for (int32_t k = 0; k + 1 < d; ++k) N_out[k] = (int32_t)a;
+            N_out[d - 1] = (int32_t)(a + 1);
+            return ok();
+        case QMC_N_EXPLICIT: {
+            const int64_t n = n_explicit;
+            if (n < 1 || n >= kMaxN) return fail(QMC_ERR_INVALID_ARG, "n = %lld outside [1, 2^31)", (long long)n);
+            int64_t zi = 1 % n;
+            for (int32_t k = 0; k < d; ++k) {
+                const int64_t zn = (zi * (a % n)) % n;
+                int64_t Nk;
+                if (k + 1 < d) {
+                    if (zi == 0 || zn == 0)
+                        return fail(QMC_ERR_INVALID_ARG, "z has a zero entry at %d; eq. 3.5 is undefined", k);
+                    const int64_t g = gcd64(zi, zn);
+                    const int64_t mn = zi < zn ? zi : zn;
+                    Nk = (zi / g) * zn / mn;  // lcm / min
+                } else {
+                    if (zi == 0) return fail(QMC_ERR_INVALID_ARG, "z_d = 0; eq. 3.5 is undefined");
+                    Nk = (n + zi - 1) / zi;
+                }
+                if (Nk < 1 || Nk > kMaxNodes)
+                    return fail(QMC_ERR_INVALID_ARG, "N_%d = %lld exceeds 2^20", k + 1, (long long)Nk);
+                N_out[k] = (int32_t)Nk;
+                zi = zn;
+            }
+            return ok();
+        }
+        default:
+            return fail(QMC_ERR_INVALID_ARG, "unknown n_mode %d", n_mode);
+    }
+}
+
+qmc_status qmc_param_count(int32_t family, int32_t d, int32_t* count) {
+    if (!count) return fail(QMC_ERR_INVALID_ARG, "count is NULL");
+    if (d < 1 || d > kMaxD) return fail(QMC_ERR_INVALID_ARG, "d = %d outside [1, %d]", d, kMaxD);
+    const int p = param_count(family, d);
+    if (p < 0) return fail(QMC_ERR_INVALID_ARG, "unknown family %d", family);
+    *count = p;
+    return ok();
+}
+
+qmc_status qmc_workspace_size(int32_t max_d, int64_t max_n, int32_t max_sets, size_t* bytes) {
+    if (!bytes) return fail(QMC_ERR_INVALID_ARG, "bytes is NULL");
+    if (max_d < 1 || max_d > kMaxD) return fail(QMC_ERR_INVALID_ARG, "max_d = %d outside [1, %d]", max_d, kMaxD);
+    if (max_n < 1 || max_n >= kMaxN) return fail(QMC_ERR_INVALID_ARG, "max_n outside [1, 2^31)");
+    if (max_sets < 1 || max_sets > kMaxSets) return fail(QMC_ERR_INVALID_ARG, "max_sets outside [1, %d]", kMaxSets);
+    // The counter region is fixed; the scratch per set shrinks as nsets grows,
+    // so the bound is the maximum over nsets <= max_sets.
+    size_t need = 0;
+    for (int s = 1; s <= max_sets; s = (s < 64 ? s + 1 : s * 2)) {
+        const size_t b = qmc::plain_workspace_bytes(s);
+        if (b > need) need = b;
+    }
+    const size_t b = qmc::plain_workspace_bytes(max_sets);
+    if (b > need) need = b;
+    *bytes = need;
+    return ok();
+}
+
+qmc_status qmc_lattice_sum(int32_t d, int64_t n, const int64_t* z, const double* shift,
+                           int32_t family, const double* params, int32_t nsets,
+                           int32_t precision, double* q_out, void* ws, size_t ws_bytes,
+                           void* stream) {
+    return qmc_lattice_sum_ex(d, n, z, shift, family, params, nsets, precision, q_out, ws,
+                              ws_bytes, stream, nullptr);
+}
+
+qmc_status qmc_lattice_sum_ex(int32_t d, int64_t n, const int64_t* z, const double* shift,
+                              int32_t family, const double* params, int32_t nsets,
+                              int32_t precision, double* q_out, void* ws, size_t ws_bytes,
+                              void* stream, const qmc_launch_config* cfg) {
+    qmc_status s = check_common(d, family, nsets, precision);
+    if (s != QMC_OK) return s;
+    if (n < 1 || n >= kMaxN) return fail(QMC_ERR_INVALID_ARG, "n = %lld outside [1, 2^31)", (long long)n);
+    if (!z || !params || !q_out) return fail(QMC_ERR_INVALID_ARG, "z, params and q_out must be non-NULL");
+    s = check_workspace(ws, ws_bytes, qmc::plain_workspace_bytes(nsets));
+    if (s != QMC_OK) return s;
+    qmc::PlainLaunch L{};
+    L.d = d;
+    L.n = (uint32_t)n;
+    L.z = z;
+    L.shift = shift;
+    L.family = family;
+    L.params = params;
+    L.P = param_count(family, d);
+    L.nsets = nsets;
+    L.fp32 = precision == QMC_FP32_COMPENSATED;
+    L.q_out = q_out;
+    L.ws = ws;
+    L.points_per_thread = 0;
+    L.max_blocks = 0;
+    if (cfg) {
+        const int m = cfg->points_per_thread;
+        if (m != 0 && m != 4 && m != 8 && m != 16)
+            return fail(QMC_ERR_INVALID_ARG, "points_per_thread = %d is not 0, 4, 8 or 16", m);
+        if (cfg->max_blocks < 0 || cfg->max_blocks > qmc::kMaxSumBlocksPerSet)
+            return fail(QMC_ERR_INVALID_ARG, "max_blocks = %d outside [0, %d]", cfg->max_blocks,
+                        qmc::kMaxSumBlocksPerSet);
+        L.points_per_thread = m;
+        L.max_blocks = cfg->max_blocks;
+    }
+    return from_hip(qmc::launch_lattice_sum(L, (hipStream_t)stream), "qmc_lattice_sum");
+}
+
+qmc_status qmc_lattice_points(int32_t d, int64_t n, const int64_t* z, int64_t i0, int64_t count,
+                              int32_t* k_out, void* stream) {
+    if (d < 1 || d > kMaxD) return fail(QMC_ERR_INVALID_ARG, "d = %d outside [1, %d]", d, kMaxD);
+    if (n < 1 || n >= kMaxN) return fail(QMC_ERR_INVALID_ARG, "n = %lld outside [1, 2^31)", (long long)n);
+    if (i0 < 0 || i0 >= kMaxN) return fail(QMC_ERR_INVALID_ARG, "i0 outside [0, 2^31)");
+    if (count < 0 || count > kMaxExport) return fail(QMC_ERR_INVALID_ARG, "count outside [0, 2^26]");
+    if (!z || (!k_out && count > 0)) return fail(QMC_ERR_INVALID_ARG, "z and k_out must be non-NULL");
+    return from_hip(qmc::launch_lattice_points(d, (uint32_t)n, z, i0, count, k_out, (hipStream_t)stream),
+                    "qmc_lattice_points");
+}
+
+qmc_status qmc_mdi_lr(int32_t d, const int32_t* N, int32_t family, const double* params,
+                      int32_t nsets, int32_t precision, double* q_out, void* ws, size_t ws_bytes,
+                      void* stream) {
+    (void)ws;
+    (void)ws_bytes;  // the sweep needs no scratch space
+    qmc_status s = check_common(d, family, nsets, precision, kMaxMdiSets);
+    if (s != QMC_OK) return s;
+    if (!N || !params || !q_out) return fail(QMC_ERR_INVALID_ARG, "N, params and q_out must be non-NULL");
+    qmc::MdiLaunch L{};
+    L.d = d;
+    L.N = N;
+    L.family = family;
+    L.params = params;
+    L.P = param_count(family, d);
+    L.nsets = nsets;
+    L.fp32 = precision == QMC_FP32_COMPENSATED;
+    L.q_out = q_out;
+    return from_hip(qmc::launch_mdi_lr(L, (hipStream_t)stream), "qmc_mdi_lr");
+}
+
+}  // extern "C"

@@ -1,0 +1,204 @@
+// Device-side building blocks shared by the lattice-sum kernels (gfx950, wave64).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace qmc {
+
+constexpr int kWave = 64;         // CDNA wavefront width
+constexpr int kBlock = 256;       // threads per workgroup of the sum kernels
+constexpr int kWaves = kBlock / kWave;
+constexpr int kDimChunk = 64;     // dimensions whose index tables sit in LDS at once
+
+// ---------------------------------------------------------------------------
+// Exact modular arithmetic on lattice indices (eq. 2.1: k = (i z) mod n).
+// Indices are residues in [0, n) with n < 2^31, so sums of two residues fit in
+// 32 bits and products of two residues fit in 62 bits.
+// ---------------------------------------------------------------------------
+
+// (a * b) mod n for 0 <= a, b < n < 2^31.  The quotient is estimated in double
+// precision -- off by at most 2 because a*b < n^2 < 2^62 -- and the remainder is
+// corrected exactly in 64-bit integers with a fixed number of conditional steps
+// (arguments outside the contract give a wrong residue, never a long loop).
+__device__ __forceinline__ uint32_t mulmod(uint64_t a, uint64_t b, uint32_t n, double inv_n) {
+    const uint64_t p = a * b;
+    const uint64_t q = (uint64_t)floor((double)p * inv_n);
+    int64_t r = (int64_t)(p - q * (uint64_t)n);
+    const int64_t nn = (int64_t)n;
+    r = r < 0 ? r + nn : r;
+    r = r < 0 ? r + nn : r;
+    r = r < 0 ? r + nn : r;
+    r = r >= nn ? r - nn : r;
+    r = r >= nn ? r - nn : r;
+    r = r >= nn ? r - nn : r;
+    return (uint32_t)r;
+}
+
+// (a * b) mod n when a * b < 2^52: the product and the remainder are exact in
+// double precision, and the floor of the rounded quotient is off by at most one.
+__device__ __forceinline__ uint32_t mulmod_small(uint32_t a, uint32_t b, double dn, double inv_n) {
+    const double p = (double)a * (double)b;
+    const double q = floor(p * inv_n);
+    double r = fma(-q, dn, p);
+    r = r < 0.0 ? r + dn : r;
+    r = r >= dn ? r - dn : r;
+    return (uint32_t)r;
+}
+
+// (a + b) mod n for residues a, b in [0, n): if a + b < n the subtraction wraps
+// to a huge unsigned value and the minimum picks a + b.
+__device__ __forceinline__ uint32_t addmod(uint32_t a, uint32_t b, uint32_t n) {
+    const uint32_t t = a + b;
+    return min(t, t - n);
+}
+
+// One step k <- (k + st) mod n with stm = st - n precomputed (mod 2^32):
+// two independent adds and a min (three VALU operations).
+__device__ __forceinline__ uint32_t stepmod(uint32_t k, uint32_t st, uint32_t stm) {
+    return min(k + st, k + stm);
+}
+
+// ---------------------------------------------------------------------------
+// Deterministic reductions (fixed order: xor butterfly within the wave, waves in
+// index order across the workgroup).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, kWave);
+    return v;
+}
+
+// Sum over the workgroup; every thread receives the total.  `red` is an LDS
+// scratch array of at least kWaves doubles.  Ends with a barrier.
+__device__ __forceinline__ double block_sum(double v, double* red) {
+    v = wave_sum(v);
+    const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
+    __syncthreads();
+    if (lane == 0) red[wv] = v;
+    __syncthreads();
+    double t = 0.0;
+#pragma unroll
+    for (int w = 0; w < kWaves; ++w) t += red[w];
+    __syncthreads();
+    return t;
+}
+
+// Three sums at once (two doubles and a small int carried as a double); every
+// thread receives the totals.  `red` holds 3 * kWaves doubles.
+__device__ __forceinline__ void block_sum3(double& a, double& b, int& c, double* red) {
+    double x = a, y = b, w = (double)c;
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+        x += __shfl_xor(x, off, kWave);
+        y += __shfl_xor(y, off, kWave);
+        w += __shfl_xor(w, off, kWave);
+    }
+    const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
+    __syncthreads();
+    if (lane == 0) {
+        red[wv] = x;
+        red[kWaves + wv] = y;
+        red[2 * kWaves + wv] = w;
+    }
+    __syncthreads();
+    double tx = 0.0, ty = 0.0, tw = 0.0;
+#pragma unroll
+    for (int i = 0; i < kWaves; ++i) {
+        tx += red[i];
+        ty += red[kWaves + i];
+        tw += red[2 * kWaves + i];
+    }
+    __syncthreads();
+    a = tx;
+    b = ty;
+    c = (int)tw;
+}
+
+// ---------------------------------------------------------------------------
+// Cross-workgroup completion: each workgroup publishes its partial and takes a
+// ticket; the workgroup that draws the last ticket reads every partial and
+// resets the ticket to zero for the next call.
+//
+// Only device-scope atomic accesses carry data between workgroups: partials are
+// written with device-scope stores (write-through past the per-XCD L2) and read
+// with device-scope loads, and every store is waited for before the ticket is
+// taken.  This avoids the whole-L2 write-back and invalidate that an agent-scope
+// release/acquire fence costs on a multi-XCD device.
+//
+// Two levels keep every counter lightly contended: workgroup b of G belongs to
+// group g = b % NG (NG = min(G, kReduceGroups)); the last workgroup of a group sums
+// the group's partials in index order and takes a ticket on the top counter; the
+// last group sums the NG group partials in order.  The order of every addition is
+// fixed, so results are bit-reproducible.
+// ---------------------------------------------------------------------------
+constexpr int kReduceGroups = 32;
+
+__device__ __forceinline__ void publish_partial(double* slot, double v) {
+    __hip_atomic_store(slot, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ double read_partial(const double* slot) {
+    return __hip_atomic_load(const_cast<double*>(slot), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// One thread: wait until this wave's device-scope stores are complete, then take
+// a ticket; the caller that draws the last of `expected` tickets resets it.
+__device__ __forceinline__ bool take_ticket(uint32_t* ticket, uint32_t expected) {
+    __builtin_amdgcn_s_waitcnt(0);
+    const uint32_t t = __hip_atomic_fetch_add(ticket, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (t + 1 == expected) {
+        __hip_atomic_store(ticket, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        return true;
+    }
+    return false;
+}
+
+// Workspace layout shared by every entry point: the first kTicketBytes hold
+// counters that are zero between calls (each call returns the ones it used to
+// zero); everything after is scratch that needs no initialisation.  Keeping the
+// counters at fixed offsets means that no call can find another call's scratch
+// data where it expects a zero counter, whatever sizes the two calls had.
+constexpr size_t kTicketBytes = size_t(1) << 20;
+constexpr int kTicketsPerReduction = kReduceGroups + 1;
+
+// Workspace slots of one reduction over G workgroups.
+struct GridSlots {
+    double* partials;        // [G] scratch
+    double* group_partials;  // [kReduceGroups] scratch
+    uint32_t* tickets;       // [kReduceGroups + 1] counters: per group, then the top one
+};
+
+// Scratch doubles of one reduction over G workgroups.
+__host__ __device__ constexpr size_t grid_scratch_doubles(int G) { return (size_t)G + kReduceGroups; }
+
+// Called by every thread of workgroup b with its workgroup total v.  Returns true
+// in exactly one workgroup, whose threads then all hold the grand total.
+// `red` is LDS scratch for block_sum; `flag` one LDS int.
+__device__ __forceinline__ bool grid_sum(double v, int b, int G, const GridSlots& s, double* red,
+                                         int* flag, double& total) {
+    const int NG = G < kReduceGroups ? G : kReduceGroups;
+    const int g = b % NG;
+    const int members = (G - g + NG - 1) / NG;
+    if (threadIdx.x == 0) {
+        publish_partial(&s.partials[b], v);
+        *flag = take_ticket(&s.tickets[g], (uint32_t)members) ? 1 : 0;
+    }
+    __syncthreads();
+    if (!*flag) return false;
+    double t = 0.0;
+    for (int i = threadIdx.x; i < members; i += kBlock) t += read_partial(&s.partials[g + i * NG]);
+    t = block_sum(t, red);
+    if (threadIdx.x == 0) {
+        publish_partial(&s.group_partials[g], t);
+        *flag = take_ticket(&s.tickets[kReduceGroups], (uint32_t)NG) ? 1 : 0;
+    }
+    __syncthreads();
+    if (!*flag) return false;
+    t = 0.0;
+    for (int i = threadIdx.x; i < NG; i += kBlock) t += read_partial(&s.group_partials[i]);
+    total = block_sum(t, red);
+    return true;
+}
+
+}  // namespace qmc

@@ -1,0 +1,230 @@
+// Integrand families of the lattice sum, written for the dims-outer / points-inner
+// loop of the sum kernels.  Each family is split into
+//   Dim      constants of one direction j (computed once per workgroup, kept in LDS),
+//   Acc      the running per-point state over directions (registers),
+//   step     one direction's contribution for lattice index k in [0, n),
+//   finish   the per-point transcendental, returning f(x) / scale,
+// and three workgroup-wide sums over directions (block_terms) that give the
+// initial state and the final scale.  Coordinates are x_j = (k + sfrac_j) / n
+// where sfrac_j is the fractional part of shift_j * n (the whole part is folded
+// into the start index), so the shifted lattice of Sec. 2.1 costs nothing per point.
+//
+// Argument sums (exp-sum, Gaussian, oscillatory) are carried in double in both
+// precisions: FP64 FMA issues at the same rate as FP32 on gfx950 when packed
+// FP32 is not used, and it keeps the argument exact to ~1e-15 for d up to 1024.
+// QMC_FP32_COMPENSATED evaluates the per-point transcendental (exp2, cos,
+// reciprocal) and the product-peak factors in single precision.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <type_traits>
+
+namespace qmc {
+
+constexpr double kLog2e = 1.4426950408889634074;
+constexpr double kSqrtLog2e = 1.2011224087864497918;
+constexpr double kInv2Pi = 0.15915494309189533577;
+
+enum FamilyId { kExpSum = 0, kProductPeak = 1, kGaussian = 2, kOscillatory = 3 };
+
+// exp2 of a double argument: split off the nearest integer in double, take the
+// fractional power in single precision (|fr| <= 1/2) and rescale exactly.
+__device__ __forceinline__ double exp2_split_f32(double s) {
+    const double r = rint(s);
+    const float fr = (float)(s - r);
+    return ldexp((double)__builtin_amdgcn_exp2f(fr), (int)r);
+}
+
+// ------------------------------------------------------------------ exp-sum
+// f = exp(sum_j c_j x_j) = 2^{sum_j a_j (k_j + sfrac_j)} with a_j = c_j log2(e) / n.
+// The argument is centred by h = log2(e) sum_j c_j / 2 (folded into the scale).
+template <bool FP32>
+struct ExpSum {
+    struct Dim {
+        double a;
+    };
+    struct Acc {
+        double s;
+    };
+    static constexpr int kRenorm = 0;
+    static constexpr bool kBlockTerms = true;
+    __device__ static void block_terms(const double* p, int d, int j, double inv_n, double sfrac,
+                                       double& ds0, double& ds1, int& ie) {
+        const double a = p[j] * kLog2e * inv_n;
+        const double h = 0.5 * kLog2e * p[j];
+        ds0 += a * sfrac - h;
+        ds1 += h;
+        (void)d;
+        (void)ie;
+    }
+    __device__ static double extra(const double*) { return 0.0; }
+    __device__ static Dim dim(const double* p, int d, int j, double inv_n, double sfrac) {
+        (void)d;
+        (void)sfrac;
+        return Dim{p[j] * kLog2e * inv_n};
+    }
+    __device__ static Acc init(double s0) { return Acc{s0}; }
+    __device__ static void step(Acc& acc, uint32_t k, const Dim& c) {
+        acc.s = fma((double)k, c.a, acc.s);
+    }
+    __device__ static void renorm(Acc&) {}
+    __device__ static double finish(const Acc& acc) {
+        if constexpr (FP32)
+            return exp2_split_f32(acc.s);
+        else
+            return exp2(acc.s);
+    }
+    __device__ static double scale(double ds1, int ie) {
+        (void)ie;
+        return exp2(ds1);
+    }
+};
+
+// ----------------------------------------------------------------- Gaussian
+// f = exp(-sum_j c_j^2 (x_j - w_j)^2) = 2^{-sum_j y_j^2},
+// y_j = c_j sqrt(log2 e) (x_j - w_j) = b_j k + g_j.
+template <bool FP32>
+struct Gaussian {
+    struct Dim {
+        double b, g;
+    };
+    struct Acc {
+        double s;
+    };
+    static constexpr int kRenorm = 0;
+    static constexpr bool kBlockTerms = false;
+    __device__ static void block_terms(const double*, int, int, double, double, double&, double&,
+                                       int&) {}
+    __device__ static double extra(const double*) { return 0.0; }
+    __device__ static Dim dim(const double* p, int d, int j, double inv_n, double sfrac) {
+        const double c = p[j] * kSqrtLog2e, w = p[d + j];
+        const double b = c * inv_n;
+        return Dim{b, fma(b, sfrac, -c * w)};
+    }
+    __device__ static Acc init(double) { return Acc{0.0}; }
+    __device__ static void step(Acc& acc, uint32_t k, const Dim& c) {
+        const double y = fma((double)k, c.b, c.g);
+        acc.s = fma(y, y, acc.s);
+    }
+    __device__ static void renorm(Acc&) {}
+    __device__ static double finish(const Acc& acc) {
+        if constexpr (FP32)
+            return exp2_split_f32(-acc.s);
+        else
+            return exp2(-acc.s);
+    }
+    __device__ static double scale(double, int) { return 1.0; }
+};
+
+// -------------------------------------------------------------- oscillatory
+// f = cos(2 pi u + sum_j c_j x_j) = cos(2 pi T),  T = u + sum_j a_j (k_j + sfrac_j)
+// in turns, a_j = c_j / (2 pi n).  Only the fractional part of T is needed.
+template <bool FP32>
+struct Oscillatory {
+    struct Dim {
+        double a;
+    };
+    struct Acc {
+        double s;
+    };
+    static constexpr int kRenorm = 0;
+    static constexpr bool kBlockTerms = true;
+    __device__ static void block_terms(const double* p, int d, int j, double inv_n, double sfrac,
+                                       double& ds0, double&, int&) {
+        (void)d;
+        ds0 += p[1 + j] * kInv2Pi * inv_n * sfrac;
+    }
+    __device__ static double extra(const double* p) { return p[0]; }
+    __device__ static Dim dim(const double* p, int d, int j, double inv_n, double) {
+        (void)d;
+        return Dim{p[1 + j] * kInv2Pi * inv_n};
+    }
+    __device__ static Acc init(double s0) { return Acc{s0}; }
+    __device__ static void step(Acc& acc, uint32_t k, const Dim& c) {
+        acc.s = fma((double)k, c.a, acc.s);
+    }
+    __device__ static void renorm(Acc&) {}
+    __device__ static double finish(const Acc& acc) {
+        const double fr = acc.s - rint(acc.s);  // in [-1/2, 1/2]
+        if constexpr (FP32)
+            return (double)__builtin_amdgcn_cosf((float)fr);  // cos(2 pi t), t in turns
+        else
+            return cospi(2.0 * fr);
+    }
+    __device__ static double scale(double, int) { return 1.0; }
+};
+
+// ------------------------------------------------------------- product peak
+// f = prod_j 1 / (c_j^-2 + (x_j - w_j)^2).  Each factor is scaled by an exact
+// power of four sigma_j = 4^-m_j that brings it near 1, so that the running
+// product stays in range; the product is renormalised with frexp every kRenorm
+// directions and the powers of two are restored exactly at the end.
+//   q'_j = sigma_j q_j = y'^2 + g,  y' = 2^-m_j (x_j - w_j) = a k + b,  g = sigma_j c_j^-2.
+__device__ __forceinline__ int peak_pow4(double c) {
+    const double q = 1.0 / (c * c) + 1.0 / 6.0;
+    return (int)rint(0.5 * log2(q));
+}
+
+// FP32_DIMS: per-direction factors in single precision (7 VALU ops per point and
+// direction).  Their constants a, b, g are rounded to FP32 once per direction, a
+// bias that is the same for every point and grows like sqrt(d) * 2^-24 over the
+// product; the launcher therefore uses single-precision factors only for
+// d <= kPeakF32MaxDims and double-precision factors beyond.
+// FP32_FINISH: the per-point reciprocal by v_rcp_f32 instead of an IEEE divide.
+constexpr int kPeakF32MaxDims = 64;
+
+template <bool FP32_DIMS, bool FP32_FINISH>
+struct ProductPeak {
+    using T = typename std::conditional<FP32_DIMS, float, double>::type;
+    struct Dim {
+        T a, b, g;
+    };
+    struct Acc {
+        T D;
+        int E;
+    };
+    static constexpr int kRenorm = FP32_DIMS ? 16 : 64;
+    static constexpr bool kBlockTerms = true;
+    __device__ static void block_terms(const double* p, int d, int j, double, double, double&,
+                                       double&, int& ie) {
+        (void)d;
+        ie += -2 * peak_pow4(p[j]);
+    }
+    __device__ static double extra(const double*) { return 0.0; }
+    __device__ static Dim dim(const double* p, int d, int j, double inv_n, double sfrac) {
+        const double c = p[j], w = p[d + j];
+        const int m = peak_pow4(c);
+        const double s = ldexp(1.0, -m);
+        return Dim{(T)(s * inv_n), (T)(s * fma(sfrac, inv_n, -w)), (T)(s * s / (c * c))};
+    }
+    __device__ static Acc init(double) { return Acc{(T)1, 0}; }
+    __device__ static void step(Acc& acc, uint32_t k, const Dim& c) {
+        const T y = fma((T)k, c.a, c.b);
+        acc.D *= fma(y, y, c.g);
+    }
+    __device__ static void renorm(Acc& acc) {
+        if constexpr (FP32_DIMS) {
+            acc.E += __builtin_amdgcn_frexp_expf(acc.D);
+            acc.D = __builtin_amdgcn_frexp_mantf(acc.D);
+        } else {
+            acc.E += __builtin_amdgcn_frexp_exp(acc.D);
+            acc.D = __builtin_amdgcn_frexp_mant(acc.D);
+        }
+    }
+    __device__ static double finish(const Acc& acc) {
+        if constexpr (FP32_DIMS) {
+            return ldexp((double)__builtin_amdgcn_rcpf(acc.D), -acc.E);
+        } else if constexpr (FP32_FINISH) {
+            const int e = __builtin_amdgcn_frexp_exp(acc.D);
+            const float m = (float)__builtin_amdgcn_frexp_mant(acc.D);
+            return ldexp((double)__builtin_amdgcn_rcpf(m), -(acc.E + e));
+        } else {
+            return ldexp(1.0 / acc.D, -acc.E);
+        }
+    }
+    __device__ static double scale(double, int ie) { return ldexp(1.0, ie); }
+};
+
+}  // namespace qmc

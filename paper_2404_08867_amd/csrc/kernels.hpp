@@ -1,0 +1,52 @@
+// Host-side launchers of the HIP kernels (internal to libqmc.so).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace qmc {
+
+// Workgroups per set that the plain-sum launcher may use: at most
+// max(1, kMaxSumBlocks / nsets), never more than kMaxSumBlocksPerSet.
+constexpr int kMaxSumBlocks = 8192;
+constexpr int kMaxSumBlocksPerSet = 2048;
+
+struct PlainLaunch {
+    int d;
+    uint32_t n;
+    const int64_t* z;
+    const double* shift;  // may be null
+    int family;
+    const double* params;
+    int P;  // parameters per set
+    int nsets;
+    bool fp32;
+    double* q_out;
+    void* ws;
+    int points_per_thread;  // 0 = choose automatically (4, 8 or 16)
+    int max_blocks;         // 0 = choose automatically
+};
+
+int sum_blocks_per_set(int nsets);
+size_t plain_workspace_bytes(int nsets);
+hipError_t launch_lattice_sum(const PlainLaunch& a, hipStream_t stream);
+
+hipError_t launch_lattice_points(int d, uint32_t n, const int64_t* z, int64_t i0, int64_t count,
+                                 int32_t* k_out, hipStream_t stream);
+
+struct MdiLaunch {
+    int d;
+    const int32_t* N;
+    int family;
+    const double* params;
+    int P;
+    int nsets;
+    bool fp32;
+    double* q_out;
+};
+hipError_t launch_mdi_lr(const MdiLaunch& a, hipStream_t stream);
+
+int device_cu_count();
+
+}  // namespace qmc

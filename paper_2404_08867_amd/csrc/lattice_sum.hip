@@ -1,0 +1,306 @@
+// Plain rank-1 lattice rule, fused into one persistent launch (eq. 1.2, eq. 2.1):
+//   Q = (1/n) sum_{i=0}^{n-1} f(x_i),  x_ij = {(k_ij + shift_j n) / n},  k_ij = (i z_j) mod n.
+//
+// Work decomposition.  Points are cut into tiles of kBlock * M consecutive
+// indices; wave w of the workgroup owns the 64 * M points
+//   i = tile_base + w*64*M + lane + 64*m,   m = 0..M-1.
+// The loop runs over directions outside and over a thread's M points inside, so
+// that each direction's constants are loaded once per M points and the per-point
+// state is M registers whatever d is.  Indices are exact residues:
+//   start:  k = (Kw_j + Lz_j[lane]) mod n,  Kw_j = (wave_base * z_j + shift_whole_j) mod n,
+//                                           Lz_j[l] = (l * z_j) mod n,
+//   step:   k <- (k + D_j) mod n,           D_j = (64 z_j) mod n,
+// with the per-direction tables built cooperatively in LDS.  One step costs two
+// 32-bit adds and a min; no 64-bit arithmetic runs per point.
+//
+// Reduction: per-thread FP64 sums, a wave64 xor butterfly, waves in order, one
+// FP64 partial per workgroup, then the two-level fixed-order grid sum of
+// common.hpp (tickets in the workspace, reset to zero by their last user).
+#include "common.hpp"
+#include "families.hpp"
+#include "kernels.hpp"
+
+namespace qmc {
+
+struct SumArgs {
+    int d;
+    uint32_t n;
+    double inv_n;
+    const int64_t* z;
+    const double* shift;
+    const double* params;
+    int P;
+    uint32_t tiles;
+    double* q_out;
+    uint32_t* tickets;   // counter region of the workspace
+    double* scratch;     // scratch region, `scratch_stride` doubles per set
+    size_t scratch_stride;
+};
+
+__device__ __forceinline__ GridSlots set_slots(const SumArgs& a, int set, int G) {
+    GridSlots s;
+    s.partials = a.scratch + (size_t)set * a.scratch_stride;
+    s.group_partials = s.partials + G;
+    s.tickets = a.tickets + (size_t)set * kTicketsPerReduction;
+    return s;
+}
+
+__device__ __forceinline__ void split_shift(const double* shift, int j, uint32_t n, uint32_t& whole,
+                                            double& frac) {
+    if (!shift) {
+        whole = 0;
+        frac = 0.0;
+        return;
+    }
+    const double t = shift[j] * (double)n;
+    const double w = floor(t);
+    frac = t - w;
+    uint32_t wi = (uint32_t)w;
+    whole = wi >= n ? wi - n : wi;
+}
+
+template <class F, int M>
+__global__ __launch_bounds__(kBlock) void lattice_sum_kernel(const SumArgs a) {
+    using Dim = typename F::Dim;
+    using Acc = typename F::Acc;
+    constexpr uint32_t kTile = kBlock * M;
+
+    __shared__ uint32_t s_lz[kDimChunk * kWave];   // [j][lane]
+    __shared__ uint32_t s_kw[kDimChunk * kWaves];  // [j][wave]
+    __shared__ uint2 s_st[kDimChunk];              // (D_j, D_j - n)
+    __shared__ uint32_t s_sh[kDimChunk];
+    __shared__ Dim s_c[kDimChunk];
+    __shared__ double s_red[3 * kWaves];
+    __shared__ int s_last;
+
+    const int set = blockIdx.y;
+    const double* p = a.params + (size_t)set * a.P;
+    const int tid = threadIdx.x, lane = tid & (kWave - 1), wv = tid / kWave;
+    const uint32_t n = a.n;
+    const double inv_n = a.inv_n;
+    const double dn = (double)n;
+    const int d = a.d;
+
+    // Workgroup constants: sums over all directions (fixed order), one reduction
+    // for all three (the int term is a sum of small integers, exact in double).
+    double ds0 = 0.0, ds1 = 0.0;
+    int ie = 0;
+    if constexpr (F::kBlockTerms) {
+        for (int j = tid; j < d; j += kBlock) {
+            uint32_t whole;
+            double frac;
+            split_shift(a.shift, j, n, whole, frac);
+            F::block_terms(p, d, j, inv_n, frac, ds0, ds1, ie);
+        }
+        block_sum3(ds0, ds1, ie, s_red);
+    }
+    const double init0 = ds0 + F::extra(p);
+
+    // Tables that do not depend on the tile: Lz, D, the shift's whole part and
+    // the family constants of directions [j0, j0 + dc).  l * z_j < 2^37, so the
+    // exact double-precision mulmod applies.
+    auto fill_dims = [&](int j0, int dc) {
+        for (int e = tid; e < dc * kWave; e += kBlock) {
+            const int j = e / kWave, l = e % kWave;
+            s_lz[e] = mulmod_small((uint32_t)l, (uint32_t)a.z[j0 + j], dn, inv_n);
+        }
+        for (int e = tid; e < dc; e += kBlock) {
+            const int j = j0 + e;
+            uint32_t whole;
+            double frac;
+            split_shift(a.shift, j, n, whole, frac);
+            const uint32_t st = mulmod_small((uint32_t)kWave, (uint32_t)a.z[j], dn, inv_n);
+            s_st[e] = make_uint2(st, st - n);
+            s_sh[e] = whole;
+            s_c[e] = F::dim(p, d, j, inv_n, frac);
+        }
+    };
+    // Per-wave start residues of one tile.
+    auto fill_tile = [&](int j0, int dc, uint32_t tile_base) {
+        for (int e = tid; e < dc * kWaves; e += kBlock) {
+            const int j = e / kWaves, w = e % kWaves;
+            const uint32_t b = (tile_base + (uint32_t)w * (kWave * M)) % n;
+            s_kw[e] = addmod(mulmod((uint64_t)b, (uint64_t)a.z[j0 + j], n, inv_n), s_sh[j], n);
+        }
+    };
+
+    const bool one_chunk = d <= kDimChunk;
+    if (one_chunk) fill_dims(0, d);
+
+    double tacc = 0.0;
+    for (uint32_t tile = blockIdx.x; tile < a.tiles; tile += gridDim.x) {
+        const uint32_t tile_base = tile * kTile;
+        Acc acc[M];
+#pragma unroll
+        for (int m = 0; m < M; ++m) acc[m] = F::init(init0);
+
+        for (int j0 = 0; j0 < d; j0 += kDimChunk) {
+            const int dc = min(kDimChunk, d - j0);
+            __syncthreads();  // all reads of the previous tables are done
+            if (!one_chunk) {
+                fill_dims(j0, dc);
+                __syncthreads();
+            }
+            fill_tile(j0, dc, tile_base);
+            __syncthreads();
+            for (int jj = 0; jj < dc; ++jj) {
+                uint32_t k = addmod(s_kw[jj * kWaves + wv], s_lz[jj * kWave + lane], n);
+                const uint2 stp = s_st[jj];
+                const uint32_t st = stp.x, stm = stp.y;
+                const Dim c = s_c[jj];
+#pragma unroll
+                for (int m = 0; m < M; ++m) {
+                    F::step(acc[m], k, c);
+                    k = stepmod(k, st, stm);
+                }
+                if constexpr (F::kRenorm > 0) {
+                    if ((j0 + jj + 1) % F::kRenorm == 0) {
+#pragma unroll
+                        for (int m = 0; m < M; ++m) F::renorm(acc[m]);
+                    }
+                }
+            }
+        }
+        const uint32_t i0 = tile_base + (uint32_t)wv * (kWave * M) + (uint32_t)lane;
+#pragma unroll
+        for (int m = 0; m < M; ++m) {
+            const double f = F::finish(acc[m]);
+            tacc += (i0 + (uint32_t)(kWave * m) < n) ? f : 0.0;
+        }
+    }
+
+    const double bsum = block_sum(tacc, s_red);  // s_red[0..kWaves) reused
+    const GridSlots slots = set_slots(a, set, (int)gridDim.x);
+    double total;
+    if (grid_sum(bsum, (int)blockIdx.x, (int)gridDim.x, slots, s_red, &s_last, total) && tid == 0)
+        a.q_out[set] = (total / (double)n) * F::scale(ds1, ie);
+}
+
+// --------------------------------------------------------------------------
+// Debug export of the indices, through the same start/step decomposition.
+// --------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void lattice_points_kernel(int d, uint32_t n, double inv_n,
+                                                                const int64_t* z, uint64_t i0,
+                                                                uint64_t count, int32_t* k_out) {
+    constexpr int M = 4;
+    const int lane = threadIdx.x % kWave, wv = threadIdx.x / kWave;
+    const uint64_t base = i0 + (uint64_t)blockIdx.x * (kBlock * M) + (uint64_t)wv * (kWave * M);
+    for (int j = 0; j < d; ++j) {
+        const uint32_t zj = (uint32_t)z[j];
+        const uint32_t kw = mulmod(base % n, zj, n, inv_n);
+        uint32_t k = addmod(kw, mulmod((uint64_t)lane, zj, n, inv_n), n);
+        const uint32_t st = mulmod((uint64_t)kWave, zj, n, inv_n), stm = st - n;
+        for (int m = 0; m < M; ++m) {
+            const uint64_t r = base - i0 + (uint64_t)lane + (uint64_t)(kWave * m);
+            if (r < count) k_out[r * d + j] = (int32_t)k;
+            k = stepmod(k, st, stm);
+        }
+    }
+}
+
+// --------------------------------------------------------------------------
+// Launchers
+// --------------------------------------------------------------------------
+int sum_blocks_per_set(int nsets) {
+    int g = kMaxSumBlocks / (nsets > 0 ? nsets : 1);
+    if (g < 1) g = 1;
+    if (g > kMaxSumBlocksPerSet) g = kMaxSumBlocksPerSet;
+    return g;
+}
+
+// Scratch doubles per set, rounded to 256 bytes.
+static size_t set_stride(int nsets) {
+    return (grid_scratch_doubles(sum_blocks_per_set(nsets)) + 31) / 32 * 32;
+}
+
+size_t plain_workspace_bytes(int nsets) {
+    return kTicketBytes + (size_t)nsets * set_stride(nsets) * sizeof(double);
+}
+
+int device_cu_count() {
+    static int cus = 0;
+    if (cus == 0) {
+        int dev = 0;
+        hipDeviceProp_t prop;
+        if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
+            cus = prop.multiProcessorCount;
+        if (cus <= 0) cus = 256;
+    }
+    return cus;
+}
+
+template <class F, int M>
+static hipError_t launch_fm(const PlainLaunch& L, hipStream_t stream) {
+    SumArgs a;
+    a.d = L.d;
+    a.n = L.n;
+    a.inv_n = 1.0 / (double)L.n;
+    a.z = L.z;
+    a.shift = L.shift;
+    a.params = L.params;
+    a.P = L.P;
+    const uint64_t tile = (uint64_t)kBlock * M;
+    a.tiles = (uint32_t)(((uint64_t)L.n + tile - 1) / tile);
+    a.q_out = L.q_out;
+    a.tickets = (uint32_t*)L.ws;
+    a.scratch = (double*)((char*)L.ws + kTicketBytes);
+    a.scratch_stride = set_stride(L.nsets);
+    int g = sum_blocks_per_set(L.nsets);
+    if (L.max_blocks > 0 && L.max_blocks < g) g = L.max_blocks;
+    if ((uint32_t)g > a.tiles) g = (int)a.tiles;
+    dim3 grid((unsigned)g, (unsigned)L.nsets);
+    hipLaunchKernelGGL((lattice_sum_kernel<F, M>), grid, dim3(kBlock), 0, stream, a);
+    return hipGetLastError();
+}
+
+template <class F>
+static hipError_t launch_f(const PlainLaunch& L, hipStream_t stream) {
+    int M = L.points_per_thread;
+    if (M == 0) {
+        // As many points per thread as still leaves >= 1.5 tiles per CU (the
+        // per-direction setup is amortised over M points, the latency over the
+        // workgroups resident on a CU).
+        const uint64_t want_tiles = 3ull * device_cu_count() / 2;
+        M = 16;
+        while (M > 4 && ((uint64_t)L.n + kBlock * M - 1) / ((uint64_t)kBlock * M) < want_tiles) M /= 2;
+    }
+    switch (M) {
+        case 4: return launch_fm<F, 4>(L, stream);
+        case 8: return launch_fm<F, 8>(L, stream);
+        case 16: return launch_fm<F, 16>(L, stream);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_lattice_sum(const PlainLaunch& L, hipStream_t stream) {
+    if (L.fp32) {
+        switch (L.family) {
+            case kExpSum: return launch_f<ExpSum<true>>(L, stream);
+            case kProductPeak:
+                if (L.d <= kPeakF32MaxDims) return launch_f<ProductPeak<true, true>>(L, stream);
+                return launch_f<ProductPeak<false, true>>(L, stream);
+            case kGaussian: return launch_f<Gaussian<true>>(L, stream);
+            case kOscillatory: return launch_f<Oscillatory<true>>(L, stream);
+        }
+    } else {
+        switch (L.family) {
+            case kExpSum: return launch_f<ExpSum<false>>(L, stream);
+            case kProductPeak: return launch_f<ProductPeak<false, false>>(L, stream);
+            case kGaussian: return launch_f<Gaussian<false>>(L, stream);
+            case kOscillatory: return launch_f<Oscillatory<false>>(L, stream);
+        }
+    }
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_lattice_points(int d, uint32_t n, const int64_t* z, int64_t i0, int64_t count,
+                                 int32_t* k_out, hipStream_t stream) {
+    if (count <= 0) return hipSuccess;
+    const uint64_t per_block = (uint64_t)kBlock * 4;
+    const unsigned grid = (unsigned)(((uint64_t)count + per_block - 1) / per_block);
+    hipLaunchKernelGGL(lattice_points_kernel, dim3(grid), dim3(kBlock), 0, stream, d, n,
+                       1.0 / (double)n, z, (uint64_t)i0, (uint64_t)count, k_out);
+    return hipGetLastError();
+}
+
+}  // namespace qmc

@@ -1,0 +1,117 @@
+"""C-ABI checks that need no GPU: the library loads, exports every symbol the
+header declares, its host helpers are right, and invalid calls fail cleanly
+before anything is launched."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2404_08867_amd import qmc
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "qmc.h")
+
+
+def _declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(qmc_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = qmc.lib()
+    names = _declared()
+    assert "qmc_lattice_sum" in names and "qmc_mdi_lr" in names
+    missing = [n for n in names if not hasattr(L, n)]
+    assert not missing, missing
+
+
+def test_version_and_status_strings():
+    assert "gfx950" in qmc.version()
+    L = qmc.lib()
+    for s in range(6):
+        assert L.qmc_status_string(s)
+    assert L.qmc_status_string(99) == b"unknown status"
+
+
+@pytest.mark.parametrize("d,n,a", [(4, 1009, 77), (20, 1048573, 123457), (50, 16777213, 9999991),
+                                   (7, 1000, 3), (1, 1, 5), (1024, 2147483647, 16807)])
+def test_korobov_is_modular_power(d, n, a):
+    assert [int(v) for v in qmc.korobov(d, n, a)] == [pow(a, j, n) for j in range(d)]
+
+
+def test_mdi_dims_paper_cases():
+    # Lemma 3.2 (n = a^d), Table 2-1 header (n = 1 + 10^d), Fig. 5 (n = 81, z = (1, 7)).
+    assert list(qmc.mdi_lr_dims(100, 64, qmc.N_A_POW_D)) == [64] * 100
+    assert list(qmc.mdi_lr_dims(6, 10, qmc.N_ONE_PLUS_A_POW_D)) == [10] * 5 + [11]
+    assert list(qmc.mdi_lr_dims(2, 7, qmc.N_EXPLICIT, 81)) == [7, 12]
+    assert list(qmc.mdi_lr_dims(3, 4, qmc.N_EXPLICIT, 161)) == [4, 4, 11]
+    for d in range(2, 7):
+        N = qmc.mdi_lr_dims(d, 10, qmc.N_EXPLICIT, 1 + 10 ** d)
+        assert int(np.prod(N.astype(np.int64))) == 11 * 10 ** (d - 1)
+
+
+def test_param_count_and_workspace():
+    assert [qmc.param_count(f, 7) for f in range(4)] == [7, 14, 14, 8]
+    assert qmc.workspace_size(20, 1 << 20, 1) >= 8 * 2048
+    assert qmc.workspace_size(50, 1 << 24, 64) >= 64 * 8
+
+
+def _status(fn, *args):
+    return fn(*args)
+
+
+def test_invalid_arguments_fail_before_launch():
+    L = qmc.lib()
+    fake = ctypes.c_void_p(0x1000)  # never dereferenced: validation fails first
+    ws = ctypes.c_void_p(0x100000)
+    # d out of range
+    assert L.qmc_lattice_sum(0, 100, fake, None, 0, fake, 1, 0, fake, ws, 1 << 20, None) == qmc.ERR_INVALID_ARG
+    assert b"d = 0" in L.qmc_last_error()
+    assert L.qmc_lattice_sum(1025, 100, fake, None, 0, fake, 1, 0, fake, ws, 1 << 20, None) == qmc.ERR_INVALID_ARG
+    # n out of range
+    assert L.qmc_lattice_sum(4, 0, fake, None, 0, fake, 1, 0, fake, ws, 1 << 20, None) == qmc.ERR_INVALID_ARG
+    assert L.qmc_lattice_sum(4, 1 << 31, fake, None, 0, fake, 1, 0, fake, ws, 1 << 20, None) == qmc.ERR_INVALID_ARG
+    # family, precision, nsets
+    assert L.qmc_lattice_sum(4, 100, fake, None, 7, fake, 1, 0, fake, ws, 1 << 20, None) == qmc.ERR_INVALID_ARG
+    assert L.qmc_lattice_sum(4, 100, fake, None, 0, fake, 1, 5, fake, ws, 1 << 20, None) == qmc.ERR_INVALID_ARG
+    assert L.qmc_lattice_sum(4, 100, fake, None, 0, fake, 0, 0, fake, ws, 1 << 20, None) == qmc.ERR_INVALID_ARG
+    # null pointers
+    assert L.qmc_lattice_sum(4, 100, None, None, 0, fake, 1, 0, fake, ws, 1 << 20, None) == qmc.ERR_INVALID_ARG
+    # workspace: null, misaligned, too small
+    assert L.qmc_lattice_sum(4, 100, fake, None, 0, fake, 1, 0, fake, None, 1 << 20, None) == qmc.ERR_WORKSPACE
+    assert L.qmc_lattice_sum(4, 100, fake, None, 0, fake, 1, 0, fake, ctypes.c_void_p(0x100008), 1 << 20,
+                             None) == qmc.ERR_WORKSPACE
+    assert L.qmc_lattice_sum(4, 100, fake, None, 0, fake, 1, 0, fake, ws, 16, None) == qmc.ERR_WORKSPACE
+    assert b"needed" in L.qmc_last_error()
+    # MDI-LR and the index export
+    assert L.qmc_mdi_lr(0, fake, 0, fake, 1, 0, fake, None, 0, None) == qmc.ERR_INVALID_ARG
+    assert L.qmc_mdi_lr(4, None, 0, fake, 1, 0, fake, None, 0, None) == qmc.ERR_INVALID_ARG
+    assert L.qmc_lattice_points(4, 100, fake, -1, 10, fake, None) == qmc.ERR_INVALID_ARG
+    assert L.qmc_lattice_points(4, 100, fake, 0, (1 << 26) + 1, fake, None) == qmc.ERR_INVALID_ARG
+    # host helpers
+    z = np.zeros(4, dtype=np.int64)
+    assert L.qmc_korobov(4, 0, 3, z.ctypes.data) == qmc.ERR_INVALID_ARG
+    N = np.zeros(3, dtype=np.int32)
+    assert L.qmc_mdi_lr_dims(3, 3, 9, 0, N.ctypes.data) == qmc.ERR_INVALID_ARG
+    assert L.qmc_mdi_lr_dims(3, 1 << 21, 0, 0, N.ctypes.data) == qmc.ERR_INVALID_ARG
+    # z(a) with a = n: z_2 = 0 makes eq. 3.5 undefined
+    assert L.qmc_mdi_lr_dims(3, 7, qmc.N_EXPLICIT, 7, N.ctypes.data) == qmc.ERR_INVALID_ARG
+
+
+def test_last_error_is_cleared_by_success():
+    L = qmc.lib()
+    z = np.zeros(4, dtype=np.int64)
+    assert L.qmc_korobov(4, 0, 3, z.ctypes.data) == qmc.ERR_INVALID_ARG
+    assert L.qmc_last_error() != b""
+    assert L.qmc_korobov(4, 11, 3, z.ctypes.data) == qmc.OK
+    assert L.qmc_last_error() == b""
+
+
+def test_python_binding_raises_when_library_missing(monkeypatch, tmp_path):
+    monkeypatch.setattr(qmc, "_lib", None)
+    monkeypatch.setattr(qmc, "LIB_PATH", str(tmp_path / "libqmc.so"))
+    with pytest.raises(qmc.QmcError):
+        qmc.lib()

@@ -1,0 +1,258 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 CPU oracle.
+
+Tolerances:
+  * point indices: bit-exact;
+  * QMC_FP64: |Q - Q_oracle| <= 1e-12 * max(|Q_oracle|, A) with A the oracle's mean |f|
+    (the scale of a mixed-sign sum);
+  * QMC_FP32_COMPENSATED: the same measure <= 1e-6 (the metric's bar).
+Sizes are chosen so that the oracle finishes in seconds while the sums still
+span several tiles with a ragged tail; the full-size workloads are checked on
+whole sums where the oracle is fast enough and on sampled sets otherwise.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2404_08867_amd import qmc
+from paper_2404_08867_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+TOL = {qmc.FP64: 1e-12, qmc.FP32_COMPENSATED: 1e-6}
+PRECS = [qmc.FP64, qmc.FP32_COMPENSATED]
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _rel(q, q_oracle, a_oracle):
+    return abs(q - q_oracle) / max(abs(q_oracle), a_oracle, 1e-300)
+
+
+def _gpu_sum(prob, precision, **kw):
+    z = qmc.korobov(prob.d, prob.n, prob.a)
+    q = qmc.lattice_sum(z, prob.n, prob.family, prob.params, precision, shift=prob.shift, **kw)
+    return float(q.item())
+
+
+def _oracle_sum(prob):
+    z = O.korobov(prob.d, prob.n, prob.a)
+    return O.lattice_sum(z, prob.n, prob.family, prob.params, prob.shift)
+
+
+# --------------------------------------------------------------- point indices
+@pytest.mark.parametrize("d,n,a,i0,count", [
+    (4, 1009, 331, 0, 1009), (3, 10007, 1234, 17, 5000), (20, 1048573, 777, 1048000, 573),
+    (5, 2147483647, 16807, 2147483000, 647), (1, 1, 0, 0, 3), (7, 64, 5, 3, 200),
+    (65, 4099, 17, 100, 3000),
+])
+def test_lattice_points_bit_exact(d, n, a, i0, count):
+    z = qmc.korobov(d, n, a)
+    assert np.array_equal(z, O.korobov(d, n, a))
+    k = qmc.lattice_points(z, n, i0, count).cpu().numpy()
+    ref = O.lattice_points(O.korobov(d, n, a), n, i0, count)
+    assert np.array_equal(k.astype(np.int64), ref)
+
+
+# ------------------------------------------------------- plain sums, small cases
+CASES = [  # (d, n): several tiles and a ragged tail; 2 and 3 direction chunks
+    (3, 10007), (20, 65537), (65, 3001), (130, 1009), (1, 997), (8, 4099),
+]
+
+
+@pytest.mark.parametrize("precision", PRECS)
+@pytest.mark.parametrize("family", [0, 1, 2, 3])
+@pytest.mark.parametrize("d,n", CASES)
+@pytest.mark.parametrize("shift", [False, True])
+def test_plain_sum_matches_oracle(precision, family, d, n, shift):
+    prob = W.random_plain(1000 * d + n + family, family, d, n, shift=shift)
+    qo, ao = _oracle_sum(prob)
+    q = _gpu_sum(prob, precision)
+    assert _rel(q, qo, ao) <= TOL[precision], (q, qo)
+
+
+@pytest.mark.parametrize("ppt", [4, 8, 16])
+@pytest.mark.parametrize("max_blocks", [1, 3, 0])
+@pytest.mark.parametrize("family", [0, 1, 2, 3])
+def test_plain_sum_every_launch_shape(ppt, max_blocks, family):
+    """Each tile size, a single persistent workgroup looping over all tiles, and
+    a ragged persistent distribution give the oracle's value."""
+    prob = W.random_plain(77 + family, family, 9, 20011, shift=True)
+    qo, ao = _oracle_sum(prob)
+    for precision in PRECS:
+        q = _gpu_sum(prob, precision, points_per_thread=ppt, max_blocks=max_blocks)
+        assert _rel(q, qo, ao) <= TOL[precision], (precision, q, qo)
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 63, 64, 65, 1023, 1025])
+def test_plain_sum_tiny_n(n):
+    for family in range(4):
+        prob = W.random_plain(n + 10 * family, family, 5, n, shift=(n % 2 == 1))
+        qo, ao = _oracle_sum(prob)
+        for precision in PRECS:
+            assert _rel(_gpu_sum(prob, precision), qo, ao) <= TOL[precision]
+
+
+def test_plain_sum_max_dimension():
+    for family in range(4):
+        prob = W.random_plain(5 + family, family, 1024, 257, shift=True)
+        qo, ao = _oracle_sum(prob)
+        for precision in PRECS:
+            assert _rel(_gpu_sum(prob, precision), qo, ao) <= TOL[precision]
+
+
+def test_plain_sum_many_sets():
+    """nsets parameter rows sharing one lattice, each checked against the oracle."""
+    torch = _torch()
+    rng = np.random.default_rng(3)
+    d, n = 6, 30011
+    z = qmc.korobov(d, n, 1234)
+    shift = rng.uniform(0, 1, d)
+    for family in range(4):
+        P = W.param_count(family, d)
+        params = np.stack([W.draw_params(rng, family, d) for _ in range(5)])
+        assert params.shape == (5, P)
+        for precision in PRECS:
+            q = qmc.lattice_sum(z, n, family, torch.tensor(params), precision, shift=shift).cpu().numpy()
+            for s in range(5):
+                qo, ao = O.lattice_sum(z, n, family, params[s], shift)
+                assert _rel(q[s], qo, ao) <= TOL[precision]
+
+
+# ------------------------------------------------------ exact pins on the device
+def test_character_identity_on_device():
+    """(1/n) sum_i cos(2 pi u + 2 pi h.(x_i + Delta)) is cos(2 pi u + 2 pi h.Delta) for h in
+    the dual lattice and 0 otherwise (eq. 2.3)."""
+    rng = np.random.default_rng(11)
+    n, d, a = 10007, 4, 1234
+    z = qmc.korobov(d, n, a)
+    shift = rng.uniform(0, 1, d)
+    u = 0.3125
+    for trial in range(6):
+        h = [int(v) for v in rng.integers(-5, 6, d - 1)]
+        if trial % 2 == 0:
+            s = sum(hj * int(zj) for hj, zj in zip(h, z[:-1]))
+            hd = (-s * pow(int(z[-1]), -1, n)) % n
+            h.append(hd - n if hd > n // 2 else hd)
+        else:
+            h.append(int(rng.integers(-5, 6)))
+        h = np.array(h)
+        in_dual = sum(int(x) * int(y) for x, y in zip(h, z)) % n == 0
+        params = np.concatenate([[u], 2 * math.pi * h.astype(float)])
+        expect = math.cos(2 * math.pi * u + 2 * math.pi * float(np.dot(h, shift))) if in_dual else 0.0
+        q = float(qmc.lattice_sum(z, n, qmc.OSCILLATORY, params, qmc.FP64, shift=shift).item())
+        assert abs(q - expect) < 1e-9, (h, q, expect)
+
+
+def test_results_are_deterministic_and_workspace_reusable():
+    prob = W.plain_d20_peak()
+    z = qmc.korobov(prob.d, prob.n, prob.a)
+    ws = qmc.Workspace(qmc.workspace_size(prob.d, prob.n, 1))
+    for precision in PRECS:
+        vals = [float(qmc.lattice_sum(z, prob.n, prob.family, prob.params, precision, ws=ws).item())
+                for _ in range(4)]
+        assert len({v.hex() for v in vals}) == 1
+
+
+# ------------------------------------------------------------ full-size workloads
+@pytest.mark.parametrize("precision", PRECS)
+def test_workload_plain_d4_expsum(precision):
+    prob = W.plain_d4_expsum()
+    qo, ao = _oracle_sum(prob)
+    assert _rel(_gpu_sum(prob, precision), qo, ao) <= TOL[precision]
+
+
+@pytest.mark.parametrize("precision", PRECS)
+def test_workload_plain_d20_peak(precision):
+    prob = W.plain_d20_peak()
+    qo, ao = _oracle_sum(prob)
+    assert _rel(_gpu_sum(prob, precision), qo, ao) <= TOL[precision]
+
+
+# ------------------------------------------------------------------------ MDI-LR
+@pytest.mark.parametrize("precision", PRECS)
+@pytest.mark.parametrize("family", [0, 1, 2, 3])
+@pytest.mark.parametrize("N", [[7], [4, 9], [3, 1, 6], [5, 4, 3, 7], [12, 12, 12, 13]])
+def test_mdi_lr_small_grids_match_brute_force(precision, family, N):
+    rng = np.random.default_rng(len(N) * 7 + family)
+    p = W.draw_params(rng, family, len(N))
+    brute = O.mdi_lr_brute(N, family, p)
+    q = float(qmc.mdi_lr(np.array(N, dtype=np.int32), family, p, precision).item())
+    if family == 3:  # mixed sign: scale by the product of the factor moduli
+        re, im = O.mdi_lr_factors(np.array(N), family, p)
+        scale = float(np.prod(np.hypot(re, im)))
+    else:
+        scale = abs(brute)
+    assert abs(q - brute) <= TOL[precision] * max(scale, 1e-300)
+
+
+@pytest.mark.parametrize("precision", PRECS)
+def test_mdi_lr_workload_d100(precision):
+    w = W.mdi_d100_gauss(nsets=1)
+    qo = O.mdi_lr(w.N, w.family, w.params[0])
+    q = float(qmc.mdi_lr(w.N.astype(np.int32), w.family, w.params[0], precision).item())
+    assert abs(q - qo) <= TOL[precision] * abs(qo)
+
+
+@pytest.mark.parametrize("precision", PRECS)
+def test_mdi_lr_many_sets_sampled(precision):
+    """Throughput launch over 4099 sets; 40 sampled sets checked against the oracle."""
+    w = W.mdi_d100_gauss(nsets=4099)
+    q = qmc.mdi_lr(w.N.astype(np.int32), w.family, w.params, precision).cpu().numpy()
+    for s in list(range(0, 4099, 103)) + [4098]:
+        qo = O.mdi_lr(w.N, w.family, w.params[s])
+        assert abs(q[s] - qo) <= TOL[precision] * abs(qo), s
+
+
+@pytest.mark.parametrize("precision", PRECS)
+@pytest.mark.parametrize("family", [0, 1, 2, 3])
+def test_mdi_lr_ragged_nodes_and_families(precision, family):
+    rng = np.random.default_rng(50 + family)
+    d = 37
+    N = qmc.mdi_lr_dims(d, 9, qmc.N_ONE_PLUS_A_POW_D)
+    params = np.stack([W.draw_params(rng, family, d) for _ in range(9)])
+    q = qmc.mdi_lr(N, family, params, precision).cpu().numpy()
+    for s in range(9):
+        qo = O.mdi_lr(N.astype(np.int64), family, params[s])
+        if family == 3:
+            re, im = O.mdi_lr_factors(N.astype(np.int64), family, params[s])
+            scale = float(np.prod(np.hypot(re, im)))
+        else:
+            scale = abs(qo)
+        assert abs(q[s] - qo) <= TOL[precision] * scale, (s, q[s], qo)
+
+
+def test_mdi_lr_paper_table23_d1000():
+    """Table 2-3 settings (d = 1000): exp of the alternating sum with N = 8 and the
+    product peak with N = 20 match the oracle sweep to FP64 accuracy."""
+    d = 1000
+    c = np.array([(-1.0) ** j for j in range(d)])
+    q = float(qmc.mdi_lr(np.full(d, 8, np.int32), qmc.EXP_SUM, c, qmc.FP64).item())
+    assert q == pytest.approx(O.mdi_lr(np.full(d, 8), O.EXP_SUM, c), rel=1e-12)
+    p = np.concatenate([np.full(d, 1 / 0.9), np.full(d, 0.6)])
+    q = float(qmc.mdi_lr(np.full(d, 20, np.int32), qmc.PRODUCT_PEAK, p, qmc.FP64).item())
+    assert q == pytest.approx(O.mdi_lr(np.full(d, 20), O.PRODUCT_PEAK, p), rel=1e-12)
+
+
+def test_one_workspace_serves_every_call_shape():
+    """Calls with different n (grid sizes), nsets, tile sizes and families share one
+    workspace in any order; each result matches the oracle (the completion counters
+    sit at fixed offsets and are left at zero by every call)."""
+    torch = _torch()
+    ws = qmc.Workspace(qmc.workspace_size(64, 1 << 21, 16))
+    rng = np.random.default_rng(21)
+    shapes = [(20, 1048573, 1, 0), (5, 3001, 5, 4), (9, 20011, 1, 16), (3, 65537, 16, 8),
+              (20, 1048573, 1, 0), (1, 7, 2, 0), (64, 4099, 3, 4), (20, 1048573, 1, 8)]
+    for i, (d, n, nsets, ppt) in enumerate(shapes):
+        fam = i % 4
+        z = qmc.korobov(d, n, W.draw_coprime(rng, n))
+        params = np.stack([W.draw_params(rng, fam, d) for _ in range(nsets)])
+        q = qmc.lattice_sum(z, n, fam, torch.tensor(params), qmc.FP64, ws=ws,
+                            points_per_thread=ppt).cpu().numpy()
+        for s in range(nsets):
+            qo, ao = O.lattice_sum(z, n, fam, params[s])
+            assert _rel(q[s], qo, ao) <= 1e-12, (i, s, q[s], qo)
