@@ -166,6 +166,86 @@ qmc_status qmc_mdi_lr(int32_t d, const int32_t* N, int32_t family, const double*
                       int32_t nsets, int32_t precision, double* q_out, void* ws,
                       size_t ws_bytes, void* stream);
 
+/* ---- adjoint of the plain rule ------------------------------------------- */
+
+/* Values and parameter gradients of the plain rule for nsets parameter sets that
+ * share the lattice (derivative of eq. 1.2 term by term):
+ *   q_out[s]          = Q_s = (1/n) sum_i f_s(x_i)
+ *   grad_out[s][p]    = gq[s] * dQ_s/dparams[s][p] = gq[s] * (1/n) sum_i df_s/dp (x_i)
+ * with the parameter layout of the family (oscillatory: u first, then c_j).
+ * Arguments as qmc_lattice_sum, plus
+ *   gq        device double[nsets] (the incoming adjoint dL/dQ_s), or NULL for 1
+ *   grad_out  device double[nsets][qmc_param_count(family, d)]
+ *   ws        device workspace of qmc_workspace_size(d, n, nsets) bytes.
+ * Supports d <= 512 (QMC_ERR_UNSUPPORTED above).  Deterministic. */
+qmc_status qmc_lattice_sum_adjoint(int32_t d, int64_t n, const int64_t* z, const double* shift,
+                                   int32_t family, const double* params, int32_t nsets,
+                                   int32_t precision, const double* gq, double* q_out,
+                                   double* grad_out, void* ws, size_t ws_bytes, void* stream);
+
+/* ---- batched plain sums: many integrands in one persistent launch ----- */
+
+/* One integrand of a batch: the plain rule of qmc_lattice_sum with its own
+ * lattice and parameters (all pointers are device pointers, caller-owned and
+ * read at every launch, so their contents may change between launches). */
+typedef struct {
+    int32_t family;        /* qmc_family */
+    int32_t d;             /* 1 .. 1024 */
+    int64_t n;             /* 1 .. 2^31 - 1 */
+    const int64_t* z;      /* device int64[d], 0 <= z_j < n */
+    const double* params;  /* device double[qmc_param_count(family, d)] */
+    const double* shift;   /* device double[d] in [0,1), or NULL */
+} qmc_problem;
+
+/* Launch configuration of the batched kernel.  Zero fields mean the default. */
+typedef struct {
+    int32_t points_per_thread; /* 4, 8 or 16: tiles of 256 * points_per_thread points (default 8) */
+    int32_t workgroups_per_cu; /* persistent workgroups per compute unit, 1 .. 8 (default 4) */
+    int32_t order;             /* 0: longest problem (n * d) first, 1: input order */
+} qmc_batch_config;
+
+typedef struct qmc_batch_plan qmc_batch_plan; /* opaque */
+typedef struct qmc_graph qmc_graph;           /* opaque */
+
+/* Build the schedule of a batch: problems ordered by cost, tiles numbered
+ * consecutively, and a device copy of the problem table (this call allocates
+ * and uploads synchronously; it launches nothing).  `problems` is a host array
+ * of `count` descriptors, 1 <= count <= 200000; it is copied.  cfg may be NULL. */
+qmc_status qmc_batch_plan_create(int32_t count, const qmc_problem* problems, int32_t precision,
+                                 const qmc_batch_config* cfg, qmc_batch_plan** plan);
+qmc_status qmc_batch_plan_destroy(qmc_batch_plan* plan);
+/* The configuration a plan uses (after qmc_batch_autotune: the tuned one). */
+qmc_status qmc_batch_plan_config(const qmc_batch_plan* plan, qmc_batch_config* cfg);
+/* Replace the configuration (rebuilds and re-uploads the problem table). */
+qmc_status qmc_batch_plan_set_config(qmc_batch_plan* plan, const qmc_batch_config* cfg);
+/* Workspace bytes for any configuration of this plan (1 MiB of counters plus one
+ * double per tile of the smallest tile size). */
+qmc_status qmc_batch_workspace_size(const qmc_batch_plan* plan, size_t* bytes);
+
+/* All Q of a batch in one persistent launch: workgroups pop tiles from an atomic
+ * queue in the workspace, evaluate them with the qmc_lattice_sum device code,
+ * and the workgroup completing a problem sums its tile partials in tile order.
+ *   q_out   device double[count], in the order of the descriptors given to the plan.
+ * Results are bit-reproducible; the launch allocates nothing and uses no memset,
+ * so it can be captured in a graph and replayed. */
+qmc_status qmc_lattice_sum_batched(const qmc_batch_plan* plan, double* q_out, void* ws,
+                                   size_t ws_bytes, void* stream);
+
+/* Autotuner: times every candidate configuration (points per thread 4/8/16 x
+ * workgroups per CU 1/2/4/8) on this batch, `reps` launches each, with HIP
+ * events on `stream`, and keeps the fastest in the plan (best may be NULL).
+ * Results are cached per batch signature in the process and in the file named by
+ * the environment variable QMC_AUTOTUNE_CACHE, if set.  Synchronises `stream`. */
+qmc_status qmc_batch_autotune(qmc_batch_plan* plan, double* q_out, void* ws, size_t ws_bytes,
+                              void* stream, int32_t reps, qmc_batch_config* best);
+
+/* Capture one qmc_lattice_sum_batched launch (plan, q_out and ws are bound) into
+ * an instantiated HIP graph; qmc_graph_launch replays it on any stream. */
+qmc_status qmc_batch_graph_create(const qmc_batch_plan* plan, double* q_out, void* ws,
+                                  size_t ws_bytes, qmc_graph** graph);
+qmc_status qmc_graph_launch(qmc_graph* graph, void* stream);
+qmc_status qmc_graph_destroy(qmc_graph* graph);
+
 #ifdef __cplusplus
 }
 #endif

@@ -7,10 +7,13 @@
 
 #include "qmc.h"
 #include "kernels.hpp"
+#include "status.hpp"
 
 namespace {
-
 thread_local std::string g_last_error;
+}
+
+namespace qmc {
 
 qmc_status fail(qmc_status s, const char* fmt, ...) {
     char buf[512];
@@ -31,6 +34,14 @@ qmc_status from_hip(hipError_t e, const char* where) {
     if (e == hipSuccess) return ok();
     return fail(QMC_ERR_DEVICE, "%s: HIP error %d (%s)", where, (int)e, hipGetErrorString(e));
 }
+
+}  // namespace qmc
+
+namespace {
+
+using qmc::fail;
+using qmc::from_hip;
+using qmc::ok;
 
 constexpr int kMaxD = 1024;
 constexpr int64_t kMaxN = (int64_t)1 << 31;  // exclusive
@@ -182,8 +193,47 @@ qmc_status qmc_workspace_size(int32_t max_d, int64_t max_n, int32_t max_sets, si
     }
     const size_t b = qmc::plain_workspace_bytes(max_sets);
     if (b > need) need = b;
+    // The adjoint keeps one vector of P + 1 doubles per workgroup and group.
+    const int pmax = 2 * (max_d < qmc::kMaxAdjDims ? max_d : qmc::kMaxAdjDims) + 1;
+    for (int s = 1; s <= max_sets; s = (s < 64 ? s + 1 : s * 2)) {
+        const size_t a = qmc::adjoint_workspace_bytes(pmax, s);
+        if (a > need) need = a;
+    }
+    const size_t a = qmc::adjoint_workspace_bytes(pmax, max_sets);
+    if (a > need) need = a;
     *bytes = need;
     return ok();
+}
+
+qmc_status qmc_lattice_sum_adjoint(int32_t d, int64_t n, const int64_t* z, const double* shift,
+                                   int32_t family, const double* params, int32_t nsets,
+                                   int32_t precision, const double* gq, double* q_out,
+                                   double* grad_out, void* ws, size_t ws_bytes, void* stream) {
+    qmc_status s = check_common(d, family, nsets, precision);
+    if (s != QMC_OK) return s;
+    if (d > qmc::kMaxAdjDims)
+        return fail(QMC_ERR_UNSUPPORTED, "the adjoint supports d <= %d (d = %d)", qmc::kMaxAdjDims, d);
+    if (n < 1 || n >= kMaxN) return fail(QMC_ERR_INVALID_ARG, "n = %lld outside [1, 2^31)", (long long)n);
+    if (!z || !params || !q_out || !grad_out)
+        return fail(QMC_ERR_INVALID_ARG, "z, params, q_out and grad_out must be non-NULL");
+    const int P = param_count(family, d);
+    s = check_workspace(ws, ws_bytes, qmc::adjoint_workspace_bytes(P, nsets));
+    if (s != QMC_OK) return s;
+    qmc::AdjLaunch L{};
+    L.d = d;
+    L.n = (uint32_t)n;
+    L.z = z;
+    L.shift = shift;
+    L.family = family;
+    L.params = params;
+    L.P = P;
+    L.nsets = nsets;
+    L.fp32 = precision == QMC_FP32_COMPENSATED;
+    L.gq = gq;
+    L.q_out = q_out;
+    L.grad_out = grad_out;
+    L.ws = ws;
+    return from_hip(qmc::launch_adjoint(L, (hipStream_t)stream), "qmc_lattice_sum_adjoint");
 }
 
 qmc_status qmc_lattice_sum(int32_t d, int64_t n, const int64_t* z, const double* shift,

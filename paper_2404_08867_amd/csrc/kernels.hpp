@@ -47,6 +47,30 @@ struct MdiLaunch {
 };
 hipError_t launch_mdi_lr(const MdiLaunch& a, hipStream_t stream);
 
+// Adjoint of the plain rule for nsets parameter sets sharing the lattice.
+constexpr int kMaxAdjBlocks = 1024;
+constexpr int kMaxAdjDims = 512;
+
+struct AdjLaunch {
+    int d;
+    uint32_t n;
+    const int64_t* z;
+    const double* shift;
+    int family;
+    const double* params;
+    int P;
+    int nsets;
+    bool fp32;
+    const double* gq;  // may be null
+    double* q_out;
+    double* grad_out;
+    void* ws;
+};
+
+int adjoint_blocks_per_set(int nsets);
+size_t adjoint_workspace_bytes(int P, int nsets);
+hipError_t launch_adjoint(const AdjLaunch& a, hipStream_t stream);
+
 int device_cu_count();
 
 }  // namespace qmc

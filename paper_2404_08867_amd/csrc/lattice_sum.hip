@@ -1,17 +1,11 @@
 // Plain rank-1 lattice rule, fused into one persistent launch (eq. 1.2, eq. 2.1):
 //   Q = (1/n) sum_{i=0}^{n-1} f(x_i),  x_ij = {(k_ij + shift_j n) / n},  k_ij = (i z_j) mod n.
 //
-// Work decomposition.  Points are cut into tiles of kBlock * M consecutive
-// indices; wave w of the workgroup owns the 64 * M points
-//   i = tile_base + w*64*M + lane + 64*m,   m = 0..M-1.
-// The loop runs over directions outside and over a thread's M points inside, so
-// that each direction's constants are loaded once per M points and the per-point
-// state is M registers whatever d is.  Indices are exact residues:
-//   start:  k = (Kw_j + Lz_j[lane]) mod n,  Kw_j = (wave_base * z_j + shift_whole_j) mod n,
-//                                           Lz_j[l] = (l * z_j) mod n,
-//   step:   k <- (k + D_j) mod n,           D_j = (64 z_j) mod n,
-// with the per-direction tables built cooperatively in LDS.  One step costs two
-// 32-bit adds and a min; no 64-bit arithmetic runs per point.
+// Work decomposition: tiles of kBlock * M consecutive indices (tile.hpp), the
+// workgroups of a set looping over tiles (persistent grid).  The loop runs over
+// directions outside and over a thread's M points inside, so that each
+// direction's constants are loaded once per M points and the per-point state is M
+// registers whatever d is; no 64-bit arithmetic runs per point.
 //
 // Reduction: per-thread FP64 sums, a wave64 xor butterfly, waves in order, one
 // FP64 partial per workgroup, then the two-level fixed-order grid sum of
@@ -19,13 +13,13 @@
 #include "common.hpp"
 #include "families.hpp"
 #include "kernels.hpp"
+#include "tile.hpp"
 
 namespace qmc {
 
 struct SumArgs {
     int d;
     uint32_t n;
-    double inv_n;
     const int64_t* z;
     const double* shift;
     const double* params;
@@ -45,135 +39,33 @@ __device__ __forceinline__ GridSlots set_slots(const SumArgs& a, int set, int G)
     return s;
 }
 
-__device__ __forceinline__ void split_shift(const double* shift, int j, uint32_t n, uint32_t& whole,
-                                            double& frac) {
-    if (!shift) {
-        whole = 0;
-        frac = 0.0;
-        return;
-    }
-    const double t = shift[j] * (double)n;
-    const double w = floor(t);
-    frac = t - w;
-    uint32_t wi = (uint32_t)w;
-    whole = wi >= n ? wi - n : wi;
-}
-
 template <class F, int M>
 __global__ __launch_bounds__(kBlock) void lattice_sum_kernel(const SumArgs a) {
-    using Dim = typename F::Dim;
-    using Acc = typename F::Acc;
     constexpr uint32_t kTile = kBlock * M;
-
-    __shared__ uint32_t s_lz[kDimChunk * kWave];   // [j][lane]
-    __shared__ uint32_t s_kw[kDimChunk * kWaves];  // [j][wave]
-    __shared__ uint2 s_st[kDimChunk];              // (D_j, D_j - n)
-    __shared__ uint32_t s_sh[kDimChunk];
-    __shared__ Dim s_c[kDimChunk];
+    __shared__ TileShared<F> s;
     __shared__ double s_red[3 * kWaves];
     __shared__ int s_last;
 
     const int set = blockIdx.y;
-    const double* p = a.params + (size_t)set * a.P;
-    const int tid = threadIdx.x, lane = tid & (kWave - 1), wv = tid / kWave;
-    const uint32_t n = a.n;
-    const double inv_n = a.inv_n;
-    const double dn = (double)n;
-    const int d = a.d;
+    const ProblemView v = make_view(a.d, a.n, a.z, a.shift, a.params + (size_t)set * a.P);
+    double init0, ds1;
+    int ie;
+    block_constants<F>(v, s_red, init0, ds1, ie);
 
-    // Workgroup constants: sums over all directions (fixed order), one reduction
-    // for all three (the int term is a sum of small integers, exact in double).
-    double ds0 = 0.0, ds1 = 0.0;
-    int ie = 0;
-    if constexpr (F::kBlockTerms) {
-        for (int j = tid; j < d; j += kBlock) {
-            uint32_t whole;
-            double frac;
-            split_shift(a.shift, j, n, whole, frac);
-            F::block_terms(p, d, j, inv_n, frac, ds0, ds1, ie);
-        }
-        block_sum3(ds0, ds1, ie, s_red);
-    }
-    const double init0 = ds0 + F::extra(p);
-
-    // Tables that do not depend on the tile: Lz, D, the shift's whole part and
-    // the family constants of directions [j0, j0 + dc).  l * z_j < 2^37, so the
-    // exact double-precision mulmod applies.
-    auto fill_dims = [&](int j0, int dc) {
-        for (int e = tid; e < dc * kWave; e += kBlock) {
-            const int j = e / kWave, l = e % kWave;
-            s_lz[e] = mulmod_small((uint32_t)l, (uint32_t)a.z[j0 + j], dn, inv_n);
-        }
-        for (int e = tid; e < dc; e += kBlock) {
-            const int j = j0 + e;
-            uint32_t whole;
-            double frac;
-            split_shift(a.shift, j, n, whole, frac);
-            const uint32_t st = mulmod_small((uint32_t)kWave, (uint32_t)a.z[j], dn, inv_n);
-            s_st[e] = make_uint2(st, st - n);
-            s_sh[e] = whole;
-            s_c[e] = F::dim(p, d, j, inv_n, frac);
-        }
-    };
-    // Per-wave start residues of one tile.
-    auto fill_tile = [&](int j0, int dc, uint32_t tile_base) {
-        for (int e = tid; e < dc * kWaves; e += kBlock) {
-            const int j = e / kWaves, w = e % kWaves;
-            const uint32_t b = (tile_base + (uint32_t)w * (kWave * M)) % n;
-            s_kw[e] = addmod(mulmod((uint64_t)b, (uint64_t)a.z[j0 + j], n, inv_n), s_sh[j], n);
-        }
-    };
-
-    const bool one_chunk = d <= kDimChunk;
-    if (one_chunk) fill_dims(0, d);
+    // With one chunk of directions the per-direction tables serve every tile.
+    const bool one_chunk = v.d <= kDimChunk;
+    if (one_chunk) fill_dims<F>(v, s, 0, v.d);
 
     double tacc = 0.0;
-    for (uint32_t tile = blockIdx.x; tile < a.tiles; tile += gridDim.x) {
-        const uint32_t tile_base = tile * kTile;
-        Acc acc[M];
-#pragma unroll
-        for (int m = 0; m < M; ++m) acc[m] = F::init(init0);
+    for (uint32_t tile = blockIdx.x; tile < a.tiles; tile += gridDim.x)
+        tacc += tile_points<F, M>(v, s, tile * kTile, init0, one_chunk);
 
-        for (int j0 = 0; j0 < d; j0 += kDimChunk) {
-            const int dc = min(kDimChunk, d - j0);
-            __syncthreads();  // all reads of the previous tables are done
-            if (!one_chunk) {
-                fill_dims(j0, dc);
-                __syncthreads();
-            }
-            fill_tile(j0, dc, tile_base);
-            __syncthreads();
-            for (int jj = 0; jj < dc; ++jj) {
-                uint32_t k = addmod(s_kw[jj * kWaves + wv], s_lz[jj * kWave + lane], n);
-                const uint2 stp = s_st[jj];
-                const uint32_t st = stp.x, stm = stp.y;
-                const Dim c = s_c[jj];
-#pragma unroll
-                for (int m = 0; m < M; ++m) {
-                    F::step(acc[m], k, c);
-                    k = stepmod(k, st, stm);
-                }
-                if constexpr (F::kRenorm > 0) {
-                    if ((j0 + jj + 1) % F::kRenorm == 0) {
-#pragma unroll
-                        for (int m = 0; m < M; ++m) F::renorm(acc[m]);
-                    }
-                }
-            }
-        }
-        const uint32_t i0 = tile_base + (uint32_t)wv * (kWave * M) + (uint32_t)lane;
-#pragma unroll
-        for (int m = 0; m < M; ++m) {
-            const double f = F::finish(acc[m]);
-            tacc += (i0 + (uint32_t)(kWave * m) < n) ? f : 0.0;
-        }
-    }
-
-    const double bsum = block_sum(tacc, s_red);  // s_red[0..kWaves) reused
+    const double bsum = block_sum(tacc, s_red);
     const GridSlots slots = set_slots(a, set, (int)gridDim.x);
     double total;
-    if (grid_sum(bsum, (int)blockIdx.x, (int)gridDim.x, slots, s_red, &s_last, total) && tid == 0)
-        a.q_out[set] = (total / (double)n) * F::scale(ds1, ie);
+    if (grid_sum(bsum, (int)blockIdx.x, (int)gridDim.x, slots, s_red, &s_last, total) &&
+        threadIdx.x == 0)
+        a.q_out[set] = (total / v.dn) * F::scale(ds1, ie);
 }
 
 // --------------------------------------------------------------------------
@@ -234,7 +126,6 @@ static hipError_t launch_fm(const PlainLaunch& L, hipStream_t stream) {
     SumArgs a;
     a.d = L.d;
     a.n = L.n;
-    a.inv_n = 1.0 / (double)L.n;
     a.z = L.z;
     a.shift = L.shift;
     a.params = L.params;

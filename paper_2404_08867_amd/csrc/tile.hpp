@@ -1,0 +1,170 @@
+// One tile of the plain rank-1 lattice rule: the device code shared by the
+// single-problem kernel (lattice_sum.hip) and the batched kernel (batched.hip).
+//
+// A tile is kBlock * M consecutive point indices; wave w of the workgroup owns
+//   i = tile_base + w*64*M + lane + 64*m,   m = 0..M-1,
+// and the loop runs over directions outside and over the thread's M points inside:
+//   start:  k = (Kw_j + Lz_j[lane]) mod n,  Kw_j = (wave_base * z_j + shift_whole_j) mod n,
+//                                           Lz_j[l] = (l * z_j) mod n,
+//   step:   k <- (k + D_j) mod n,           D_j = (64 z_j) mod n           (eq. 2.1)
+// with the per-direction tables built cooperatively in LDS, kDimChunk directions
+// at a time.  One step is two 32-bit adds and a min.
+#pragma once
+
+#include "common.hpp"
+#include "families.hpp"
+
+namespace qmc {
+
+// A problem as seen by the device: lattice, shift and one parameter row.
+struct ProblemView {
+    int d;
+    uint32_t n;
+    double inv_n;
+    double dn;
+    const int64_t* z;
+    const double* shift;  // may be null
+    const double* p;      // parameter row
+};
+
+__device__ __forceinline__ ProblemView make_view(int d, uint32_t n, const int64_t* z,
+                                                 const double* shift, const double* p) {
+    ProblemView v;
+    v.d = d;
+    v.n = n;
+    v.dn = (double)n;
+    v.inv_n = 1.0 / v.dn;
+    v.z = z;
+    v.shift = shift;
+    v.p = p;
+    return v;
+}
+
+// Fractional shift in index units: shift_j * n = whole + frac, whole in [0, n).
+__device__ __forceinline__ void split_shift(const double* shift, int j, uint32_t n, uint32_t& whole,
+                                            double& frac) {
+    if (!shift) {
+        whole = 0;
+        frac = 0.0;
+        return;
+    }
+    const double t = shift[j] * (double)n;
+    const double w = floor(t);
+    frac = t - w;
+    const uint32_t wi = (uint32_t)w;
+    whole = wi >= n ? wi - n : wi;
+}
+
+template <class F>
+struct TileShared {
+    uint32_t lz[kDimChunk * kWave];   // [j][lane]
+    uint32_t kw[kDimChunk * kWaves];  // [j][wave]
+    uint2 st[kDimChunk];              // (D_j, D_j - n)
+    uint32_t sh[kDimChunk];           // whole part of the shift
+    typename F::Dim c[kDimChunk];     // family constants
+};
+
+// Workgroup constants of a problem: sums over all directions in a fixed order.
+// Every thread receives init0 (initial accumulator), ds1 and ie (final scale).
+template <class F>
+__device__ __forceinline__ void block_constants(const ProblemView& v, double* red, double& init0,
+                                                double& ds1, int& ie) {
+    double ds0 = 0.0;
+    ds1 = 0.0;
+    ie = 0;
+    if constexpr (F::kBlockTerms) {
+        for (int j = threadIdx.x; j < v.d; j += kBlock) {
+            uint32_t whole;
+            double frac;
+            split_shift(v.shift, j, v.n, whole, frac);
+            F::block_terms(v.p, v.d, j, v.inv_n, frac, ds0, ds1, ie);
+        }
+        block_sum3(ds0, ds1, ie, red);
+    }
+    init0 = ds0 + F::extra(v.p);
+}
+
+// Tables that do not depend on the tile for directions [j0, j0 + dc).
+// l * z_j < 2^37 and 64 * z_j < 2^37, so the exact double-precision mulmod applies.
+template <class F>
+__device__ __forceinline__ void fill_dims(const ProblemView& v, TileShared<F>& s, int j0, int dc) {
+    const int tid = threadIdx.x;
+    for (int e = tid; e < dc * kWave; e += kBlock) {
+        const int j = e / kWave, l = e % kWave;
+        s.lz[e] = mulmod_small((uint32_t)l, (uint32_t)v.z[j0 + j], v.dn, v.inv_n);
+    }
+    for (int e = tid; e < dc; e += kBlock) {
+        const int j = j0 + e;
+        uint32_t whole;
+        double frac;
+        split_shift(v.shift, j, v.n, whole, frac);
+        const uint32_t st = mulmod_small((uint32_t)kWave, (uint32_t)v.z[j], v.dn, v.inv_n);
+        s.st[e] = make_uint2(st, st - v.n);
+        s.sh[e] = whole;
+        s.c[e] = F::dim(v.p, v.d, j, v.inv_n, frac);
+    }
+}
+
+// Per-wave start residues of one tile (general 62-bit products).
+template <class F, int M>
+__device__ __forceinline__ void fill_tile(const ProblemView& v, TileShared<F>& s, int j0, int dc,
+                                          uint32_t tile_base) {
+    for (int e = threadIdx.x; e < dc * kWaves; e += kBlock) {
+        const int j = e / kWaves, w = e % kWaves;
+        const uint32_t b = (tile_base + (uint32_t)w * (kWave * M)) % v.n;
+        s.kw[e] = addmod(mulmod((uint64_t)b, (uint64_t)v.z[j0 + j], v.n, v.inv_n), s.sh[j], v.n);
+    }
+}
+
+// The thread's sum of f / scale over its M points of the tile (points >= n
+// contribute zero).  If `dims_ready`, s already holds fill_dims(v, s, 0, d) and
+// d <= kDimChunk.  Begins with a barrier; the caller may reuse s afterwards only
+// after another barrier.
+template <class F, int M>
+__device__ __forceinline__ double tile_points(const ProblemView& v, TileShared<F>& s,
+                                              uint32_t tile_base, double init0, bool dims_ready) {
+    using Acc = typename F::Acc;
+    using Dim = typename F::Dim;
+    const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
+    const uint32_t n = v.n;
+    Acc acc[M];
+#pragma unroll
+    for (int m = 0; m < M; ++m) acc[m] = F::init(init0);
+
+    for (int j0 = 0; j0 < v.d; j0 += kDimChunk) {
+        const int dc = min(kDimChunk, v.d - j0);
+        __syncthreads();  // every read of the previous tables is done
+        if (!dims_ready) {
+            fill_dims<F>(v, s, j0, dc);
+            __syncthreads();
+        }
+        fill_tile<F, M>(v, s, j0, dc, tile_base);
+        __syncthreads();
+        for (int jj = 0; jj < dc; ++jj) {
+            uint32_t k = addmod(s.kw[jj * kWaves + wv], s.lz[jj * kWave + lane], n);
+            const uint2 stp = s.st[jj];
+            const Dim c = s.c[jj];
+#pragma unroll
+            for (int m = 0; m < M; ++m) {
+                F::step(acc[m], k, c);
+                k = stepmod(k, stp.x, stp.y);
+            }
+            if constexpr (F::kRenorm > 0) {
+                if ((j0 + jj + 1) % F::kRenorm == 0) {
+#pragma unroll
+                    for (int m = 0; m < M; ++m) F::renorm(acc[m]);
+                }
+            }
+        }
+    }
+    const uint32_t i0 = tile_base + (uint32_t)wv * (kWave * M) + (uint32_t)lane;
+    double t = 0.0;
+#pragma unroll
+    for (int m = 0; m < M; ++m) {
+        const double f = F::finish(acc[m]);
+        t += (i0 + (uint32_t)(kWave * m) < n) ? f : 0.0;
+    }
+    return t;
+}
+
+}  // namespace qmc

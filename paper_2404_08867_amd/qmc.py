@@ -61,8 +61,24 @@ def lib() -> ctypes.CDLL:
         L.qmc_lattice_sum_ex.argtypes = [i32, i64, dp, dp, i32, dp, i32, i32, dp, vp, sz, vp, vp]
         L.qmc_lattice_points.argtypes = [i32, i64, dp, i64, i64, dp, vp]
         L.qmc_mdi_lr.argtypes = [i32, dp, i32, dp, i32, i32, dp, vp, sz, vp]
+        L.qmc_lattice_sum_adjoint.argtypes = [i32, i64, dp, dp, i32, dp, i32, i32, dp, dp, dp, vp, sz, vp]
+        L.qmc_batch_plan_create.argtypes = [i32, vp, i32, vp, vp]
+        L.qmc_batch_plan_destroy.argtypes = [vp]
+        L.qmc_batch_plan_config.argtypes = [vp, vp]
+        L.qmc_batch_plan_set_config.argtypes = [vp, vp]
+        L.qmc_batch_workspace_size.argtypes = [vp, vp]
+        L.qmc_lattice_sum_batched.argtypes = [vp, dp, vp, sz, vp]
+        L.qmc_batch_autotune.argtypes = [vp, dp, vp, sz, vp, i32, vp]
+        L.qmc_batch_graph_create.argtypes = [vp, dp, vp, sz, vp]
+        L.qmc_graph_launch.argtypes = [vp, vp]
+        L.qmc_graph_destroy.argtypes = [vp]
         for name in ("qmc_korobov", "qmc_mdi_lr_dims", "qmc_param_count", "qmc_workspace_size",
-                     "qmc_lattice_sum", "qmc_lattice_sum_ex", "qmc_lattice_points", "qmc_mdi_lr"):
+                     "qmc_lattice_sum", "qmc_lattice_sum_ex", "qmc_lattice_points", "qmc_mdi_lr",
+                     "qmc_lattice_sum_adjoint",
+                     "qmc_batch_plan_create", "qmc_batch_plan_destroy", "qmc_batch_plan_config",
+                     "qmc_batch_plan_set_config", "qmc_batch_workspace_size",
+                     "qmc_lattice_sum_batched", "qmc_batch_autotune", "qmc_batch_graph_create",
+                     "qmc_graph_launch", "qmc_graph_destroy"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -225,3 +241,193 @@ def mdi_lr(N, family: int, params, precision: int = FP64, device="cuda", out=Non
     if out is not None:
         return out
     return q[0] if squeeze else q
+
+
+# ---- batched sums ---------------------------------------------------------------
+class Problem(ctypes.Structure):
+    """qmc_problem: one integrand of a batch (device pointers)."""
+    _fields_ = [("family", ctypes.c_int32), ("d", ctypes.c_int32), ("n", ctypes.c_int64),
+                ("z", ctypes.c_void_p), ("params", ctypes.c_void_p), ("shift", ctypes.c_void_p)]
+
+
+class BatchConfig(ctypes.Structure):
+    """qmc_batch_config: points per thread, workgroups per CU, order (0 = longest first)."""
+    _fields_ = [("points_per_thread", ctypes.c_int32), ("workgroups_per_cu", ctypes.c_int32),
+                ("order", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {"points_per_thread": self.points_per_thread,
+                "workgroups_per_cu": self.workgroups_per_cu, "order": self.order}
+
+
+class BatchPlan:
+    """A batch of plain lattice sums evaluated in one persistent launch.
+
+    `problems` is a list of (family, z, n, params, shift) with z, params, shift as
+    1-D host arrays or tensors; they are packed into three flat device tensors
+    that this object keeps alive (the plan holds pointers into them)."""
+
+    def __init__(self, problems, precision: int = FP32_COMPENSATED, config: dict | None = None,
+                 device="cuda"):
+        torch = _torch()
+        self.device = device
+        self.count = len(problems)
+        zs, ps, ss, descs = [], [], [], []
+        zoff = poff = soff = 0
+        for fam, z, n, params, shift in problems:
+            z = np.asarray(z.cpu() if hasattr(z, "cpu") else z, dtype=np.int64).ravel()
+            params = np.asarray(params.cpu() if hasattr(params, "cpu") else params, dtype=np.float64).ravel()
+            descs.append((int(fam), int(z.size), int(n), zoff, poff, None if shift is None else soff))
+            zs.append(z)
+            ps.append(params)
+            zoff += z.size
+            poff += params.size
+            if shift is not None:
+                sh = np.asarray(shift.cpu() if hasattr(shift, "cpu") else shift, dtype=np.float64).ravel()
+                ss.append(sh)
+                soff += sh.size
+        self.z = torch.as_tensor(np.concatenate(zs), device=device)
+        self.params = torch.as_tensor(np.concatenate(ps), device=device)
+        self.shift = torch.as_tensor(np.concatenate(ss) if ss else np.zeros(1), device=device)
+        arr = (Problem * self.count)()
+        zb, pb, sb = self.z.data_ptr(), self.params.data_ptr(), self.shift.data_ptr()
+        for i, (fam, d, n, zo, po, so) in enumerate(descs):
+            arr[i] = Problem(fam, d, n, zb + 8 * zo, pb + 8 * po, None if so is None else sb + 8 * so)
+        cfg = None
+        if config:
+            cfg = BatchConfig(config.get("points_per_thread", 0), config.get("workgroups_per_cu", 0),
+                              config.get("order", 0))
+        self._plan = ctypes.c_void_p()
+        _check(lib().qmc_batch_plan_create(self.count, ctypes.byref(arr), precision,
+                                           ctypes.byref(cfg) if cfg is not None else None,
+                                           ctypes.byref(self._plan)), "qmc_batch_plan_create")
+        b = ctypes.c_size_t(0)
+        _check(lib().qmc_batch_workspace_size(self._plan, ctypes.byref(b)), "qmc_batch_workspace_size")
+        self.ws = Workspace(int(b.value), device)
+
+    @classmethod
+    def from_batch(cls, batch, precision: int = FP32_COMPENSATED, config=None, device="cuda"):
+        """Plan for a workloads.Batch (Korobov z from qmc_korobov for each problem)."""
+        probs = [(p.family, korobov(p.d, p.n, p.a), p.n, p.params, p.shift) for p in batch.problems]
+        return cls(probs, precision, config, device)
+
+    @property
+    def config(self) -> dict:
+        c = BatchConfig()
+        _check(lib().qmc_batch_plan_config(self._plan, ctypes.byref(c)), "qmc_batch_plan_config")
+        return c.as_dict()
+
+    def set_config(self, **kw):
+        c = BatchConfig(kw.get("points_per_thread", 8), kw.get("workgroups_per_cu", 4), kw.get("order", 0))
+        _check(lib().qmc_batch_plan_set_config(self._plan, ctypes.byref(c)), "qmc_batch_plan_set_config")
+
+    def run(self, out=None):
+        torch = _torch()
+        q = out if out is not None else torch.empty(self.count, dtype=torch.float64, device=self.device)
+        _check(lib().qmc_lattice_sum_batched(self._plan, _ptr(q), self.ws.ptr, self.ws.nbytes, _stream()),
+               "qmc_lattice_sum_batched")
+        return q
+
+    def autotune(self, reps: int = 2, out=None) -> dict:
+        torch = _torch()
+        q = out if out is not None else torch.empty(self.count, dtype=torch.float64, device=self.device)
+        best = BatchConfig()
+        _check(lib().qmc_batch_autotune(self._plan, _ptr(q), self.ws.ptr, self.ws.nbytes, _stream(), reps,
+                                        ctypes.byref(best)), "qmc_batch_autotune")
+        return best.as_dict()
+
+    def graph(self, out):
+        """A native HIP graph replaying one batched launch into `out`."""
+        return Graph(self, out)
+
+    def __del__(self):
+        if getattr(self, "_plan", None) and _lib is not None:
+            _lib.qmc_batch_plan_destroy(self._plan)
+            self._plan = None
+
+
+class Graph:
+    def __init__(self, plan: BatchPlan, out):
+        self._keep = (plan, out)
+        self._g = ctypes.c_void_p()
+        _check(lib().qmc_batch_graph_create(plan._plan, _ptr(out), plan.ws.ptr, plan.ws.nbytes,
+                                            ctypes.byref(self._g)), "qmc_batch_graph_create")
+
+    def launch(self):
+        _check(lib().qmc_graph_launch(self._g, _stream()), "qmc_graph_launch")
+
+    def __del__(self):
+        if getattr(self, "_g", None) and _lib is not None:
+            _lib.qmc_graph_destroy(self._g)
+            self._g = None
+
+
+# ---- adjoint -----------------------------------------------------------------
+def lattice_sum_adjoint(z, n: int, family: int, params, precision: int = FP64, shift=None, gq=None,
+                        ws: Workspace | None = None, device="cuda"):
+    """(Q, gq * dQ/dparams) of the plain rule for each parameter row (qmc_lattice_sum_adjoint).
+
+    params: float64 [P] or [nsets, P]; gq: float64 [nsets] or None (= 1).
+    Returns (q [nsets], grad [nsets, P]) device tensors (squeezed for 1-D params)."""
+    torch = _torch()
+    zt = _dev(z, torch.int64, device)
+    pt = _dev(params, torch.float64, device)
+    squeeze = pt.dim() == 1
+    if squeeze:
+        pt = pt.unsqueeze(0)
+    d = int(zt.numel())
+    nsets, P = int(pt.shape[0]), int(pt.shape[1])
+    st = None if shift is None else _dev(shift, torch.float64, device)
+    gt = None if gq is None else _dev(gq, torch.float64, device).reshape(-1)
+    if gt is not None and gt.numel() != nsets:
+        raise QmcError(ERR_INVALID_ARG, "gq must have one value per parameter set")
+    q = torch.empty(nsets, dtype=torch.float64, device=device)
+    g = torch.empty((nsets, P), dtype=torch.float64, device=device)
+    w = _workspace(d, n, nsets, device, ws)
+    _check(lib().qmc_lattice_sum_adjoint(d, n, _ptr(zt), _ptr(st), family, _ptr(pt), nsets, precision,
+                                         _ptr(gt), _ptr(q), _ptr(g), w.ptr, w.nbytes, _stream()),
+           "qmc_lattice_sum_adjoint")
+    if squeeze:
+        return q[0], g[0]
+    return q, g
+
+
+def _autograd_class():
+    torch = _torch()
+
+    class LatticeSumFunction(torch.autograd.Function):
+        """Q = lattice_sum(params) with dQ/dparams from the adjoint kernel.
+
+        forward: qmc_lattice_sum;  backward(gQ): qmc_lattice_sum_adjoint with gq = gQ."""
+
+        @staticmethod
+        def forward(ctx, params, z, n, family, precision, shift):
+            ctx.save_for_backward(params, z, shift if shift is not None else torch.empty(0))
+            ctx.n, ctx.family, ctx.precision, ctx.has_shift = n, family, precision, shift is not None
+            return lattice_sum(z, n, family, params, precision, shift=shift)
+
+        @staticmethod
+        def backward(ctx, gq):
+            params, z, shift = ctx.saved_tensors
+            sh = shift if ctx.has_shift else None
+            one_d = params.dim() == 1
+            g_in = gq.reshape(1) if one_d else gq.contiguous()
+            _, grad = lattice_sum_adjoint(z, ctx.n, ctx.family, params, ctx.precision, shift=sh,
+                                          gq=g_in, device=params.device)
+            return grad, None, None, None, None, None
+
+    return LatticeSumFunction
+
+
+_LSF = None
+
+
+def lattice_sum_autograd(params, z, n: int, family: int, precision: int = FP64, shift=None):
+    """Differentiable Q (w.r.t. params) through the HIP forward and adjoint kernels."""
+    global _LSF
+    torch = _torch()
+    if _LSF is None:
+        _LSF = _autograd_class()
+    zt = _dev(z, torch.int64, params.device)
+    st = None if shift is None else _dev(shift, torch.float64, params.device)
+    return _LSF.apply(params, zt, n, family, precision, st)

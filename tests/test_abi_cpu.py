@@ -115,3 +115,30 @@ def test_python_binding_raises_when_library_missing(monkeypatch, tmp_path):
     monkeypatch.setattr(qmc, "LIB_PATH", str(tmp_path / "libqmc.so"))
     with pytest.raises(qmc.QmcError):
         qmc.lib()
+
+
+def test_batch_plan_rejects_invalid_problems():
+    L = qmc.lib()
+    fake = 0x1000
+    plan = ctypes.c_void_p()
+
+    def create(probs, precision=0, cfg=None):
+        arr = (qmc.Problem * len(probs))(*probs)
+        return L.qmc_batch_plan_create(len(probs), ctypes.byref(arr), precision,
+                                       ctypes.byref(cfg) if cfg is not None else None, ctypes.byref(plan))
+
+    good = qmc.Problem(0, 4, 1009, fake, fake, None)
+    assert L.qmc_batch_plan_create(0, None, 0, None, ctypes.byref(plan)) == qmc.ERR_INVALID_ARG
+    assert create([good, qmc.Problem(9, 4, 1009, fake, fake, None)]) == qmc.ERR_INVALID_ARG
+    assert b"problem 1" in L.qmc_last_error()
+    assert create([qmc.Problem(0, 0, 1009, fake, fake, None)]) == qmc.ERR_INVALID_ARG
+    assert create([qmc.Problem(0, 4, 0, fake, fake, None)]) == qmc.ERR_INVALID_ARG
+    assert create([qmc.Problem(0, 4, 1 << 31, fake, fake, None)]) == qmc.ERR_INVALID_ARG
+    assert create([qmc.Problem(0, 4, 1009, None, fake, None)]) == qmc.ERR_INVALID_ARG
+    assert create([good], precision=7) == qmc.ERR_INVALID_ARG
+    assert create([good], cfg=qmc.BatchConfig(5, 4, 0)) == qmc.ERR_INVALID_ARG
+    assert create([good], cfg=qmc.BatchConfig(8, 9, 0)) == qmc.ERR_INVALID_ARG
+    assert create([good], cfg=qmc.BatchConfig(8, 4, 2)) == qmc.ERR_INVALID_ARG
+    assert L.qmc_lattice_sum_batched(None, fake, fake, 0, None) == qmc.ERR_INVALID_ARG
+    assert L.qmc_graph_launch(None, None) == qmc.ERR_INVALID_ARG
+    assert L.qmc_batch_plan_destroy(None) == qmc.OK

@@ -1,0 +1,128 @@
+"""Batched plain sums (one persistent launch for many integrands) against the oracle."""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2404_08867_amd import qmc
+from paper_2404_08867_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+TOL = {qmc.FP64: 1e-12, qmc.FP32_COMPENSATED: 1e-6}
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _mixed_problems(seed, count, dmax=130, nmax=60000):
+    rng = np.random.default_rng(seed)
+    probs = []
+    for b in range(count):
+        fam = b % 4
+        d = int(rng.integers(1, dmax + 1))
+        n = int(rng.choice([1, 2, 63, 1025, int(rng.integers(3, nmax))])) if b % 7 == 0 else int(rng.integers(3, nmax))
+        a = W.draw_coprime(rng, n)
+        p = W.draw_params(rng, fam, d)
+        shift = rng.uniform(0, 1, d) if b % 3 == 0 else None
+        probs.append((fam, qmc.korobov(d, n, a), n, p, shift))
+    return probs
+
+
+def _oracle(probs):
+    out = []
+    for fam, z, n, p, shift in probs:
+        out.append(O.lattice_sum(z, n, fam, p, shift))
+    return out
+
+
+def _check(q, ref, precision):
+    for i, (qo, ao) in enumerate(ref):
+        assert abs(q[i] - qo) / max(abs(qo), ao, 1e-300) <= TOL[precision], (i, q[i], qo)
+
+
+@pytest.mark.parametrize("precision", [qmc.FP64, qmc.FP32_COMPENSATED])
+def test_batched_matches_oracle(precision):
+    probs = _mixed_problems(1, 41)
+    plan = qmc.BatchPlan(probs, precision)
+    q = plan.run().cpu().numpy()
+    _check(q, _oracle(probs), precision)
+
+
+def test_batched_every_configuration_is_exact_and_reproducible():
+    probs = _mixed_problems(2, 23, dmax=70, nmax=30000)
+    ref = _oracle(probs)
+    for precision in (qmc.FP64, qmc.FP32_COMPENSATED):
+        plan = qmc.BatchPlan(probs, precision)
+        for M in (4, 8, 16):
+            for wpc in (1, 8):
+                for order in (0, 1):
+                    plan.set_config(points_per_thread=M, workgroups_per_cu=wpc, order=order)
+                    assert plan.config == {"points_per_thread": M, "workgroups_per_cu": wpc, "order": order}
+                    q1 = plan.run().cpu().numpy()
+                    q2 = plan.run().cpu().numpy()
+                    assert np.array_equal(q1.view(np.int64), q2.view(np.int64))
+                    _check(q1, ref, precision)
+
+
+def test_batched_agrees_with_single_problem_kernel():
+    probs = _mixed_problems(3, 12, dmax=40, nmax=200000)
+    q = qmc.BatchPlan(probs, qmc.FP64).run().cpu().numpy()
+    for i, (fam, z, n, p, shift) in enumerate(probs):
+        qs = float(qmc.lattice_sum(z, n, fam, p, qmc.FP64, shift=shift).item())
+        assert abs(q[i] - qs) <= 1e-13 * max(abs(qs), 1.0), i
+
+
+def test_batched_graph_replays_match_eager():
+    """A captured batched launch replayed several times, with eager work in between,
+    returns the eager result every time (no memset nodes; counters self-reset)."""
+    torch = _torch()
+    probs = _mixed_problems(4, 17, dmax=50, nmax=40000)
+    plan = qmc.BatchPlan(probs, qmc.FP32_COMPENSATED)
+    eager = plan.run().cpu().numpy()
+    out = torch.full((len(probs),), -1.0, dtype=torch.float64, device="cuda")
+    g = plan.graph(out)
+    other = _mixed_problems(5, 1, dmax=10, nmax=5000)[0]
+    for r in range(4):
+        out.fill_(-1.0)
+        g.launch()
+        torch.cuda.synchronize()
+        assert np.array_equal(out.cpu().numpy().view(np.int64), eager.view(np.int64)), r
+        # eager work between replays: torch ops and a plain sum on the default workspace
+        _ = (torch.arange(1000, device="cuda", dtype=torch.float64) ** 2).sum().item()
+        fam, z, n, p, sh = other
+        qmc.lattice_sum(z, n, fam, p, qmc.FP64, shift=sh)
+        torch.cuda.synchronize()
+    del g
+
+
+def test_batched_autotune_picks_a_valid_config(tmp_path, monkeypatch):
+    monkeypatch.setenv("QMC_AUTOTUNE_CACHE", str(tmp_path / "tune.txt"))
+    probs = _mixed_problems(6, 30, dmax=60, nmax=100000)
+    ref = _oracle(probs)
+    plan = qmc.BatchPlan(probs, qmc.FP32_COMPENSATED)
+    best = plan.autotune(reps=1)
+    assert best["points_per_thread"] in (4, 8, 16) and 1 <= best["workgroups_per_cu"] <= 8
+    assert plan.config == best
+    _check(plan.run().cpu().numpy(), ref, qmc.FP32_COMPENSATED)
+    # the cached entry is reused by a new plan of the same batch
+    plan2 = qmc.BatchPlan(probs, qmc.FP32_COMPENSATED)
+    assert plan2.autotune(reps=1) == best
+    assert (tmp_path / "tune.txt").read_text().strip()
+
+
+def test_batched_workload_4096_sampled():
+    """The 4096-integrand workload in one FP32-compensated launch; a sample of the
+    integrands (all of small cost plus a few larger ones) is checked against the oracle."""
+    batch = W.batched_4096()
+    plan = qmc.BatchPlan.from_batch(batch, qmc.FP32_COMPENSATED)
+    q = plan.run().cpu().numpy()
+    assert np.all(np.isfinite(q))
+    cost = np.array([p.n * p.d for p in batch.problems])
+    order = np.argsort(cost)
+    sample = list(order[:12]) + list(order[len(order) // 2: len(order) // 2 + 2])
+    for i in sample:
+        p = batch.problems[i]
+        qo, ao = O.lattice_sum(O.korobov(p.d, p.n, p.a), p.n, p.family, p.params)
+        assert abs(q[i] - qo) / max(abs(qo), ao) <= 1e-6, (i, p.d, p.n, p.family, q[i], qo)
