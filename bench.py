@@ -36,15 +36,25 @@ METRIC = "lattice-point integrand evals/sec at rel err ≤1e-6 vs FP64 oracle (1
 # VALU issue peak of MI355X without packed FP32: 256 CUs x 64 lanes x 2.4 GHz.
 PEAK_LANE_OPS = 256 * 64 * 2.4e9
 
-# Algorithmic VALU lane-operations per lattice point (one d-dimensional
-# integrand evaluation): d * (3 index + 2 coordinate + c_fam) + T + 6, with
-# c_fam = 1 (exp-sum, oscillatory), 2 (Gaussian), 3 (product peak), one
-# transcendental T and 6 for accumulation and scaling.
+# Algorithmic VALU issue slots per lattice point (one d-dimensional integrand
+# evaluation with exact integer indices):
+#   d * (3 index step + 1 index-to-float conversion + c_fam) + 2 + 2
+# c_fam = VALU operations of the family per direction once the coordinate's scale
+# and offset are folded into its first FMA: 1 (exp-sum, oscillatory: the argument
+# FMA), 2 (Gaussian: y, then y^2 accumulated), 3 (product peak: y, y^2 + c^-2, the
+# product); 2 issue slots for the per-point half-rate transcendental; 2 for the
+# FP64 accumulation (convert, add).
 C_FAM = {0: 1, 1: 3, 2: 2, 3: 1}
 
 
 def work_per_point(d: int, family: int) -> int:
-    return d * (3 + 2 + C_FAM[family]) + 1 + 6
+    return d * (3 + 1 + C_FAM[family]) + 2 + 2
+
+
+# The adjoint adds, per point and direction, the index step, the conversion, the
+# coordinate FMA and the accumulation of w * h(x), and one more transcendental.
+def work_per_point_adjoint(d: int, family: int) -> int:
+    return work_per_point(d, family) + d * (3 + 1 + 1 + 1) + 2
 
 
 def parse():
@@ -53,7 +63,8 @@ def parse():
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--workload", default="plain_d20_peak",
-                    choices=["plain_d20_peak", "plain_d4_expsum", "mdi_d100_gauss"])
+                    choices=["plain_d20_peak", "plain_d4_expsum", "mdi_d100_gauss", "batched_4096",
+                             "adjoint_d50_osc"])
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
                     help="wall-clock budget of the oracle's CPU-baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -166,11 +177,109 @@ def bench_mdi(args, torch, qmc, W):
         results[name] = dict(step_s=step_s, kern_s=kern_s, lat_s=lat_s, q=out.cpu().numpy())
         del g
     units = int(w.N.sum()) * nsets  # one-dimensional factor evaluations per launch
-    wpp = 2 + 1 + 2  # per factor: FMA, square, transcendental, accumulate (Gaussian)
+    wpp = 6  # per Gaussian factor: FMA, square, exp2 (2 issue slots), convert + FP64 add
     config = {"workload": w.name, "d": w.d, "N": int(w.N[0]), "nsets": nsets,
               "family": W.FAMILY_NAMES[w.family], "precision": "fp32_compensated",
               "unit_of_work": "one-dimensional factor evaluation"}
     return w, results, units, wpp, config
+
+
+def time_eager(torch, launch, steps, warmup):
+    """For launches much longer than their launch overhead: W eager warm-ups, then
+    K eager launches between two synchronisations, HIP events around them."""
+    for _ in range(warmup):
+        launch()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record()
+    for _ in range(steps):
+        launch()
+    e1.record()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    return (t1 - t0) / steps, e0.elapsed_time(e1) * 1e-3 / steps
+
+
+def bench_batched(args, torch, qmc, W):
+    batch = W.batched_4096()
+    units = sum(p.n for p in batch.problems)
+    wpp = sum(p.n * work_per_point(p.d, p.family) for p in batch.problems) / units
+    results = {}
+    tuned = None
+    for prec, name in ((qmc.FP32_COMPENSATED, "fp32c"), (qmc.FP64, "fp64")):
+        plan = qmc.BatchPlan.from_batch(batch, prec, config=tuned)
+        out = torch.zeros(plan.count, dtype=torch.float64, device="cuda")
+        if tuned is None:
+            tuned = plan.autotune(reps=1, out=out)
+        step_s, kern_s = time_eager(torch, lambda: plan.run(out=out), args.steps, args.warmup)
+        results[name] = dict(step_s=step_s, kern_s=kern_s, lat_s=step_s, q=out.cpu().numpy())
+        del plan
+    config = {"workload": batch.name, "integrands": len(batch.problems), "points": units,
+              "point_dims": int(sum(p.n * p.d for p in batch.problems)),
+              "families": "exp_sum/product_peak/gaussian", "precision": "fp32_compensated",
+              "schedule": dict(tuned)}
+    return batch, results, units, wpp, config
+
+
+def bench_adjoint(args, torch, qmc, W):
+    w = W.adjoint_d50_osc()
+    z = torch.tensor(qmc.korobov(w.d, w.n, w.a), device="cuda")
+    params = torch.tensor(w.params, dtype=torch.float64, device="cuda")
+    nsets = params.shape[0]
+    ws = qmc.Workspace(qmc.workspace_size(w.d, w.n, nsets))
+    results = {}
+    for prec, name in ((qmc.FP32_COMPENSATED, "fp32c"), (qmc.FP64, "fp64")):
+        holder = {}
+
+        def launch(prec=prec):
+            holder["r"] = qmc.lattice_sum_adjoint(z, w.n, w.family, params, prec, ws=ws)
+
+        step_s, kern_s = time_eager(torch, launch, args.steps, args.warmup)
+        q, g = holder["r"]
+        results[name] = dict(step_s=step_s, kern_s=kern_s, lat_s=step_s, q=q.cpu().numpy(),
+                             g=g.cpu().numpy())
+    units = w.n * nsets  # point-set evaluations of f and all its parameter derivatives
+    wpp = work_per_point_adjoint(w.d, w.family)
+    config = {"workload": w.name, "d": w.d, "n": w.n, "nsets": nsets, "a": w.a,
+              "family": W.FAMILY_NAMES[w.family], "precision": "fp32_compensated",
+              "unit_of_work": "one point of one parameter set, value and full gradient"}
+    return w, results, units, wpp, config
+
+
+def oracle_batched_baseline(batch, qs32, qs64, seconds):
+    """Oracle over the integrands in increasing cost until the time budget is spent."""
+    import oracle as O
+    order = sorted(range(len(batch.problems)), key=lambda i: batch.problems[i].n * batch.problems[i].d)
+    t0 = time.perf_counter()
+    pts, e32, e64, k = 0, 0.0, 0.0, 0
+    for i in order:
+        p = batch.problems[i]
+        qo, ao = O.lattice_sum(O.korobov(p.d, p.n, p.a), p.n, p.family, p.params)
+        pts += p.n
+        k += 1
+        e32 = max(e32, abs(qs32[i] - qo) / max(abs(qo), ao))
+        e64 = max(e64, abs(qs64[i] - qo) / max(abs(qo), ao))
+        if time.perf_counter() - t0 > seconds:
+            break
+    dt = time.perf_counter() - t0
+    return pts / dt, k, e32, e64
+
+
+def oracle_adjoint_baseline(w, r32, r64):
+    import numpy as np
+    import oracle as O
+    z = O.korobov(w.d, w.n, w.a)
+    t0 = time.perf_counter()
+    qo, go = O.lattice_grad(z, w.n, w.family, w.params[0])
+    dt = time.perf_counter() - t0
+    scale = float(np.max(np.abs(go)))
+    errs = []
+    for r in (r32, r64):
+        e = max(abs(r["q"][0] - qo) / max(abs(qo), 0.5), float(np.max(np.abs(r["g"][0] - go))) / scale)
+        errs.append(e)
+    return w.n / dt, errs[0], errs[1]
 
 
 def main():
@@ -193,6 +302,10 @@ def main():
 
     if args.workload == "mdi_d100_gauss":
         prob, res, units, wpp, config = bench_mdi(args, torch, qmc, W)
+    elif args.workload == "batched_4096":
+        prob, res, units, wpp, config = bench_batched(args, torch, qmc, W)
+    elif args.workload == "adjoint_d50_osc":
+        prob, res, units, wpp, config = bench_adjoint(args, torch, qmc, W)
     else:
         prob, res, units, wpp, config = bench_plain(args, torch, qmc, W)
 
@@ -202,7 +315,9 @@ def main():
     achieved = wpp * units / main_r["kern_s"]
     line.update({
         "value": value,
-        "unit": "lattice-point evals/s" if args.workload != "mdi_d100_gauss" else "factor evals/s",
+        "unit": {"mdi_d100_gauss": "factor evals/s",
+                 "adjoint_d50_osc": "point-set evals (value + gradient)/s"}.get(
+                     args.workload, "lattice-point evals/s"),
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
@@ -217,7 +332,7 @@ def main():
             "bound": "alu",
             "achieved": achieved / 1e12,
             "peak": PEAK_LANE_OPS / 1e12,
-            "unit": "T VALU lane-ops/s",
+            "unit": "T VALU issue slots/s (lane-ops)",
             "frac": achieved / PEAK_LANE_OPS,
             "traffic": None,
             "work_per_unit": wpp,
@@ -229,7 +344,14 @@ def main():
     })
 
     if not args.no_cpu_baseline:
-        if args.workload == "mdi_d100_gauss":
+        if args.workload == "batched_4096":
+            rate, k, e32, e64 = oracle_batched_baseline(prob, res["fp32c"]["q"], res["fp64"]["q"],
+                                                        args.cpu_seconds)
+            sample = f"the {k} cheapest of {len(prob.problems)} integrands (time budget {args.cpu_seconds:.0f} s)"
+        elif args.workload == "adjoint_d50_osc":
+            rate, e32, e64 = oracle_adjoint_baseline(prob, res["fp32c"], res["fp64"])
+            sample = "parameter set 0 of 64, all n points, value and 51 gradient components"
+        elif args.workload == "mdi_d100_gauss":
             rate, reps, vals = oracle_mdi_baseline(prob, len(prob.params), args.cpu_seconds)
             qs32, qs64 = res["fp32c"]["q"], res["fp64"]["q"]
             e32 = max(abs(qs32[s] - v) / abs(v) for s, v in enumerate(vals))
