@@ -28,10 +28,11 @@
  *     stream).  Results are valid once the stream has been synchronised.
  *   - No entry point that launches work allocates memory.  Scratch space comes
  *     from the caller's workspace `ws` (device, 256-byte aligned, at least the
- *     size reported by the matching *_workspace_size query).  Its first 1 MiB
- *     holds completion counters: a workspace must be zero-filled once before its
- *     first use, and every call leaves the counters at zero again, so one
- *     workspace serves any sequence of calls to any entry point without clearing.
+ *     size reported by the matching *_workspace_size query).  Its first 4 MiB
+ *     hold completion counters and reduction slots: a workspace must be
+ *     zero-filled once before its first use, and every call leaves that region at
+ *     zero again, so one workspace serves any sequence of calls to any entry point
+ *     without clearing.
  *     Calls that run concurrently need distinct workspaces.
  *   - Scalar arguments are validated before anything is launched:
  *       1 <= d <= 1024, 1 <= n < 2^31, 1 <= nsets <= 4096 (qmc_mdi_lr: 2^24),

@@ -312,7 +312,7 @@ static size_t adjoint_set_stride(int P, int nsets) {
 }
 
 size_t adjoint_workspace_bytes(int P, int nsets) {
-    return kTicketBytes + ((size_t)nsets * adjoint_set_stride(P, nsets) * sizeof(double) + 255) / 256 * 256;
+    return kZeroBytes + ((size_t)nsets * adjoint_set_stride(P, nsets) * sizeof(double) + 255) / 256 * 256;
 }
 
 template <int FAM, bool FP32, class A, int M>
@@ -330,7 +330,7 @@ static hipError_t launch_adj_m(const AdjLaunch& L, hipStream_t stream) {
     a.q_out = L.q_out;
     a.grad_out = L.grad_out;
     a.tickets = (uint32_t*)L.ws;
-    a.scratch = (double*)((char*)L.ws + kTicketBytes);
+    a.scratch = (double*)((char*)L.ws + kZeroBytes);
     int g = adjoint_blocks_per_set(L.nsets);
     if ((uint32_t)g > a.tiles) g = (int)a.tiles;
     a.scratch_stride = adjoint_set_stride(L.P, L.nsets);

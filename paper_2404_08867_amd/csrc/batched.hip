@@ -119,7 +119,7 @@ static hipError_t launch_batched_m(const BatchLaunch& L, hipStream_t stream) {
     a.total_tiles = L.total_tiles;
     a.q_out = L.q_out;
     a.counters = (uint32_t*)L.ws;
-    a.partials = (double*)((char*)L.ws + kTicketBytes);
+    a.partials = (double*)((char*)L.ws + kZeroBytes);
     hipLaunchKernelGGL((batched_kernel<FP32, M>), dim3((unsigned)L.grid), dim3(kBlock), 0, stream, a);
     return hipGetLastError();
 }

@@ -160,6 +160,10 @@ __device__ __forceinline__ bool take_ticket(uint32_t* ticket, uint32_t expected)
 // counters at fixed offsets means that no call can find another call's scratch
 // data where it expects a zero counter, whatever sizes the two calls had.
 constexpr size_t kTicketBytes = size_t(1) << 20;
+// Then kSlotBytes of tagged slots (plain-sum grid reduction), also zero between
+// calls; scratch that needs no initialisation starts at kZeroBytes.
+constexpr size_t kSlotBytes = size_t(3) << 20;
+constexpr size_t kZeroBytes = kTicketBytes + kSlotBytes;
 constexpr int kTicketsPerReduction = kReduceGroups + 1;
 
 // Workspace slots of one reduction over G workgroups.
@@ -172,32 +176,82 @@ struct GridSlots {
 // Scratch doubles of one reduction over G workgroups.
 __host__ __device__ constexpr size_t grid_scratch_doubles(int G) { return (size_t)G + kReduceGroups; }
 
+// Scalar grid sum with tagged slots.  A slot holds the bits of a double XOR
+// kSlotTag, so a zero slot means "not written yet" (the workspace is zero-filled
+// and every reader clears the slots it consumed).  A writer publishes its slot
+// and takes its ticket without waiting for the store to land; the reader that
+// drew the last ticket waits on each slot until it is non-zero.  That wait ends:
+// every slot it waits on belongs to a workgroup that issued the store before
+// taking its ticket.  This keeps two store-completion round trips off the
+// critical path of the last workgroup.
+constexpr uint64_t kSlotTag = 0x7ff8dead5eedbeefull;  // a NaN pattern no partial takes
+
+__device__ __forceinline__ void put_slot(double* slot, double v) {
+    uint64_t e = (uint64_t)__double_as_longlong(v) ^ kSlotTag;
+    if (e == 0) e = 0x7ff8000000000000ull ^ kSlotTag;  // the tag pattern itself: store a quiet NaN
+    __hip_atomic_store(reinterpret_cast<uint64_t*>(slot), e, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ double take_slot(double* slot) {
+    uint64_t* p = reinterpret_cast<uint64_t*>(slot);
+    uint64_t x;
+    while ((x = __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) == 0) {
+        __builtin_amdgcn_s_sleep(1);
+    }
+    __hip_atomic_store(p, (uint64_t)0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return __longlong_as_double((long long)(x ^ kSlotTag));
+}
+
+// One thread: take a ticket without waiting for earlier stores (their readers
+// wait on the tagged slots instead).
+__device__ __forceinline__ bool take_ticket_nowait(uint32_t* ticket, uint32_t expected) {
+    const uint32_t t = __hip_atomic_fetch_add(ticket, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (t + 1 == expected) {
+        __hip_atomic_store(ticket, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        return true;
+    }
+    return false;
+}
+
 // Called by every thread of workgroup b with its workgroup total v.  Returns true
-// in exactly one workgroup, whose threads then all hold the grand total.
+// in exactly one workgroup, whose threads then all hold the grand total.  The
+// group partial of group g sums its members b = g, g + NG, ... in that order and
+// the total sums the groups in order, whoever arrives last.
 // `red` is LDS scratch for block_sum; `flag` one LDS int.
 __device__ __forceinline__ bool grid_sum(double v, int b, int G, const GridSlots& s, double* red,
                                          int* flag, double& total) {
     const int NG = G < kReduceGroups ? G : kReduceGroups;
     const int g = b % NG;
     const int members = (G - g + NG - 1) / NG;
+    const int me = b / NG;  // this workgroup's position in its group
     if (threadIdx.x == 0) {
-        publish_partial(&s.partials[b], v);
-        *flag = take_ticket(&s.tickets[g], (uint32_t)members) ? 1 : 0;
+        if (members > 1) put_slot(&s.partials[b], v);
+        *flag = (members == 1 || take_ticket_nowait(&s.tickets[g], (uint32_t)members)) ? 1 : 0;
     }
     __syncthreads();
     if (!*flag) return false;
     double t = 0.0;
-    for (int i = threadIdx.x; i < members; i += kBlock) t += read_partial(&s.partials[g + i * NG]);
+    for (int i = threadIdx.x; i < members; i += kBlock)
+        t += (i == me) ? v : take_slot(&s.partials[g + i * NG]);
+    if (members > 1 && threadIdx.x == 0) {
+        // Own slot: cleared by the thread that wrote it, so the clear follows the store.
+        __hip_atomic_store(reinterpret_cast<uint64_t*>(&s.partials[b]), (uint64_t)0, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+    }
     t = block_sum(t, red);
     if (threadIdx.x == 0) {
-        publish_partial(&s.group_partials[g], t);
-        *flag = take_ticket(&s.tickets[kReduceGroups], (uint32_t)NG) ? 1 : 0;
+        if (NG > 1) put_slot(&s.group_partials[g], t);
+        *flag = (NG == 1 || take_ticket_nowait(&s.tickets[kReduceGroups], (uint32_t)NG)) ? 1 : 0;
     }
     __syncthreads();
     if (!*flag) return false;
-    t = 0.0;
-    for (int i = threadIdx.x; i < NG; i += kBlock) t += read_partial(&s.group_partials[i]);
-    total = block_sum(t, red);
+    double u = 0.0;
+    for (int i = threadIdx.x; i < NG; i += kBlock) u += (i == g) ? t : take_slot(&s.group_partials[i]);
+    if (NG > 1 && threadIdx.x == 0) {
+        __hip_atomic_store(reinterpret_cast<uint64_t*>(&s.group_partials[g]), (uint64_t)0,
+                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    total = block_sum(u, red);
     return true;
 }
 

@@ -46,14 +46,33 @@ __global__ __launch_bounds__(kBlock) void lattice_sum_kernel(const SumArgs a) {
     __shared__ double s_red[3 * kWaves];
     __shared__ int s_last;
 
+    // Small problems: copy z, shift and the parameter row into LDS with one burst
+    // of loads, so that the prologue pays one memory round trip instead of one per
+    // dependent step.
+    __shared__ int64_t s_z[kDimChunk];
+    __shared__ double s_shift[kDimChunk];
+    __shared__ double s_p[2 * kDimChunk + 1];
+
     const int set = blockIdx.y;
-    const ProblemView v = make_view(a.d, a.n, a.z, a.shift, a.params + (size_t)set * a.P);
+    ProblemView v = make_view(a.d, a.n, a.z, a.shift, a.params + (size_t)set * a.P);
+    const bool one_chunk = v.d <= kDimChunk;
+    if (one_chunk) {
+        const int t = threadIdx.x;
+        if (t < v.d) {
+            s_z[t] = v.z[t];
+            if (v.shift) s_shift[t] = v.shift[t];
+        }
+        if (t < a.P) s_p[t] = v.p[t];
+        __syncthreads();
+        v.z = s_z;
+        v.p = s_p;
+        if (v.shift) v.shift = s_shift;
+    }
     double init0, ds1;
     int ie;
     block_constants<F>(v, s_red, init0, ds1, ie);
 
     // With one chunk of directions the per-direction tables serve every tile.
-    const bool one_chunk = v.d <= kDimChunk;
     if (one_chunk) fill_dims<F>(v, s, 0, v.d);
 
     double tacc = 0.0;
@@ -106,7 +125,9 @@ static size_t set_stride(int nsets) {
 }
 
 size_t plain_workspace_bytes(int nsets) {
-    return kTicketBytes + (size_t)nsets * set_stride(nsets) * sizeof(double);
+    // The tagged slots live in the zero region; nsets * set_stride <= 8192 + 40 * nsets
+    // doubles (<= 1.4 MiB for nsets <= 4096) fits in kSlotBytes.
+    return kZeroBytes;
 }
 
 int device_cu_count() {
@@ -134,7 +155,7 @@ static hipError_t launch_fm(const PlainLaunch& L, hipStream_t stream) {
     a.tiles = (uint32_t)(((uint64_t)L.n + tile - 1) / tile);
     a.q_out = L.q_out;
     a.tickets = (uint32_t*)L.ws;
-    a.scratch = (double*)((char*)L.ws + kTicketBytes);
+    a.scratch = (double*)((char*)L.ws + kTicketBytes);  // tagged-slot part of the zero region
     a.scratch_stride = set_stride(L.nsets);
     int g = sum_blocks_per_set(L.nsets);
     if (L.max_blocks > 0 && L.max_blocks < g) g = L.max_blocks;

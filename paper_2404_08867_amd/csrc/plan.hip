@@ -225,7 +225,7 @@ qmc_status qmc_batch_plan_create(int32_t count, const qmc_problem* problems, int
         delete p;
         return fail(QMC_ERR_UNSUPPORTED, "too many problems for the workspace counter region");
     }
-    p->ws_bytes = qmc::kTicketBytes + ((max_tiles * sizeof(double) + 255) / 256) * 256;
+    p->ws_bytes = qmc::kZeroBytes + ((max_tiles * sizeof(double) + 255) / 256) * 256;
     s = build_tables(p);
     if (s != QMC_OK) {
         if (p->d_probs) (void)hipFree(p->d_probs);
