@@ -45,7 +45,7 @@ using qmc::ok;
 
 constexpr int kMaxD = 1024;
 constexpr int64_t kMaxN = (int64_t)1 << 31;  // exclusive
-constexpr int kMaxSets = 4096;           // plain sums: one grid row and 33 counters per set
+constexpr int kMaxSets = qmc::kMaxSumSets;  // plain sums: one grid row and 33 counters per set
 constexpr int kMaxMdiSets = 1 << 24;     // MDI-LR: sets are spread over workgroups
 constexpr int64_t kMaxNodes = (int64_t)1 << 20;
 constexpr int64_t kMaxExport = (int64_t)1 << 26;

@@ -51,8 +51,14 @@ __device__ __forceinline__ void run_tile(const BatchArgs& a, int pi, const DevPr
     const ProblemView v = make_view(pr.d, pr.n, pr.z, pr.shift, pr.params);
     double init0, ds1;
     int ie;
-    block_constants<F>(v, red, init0, ds1, ie);
-    const double t = tile_points<F, M>(v, s, local_tile * kTile, init0, false);
+    double t;
+    if (v.d <= kDimChunk) {
+        setup_one_chunk<F, M>(v, s, red, local_tile * kTile, init0, ds1, ie);
+        t = tile_points_one_chunk<F, M>(v, s, local_tile * kTile, init0, true);
+    } else {
+        block_constants<F>(v, red, init0, ds1, ie);
+        t = tile_points<F, M>(v, s, local_tile * kTile, init0);
+    }
     const double bsum = block_sum(t, red);
     if (threadIdx.x == 0) {
         publish_partial(&a.partials[pr.tile_begin + local_tile], bsum);

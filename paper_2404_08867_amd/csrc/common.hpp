@@ -166,14 +166,19 @@ constexpr size_t kSlotBytes = size_t(3) << 20;
 constexpr size_t kZeroBytes = kTicketBytes + kSlotBytes;
 constexpr int kTicketsPerReduction = kReduceGroups + 1;
 
-// Workspace slots of one reduction over G workgroups.
+// Workspace slots of one reduction over G workgroups.  Slot i sits at
+// partials[i * slot_stride] (group slots likewise), ticket g at
+// tickets[g * ticket_stride]: strides of a cache line or more keep the writers of
+// different slots, and the atomics on different tickets, off each other's lines.
 struct GridSlots {
-    double* partials;        // [G] scratch
-    double* group_partials;  // [kReduceGroups] scratch
+    double* partials;        // [G] slots
+    double* group_partials;  // [kReduceGroups] slots
     uint32_t* tickets;       // [kReduceGroups + 1] counters: per group, then the top one
+    int slot_stride;         // doubles between consecutive slots
+    int ticket_stride;       // counters between consecutive tickets
 };
 
-// Scratch doubles of one reduction over G workgroups.
+// Slots of one reduction over G workgroups.
 __host__ __device__ constexpr size_t grid_scratch_doubles(int G) { return (size_t)G + kReduceGroups; }
 
 // Scalar grid sum with tagged slots.  A slot holds the bits of a double XOR
@@ -224,31 +229,39 @@ __device__ __forceinline__ bool grid_sum(double v, int b, int G, const GridSlots
     const int g = b % NG;
     const int members = (G - g + NG - 1) / NG;
     const int me = b / NG;  // this workgroup's position in its group
+    const size_t ss = (size_t)s.slot_stride;
     if (threadIdx.x == 0) {
-        if (members > 1) put_slot(&s.partials[b], v);
-        *flag = (members == 1 || take_ticket_nowait(&s.tickets[g], (uint32_t)members)) ? 1 : 0;
+        if (members > 1) put_slot(&s.partials[b * ss], v);
+        *flag = (members == 1 ||
+                 take_ticket_nowait(&s.tickets[(size_t)g * s.ticket_stride], (uint32_t)members))
+                    ? 1
+                    : 0;
     }
     __syncthreads();
     if (!*flag) return false;
     double t = 0.0;
     for (int i = threadIdx.x; i < members; i += kBlock)
-        t += (i == me) ? v : take_slot(&s.partials[g + i * NG]);
+        t += (i == me) ? v : take_slot(&s.partials[(g + (size_t)i * NG) * ss]);
     if (members > 1 && threadIdx.x == 0) {
         // Own slot: cleared by the thread that wrote it, so the clear follows the store.
-        __hip_atomic_store(reinterpret_cast<uint64_t*>(&s.partials[b]), (uint64_t)0, __ATOMIC_RELAXED,
-                           __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(reinterpret_cast<uint64_t*>(&s.partials[b * ss]), (uint64_t)0,
+                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
     t = block_sum(t, red);
     if (threadIdx.x == 0) {
-        if (NG > 1) put_slot(&s.group_partials[g], t);
-        *flag = (NG == 1 || take_ticket_nowait(&s.tickets[kReduceGroups], (uint32_t)NG)) ? 1 : 0;
+        if (NG > 1) put_slot(&s.group_partials[g * ss], t);
+        *flag = (NG == 1 || take_ticket_nowait(&s.tickets[(size_t)kReduceGroups * s.ticket_stride],
+                                               (uint32_t)NG))
+                    ? 1
+                    : 0;
     }
     __syncthreads();
     if (!*flag) return false;
     double u = 0.0;
-    for (int i = threadIdx.x; i < NG; i += kBlock) u += (i == g) ? t : take_slot(&s.group_partials[i]);
+    for (int i = threadIdx.x; i < NG; i += kBlock)
+        u += (i == g) ? t : take_slot(&s.group_partials[i * ss]);
     if (NG > 1 && threadIdx.x == 0) {
-        __hip_atomic_store(reinterpret_cast<uint64_t*>(&s.group_partials[g]), (uint64_t)0,
+        __hip_atomic_store(reinterpret_cast<uint64_t*>(&s.group_partials[g * ss]), (uint64_t)0,
                            __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
     total = block_sum(u, red);

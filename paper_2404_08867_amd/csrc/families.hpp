@@ -162,9 +162,11 @@ struct Oscillatory {
 // product stays in range; the product is renormalised with frexp every kRenorm
 // directions and the powers of two are restored exactly at the end.
 //   q'_j = sigma_j q_j = y'^2 + g,  y' = 2^-m_j (x_j - w_j) = a k + b,  g = sigma_j c_j^-2.
+// m = floor(e / 2) for q = c^-2 + 1/6 = mant 2^e, mant in [1/2, 1), puts q / 4^m in
+// [1/2, 2); q needs only its exponent, so an approximate reciprocal serves.
 __device__ __forceinline__ int peak_pow4(double c) {
-    const double q = 1.0 / (c * c) + 1.0 / 6.0;
-    return (int)rint(0.5 * log2(q));
+    const double q = __builtin_amdgcn_rcp(c * c) + 1.0 / 6.0;
+    return __builtin_amdgcn_frexp_exp(q) >> 1;
 }
 
 // FP32_DIMS: per-direction factors in single precision (7 VALU ops per point and

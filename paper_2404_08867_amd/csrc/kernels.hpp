@@ -11,6 +11,8 @@ namespace qmc {
 // max(1, kMaxSumBlocks / nsets), never more than kMaxSumBlocksPerSet.
 constexpr int kMaxSumBlocks = 8192;
 constexpr int kMaxSumBlocksPerSet = 2048;
+// Parameter sets of one plain-sum call (the ticket layout holds this many).
+constexpr int kMaxSumSets = 4096;
 
 struct PlainLaunch {
     int d;

@@ -9,7 +9,8 @@
 //
 // Reduction: per-thread FP64 sums, a wave64 xor butterfly, waves in order, one
 // FP64 partial per workgroup, then the two-level fixed-order grid sum of
-// common.hpp (tickets in the workspace, reset to zero by their last user).
+// common.hpp (tickets and tagged slots in the workspace's zero region, left zero
+// by their last user).
 #include "common.hpp"
 #include "families.hpp"
 #include "kernels.hpp"
@@ -27,15 +28,20 @@ struct SumArgs {
     uint32_t tiles;
     double* q_out;
     uint32_t* tickets;   // counter region of the workspace
-    double* scratch;     // scratch region, `scratch_stride` doubles per set
+    double* scratch;     // tagged slots, `scratch_stride` doubles per set
     size_t scratch_stride;
+    int slot_stride;     // doubles between two slots of a set
 };
 
+// Set `set` owns slots [set * scratch_stride, ...) and the tickets
+// set, set + kMaxSumSets, ..., one per 16 KiB line of the counter region.
 __device__ __forceinline__ GridSlots set_slots(const SumArgs& a, int set, int G) {
     GridSlots s;
     s.partials = a.scratch + (size_t)set * a.scratch_stride;
-    s.group_partials = s.partials + G;
-    s.tickets = a.tickets + (size_t)set * kTicketsPerReduction;
+    s.group_partials = s.partials + (size_t)G * a.slot_stride;
+    s.tickets = a.tickets + set;
+    s.slot_stride = a.slot_stride;
+    s.ticket_stride = kMaxSumSets;
     return s;
 }
 
@@ -46,38 +52,22 @@ __global__ __launch_bounds__(kBlock) void lattice_sum_kernel(const SumArgs a) {
     __shared__ double s_red[3 * kWaves];
     __shared__ int s_last;
 
-    // Small problems: copy z, shift and the parameter row into LDS with one burst
-    // of loads, so that the prologue pays one memory round trip instead of one per
-    // dependent step.
-    __shared__ int64_t s_z[kDimChunk];
-    __shared__ double s_shift[kDimChunk];
-    __shared__ double s_p[2 * kDimChunk + 1];
-
     const int set = blockIdx.y;
-    ProblemView v = make_view(a.d, a.n, a.z, a.shift, a.params + (size_t)set * a.P);
-    const bool one_chunk = v.d <= kDimChunk;
-    if (one_chunk) {
-        const int t = threadIdx.x;
-        if (t < v.d) {
-            s_z[t] = v.z[t];
-            if (v.shift) s_shift[t] = v.shift[t];
-        }
-        if (t < a.P) s_p[t] = v.p[t];
-        __syncthreads();
-        v.z = s_z;
-        v.p = s_p;
-        if (v.shift) v.shift = s_shift;
-    }
+    const ProblemView v = make_view(a.d, a.n, a.z, a.shift, a.params + (size_t)set * a.P);
     double init0, ds1;
     int ie;
-    block_constants<F>(v, s_red, init0, ds1, ie);
-
-    // With one chunk of directions the per-direction tables serve every tile.
-    if (one_chunk) fill_dims<F>(v, s, 0, v.d);
-
     double tacc = 0.0;
-    for (uint32_t tile = blockIdx.x; tile < a.tiles; tile += gridDim.x)
-        tacc += tile_points<F, M>(v, s, tile * kTile, init0, one_chunk);
+    if (v.d <= kDimChunk) {
+        // One set of direction tables serves every tile; the first tile's start
+        // residues are built with them.
+        setup_one_chunk<F, M>(v, s, s_red, blockIdx.x * kTile, init0, ds1, ie);
+        for (uint32_t tile = blockIdx.x; tile < a.tiles; tile += gridDim.x)
+            tacc += tile_points_one_chunk<F, M>(v, s, tile * kTile, init0, tile == blockIdx.x);
+    } else {
+        block_constants<F>(v, s_red, init0, ds1, ie);
+        for (uint32_t tile = blockIdx.x; tile < a.tiles; tile += gridDim.x)
+            tacc += tile_points<F, M>(v, s, tile * kTile, init0);
+    }
 
     const double bsum = block_sum(tacc, s_red);
     const GridSlots slots = set_slots(a, set, (int)gridDim.x);
@@ -119,14 +109,22 @@ int sum_blocks_per_set(int nsets) {
     return g;
 }
 
-// Scratch doubles per set, rounded to 256 bytes.
+// Slot spacing: one 128-byte line per slot when every set's slots fit the slot
+// region that way, else packed.  Packed, nsets * set_stride <= 8192 + 64 * nsets
+// doubles (<= 2.2 MiB for nsets <= kMaxSumSets) fits in kSlotBytes.
+static int slot_stride(int nsets) {
+    const size_t lined = (size_t)nsets * grid_scratch_doubles(sum_blocks_per_set(nsets)) * 16;
+    return lined * sizeof(double) <= kSlotBytes ? 16 : 1;
+}
+
+// Slot doubles per set, rounded to 256 bytes.
 static size_t set_stride(int nsets) {
-    return (grid_scratch_doubles(sum_blocks_per_set(nsets)) + 31) / 32 * 32;
+    return (grid_scratch_doubles(sum_blocks_per_set(nsets)) * slot_stride(nsets) + 31) / 32 * 32;
 }
 
 size_t plain_workspace_bytes(int nsets) {
-    // The tagged slots live in the zero region; nsets * set_stride <= 8192 + 40 * nsets
-    // doubles (<= 1.4 MiB for nsets <= 4096) fits in kSlotBytes.
+    // Tickets and tagged slots both live in the zero region.
+    (void)nsets;
     return kZeroBytes;
 }
 
@@ -157,6 +155,7 @@ static hipError_t launch_fm(const PlainLaunch& L, hipStream_t stream) {
     a.tickets = (uint32_t*)L.ws;
     a.scratch = (double*)((char*)L.ws + kTicketBytes);  // tagged-slot part of the zero region
     a.scratch_stride = set_stride(L.nsets);
+    a.slot_stride = slot_stride(L.nsets);
     int g = sum_blocks_per_set(L.nsets);
     if (L.max_blocks > 0 && L.max_blocks < g) g = L.max_blocks;
     if ((uint32_t)g > a.tiles) g = (int)a.tiles;

@@ -116,47 +116,36 @@ __device__ __forceinline__ void fill_tile(const ProblemView& v, TileShared<F>& s
     }
 }
 
-// The thread's sum of f / scale over its M points of the tile (points >= n
-// contribute zero).  If `dims_ready`, s already holds fill_dims(v, s, 0, d) and
-// d <= kDimChunk.  Begins with a barrier; the caller may reuse s afterwards only
-// after another barrier.
+// Accumulates directions [j0, j0 + dc) into the thread's M point states, from
+// the direction tables (fill_dims) and the tile's start residues (fill_tile) in s.
 template <class F, int M>
-__device__ __forceinline__ double tile_points(const ProblemView& v, TileShared<F>& s,
-                                              uint32_t tile_base, double init0, bool dims_ready) {
-    using Acc = typename F::Acc;
+__device__ __forceinline__ void chunk_points(typename F::Acc (&acc)[M], const TileShared<F>& s, int j0,
+                                             int dc, uint32_t n) {
     using Dim = typename F::Dim;
     const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
-    const uint32_t n = v.n;
-    Acc acc[M];
+    for (int jj = 0; jj < dc; ++jj) {
+        uint32_t k = addmod(s.kw[jj * kWaves + wv], s.lz[jj * kWave + lane], n);
+        const uint2 stp = s.st[jj];
+        const Dim c = s.c[jj];
 #pragma unroll
-    for (int m = 0; m < M; ++m) acc[m] = F::init(init0);
-
-    for (int j0 = 0; j0 < v.d; j0 += kDimChunk) {
-        const int dc = min(kDimChunk, v.d - j0);
-        __syncthreads();  // every read of the previous tables is done
-        if (!dims_ready) {
-            fill_dims<F>(v, s, j0, dc);
-            __syncthreads();
+        for (int m = 0; m < M; ++m) {
+            F::step(acc[m], k, c);
+            k = stepmod(k, stp.x, stp.y);
         }
-        fill_tile<F, M>(v, s, j0, dc, tile_base);
-        __syncthreads();
-        for (int jj = 0; jj < dc; ++jj) {
-            uint32_t k = addmod(s.kw[jj * kWaves + wv], s.lz[jj * kWave + lane], n);
-            const uint2 stp = s.st[jj];
-            const Dim c = s.c[jj];
+        if constexpr (F::kRenorm > 0) {
+            if ((j0 + jj + 1) % F::kRenorm == 0) {
 #pragma unroll
-            for (int m = 0; m < M; ++m) {
-                F::step(acc[m], k, c);
-                k = stepmod(k, stp.x, stp.y);
-            }
-            if constexpr (F::kRenorm > 0) {
-                if ((j0 + jj + 1) % F::kRenorm == 0) {
-#pragma unroll
-                    for (int m = 0; m < M; ++m) F::renorm(acc[m]);
-                }
+                for (int m = 0; m < M; ++m) F::renorm(acc[m]);
             }
         }
     }
+}
+
+// The thread's sum of f / scale over its M points (points >= n contribute zero).
+template <class F, int M>
+__device__ __forceinline__ double finish_points(const typename F::Acc (&acc)[M], uint32_t tile_base,
+                                                uint32_t n) {
+    const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
     const uint32_t i0 = tile_base + (uint32_t)wv * (kWave * M) + (uint32_t)lane;
     double t = 0.0;
 #pragma unroll
@@ -165,6 +154,112 @@ __device__ __forceinline__ double tile_points(const ProblemView& v, TileShared<F
         t += (i0 + (uint32_t)(kWave * m) < n) ? f : 0.0;
     }
     return t;
+}
+
+// The thread's sum of f / scale over its M points of the tile, any d: the
+// tables are rebuilt chunk by chunk.  Begins with a barrier; the caller may
+// reuse s afterwards only after another barrier.
+template <class F, int M>
+__device__ __forceinline__ double tile_points(const ProblemView& v, TileShared<F>& s,
+                                              uint32_t tile_base, double init0) {
+    typename F::Acc acc[M];
+#pragma unroll
+    for (int m = 0; m < M; ++m) acc[m] = F::init(init0);
+    for (int j0 = 0; j0 < v.d; j0 += kDimChunk) {
+        const int dc = min(kDimChunk, v.d - j0);
+        __syncthreads();  // every read of the previous tables is done
+        fill_dims<F>(v, s, j0, dc);
+        __syncthreads();
+        fill_tile<F, M>(v, s, j0, dc, tile_base);
+        __syncthreads();
+        chunk_points<F, M>(acc, s, j0, dc, v.n);
+    }
+    return finish_points<F, M>(acc, tile_base, v.n);
+}
+
+// ---------------------------------------------------------------------------
+// Problems with d <= kDimChunk keep one set of direction tables for every tile.
+// setup_one_chunk builds all of them in one pass with one barrier: the index
+// table Lz by every thread, the direction constants and the workgroup sums by
+// wave 0 (lane j owns direction j), and the start residues of the workgroup's
+// first tile (at first_base) by the other waves.
+// ---------------------------------------------------------------------------
+template <class F, int M>
+__device__ __forceinline__ void setup_one_chunk(const ProblemView& v, TileShared<F>& s, double* red,
+                                                uint32_t first_base, double& init0, double& ds1,
+                                                int& ie) {
+    const int tid = threadIdx.x, d = v.d;
+    for (int e = tid; e < d * kWave; e += kBlock) {
+        const int j = e / kWave, l = e % kWave;
+        s.lz[e] = mulmod_small((uint32_t)l, (uint32_t)v.z[j], v.dn, v.inv_n);
+    }
+    if (tid < kWave) {
+        double t0 = 0.0, t1 = 0.0;
+        int te = 0;
+        if (tid < d) {
+            const int j = tid;
+            uint32_t whole;
+            double frac;
+            split_shift(v.shift, j, v.n, whole, frac);
+            if constexpr (F::kBlockTerms) F::block_terms(v.p, d, j, v.inv_n, frac, t0, t1, te);
+            const uint32_t st = mulmod_small((uint32_t)kWave, (uint32_t)v.z[j], v.dn, v.inv_n);
+            s.st[j] = make_uint2(st, st - v.n);
+            s.sh[j] = whole;
+            s.c[j] = F::dim(v.p, d, j, v.inv_n, frac);
+        }
+        if constexpr (F::kBlockTerms) {
+            double x = t0, y = t1, w = (double)te;
+#pragma unroll
+            for (int off = 32; off >= 1; off >>= 1) {
+                x += __shfl_xor(x, off, kWave);
+                y += __shfl_xor(y, off, kWave);
+                w += __shfl_xor(w, off, kWave);
+            }
+            if (tid == 0) {
+                red[0] = x;
+                red[1] = y;
+                red[2] = w;
+            }
+        }
+    } else {
+        for (int e = tid - kWave; e < d * kWaves; e += kBlock - kWave) {
+            const int j = e / kWaves, w = e % kWaves;
+            uint32_t whole;
+            double frac;
+            split_shift(v.shift, j, v.n, whole, frac);
+            const uint32_t b = (first_base + (uint32_t)w * (kWave * M)) % v.n;
+            s.kw[e] = addmod(mulmod((uint64_t)b, (uint64_t)v.z[j], v.n, v.inv_n), whole, v.n);
+        }
+    }
+    __syncthreads();
+    double ds0 = 0.0;
+    ds1 = 0.0;
+    ie = 0;
+    if constexpr (F::kBlockTerms) {
+        ds0 = red[0];
+        ds1 = red[1];
+        ie = (int)red[2];
+    }
+    init0 = ds0 + F::extra(v.p);
+}
+
+// One tile of a problem set up by setup_one_chunk.  With `kw_ready` the start
+// residues of this tile are already in s; otherwise they are rebuilt between two
+// barriers.  The caller may overwrite s afterwards only after a barrier.
+template <class F, int M>
+__device__ __forceinline__ double tile_points_one_chunk(const ProblemView& v, TileShared<F>& s,
+                                                        uint32_t tile_base, double init0,
+                                                        bool kw_ready) {
+    if (!kw_ready) {
+        __syncthreads();  // every read of the previous tile's residues is done
+        fill_tile<F, M>(v, s, 0, v.d, tile_base);
+        __syncthreads();
+    }
+    typename F::Acc acc[M];
+#pragma unroll
+    for (int m = 0; m < M; ++m) acc[m] = F::init(init0);
+    chunk_points<F, M>(acc, s, 0, v.d, v.n);
+    return finish_points<F, M>(acc, tile_base, v.n);
 }
 
 }  // namespace qmc
