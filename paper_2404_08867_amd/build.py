@@ -27,13 +27,22 @@ DEVICE_FLAGS = [
 ]
 
 
+# Per-source additions.  The plain-sum kernels take scalar arguments, the
+# prologue's eight first: preloaded into scalar registers at wave start (gfx950
+# supports kernel-argument preloading; the code object keeps a fallback
+# prologue that loads them for firmware without it).
+SOURCE_FLAGS = {
+    "lattice_sum.hip": ["-mllvm", "-amdgpu-kernarg-preload-count=8"],
+}
+
+
 def sources():
     return sorted(f for f in os.listdir(CSRC) if f.endswith(".hip"))
 
 
 def _compile(src: str, verbose: bool) -> str:
     obj = os.path.join(BUILD, src.replace(".hip", ".o"))
-    cmd = [HIPCC, "-c", *DEVICE_FLAGS, os.path.join(CSRC, src), "-o", obj]
+    cmd = [HIPCC, "-c", *DEVICE_FLAGS, *SOURCE_FLAGS.get(src, []), os.path.join(CSRC, src), "-o", obj]
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)

@@ -23,6 +23,7 @@ namespace qmc {
 struct AdjArgs {
     int d;
     uint32_t n;
+    double inv_n;  // 1.0 / n
     const int64_t* z;
     const double* shift;
     const double* params;
@@ -118,8 +119,10 @@ struct AdjPeak {
     __device__ static int ib(int j, int d) { return d + j; }
 };
 
-// Vector form of grid_sum: every workgroup holds L values in LDS `v`; returns true
-// in exactly one workgroup, whose `v` then holds the totals over all workgroups.
+// Vector grid sum (two levels, grouped as in grid_sum_wave0): every workgroup
+// holds L values in LDS `v`; returns true in exactly one workgroup, whose `v` then
+// holds the totals over all workgroups.  Partials are stored and waited for
+// before each ticket.
 __device__ __forceinline__ bool grid_sum_vec(double* v, int L, int b, int G, double* partials,
                                              double* group_partials, uint32_t* tickets, int* flag) {
     const int NG = G < kReduceGroups ? G : kReduceGroups;
@@ -166,7 +169,7 @@ __global__ __launch_bounds__(kBlock) void adjoint_kernel(const AdjArgs a) {
     const int tid = threadIdx.x, lane = tid & (kWave - 1), wv = tid / kWave;
     const int P = a.P, L = P + 1;  // slot P holds the sum of f / scale
     const double* p = a.params + (size_t)set * P;
-    const ProblemView v = make_view(a.d, a.n, a.z, a.shift, p);
+    const ProblemView v = make_view(a.d, a.n, a.inv_n, a.z, a.shift, p);
     double init0, ds1;
     int ie;
     block_constants<F>(v, s_red, init0, ds1, ie);
@@ -265,9 +268,9 @@ __global__ __launch_bounds__(kBlock) void adjoint_kernel(const AdjArgs a) {
                     A::dir(x, c, wt[m], ga, gb);
                     k = stepmod(k, stp.x, stp.y);
                 }
-                ga = wave_sum(ga);
-                if constexpr (A::kTwo) gb = wave_sum(gb);
-                if (lane == 0) {
+                ga = wave_total(ga);
+                if constexpr (A::kTwo) gb = wave_total(gb);
+                if (lane == kWaveTotalLane) {
                     s_g[wv * L + A::ia(j0 + jj, v.d)] += ga;
                     if constexpr (A::kTwo) s_g[wv * L + A::ib(j0 + jj, v.d)] += gb;
                 }
@@ -320,6 +323,7 @@ static hipError_t launch_adj_m(const AdjLaunch& L, hipStream_t stream) {
     AdjArgs a;
     a.d = L.d;
     a.n = L.n;
+    a.inv_n = 1.0 / (double)L.n;
     a.z = L.z;
     a.shift = L.shift;
     a.params = L.params;

@@ -48,7 +48,7 @@ __device__ __forceinline__ void run_tile(const BatchArgs& a, int pi, const DevPr
                                          uint32_t local_tile, TileShared<F>& s, double* red,
                                          int* flag) {
     constexpr uint32_t kTile = kBlock * M;
-    const ProblemView v = make_view(pr.d, pr.n, pr.z, pr.shift, pr.params);
+    const ProblemView v = make_view(pr.d, pr.n, pr.inv_n, pr.z, pr.shift, pr.params);
     double init0, ds1;
     int ie;
     double t;

@@ -12,6 +12,7 @@ struct DevProblem {
     const int64_t* z;
     const double* params;
     const double* shift;   // may be null
+    double inv_n;          // 1.0 / n
     uint32_t n;
     int32_t d;
     int32_t family;

@@ -60,22 +60,43 @@ __device__ __forceinline__ uint32_t stepmod(uint32_t k, uint32_t st, uint32_t st
 }
 
 // ---------------------------------------------------------------------------
-// Deterministic reductions (fixed order: xor butterfly within the wave, waves in
-// index order across the workgroup).
+// Deterministic reductions (fixed order within the wave, waves in index order
+// across the workgroup).
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, kWave);
+
+// A double moved across lanes by one DPP pattern (both 32-bit halves); lanes of
+// rows outside ROW_MASK receive 0.
+template <int CTRL, int ROW_MASK = 0xf>
+__device__ __forceinline__ double dpp_move(double v) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, ROW_MASK, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, ROW_MASK, 0xf, false);
+    return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
+// Sum over the wave's 64 lanes with DPP lane moves (no LDS traffic): pairs and
+// quads by quad permutations, rows of 8 and 16 by the half-row and row mirrors,
+// then rows 0+1 and 2+3 by a broadcast of lane 15, and all four rows by a
+// broadcast of lane 31.  The total lands in lane kWave - 1; other lanes hold
+// partial sums.  The order of the additions is fixed.
+constexpr int kWaveTotalLane = kWave - 1;
+__device__ __forceinline__ double wave_total(double v) {
+    v += dpp_move<0xB1>(v);        // quad_perm [1,0,3,2]
+    v += dpp_move<0x4E>(v);        // quad_perm [2,3,0,1]
+    v += dpp_move<0x141>(v);       // row_half_mirror
+    v += dpp_move<0x140>(v);       // row_mirror
+    v += dpp_move<0x142, 0xa>(v);  // row_bcast:15 into rows 1 and 3
+    v += dpp_move<0x143, 0xc>(v);  // row_bcast:31 into rows 2 and 3
     return v;
 }
 
 // Sum over the workgroup; every thread receives the total.  `red` is an LDS
 // scratch array of at least kWaves doubles.  Ends with a barrier.
 __device__ __forceinline__ double block_sum(double v, double* red) {
-    v = wave_sum(v);
+    v = wave_total(v);
     const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
     __syncthreads();
-    if (lane == 0) red[wv] = v;
+    if (lane == kWaveTotalLane) red[wv] = v;
     __syncthreads();
     double t = 0.0;
 #pragma unroll
@@ -87,16 +108,10 @@ __device__ __forceinline__ double block_sum(double v, double* red) {
 // Three sums at once (two doubles and a small int carried as a double); every
 // thread receives the totals.  `red` holds 3 * kWaves doubles.
 __device__ __forceinline__ void block_sum3(double& a, double& b, int& c, double* red) {
-    double x = a, y = b, w = (double)c;
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) {
-        x += __shfl_xor(x, off, kWave);
-        y += __shfl_xor(y, off, kWave);
-        w += __shfl_xor(w, off, kWave);
-    }
+    const double x = wave_total(a), y = wave_total(b), w = wave_total((double)c);
     const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
     __syncthreads();
-    if (lane == 0) {
+    if (lane == kWaveTotalLane) {
         red[wv] = x;
         red[kWaves + wv] = y;
         red[2 * kWaves + wv] = w;
@@ -218,53 +233,77 @@ __device__ __forceinline__ bool take_ticket_nowait(uint32_t* ticket, uint32_t ex
     return false;
 }
 
-// Called by every thread of workgroup b with its workgroup total v.  Returns true
-// in exactly one workgroup, whose threads then all hold the grand total.  The
-// group partial of group g sums its members b = g, g + NG, ... in that order and
-// the total sums the groups in order, whoever arrives last.
-// `red` is LDS scratch for block_sum; `flag` one LDS int.
-__device__ __forceinline__ bool grid_sum(double v, int b, int G, const GridSlots& s, double* red,
-                                         int* flag, double& total) {
+// A double of one lane, delivered to every lane of the wave.
+__device__ __forceinline__ double lane_value(double v, int lane) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)b, lane);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
+    return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
+// Workgroup sum delivered to wave 0: each wave's total goes to red[kWaves + w]
+// and, one barrier later, wave 0 adds them in wave order.  Lanes of wave 0
+// return the total, the other waves 0 (they need not take part in what follows).
+// red[kWaves .. 2 kWaves) must be free: no thread may still read them.
+__device__ __forceinline__ double block_sum_wave0(double v, double* red) {
+    v = wave_total(v);
+    const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
+    if (lane == kWaveTotalLane) red[kWaves + wv] = v;
+    __syncthreads();
+    double t = 0.0;
+    if (wv == 0) {
+#pragma unroll
+        for (int w = 0; w < kWaves; ++w) t += red[kWaves + w];
+    }
+    return t;
+}
+
+// Grid sum run by wave 0 alone, with no workgroup barrier.  Called by the 64
+// lanes of wave 0 of workgroup b of G, all holding the workgroup total v.
+// Returns true in exactly one workgroup, whose wave-0 lanes then hold the grand
+// total.  Member i of a group is lane i and group i is lane i of the top level,
+// so the order of every addition is fixed whoever arrives last.
+// Needs ceil(G / kReduceGroups) <= kWave and kReduceGroups <= kWave.
+__device__ __forceinline__ bool grid_sum_wave0(double v, int b, int G, const GridSlots& s,
+                                               double& total) {
+    const int lane = threadIdx.x;
     const int NG = G < kReduceGroups ? G : kReduceGroups;
     const int g = b % NG;
     const int members = (G - g + NG - 1) / NG;
     const int me = b / NG;  // this workgroup's position in its group
     const size_t ss = (size_t)s.slot_stride;
-    if (threadIdx.x == 0) {
+    int last = 0;
+    if (lane == 0) {
         if (members > 1) put_slot(&s.partials[b * ss], v);
-        *flag = (members == 1 ||
-                 take_ticket_nowait(&s.tickets[(size_t)g * s.ticket_stride], (uint32_t)members))
-                    ? 1
-                    : 0;
+        last = (members == 1 ||
+                take_ticket_nowait(&s.tickets[(size_t)g * s.ticket_stride], (uint32_t)members))
+                   ? 1
+                   : 0;
     }
-    __syncthreads();
-    if (!*flag) return false;
+    if (!__builtin_amdgcn_readlane(last, 0)) return false;
     double t = 0.0;
-    for (int i = threadIdx.x; i < members; i += kBlock)
-        t += (i == me) ? v : take_slot(&s.partials[(g + (size_t)i * NG) * ss]);
-    if (members > 1 && threadIdx.x == 0) {
-        // Own slot: cleared by the thread that wrote it, so the clear follows the store.
+    if (lane < members) t = (lane == me) ? v : take_slot(&s.partials[(g + (size_t)lane * NG) * ss]);
+    if (members > 1 && lane == 0) {
+        // Own slot: cleared by the lane that wrote it, so the clear follows the store.
         __hip_atomic_store(reinterpret_cast<uint64_t*>(&s.partials[b * ss]), (uint64_t)0,
                            __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
-    t = block_sum(t, red);
-    if (threadIdx.x == 0) {
+    t = lane_value(wave_total(t), kWaveTotalLane);
+    if (lane == 0) {
         if (NG > 1) put_slot(&s.group_partials[g * ss], t);
-        *flag = (NG == 1 || take_ticket_nowait(&s.tickets[(size_t)kReduceGroups * s.ticket_stride],
-                                               (uint32_t)NG))
-                    ? 1
-                    : 0;
+        last = (NG == 1 || take_ticket_nowait(&s.tickets[(size_t)kReduceGroups * s.ticket_stride],
+                                              (uint32_t)NG))
+                   ? 1
+                   : 0;
     }
-    __syncthreads();
-    if (!*flag) return false;
+    if (!__builtin_amdgcn_readlane(last, 0)) return false;
     double u = 0.0;
-    for (int i = threadIdx.x; i < NG; i += kBlock)
-        u += (i == g) ? t : take_slot(&s.group_partials[i * ss]);
-    if (NG > 1 && threadIdx.x == 0) {
+    if (lane < NG) u = (lane == g) ? t : take_slot(&s.group_partials[lane * ss]);
+    if (NG > 1 && lane == 0) {
         __hip_atomic_store(reinterpret_cast<uint64_t*>(&s.group_partials[g * ss]), (uint64_t)0,
                            __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
-    total = block_sum(u, red);
+    total = lane_value(wave_total(u), kWaveTotalLane);
     return true;
 }
 

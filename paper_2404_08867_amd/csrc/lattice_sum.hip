@@ -7,10 +7,10 @@
 // direction's constants are loaded once per M points and the per-point state is M
 // registers whatever d is; no 64-bit arithmetic runs per point.
 //
-// Reduction: per-thread FP64 sums, a wave64 xor butterfly, waves in order, one
+// Reduction: per-thread FP64 sums, a DPP wave reduction, waves in order, one
 // FP64 partial per workgroup, then the two-level fixed-order grid sum of
-// common.hpp (tickets and tagged slots in the workspace's zero region, left zero
-// by their last user).
+// common.hpp, run by wave 0 (tickets and tagged slots in the workspace's zero
+// region, left zero by their last user).
 #include "common.hpp"
 #include "families.hpp"
 #include "kernels.hpp"
@@ -18,42 +18,49 @@
 
 namespace qmc {
 
+// Kernel arguments: the ones the prologue needs come first, so that a build with
+// kernel-argument preloading has them in scalar registers at wave start instead
+// of behind a load from the argument segment.
 struct SumArgs {
-    int d;
-    uint32_t n;
     const int64_t* z;
-    const double* shift;
     const double* params;
+    const double* shift;  // may be null
+    double inv_n;         // 1.0 / n
+    uint32_t n;
+    int d;
     int P;
     uint32_t tiles;
     double* q_out;
-    uint32_t* tickets;   // counter region of the workspace
-    double* scratch;     // tagged slots, `scratch_stride` doubles per set
-    size_t scratch_stride;
-    int slot_stride;     // doubles between two slots of a set
+    uint32_t* tickets;    // counter region of the workspace
+    double* scratch;      // tagged slots, `scratch_stride` doubles per set
+    uint32_t scratch_stride;
+    int slot_stride;      // doubles between two slots of a set
 };
 
 // Set `set` owns slots [set * scratch_stride, ...) and the tickets
 // set, set + kMaxSumSets, ..., one per 16 KiB line of the counter region.
-__device__ __forceinline__ GridSlots set_slots(const SumArgs& a, int set, int G) {
+__device__ __forceinline__ GridSlots set_slots(double* scratch, uint32_t scratch_stride,
+                                               int slot_stride, uint32_t* tickets, int set, int G) {
     GridSlots s;
-    s.partials = a.scratch + (size_t)set * a.scratch_stride;
-    s.group_partials = s.partials + (size_t)G * a.slot_stride;
-    s.tickets = a.tickets + set;
-    s.slot_stride = a.slot_stride;
+    s.partials = scratch + (size_t)set * scratch_stride;
+    s.group_partials = s.partials + (size_t)G * slot_stride;
+    s.tickets = tickets + set;
+    s.slot_stride = slot_stride;
     s.ticket_stride = kMaxSumSets;
     return s;
 }
 
 template <class F, int M>
-__global__ __launch_bounds__(kBlock) void lattice_sum_kernel(const SumArgs a) {
+__global__ __launch_bounds__(kBlock) void lattice_sum_kernel(
+    const int64_t* z, const double* params, const double* shift, double inv_n, uint32_t n, int d,
+    int P, uint32_t tiles, double* q_out, uint32_t* tickets, double* scratch,
+    uint32_t scratch_stride, int slot_stride) {
     constexpr uint32_t kTile = kBlock * M;
     __shared__ TileShared<F> s;
     __shared__ double s_red[3 * kWaves];
-    __shared__ int s_last;
 
     const int set = blockIdx.y;
-    const ProblemView v = make_view(a.d, a.n, a.z, a.shift, a.params + (size_t)set * a.P);
+    const ProblemView v = make_view(d, n, inv_n, z, shift, params + (size_t)set * P);
     double init0, ds1;
     int ie;
     double tacc = 0.0;
@@ -61,21 +68,28 @@ __global__ __launch_bounds__(kBlock) void lattice_sum_kernel(const SumArgs a) {
         // One set of direction tables serves every tile; the first tile's start
         // residues are built with them.
         setup_one_chunk<F, M>(v, s, s_red, blockIdx.x * kTile, init0, ds1, ie);
-        for (uint32_t tile = blockIdx.x; tile < a.tiles; tile += gridDim.x)
+        for (uint32_t tile = blockIdx.x; tile < tiles; tile += gridDim.x)
             tacc += tile_points_one_chunk<F, M>(v, s, tile * kTile, init0, tile == blockIdx.x);
     } else {
         block_constants<F>(v, s_red, init0, ds1, ie);
-        for (uint32_t tile = blockIdx.x; tile < a.tiles; tile += gridDim.x)
+        for (uint32_t tile = blockIdx.x; tile < tiles; tile += gridDim.x)
             tacc += tile_points<F, M>(v, s, tile * kTile, init0);
     }
 
-    const double bsum = block_sum(tacc, s_red);
-    const GridSlots slots = set_slots(a, set, (int)gridDim.x);
+    // Workgroup total to wave 0 (red[kWaves..) is untouched by the setup), then the
+    // grid sum by wave 0 alone; the other waves are done.
+    const double bsum = block_sum_wave0(tacc, s_red);
+    if (threadIdx.x >= kWave) return;
+    const GridSlots slots =
+        set_slots(scratch, scratch_stride, slot_stride, tickets, set, (int)gridDim.x);
     double total;
-    if (grid_sum(bsum, (int)blockIdx.x, (int)gridDim.x, slots, s_red, &s_last, total) &&
-        threadIdx.x == 0)
-        a.q_out[set] = (total / v.dn) * F::scale(ds1, ie);
+    if (grid_sum_wave0(bsum, (int)blockIdx.x, (int)gridDim.x, slots, total) && threadIdx.x == 0)
+        q_out[set] = (total / v.dn) * F::scale(ds1, ie);
 }
+
+static_assert((kMaxSumBlocksPerSet + kReduceGroups - 1) / kReduceGroups <= kWave &&
+                  kReduceGroups <= kWave,
+              "grid_sum_wave0 puts one group member, and one group, per lane");
 
 // --------------------------------------------------------------------------
 // Debug export of the indices, through the same start/step decomposition.
@@ -143,24 +157,27 @@ int device_cu_count() {
 template <class F, int M>
 static hipError_t launch_fm(const PlainLaunch& L, hipStream_t stream) {
     SumArgs a;
-    a.d = L.d;
-    a.n = L.n;
     a.z = L.z;
-    a.shift = L.shift;
     a.params = L.params;
+    a.shift = L.shift;
+    a.inv_n = 1.0 / (double)L.n;
+    a.n = L.n;
+    a.d = L.d;
     a.P = L.P;
     const uint64_t tile = (uint64_t)kBlock * M;
     a.tiles = (uint32_t)(((uint64_t)L.n + tile - 1) / tile);
     a.q_out = L.q_out;
     a.tickets = (uint32_t*)L.ws;
     a.scratch = (double*)((char*)L.ws + kTicketBytes);  // tagged-slot part of the zero region
-    a.scratch_stride = set_stride(L.nsets);
+    a.scratch_stride = (uint32_t)set_stride(L.nsets);
     a.slot_stride = slot_stride(L.nsets);
     int g = sum_blocks_per_set(L.nsets);
     if (L.max_blocks > 0 && L.max_blocks < g) g = L.max_blocks;
     if ((uint32_t)g > a.tiles) g = (int)a.tiles;
     dim3 grid((unsigned)g, (unsigned)L.nsets);
-    hipLaunchKernelGGL((lattice_sum_kernel<F, M>), grid, dim3(kBlock), 0, stream, a);
+    hipLaunchKernelGGL((lattice_sum_kernel<F, M>), grid, dim3(kBlock), 0, stream, a.z, a.params,
+                       a.shift, a.inv_n, a.n, a.d, a.P, a.tiles, a.q_out, a.tickets, a.scratch,
+                       a.scratch_stride, a.slot_stride);
     return hipGetLastError();
 }
 

@@ -98,6 +98,7 @@ qmc_status build_tables(qmc_batch_plan* p) {
         e.d = q.d;
         e.family = q.family;
         e.out_index = ord[i];
+        e.inv_n = 1.0 / (double)q.n;
         e.tile_begin = (uint32_t)t;
         e.tiles = (uint32_t)tiles_of(q.n, M);
         t += e.tiles;

@@ -27,13 +27,15 @@ struct ProblemView {
     const double* p;      // parameter row
 };
 
-__device__ __forceinline__ ProblemView make_view(int d, uint32_t n, const int64_t* z,
+// inv_n is 1.0 / n rounded to double (the host passes it, so that no workgroup
+// spends a divide on it).
+__device__ __forceinline__ ProblemView make_view(int d, uint32_t n, double inv_n, const int64_t* z,
                                                  const double* shift, const double* p) {
     ProblemView v;
     v.d = d;
     v.n = n;
     v.dn = (double)n;
-    v.inv_n = 1.0 / v.dn;
+    v.inv_n = inv_n;
     v.z = z;
     v.shift = shift;
     v.p = p;
@@ -84,15 +86,37 @@ __device__ __forceinline__ void block_constants(const ProblemView& v, double* re
     init0 = ds0 + F::extra(v.p);
 }
 
+// Lz_j[l] = (l z_j) mod n for directions [j0, j0 + dc), dc <= kDimChunk: thread
+// (wave w, lane l) fills rows j = w, w + kWaves, ...  All of its loads of z are
+// issued before the first is used, so the table costs one memory round trip.
+// l * z_j < 2^37, so the exact double-precision mulmod applies.
+template <class F>
+__device__ __forceinline__ void fill_lz(const ProblemView& v, TileShared<F>& s, int j0, int dc) {
+    constexpr int kRows = kDimChunk / kWaves;
+    const int l = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
+    // z_j < 2^31: its low 32-bit word (little-endian) is the value.
+    const uint32_t* z32 = reinterpret_cast<const uint32_t*>(v.z + j0);
+    uint32_t zr[kRows];
+#pragma unroll
+    for (int r = 0; r < kRows; ++r) {
+        // Rows past dc load the last direction again: an unconditional, in-bounds
+        // load lets every load issue before the first wait.
+        const int j = min(wv + r * kWaves, dc - 1);
+        zr[r] = z32[2 * j];
+    }
+#pragma unroll
+    for (int r = 0; r < kRows; ++r) {
+        const int j = wv + r * kWaves;
+        if (j < dc) s.lz[j * kWave + l] = mulmod_small((uint32_t)l, zr[r], v.dn, v.inv_n);
+    }
+}
+
 // Tables that do not depend on the tile for directions [j0, j0 + dc).
-// l * z_j < 2^37 and 64 * z_j < 2^37, so the exact double-precision mulmod applies.
+// 64 * z_j < 2^37, so the exact double-precision mulmod applies.
 template <class F>
 __device__ __forceinline__ void fill_dims(const ProblemView& v, TileShared<F>& s, int j0, int dc) {
     const int tid = threadIdx.x;
-    for (int e = tid; e < dc * kWave; e += kBlock) {
-        const int j = e / kWave, l = e % kWave;
-        s.lz[e] = mulmod_small((uint32_t)l, (uint32_t)v.z[j0 + j], v.dn, v.inv_n);
-    }
+    fill_lz<F>(v, s, j0, dc);
     for (int e = tid; e < dc; e += kBlock) {
         const int j = j0 + e;
         uint32_t whole;
@@ -189,10 +213,7 @@ __device__ __forceinline__ void setup_one_chunk(const ProblemView& v, TileShared
                                                 uint32_t first_base, double& init0, double& ds1,
                                                 int& ie) {
     const int tid = threadIdx.x, d = v.d;
-    for (int e = tid; e < d * kWave; e += kBlock) {
-        const int j = e / kWave, l = e % kWave;
-        s.lz[e] = mulmod_small((uint32_t)l, (uint32_t)v.z[j], v.dn, v.inv_n);
-    }
+    fill_lz<F>(v, s, 0, d);
     if (tid < kWave) {
         double t0 = 0.0, t1 = 0.0;
         int te = 0;
@@ -208,14 +229,8 @@ __device__ __forceinline__ void setup_one_chunk(const ProblemView& v, TileShared
             s.c[j] = F::dim(v.p, d, j, v.inv_n, frac);
         }
         if constexpr (F::kBlockTerms) {
-            double x = t0, y = t1, w = (double)te;
-#pragma unroll
-            for (int off = 32; off >= 1; off >>= 1) {
-                x += __shfl_xor(x, off, kWave);
-                y += __shfl_xor(y, off, kWave);
-                w += __shfl_xor(w, off, kWave);
-            }
-            if (tid == 0) {
+            const double x = wave_total(t0), y = wave_total(t1), w = wave_total((double)te);
+            if (tid == kWaveTotalLane) {
                 red[0] = x;
                 red[1] = y;
                 red[2] = w;
