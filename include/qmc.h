@@ -131,8 +131,8 @@ qmc_status qmc_lattice_sum(int32_t d, int64_t n, const int64_t* z, const double*
 
 /* Launch configuration of the plain-sum kernel.  Zero fields mean "choose
  * automatically".  points_per_thread must be 0, 4, 8 or 16 (the tile is
- * 256 * points_per_thread consecutive points); max_blocks caps the persistent
- * grid per parameter set (1 .. 2048, and never above the workspace bound). */
+ * 1024 * points_per_thread consecutive points); max_blocks caps the persistent
+ * grid of 1024-thread workgroups per parameter set (1 .. 512). */
 typedef struct {
     int32_t points_per_thread;
     int32_t max_blocks;

@@ -91,7 +91,8 @@ __device__ __forceinline__ double wave_total(double v) {
 }
 
 // Sum over the workgroup; every thread receives the total.  `red` is an LDS
-// scratch array of at least kWaves doubles.  Ends with a barrier.
+// scratch array of at least B / kWave doubles.  Ends with a barrier.
+template <int B = kBlock>
 __device__ __forceinline__ double block_sum(double v, double* red) {
     v = wave_total(v);
     const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
@@ -100,29 +101,30 @@ __device__ __forceinline__ double block_sum(double v, double* red) {
     __syncthreads();
     double t = 0.0;
 #pragma unroll
-    for (int w = 0; w < kWaves; ++w) t += red[w];
+    for (int w = 0; w < (B / kWave); ++w) t += red[w];
     __syncthreads();
     return t;
 }
 
 // Three sums at once (two doubles and a small int carried as a double); every
-// thread receives the totals.  `red` holds 3 * kWaves doubles.
+// thread receives the totals.  `red` holds 3 * B / kWave doubles.
+template <int B = kBlock>
 __device__ __forceinline__ void block_sum3(double& a, double& b, int& c, double* red) {
     const double x = wave_total(a), y = wave_total(b), w = wave_total((double)c);
     const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
     __syncthreads();
     if (lane == kWaveTotalLane) {
         red[wv] = x;
-        red[kWaves + wv] = y;
-        red[2 * kWaves + wv] = w;
+        red[(B / kWave) + wv] = y;
+        red[2 * (B / kWave) + wv] = w;
     }
     __syncthreads();
     double tx = 0.0, ty = 0.0, tw = 0.0;
 #pragma unroll
-    for (int i = 0; i < kWaves; ++i) {
+    for (int i = 0; i < (B / kWave); ++i) {
         tx += red[i];
-        ty += red[kWaves + i];
-        tw += red[2 * kWaves + i];
+        ty += red[(B / kWave) + i];
+        tw += red[2 * (B / kWave) + i];
     }
     __syncthreads();
     a = tx;
@@ -241,19 +243,21 @@ __device__ __forceinline__ double lane_value(double v, int lane) {
     return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
 }
 
-// Workgroup sum delivered to wave 0: each wave's total goes to red[kWaves + w]
-// and, one barrier later, wave 0 adds them in wave order.  Lanes of wave 0
-// return the total, the other waves 0 (they need not take part in what follows).
-// red[kWaves .. 2 kWaves) must be free: no thread may still read them.
+// Workgroup sum delivered to wave 0: the total of wave w (of W = B / kWave) goes
+// to red[W + w] and, one barrier later, wave 0 adds them in wave order.  Lanes of
+// wave 0 return the total, the other waves 0 (they need not take part in what
+// follows).  red[W .. 2 W) must be free: no thread may still read them.
+template <int B = kBlock>
 __device__ __forceinline__ double block_sum_wave0(double v, double* red) {
+    constexpr int W = B / kWave;
     v = wave_total(v);
     const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
-    if (lane == kWaveTotalLane) red[kWaves + wv] = v;
+    if (lane == kWaveTotalLane) red[W + wv] = v;
     __syncthreads();
     double t = 0.0;
     if (wv == 0) {
 #pragma unroll
-        for (int w = 0; w < kWaves; ++w) t += red[kWaves + w];
+        for (int w = 0; w < W; ++w) t += red[W + w];
     }
     return t;
 }

@@ -7,10 +7,14 @@
 
 namespace qmc {
 
+// Threads per workgroup of the plain-sum kernel: 16 waves, so that one
+// workgroup per CU already hides latency and the grid has few workgroups to
+// dispatch and to reduce.
+constexpr int kSumBlock = 1024;
 // Workgroups per set that the plain-sum launcher may use: at most
 // max(1, kMaxSumBlocks / nsets), never more than kMaxSumBlocksPerSet.
-constexpr int kMaxSumBlocks = 8192;
-constexpr int kMaxSumBlocksPerSet = 2048;
+constexpr int kMaxSumBlocks = 2048;
+constexpr int kMaxSumBlocksPerSet = 512;
 // Parameter sets of one plain-sum call (the ticket layout holds this many).
 constexpr int kMaxSumSets = 4096;
 

@@ -1,7 +1,7 @@
 // Plain rank-1 lattice rule, fused into one persistent launch (eq. 1.2, eq. 2.1):
 //   Q = (1/n) sum_{i=0}^{n-1} f(x_i),  x_ij = {(k_ij + shift_j n) / n},  k_ij = (i z_j) mod n.
 //
-// Work decomposition: tiles of kBlock * M consecutive indices (tile.hpp), the
+// Work decomposition: tiles of kSumBlock * M consecutive indices (tile.hpp), the
 // workgroups of a set looping over tiles (persistent grid).  The loop runs over
 // directions outside and over a thread's M points inside, so that each
 // direction's constants are loaded once per M points and the per-point state is M
@@ -50,14 +50,14 @@ __device__ __forceinline__ GridSlots set_slots(double* scratch, uint32_t scratch
     return s;
 }
 
-template <class F, int M>
-__global__ __launch_bounds__(kBlock) void lattice_sum_kernel(
+template <class F, int M, int B>
+__global__ __launch_bounds__(B) void lattice_sum_kernel(
     const int64_t* z, const double* params, const double* shift, double inv_n, uint32_t n, int d,
     int P, uint32_t tiles, double* q_out, uint32_t* tickets, double* scratch,
     uint32_t scratch_stride, int slot_stride) {
-    constexpr uint32_t kTile = kBlock * M;
-    __shared__ TileShared<F> s;
-    __shared__ double s_red[3 * kWaves];
+    constexpr uint32_t kTile = B * M;
+    __shared__ TileShared<F, B> s;
+    __shared__ double s_red[3 * (B / kWave)];
 
     const int set = blockIdx.y;
     const ProblemView v = make_view(d, n, inv_n, z, shift, params + (size_t)set * P);
@@ -67,18 +67,18 @@ __global__ __launch_bounds__(kBlock) void lattice_sum_kernel(
     if (v.d <= kDimChunk) {
         // One set of direction tables serves every tile; the first tile's start
         // residues are built with them.
-        setup_one_chunk<F, M>(v, s, s_red, blockIdx.x * kTile, init0, ds1, ie);
+        setup_one_chunk<F, M, B>(v, s, s_red, blockIdx.x * kTile, init0, ds1, ie);
         for (uint32_t tile = blockIdx.x; tile < tiles; tile += gridDim.x)
-            tacc += tile_points_one_chunk<F, M>(v, s, tile * kTile, init0, tile == blockIdx.x);
+            tacc += tile_points_one_chunk<F, M, B>(v, s, tile * kTile, init0, tile == blockIdx.x);
     } else {
-        block_constants<F>(v, s_red, init0, ds1, ie);
+        block_constants<F, B>(v, s_red, init0, ds1, ie);
         for (uint32_t tile = blockIdx.x; tile < tiles; tile += gridDim.x)
-            tacc += tile_points<F, M>(v, s, tile * kTile, init0);
+            tacc += tile_points<F, M, B>(v, s, tile * kTile, init0);
     }
 
-    // Workgroup total to wave 0 (red[kWaves..) is untouched by the setup), then the
-    // grid sum by wave 0 alone; the other waves are done.
-    const double bsum = block_sum_wave0(tacc, s_red);
+    // Workgroup total to wave 0 (red[B / kWave ..) is untouched by the setup), then
+    // the grid sum by wave 0 alone; the other waves are done.
+    const double bsum = block_sum_wave0<B>(tacc, s_red);
     if (threadIdx.x >= kWave) return;
     const GridSlots slots =
         set_slots(scratch, scratch_stride, slot_stride, tickets, set, (int)gridDim.x);
@@ -124,8 +124,8 @@ int sum_blocks_per_set(int nsets) {
 }
 
 // Slot spacing: one 128-byte line per slot when every set's slots fit the slot
-// region that way, else packed.  Packed, nsets * set_stride <= 8192 + 64 * nsets
-// doubles (<= 2.2 MiB for nsets <= kMaxSumSets) fits in kSlotBytes.
+// region that way, else packed.  Packed, nsets * set_stride <= 2048 + 64 * nsets
+// doubles (<= 2.1 MiB for nsets <= kMaxSumSets) fits in kSlotBytes.
 static int slot_stride(int nsets) {
     const size_t lined = (size_t)nsets * grid_scratch_doubles(sum_blocks_per_set(nsets)) * 16;
     return lined * sizeof(double) <= kSlotBytes ? 16 : 1;
@@ -164,7 +164,7 @@ static hipError_t launch_fm(const PlainLaunch& L, hipStream_t stream) {
     a.n = L.n;
     a.d = L.d;
     a.P = L.P;
-    const uint64_t tile = (uint64_t)kBlock * M;
+    const uint64_t tile = (uint64_t)kSumBlock * M;
     a.tiles = (uint32_t)(((uint64_t)L.n + tile - 1) / tile);
     a.q_out = L.q_out;
     a.tickets = (uint32_t*)L.ws;
@@ -175,9 +175,9 @@ static hipError_t launch_fm(const PlainLaunch& L, hipStream_t stream) {
     if (L.max_blocks > 0 && L.max_blocks < g) g = L.max_blocks;
     if ((uint32_t)g > a.tiles) g = (int)a.tiles;
     dim3 grid((unsigned)g, (unsigned)L.nsets);
-    hipLaunchKernelGGL((lattice_sum_kernel<F, M>), grid, dim3(kBlock), 0, stream, a.z, a.params,
-                       a.shift, a.inv_n, a.n, a.d, a.P, a.tiles, a.q_out, a.tickets, a.scratch,
-                       a.scratch_stride, a.slot_stride);
+    hipLaunchKernelGGL((lattice_sum_kernel<F, M, kSumBlock>), grid, dim3(kSumBlock), 0, stream,
+                       a.z, a.params, a.shift, a.inv_n, a.n, a.d, a.P, a.tiles, a.q_out, a.tickets,
+                       a.scratch, a.scratch_stride, a.slot_stride);
     return hipGetLastError();
 }
 
@@ -190,7 +190,8 @@ static hipError_t launch_f(const PlainLaunch& L, hipStream_t stream) {
         // workgroups resident on a CU).
         const uint64_t want_tiles = 3ull * device_cu_count() / 2;
         M = 16;
-        while (M > 4 && ((uint64_t)L.n + kBlock * M - 1) / ((uint64_t)kBlock * M) < want_tiles) M /= 2;
+        while (M > 4 && ((uint64_t)L.n + kSumBlock * M - 1) / ((uint64_t)kSumBlock * M) < want_tiles)
+            M /= 2;
     }
     switch (M) {
         case 4: return launch_fm<F, 4>(L, stream);

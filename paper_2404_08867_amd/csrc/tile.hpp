@@ -1,7 +1,8 @@
 // One tile of the plain rank-1 lattice rule: the device code shared by the
 // single-problem kernel (lattice_sum.hip) and the batched kernel (batched.hip).
 //
-// A tile is kBlock * M consecutive point indices; wave w of the workgroup owns
+// A tile is B * M consecutive point indices (B threads per workgroup, a
+// template parameter of every function here, kBlock by default); wave w owns
 //   i = tile_base + w*64*M + lane + 64*m,   m = 0..M-1,
 // and the loop runs over directions outside and over the thread's M points inside:
 //   start:  k = (Kw_j + Lz_j[lane]) mod n,  Kw_j = (wave_base * z_j + shift_whole_j) mod n,
@@ -57,10 +58,11 @@ __device__ __forceinline__ void split_shift(const double* shift, int j, uint32_t
     whole = wi >= n ? wi - n : wi;
 }
 
-template <class F>
+// B: threads per workgroup (a multiple of kWave).
+template <class F, int B = kBlock>
 struct TileShared {
     uint32_t lz[kDimChunk * kWave];   // [j][lane]
-    uint32_t kw[kDimChunk * kWaves];  // [j][wave]
+    uint32_t kw[kDimChunk * (B / kWave)];  // [j][wave]
     uint2 st[kDimChunk];              // (D_j, D_j - n)
     uint32_t sh[kDimChunk];           // whole part of the shift
     typename F::Dim c[kDimChunk];     // family constants
@@ -68,31 +70,31 @@ struct TileShared {
 
 // Workgroup constants of a problem: sums over all directions in a fixed order.
 // Every thread receives init0 (initial accumulator), ds1 and ie (final scale).
-template <class F>
+template <class F, int B = kBlock>
 __device__ __forceinline__ void block_constants(const ProblemView& v, double* red, double& init0,
                                                 double& ds1, int& ie) {
     double ds0 = 0.0;
     ds1 = 0.0;
     ie = 0;
     if constexpr (F::kBlockTerms) {
-        for (int j = threadIdx.x; j < v.d; j += kBlock) {
+        for (int j = threadIdx.x; j < v.d; j += B) {
             uint32_t whole;
             double frac;
             split_shift(v.shift, j, v.n, whole, frac);
             F::block_terms(v.p, v.d, j, v.inv_n, frac, ds0, ds1, ie);
         }
-        block_sum3(ds0, ds1, ie, red);
+        block_sum3<B>(ds0, ds1, ie, red);
     }
     init0 = ds0 + F::extra(v.p);
 }
 
 // Lz_j[l] = (l z_j) mod n for directions [j0, j0 + dc), dc <= kDimChunk: thread
-// (wave w, lane l) fills rows j = w, w + kWaves, ...  All of its loads of z are
+// (wave w, lane l) fills rows j = w, w + B / kWave, ...  All of its loads of z are
 // issued before the first is used, so the table costs one memory round trip.
 // l * z_j < 2^37, so the exact double-precision mulmod applies.
-template <class F>
-__device__ __forceinline__ void fill_lz(const ProblemView& v, TileShared<F>& s, int j0, int dc) {
-    constexpr int kRows = kDimChunk / kWaves;
+template <class F, int B>
+__device__ __forceinline__ void fill_lz(const ProblemView& v, TileShared<F, B>& s, int j0, int dc) {
+    constexpr int kRows = kDimChunk / (B / kWave);
     const int l = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
     // z_j < 2^31: its low 32-bit word (little-endian) is the value.
     const uint32_t* z32 = reinterpret_cast<const uint32_t*>(v.z + j0);
@@ -101,23 +103,23 @@ __device__ __forceinline__ void fill_lz(const ProblemView& v, TileShared<F>& s, 
     for (int r = 0; r < kRows; ++r) {
         // Rows past dc load the last direction again: an unconditional, in-bounds
         // load lets every load issue before the first wait.
-        const int j = min(wv + r * kWaves, dc - 1);
+        const int j = min(wv + r * (B / kWave), dc - 1);
         zr[r] = z32[2 * j];
     }
 #pragma unroll
     for (int r = 0; r < kRows; ++r) {
-        const int j = wv + r * kWaves;
+        const int j = wv + r * (B / kWave);
         if (j < dc) s.lz[j * kWave + l] = mulmod_small((uint32_t)l, zr[r], v.dn, v.inv_n);
     }
 }
 
 // Tables that do not depend on the tile for directions [j0, j0 + dc).
 // 64 * z_j < 2^37, so the exact double-precision mulmod applies.
-template <class F>
-__device__ __forceinline__ void fill_dims(const ProblemView& v, TileShared<F>& s, int j0, int dc) {
+template <class F, int B>
+__device__ __forceinline__ void fill_dims(const ProblemView& v, TileShared<F, B>& s, int j0, int dc) {
     const int tid = threadIdx.x;
-    fill_lz<F>(v, s, j0, dc);
-    for (int e = tid; e < dc; e += kBlock) {
+    fill_lz<F, B>(v, s, j0, dc);
+    for (int e = tid; e < dc; e += B) {
         const int j = j0 + e;
         uint32_t whole;
         double frac;
@@ -130,11 +132,11 @@ __device__ __forceinline__ void fill_dims(const ProblemView& v, TileShared<F>& s
 }
 
 // Per-wave start residues of one tile (general 62-bit products).
-template <class F, int M>
-__device__ __forceinline__ void fill_tile(const ProblemView& v, TileShared<F>& s, int j0, int dc,
+template <class F, int M, int B>
+__device__ __forceinline__ void fill_tile(const ProblemView& v, TileShared<F, B>& s, int j0, int dc,
                                           uint32_t tile_base) {
-    for (int e = threadIdx.x; e < dc * kWaves; e += kBlock) {
-        const int j = e / kWaves, w = e % kWaves;
+    for (int e = threadIdx.x; e < dc * (B / kWave); e += B) {
+        const int j = e / (B / kWave), w = e % (B / kWave);
         const uint32_t b = (tile_base + (uint32_t)w * (kWave * M)) % v.n;
         s.kw[e] = addmod(mulmod((uint64_t)b, (uint64_t)v.z[j0 + j], v.n, v.inv_n), s.sh[j], v.n);
     }
@@ -142,13 +144,13 @@ __device__ __forceinline__ void fill_tile(const ProblemView& v, TileShared<F>& s
 
 // Accumulates directions [j0, j0 + dc) into the thread's M point states, from
 // the direction tables (fill_dims) and the tile's start residues (fill_tile) in s.
-template <class F, int M>
-__device__ __forceinline__ void chunk_points(typename F::Acc (&acc)[M], const TileShared<F>& s, int j0,
+template <class F, int M, int B>
+__device__ __forceinline__ void chunk_points(typename F::Acc (&acc)[M], const TileShared<F, B>& s, int j0,
                                              int dc, uint32_t n) {
     using Dim = typename F::Dim;
     const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
     for (int jj = 0; jj < dc; ++jj) {
-        uint32_t k = addmod(s.kw[jj * kWaves + wv], s.lz[jj * kWave + lane], n);
+        uint32_t k = addmod(s.kw[jj * (B / kWave) + wv], s.lz[jj * kWave + lane], n);
         const uint2 stp = s.st[jj];
         const Dim c = s.c[jj];
 #pragma unroll
@@ -183,8 +185,8 @@ __device__ __forceinline__ double finish_points(const typename F::Acc (&acc)[M],
 // The thread's sum of f / scale over its M points of the tile, any d: the
 // tables are rebuilt chunk by chunk.  Begins with a barrier; the caller may
 // reuse s afterwards only after another barrier.
-template <class F, int M>
-__device__ __forceinline__ double tile_points(const ProblemView& v, TileShared<F>& s,
+template <class F, int M, int B>
+__device__ __forceinline__ double tile_points(const ProblemView& v, TileShared<F, B>& s,
                                               uint32_t tile_base, double init0) {
     typename F::Acc acc[M];
 #pragma unroll
@@ -192,11 +194,11 @@ __device__ __forceinline__ double tile_points(const ProblemView& v, TileShared<F
     for (int j0 = 0; j0 < v.d; j0 += kDimChunk) {
         const int dc = min(kDimChunk, v.d - j0);
         __syncthreads();  // every read of the previous tables is done
-        fill_dims<F>(v, s, j0, dc);
+        fill_dims<F, B>(v, s, j0, dc);
         __syncthreads();
-        fill_tile<F, M>(v, s, j0, dc, tile_base);
+        fill_tile<F, M, B>(v, s, j0, dc, tile_base);
         __syncthreads();
-        chunk_points<F, M>(acc, s, j0, dc, v.n);
+        chunk_points<F, M, B>(acc, s, j0, dc, v.n);
     }
     return finish_points<F, M>(acc, tile_base, v.n);
 }
@@ -208,12 +210,12 @@ __device__ __forceinline__ double tile_points(const ProblemView& v, TileShared<F
 // wave 0 (lane j owns direction j), and the start residues of the workgroup's
 // first tile (at first_base) by the other waves.
 // ---------------------------------------------------------------------------
-template <class F, int M>
-__device__ __forceinline__ void setup_one_chunk(const ProblemView& v, TileShared<F>& s, double* red,
+template <class F, int M, int B>
+__device__ __forceinline__ void setup_one_chunk(const ProblemView& v, TileShared<F, B>& s, double* red,
                                                 uint32_t first_base, double& init0, double& ds1,
                                                 int& ie) {
     const int tid = threadIdx.x, d = v.d;
-    fill_lz<F>(v, s, 0, d);
+    fill_lz<F, B>(v, s, 0, d);
     if (tid < kWave) {
         double t0 = 0.0, t1 = 0.0;
         int te = 0;
@@ -237,8 +239,8 @@ __device__ __forceinline__ void setup_one_chunk(const ProblemView& v, TileShared
             }
         }
     } else {
-        for (int e = tid - kWave; e < d * kWaves; e += kBlock - kWave) {
-            const int j = e / kWaves, w = e % kWaves;
+        for (int e = tid - kWave; e < d * (B / kWave); e += B - kWave) {
+            const int j = e / (B / kWave), w = e % (B / kWave);
             uint32_t whole;
             double frac;
             split_shift(v.shift, j, v.n, whole, frac);
@@ -261,19 +263,19 @@ __device__ __forceinline__ void setup_one_chunk(const ProblemView& v, TileShared
 // One tile of a problem set up by setup_one_chunk.  With `kw_ready` the start
 // residues of this tile are already in s; otherwise they are rebuilt between two
 // barriers.  The caller may overwrite s afterwards only after a barrier.
-template <class F, int M>
-__device__ __forceinline__ double tile_points_one_chunk(const ProblemView& v, TileShared<F>& s,
+template <class F, int M, int B>
+__device__ __forceinline__ double tile_points_one_chunk(const ProblemView& v, TileShared<F, B>& s,
                                                         uint32_t tile_base, double init0,
                                                         bool kw_ready) {
     if (!kw_ready) {
         __syncthreads();  // every read of the previous tile's residues is done
-        fill_tile<F, M>(v, s, 0, v.d, tile_base);
+        fill_tile<F, M, B>(v, s, 0, v.d, tile_base);
         __syncthreads();
     }
     typename F::Acc acc[M];
 #pragma unroll
     for (int m = 0; m < M; ++m) acc[m] = F::init(init0);
-    chunk_points<F, M>(acc, s, 0, v.d, v.n);
+    chunk_points<F, M, B>(acc, s, 0, v.d, v.n);
     return finish_points<F, M>(acc, tile_base, v.n);
 }
 
