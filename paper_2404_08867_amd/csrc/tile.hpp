@@ -88,28 +88,37 @@ __device__ __forceinline__ void block_constants(const ProblemView& v, double* re
     init0 = ds0 + F::extra(v.p);
 }
 
-// Lz_j[l] = (l z_j) mod n for directions [j0, j0 + dc), dc <= kDimChunk: thread
-// (wave w, lane l) fills rows j = w, w + B / kWave, ...  All of its loads of z are
-// issued before the first is used, so the table costs one memory round trip.
-// l * z_j < 2^37, so the exact double-precision mulmod applies.
+// Lz_j[l] = (l z_j) mod n for directions [j0, j0 + dc), dc <= kDimChunk.
+// l * z_j < 2^37, so the exact double-precision mulmod applies.  When a thread
+// owns at most four rows (B >= 1024), thread (wave w, lane l) fills rows
+// j = w, w + B / kWave, ... and issues all of its loads of z before the first is
+// used, so the table costs one memory round trip; otherwise a plain strided
+// loop keeps the register count (and the occupancy) of smaller workgroups.
 template <class F, int B>
 __device__ __forceinline__ void fill_lz(const ProblemView& v, TileShared<F, B>& s, int j0, int dc) {
     constexpr int kRows = kDimChunk / (B / kWave);
-    const int l = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
-    // z_j < 2^31: its low 32-bit word (little-endian) is the value.
-    const uint32_t* z32 = reinterpret_cast<const uint32_t*>(v.z + j0);
-    uint32_t zr[kRows];
+    if constexpr (kRows <= 4) {
+        const int l = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
+        // z_j < 2^31: its low 32-bit word (little-endian) is the value.
+        const uint32_t* z32 = reinterpret_cast<const uint32_t*>(v.z + j0);
+        uint32_t zr[kRows];
 #pragma unroll
-    for (int r = 0; r < kRows; ++r) {
-        // Rows past dc load the last direction again: an unconditional, in-bounds
-        // load lets every load issue before the first wait.
-        const int j = min(wv + r * (B / kWave), dc - 1);
-        zr[r] = z32[2 * j];
-    }
+        for (int r = 0; r < kRows; ++r) {
+            // Rows past dc load the last direction again: an unconditional,
+            // in-bounds load lets every load issue before the first wait.
+            const int j = min(wv + r * (B / kWave), dc - 1);
+            zr[r] = z32[2 * j];
+        }
 #pragma unroll
-    for (int r = 0; r < kRows; ++r) {
-        const int j = wv + r * (B / kWave);
-        if (j < dc) s.lz[j * kWave + l] = mulmod_small((uint32_t)l, zr[r], v.dn, v.inv_n);
+        for (int r = 0; r < kRows; ++r) {
+            const int j = wv + r * (B / kWave);
+            if (j < dc) s.lz[j * kWave + l] = mulmod_small((uint32_t)l, zr[r], v.dn, v.inv_n);
+        }
+    } else {
+        for (int e = threadIdx.x; e < dc * kWave; e += B) {
+            const int j = e / kWave, l = e % kWave;
+            s.lz[e] = mulmod_small((uint32_t)l, (uint32_t)v.z[j0 + j], v.dn, v.inv_n);
+        }
     }
 }
 
