@@ -68,7 +68,57 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
                     help="wall-clock budget of the oracle's CPU-baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="first run a plain device-to-device copy of this many MiB three times "
+                         "(the reference for scaling rocprofv3 FETCH_SIZE / WRITE_SIZE)")
     return ap.parse_args()
+
+
+# HBM traffic of the plain-sum kernel as measured with rocprofv3 counters and
+# recorded in the profile summary, together with a SHA-256 of the kernel's
+# sources at the time: reported only while the sources still match.
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "lattice_sum_plain_d20_peak.md")
+KERNEL_SOURCES = ["lattice_sum.hip", "tile.hpp", "common.hpp", "families.hpp", "kernels.hpp"]
+
+
+def kernel_sources_sha256() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2404_08867_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def measured_traffic():
+    """Bytes per launch from the profile summary, or None if absent or stale."""
+    try:
+        with open(TRAFFIC_PROFILE) as f:
+            text = f.read()
+    except OSError:
+        return None
+    fields = {}
+    for ln in text.splitlines():
+        if ln.startswith("traffic_bytes_per_launch:") or ln.startswith("kernel_sources_sha256:"):
+            k, v = ln.split(":", 1)
+            fields[k.strip()] = v.strip().strip("`")
+    if fields.get("kernel_sources_sha256") != kernel_sources_sha256():
+        return None
+    try:
+        return float(fields["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def copy_probe(torch, mib):
+    """A plain device copy of `mib` MiB, three times (counter calibration)."""
+    n = mib * (1 << 20) // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    del src, dst
 
 
 def oracle_baseline(prob, seconds):
@@ -299,6 +349,8 @@ def main():
         sys.exit(1)
     torch.cuda.set_device(0)
     qmc.lib()  # fail loudly if the HIP library is missing
+    if args.copy_probe_mib > 0:
+        copy_probe(torch, args.copy_probe_mib)
 
     if args.workload == "mdi_d100_gauss":
         prob, res, units, wpp, config = bench_mdi(args, torch, qmc, W)
@@ -334,7 +386,7 @@ def main():
             "peak": PEAK_LANE_OPS / 1e12,
             "unit": "T VALU issue slots/s (lane-ops)",
             "frac": achieved / PEAK_LANE_OPS,
-            "traffic": None,
+            "traffic": measured_traffic() if args.workload == "plain_d20_peak" else None,
             "work_per_unit": wpp,
             "kernel_us": main_r["kern_s"] * 1e6,
         },
