@@ -54,6 +54,7 @@ def _load():
     lib.oracle_lattice_sum.argtypes = [i32, i64, dp, dp, i32, dp, dp, dp]
     lib.oracle_lattice_partial.argtypes = [i32, i64, dp, dp, i32, dp, i64, i64, dp]
     lib.oracle_lattice_grad.argtypes = [i32, i64, dp, dp, i32, dp, dp, dp]
+    lib.oracle_shift_ensemble.argtypes = [i32, i64, dp, i32, dp, dp, i32, dp, dp, dp]
     lib.oracle_mdi_dims.argtypes = [i32, dp, i64, dp]
     lib.oracle_mdi_lr_brute.argtypes = [i32, dp, i32, dp, dp]
     lib.oracle_mdi_lr_sweep.argtypes = [i32, dp, i32, dp, dp]
@@ -137,6 +138,20 @@ def lattice_grad(z, n: int, family: int, params, shift=None):
     _check(_load().oracle_lattice_grad(z.size, n, _ptr(z), _ptr(shift), family, _ptr(params),
                                        _ptr(q), _ptr(g)), "lattice_grad")
     return float(q[0]), g
+
+
+def shift_ensemble(z, n: int, family: int, params, shifts):
+    """Randomly shifted rule over the rows of `shifts` (R x d): (Q[R], mean, standard error)."""
+    z = _i64(z)
+    params = _f64(params)
+    shifts = _f64(np.atleast_2d(shifts))
+    R = shifts.shape[0]
+    q = np.zeros(R)
+    mean = np.zeros(1)
+    se = np.zeros(1)
+    _check(_load().oracle_shift_ensemble(z.size, n, _ptr(z), family, _ptr(params), _ptr(shifts), R,
+                                         _ptr(q), _ptr(mean), _ptr(se)), "shift_ensemble")
+    return q, float(mean[0]), float(se[0])
 
 
 def mdi_dims(z, n: int) -> np.ndarray:

@@ -287,6 +287,35 @@ int oracle_lattice_grad(int d, int64_t n, const int64_t* z, const double* shift,
 }
 
 /* ------------------------------------------------------------------------- */
+/* Randomly shifted lattice rule (Sec. 2.1: the shifted lattice P + Delta and   */
+/* the root-mean-square error over a shift drawn uniformly from [0,1]^d).      */
+/* The R shifts are inputs (rows of `shifts`, drawn by the caller):            */
+/*   Q_r  = (1/n) sum_i f({x_i + Delta_r}),        r = 0..R-1,                 */
+/*   mean = (1/R) sum_r Q_r,                                                    */
+/*   se   = sqrt( sum_r (Q_r - mean)^2 / (R (R - 1)) ),                         */
+/* the standard error of the mean of R independent estimates (0 when R = 1).   */
+/* Both sums are Neumaier sums in r order; the variance is taken in two passes. */
+/* ------------------------------------------------------------------------- */
+int oracle_shift_ensemble(int d, int64_t n, const int64_t* z, int family, const double* params,
+                          const double* shifts, int R, double* q_out, double* mean_out,
+                          double* se_out) {
+    if (R < 1 || !shifts || !q_out) return OR_BAD_ARG;
+    for (int r = 0; r < R; ++r) {
+        int rc = oracle_lattice_sum(d, n, z, shifts + (size_t)r * (size_t)d, family, params,
+                                    &q_out[r], NULL);
+        if (rc != OR_OK) return rc;
+    }
+    neu_t sum = {0.0, 0.0};
+    for (int r = 0; r < R; ++r) neu_add(&sum, q_out[r]);
+    const double mean = neu_value(&sum) / (double)R;
+    neu_t ss = {0.0, 0.0};
+    for (int r = 0; r < R; ++r) neu_add(&ss, (q_out[r] - mean) * (q_out[r] - mean));
+    if (mean_out) *mean_out = mean;
+    if (se_out) *se_out = R > 1 ? sqrt(neu_value(&ss) / ((double)R * (double)(R - 1))) : 0.0;
+    return OR_OK;
+}
+
+/* ------------------------------------------------------------------------- */
 /* Per-direction node counts of the transformed grid (eq. 3.5):              */
 /*   n_i = lcm(z_i, z_{i+1}) / min(z_i, z_{i+1}),  i < d;   n_d = ceil(n / z_d). */
 /* ------------------------------------------------------------------------- */
