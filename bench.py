@@ -33,28 +33,52 @@ if ROOT not in sys.path:
 
 METRIC = "lattice-point integrand evals/sec at rel err ≤1e-6 vs FP64 oracle (1 GPU)"
 
-# VALU issue peak of MI355X without packed FP32: 256 CUs x 64 lanes x 2.4 GHz.
-PEAK_LANE_OPS = 256 * 64 * 2.4e9
+# ALU peak of MI355X in 32-bit VALU lane-operation slots: 256 CUs x 128 lanes x
+# 2.4 GHz = 78.6 T/s, AMD's FP32 vector rate (157.3 TFLOP/s, an FMA counted as two
+# flops).  One instruction type alone issues at half of it (64 lanes per CU per
+# clock, measured), but the lattice loops mix 32-bit integer and FP32 work and run
+# above that rate, so the 128-lane figure is the ceiling.  Costs in slots:
+C32 = 1   # 32-bit integer or FP32 operation
+C64 = 2   # FP64 operation (FP64 vector rate 78.6 TFLOP/s: half the 32-bit rate)
+CT = 4    # v_exp_f32 / v_rcp_f32 / v_cos_f32 (a quarter of the 32-bit rate, measured)
+PEAK_SLOTS = 256 * 128 * 2.4e9
 
-# Algorithmic VALU issue slots per lattice point (one d-dimensional integrand
-# evaluation with exact integer indices):
-#   d * (3 index step + 1 index-to-float conversion + c_fam) + 2 + 2
-# c_fam = VALU operations of the family per direction once the coordinate's scale
-# and offset are folded into its first FMA: 1 (exp-sum, oscillatory: the argument
-# FMA), 2 (Gaussian: y, then y^2 accumulated), 3 (product peak: y, y^2 + c^-2, the
-# product); 2 issue slots for the per-point half-rate transcendental; 2 for the
-# FP64 accumulation (convert, add).
-C_FAM = {0: 1, 1: 3, 2: 2, 3: 1}
+# Algorithmic work per lattice point of the QMC_FP32_COMPENSATED path, in slots:
+# per direction, the index step (two adds and a min) and the conversion of the
+# index, plus the family's operations once the coordinate's scale and offset are
+# folded into its first FMA; per point, one transcendental and the FP64
+# accumulation (convert, add).
+#   exp-sum, oscillatory: FP64 argument FMA;
+#   Gaussian:             FP64 y = b k + g, FP64 y^2 accumulated;
+#   product peak:         FP32 y, y^2 + g, product (FP64 for d > 64).
+INDEX = 3 * C32
+ACCUM = 2 * C64
+PEAK_F32_MAX_DIMS = 64
 
 
 def work_per_point(d: int, family: int) -> int:
-    return d * (3 + 1 + C_FAM[family]) + 2 + 2
+    if family == 1:  # product peak
+        if d <= PEAK_F32_MAX_DIMS:
+            per_dim = INDEX + C32 + 3 * C32
+        else:
+            per_dim = INDEX + C64 + 3 * C64
+    elif family == 2:  # Gaussian
+        per_dim = INDEX + C64 + 2 * C64
+    else:  # exp-sum, oscillatory
+        per_dim = INDEX + C64 + C64
+    return d * per_dim + CT + ACCUM
 
 
-# The adjoint adds, per point and direction, the index step, the conversion, the
-# coordinate FMA and the accumulation of w * h(x), and one more transcendental.
+# The adjoint's second sweep regenerates each direction's indices and accumulates
+# w(x) h_j(x_j): index step, conversion, coordinate FMA and accumulating FMA (FP64),
+# plus a second transcendental per point.
 def work_per_point_adjoint(d: int, family: int) -> int:
-    return work_per_point(d, family) + d * (3 + 1 + 1 + 1) + 2
+    return work_per_point(d, family) + d * (INDEX + 3 * C64) + CT
+
+
+# MDI-LR factor evaluation (Gaussian, FP32c): node, argument, square, exp2, FP64
+# accumulation.
+WORK_PER_MDI_FACTOR = 3 * C32 + CT + ACCUM
 
 
 def parse():
@@ -64,7 +88,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--workload", default="plain_d20_peak",
                     choices=["plain_d20_peak", "plain_d4_expsum", "mdi_d100_gauss", "batched_4096",
-                             "adjoint_d50_osc"])
+                             "adjoint_d50_osc", "shifts_d20_peak"])
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
                     help="wall-clock budget of the oracle's CPU-baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -211,6 +235,54 @@ def bench_plain(args, torch, qmc, W):
     return prob, results, units, wpp, config
 
 
+def bench_shifts(args, torch, qmc, W):
+    """Random-shift ensemble: one step is the R = 64 shifted sums of plain_d20_peak
+    and their mean and standard error (two launches)."""
+    w = W.shifts_d20_peak()
+    z = torch.tensor(qmc.korobov(w.d, w.n, w.a), device="cuda")
+    params = torch.tensor(w.params, dtype=torch.float64, device="cuda")
+    shifts = torch.tensor(w.shifts, dtype=torch.float64, device="cuda")
+    R = shifts.shape[0]
+    ws = qmc.Workspace(qmc.workspace_size(w.d, w.n, R))
+    results = {}
+    for prec, name in ((qmc.FP32_COMPENSATED, "fp32c"), (qmc.FP64, "fp64")):
+        q = torch.zeros(R, dtype=torch.float64, device="cuda")
+        stats = torch.zeros(2, dtype=torch.float64, device="cuda")
+
+        def launch(prec=prec, q=q, stats=stats):
+            qmc.lattice_sum_shifts(z, w.n, w.family, params, shifts, prec, ws=ws, out=q,
+                                   stats_out=stats)
+
+        step_s, kern_s, lat_s, g = time_graph(torch, launch, args.steps, args.warmup)
+        results[name] = dict(step_s=step_s, kern_s=kern_s, lat_s=lat_s, q=q.cpu().numpy(),
+                             stats=stats.cpu().numpy())
+        del g
+    units = w.n * R
+    wpp = work_per_point(w.d, w.family)
+    config = {"workload": w.name, "d": w.d, "n": w.n, "a": w.a, "shifts": R,
+              "family": W.FAMILY_NAMES[w.family], "precision": "fp32_compensated",
+              "lattice": "korobov", "unit_of_work": "one point of one shifted lattice"}
+    return w, results, units, wpp, config
+
+
+def oracle_shifts_baseline(w, r32, r64, seconds):
+    """The oracle's shifted sums in shift order until the time budget is spent."""
+    import oracle as O
+    z = O.korobov(w.d, w.n, w.a)
+    t0 = time.perf_counter()
+    e32 = e64 = 0.0
+    k = 0
+    for r in range(w.shifts.shape[0]):
+        qo, ao = O.lattice_sum(z, w.n, w.family, w.params, w.shifts[r])
+        e32 = max(e32, abs(r32["q"][r] - qo) / max(abs(qo), ao))
+        e64 = max(e64, abs(r64["q"][r] - qo) / max(abs(qo), ao))
+        k += 1
+        if time.perf_counter() - t0 > seconds:
+            break
+    dt = time.perf_counter() - t0
+    return w.n * k / dt, k, e32, e64
+
+
 def bench_mdi(args, torch, qmc, W):
     nsets = 65536
     w = W.mdi_d100_gauss(nsets=nsets)
@@ -227,7 +299,7 @@ def bench_mdi(args, torch, qmc, W):
         results[name] = dict(step_s=step_s, kern_s=kern_s, lat_s=lat_s, q=out.cpu().numpy())
         del g
     units = int(w.N.sum()) * nsets  # one-dimensional factor evaluations per launch
-    wpp = 6  # per Gaussian factor: FMA, square, exp2 (2 issue slots), convert + FP64 add
+    wpp = WORK_PER_MDI_FACTOR
     config = {"workload": w.name, "d": w.d, "N": int(w.N[0]), "nsets": nsets,
               "family": W.FAMILY_NAMES[w.family], "precision": "fp32_compensated",
               "unit_of_work": "one-dimensional factor evaluation"}
@@ -358,17 +430,20 @@ def main():
         prob, res, units, wpp, config = bench_batched(args, torch, qmc, W)
     elif args.workload == "adjoint_d50_osc":
         prob, res, units, wpp, config = bench_adjoint(args, torch, qmc, W)
+    elif args.workload == "shifts_d20_peak":
+        prob, res, units, wpp, config = bench_shifts(args, torch, qmc, W)
     else:
         prob, res, units, wpp, config = bench_plain(args, torch, qmc, W)
 
     line = {"metric": METRIC}
     main_r = res["fp32c"]
     value = units / main_r["step_s"]
-    achieved = wpp * units / main_r["kern_s"]
+    achieved = wpp * units / main_r["kern_s"]  # slots per second
     line.update({
         "value": value,
         "unit": {"mdi_d100_gauss": "factor evals/s",
-                 "adjoint_d50_osc": "point-set evals (value + gradient)/s"}.get(
+                 "adjoint_d50_osc": "point-set evals (value + gradient)/s",
+                 "shifts_d20_peak": "shifted-lattice point evals/s"}.get(
                      args.workload, "lattice-point evals/s"),
         "n_gpus": 1,
         "steps": args.steps,
@@ -383,9 +458,9 @@ def main():
         "roofline": {
             "bound": "alu",
             "achieved": achieved / 1e12,
-            "peak": PEAK_LANE_OPS / 1e12,
-            "unit": "T VALU issue slots/s (lane-ops)",
-            "frac": achieved / PEAK_LANE_OPS,
+            "peak": PEAK_SLOTS / 1e12,
+            "unit": "T 32-bit VALU lane-op slots/s",
+            "frac": achieved / PEAK_SLOTS,
             "traffic": measured_traffic() if args.workload == "plain_d20_peak" else None,
             "work_per_unit": wpp,
             "kernel_us": main_r["kern_s"] * 1e6,
@@ -403,6 +478,9 @@ def main():
         elif args.workload == "adjoint_d50_osc":
             rate, e32, e64 = oracle_adjoint_baseline(prob, res["fp32c"], res["fp64"])
             sample = "parameter set 0 of 64, all n points, value and 51 gradient components"
+        elif args.workload == "shifts_d20_peak":
+            rate, k, e32, e64 = oracle_shifts_baseline(prob, res["fp32c"], res["fp64"], args.cpu_seconds)
+            sample = f"the first {k} of {prob.shifts.shape[0]} shifted lattices (n={prob.n} points each)"
         elif args.workload == "mdi_d100_gauss":
             rate, reps, vals = oracle_mdi_baseline(prob, len(prob.params), args.cpu_seconds)
             qs32, qs64 = res["fp32c"]["q"], res["fp64"]["q"]

@@ -129,6 +129,28 @@ qmc_status qmc_lattice_sum(int32_t d, int64_t n, const int64_t* z, const double*
                            int32_t precision, double* q_out, void* ws, size_t ws_bytes,
                            void* stream);
 
+/* Randomly shifted lattice rule (Sec. 2.1: the shifted lattice P + Delta, whose
+ * error averaged over a shift drawn uniformly from [0,1]^d is the quality measure
+ * of randomly shifted rules).  For R = nshifts shifts sharing z and one parameter
+ * set, in one launch:
+ *   Q_r = (1/n) sum_{i=0}^{n-1} f({k_i / n + Delta_r}),   r = 0..R-1,
+ * then, if stats_out is not NULL, a second small launch on the same stream writes
+ *   stats_out[0] = mean = (1/R) sum_r Q_r,
+ *   stats_out[1] = sqrt(sum_r (Q_r - mean)^2 / (R (R - 1)))   (0 for R = 1),
+ * the standard error of the mean, both summed in a fixed order.  The shifts are
+ * inputs: the caller draws them (e.g. i.i.d. uniform on [0,1)^d).
+ *   z          device int64[d], 0 <= z_j < n
+ *   shifts     device double[R][d], each in [0,1) (caller's contract)
+ *   nshifts    R in [1, 4096]
+ *   params     device double[qmc_param_count(family, d)], one set shared by all shifts
+ *   q_out      device double[R]
+ *   stats_out  device double[2], or NULL
+ *   ws         device workspace of qmc_workspace_size(d, n, R) bytes */
+qmc_status qmc_lattice_sum_shifts(int32_t d, int64_t n, const int64_t* z, const double* shifts,
+                                  int32_t nshifts, int32_t family, const double* params,
+                                  int32_t precision, double* q_out, double* stats_out, void* ws,
+                                  size_t ws_bytes, void* stream);
+
 /* Launch configuration of the plain-sum kernel.  Zero fields mean "choose
  * automatically".  points_per_thread must be 0, 4, 8 or 16 (the tile is
  * 1024 * points_per_thread consecutive points); max_blocks caps the persistent

@@ -263,6 +263,8 @@ qmc_status qmc_lattice_sum_ex(int32_t d, int64_t n, const int64_t* z, const doub
     L.params = params;
     L.P = param_count(family, d);
     L.nsets = nsets;
+    L.param_stride = L.P;
+    L.shift_stride = 0;
     L.fp32 = precision == QMC_FP32_COMPENSATED;
     L.q_out = q_out;
     L.ws = ws;
@@ -279,6 +281,36 @@ qmc_status qmc_lattice_sum_ex(int32_t d, int64_t n, const int64_t* z, const doub
         L.max_blocks = cfg->max_blocks;
     }
     return from_hip(qmc::launch_lattice_sum(L, (hipStream_t)stream), "qmc_lattice_sum");
+}
+
+qmc_status qmc_lattice_sum_shifts(int32_t d, int64_t n, const int64_t* z, const double* shifts,
+                                  int32_t nshifts, int32_t family, const double* params,
+                                  int32_t precision, double* q_out, double* stats_out, void* ws,
+                                  size_t ws_bytes, void* stream) {
+    qmc_status s = check_common(d, family, nshifts, precision);
+    if (s != QMC_OK) return s;
+    if (n < 1 || n >= kMaxN) return fail(QMC_ERR_INVALID_ARG, "n = %lld outside [1, 2^31)", (long long)n);
+    if (!z || !shifts || !params || !q_out)
+        return fail(QMC_ERR_INVALID_ARG, "z, shifts, params and q_out must be non-NULL");
+    s = check_workspace(ws, ws_bytes, qmc::plain_workspace_bytes(nshifts));
+    if (s != QMC_OK) return s;
+    qmc::PlainLaunch L{};
+    L.d = d;
+    L.n = (uint32_t)n;
+    L.z = z;
+    L.shift = shifts;
+    L.family = family;
+    L.params = params;
+    L.P = param_count(family, d);
+    L.nsets = nshifts;
+    L.param_stride = 0;
+    L.shift_stride = d;
+    L.fp32 = precision == QMC_FP32_COMPENSATED;
+    L.q_out = q_out;
+    L.ws = ws;
+    hipError_t e = qmc::launch_lattice_sum(L, (hipStream_t)stream);
+    if (e == hipSuccess && stats_out) e = qmc::launch_shift_stats(q_out, nshifts, stats_out, (hipStream_t)stream);
+    return from_hip(e, "qmc_lattice_sum_shifts");
 }
 
 qmc_status qmc_lattice_points(int32_t d, int64_t n, const int64_t* z, int64_t i0, int64_t count,

@@ -27,6 +27,10 @@ struct PlainLaunch {
     const double* params;
     int P;  // parameters per set
     int nsets;
+    // Set s reads params + s * param_stride and shift + s * shift_stride: (P, 0) for
+    // parameter sets sharing one shift, (0, d) for shifts sharing one parameter set.
+    int param_stride;
+    int shift_stride;
     bool fp32;
     double* q_out;
     void* ws;
@@ -37,6 +41,9 @@ struct PlainLaunch {
 int sum_blocks_per_set(int nsets);
 size_t plain_workspace_bytes(int nsets);
 hipError_t launch_lattice_sum(const PlainLaunch& a, hipStream_t stream);
+
+// Mean and standard error of the mean of q[0..R) into stats[0..1] (one wave).
+hipError_t launch_shift_stats(const double* q, int R, double* stats, hipStream_t stream);
 
 hipError_t launch_lattice_points(int d, uint32_t n, const int64_t* z, int64_t i0, int64_t count,
                                  int32_t* k_out, hipStream_t stream);

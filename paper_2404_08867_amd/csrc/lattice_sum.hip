@@ -28,7 +28,8 @@ struct SumArgs {
     double inv_n;         // 1.0 / n
     uint32_t n;
     int d;
-    int P;
+    int param_stride;     // doubles between the parameter rows of two sets (0: shared)
+    int shift_stride;     // doubles between the shift rows of two sets (0: shared)
     uint32_t tiles;
     double* q_out;
     uint32_t* tickets;    // counter region of the workspace
@@ -53,14 +54,16 @@ __device__ __forceinline__ GridSlots set_slots(double* scratch, uint32_t scratch
 template <class F, int M, int B>
 __global__ __launch_bounds__(B) void lattice_sum_kernel(
     const int64_t* z, const double* params, const double* shift, double inv_n, uint32_t n, int d,
-    int P, uint32_t tiles, double* q_out, uint32_t* tickets, double* scratch,
-    uint32_t scratch_stride, int slot_stride) {
+    int param_stride, int shift_stride, uint32_t tiles, double* q_out, uint32_t* tickets,
+    double* scratch, uint32_t scratch_stride, int slot_stride) {
     constexpr uint32_t kTile = B * M;
     __shared__ TileShared<F, B> s;
     __shared__ double s_red[3 * (B / kWave)];
 
     const int set = blockIdx.y;
-    const ProblemView v = make_view(d, n, inv_n, z, shift, params + (size_t)set * P);
+    const ProblemView v =
+        make_view(d, n, inv_n, z, shift ? shift + (size_t)set * shift_stride : nullptr,
+                  params + (size_t)set * param_stride);
     double init0, ds1;
     int ie;
     double tacc = 0.0;
@@ -90,6 +93,34 @@ __global__ __launch_bounds__(B) void lattice_sum_kernel(
 static_assert((kMaxSumBlocksPerSet + kReduceGroups - 1) / kReduceGroups <= kWave &&
                   kReduceGroups <= kWave,
               "grid_sum_wave0 puts one group member, and one group, per lane");
+
+// --------------------------------------------------------------------------
+// Randomly shifted rule (Sec. 2.1): after the R shifted sums, their mean and the
+// standard error of the mean, sqrt(sum_r (Q_r - mean)^2 / (R (R - 1))) (0 for
+// R = 1).  One wave; lane l owns r = l, l + 64, ... and the lanes are combined by
+// the fixed-order wave reduction, so the result is reproducible.
+// --------------------------------------------------------------------------
+__global__ __launch_bounds__(kWave) void shift_stats_kernel(const double* q, int R, double* stats) {
+    const int lane = threadIdx.x;
+    double s = 0.0;
+    for (int r = lane; r < R; r += kWave) s += q[r];
+    const double mean = lane_value(wave_total(s), kWaveTotalLane) / (double)R;
+    double v = 0.0;
+    for (int r = lane; r < R; r += kWave) {
+        const double e = q[r] - mean;
+        v = fma(e, e, v);
+    }
+    const double ss = lane_value(wave_total(v), kWaveTotalLane);
+    if (lane == 0) {
+        stats[0] = mean;
+        stats[1] = R > 1 ? sqrt(ss / ((double)R * (double)(R - 1))) : 0.0;
+    }
+}
+
+hipError_t launch_shift_stats(const double* q, int R, double* stats, hipStream_t stream) {
+    hipLaunchKernelGGL(shift_stats_kernel, dim3(1), dim3(kWave), 0, stream, q, R, stats);
+    return hipGetLastError();
+}
 
 // --------------------------------------------------------------------------
 // Debug export of the indices, through the same start/step decomposition.
@@ -163,7 +194,8 @@ static hipError_t launch_fm(const PlainLaunch& L, hipStream_t stream) {
     a.inv_n = 1.0 / (double)L.n;
     a.n = L.n;
     a.d = L.d;
-    a.P = L.P;
+    a.param_stride = L.param_stride;
+    a.shift_stride = L.shift_stride;
     const uint64_t tile = (uint64_t)kSumBlock * M;
     a.tiles = (uint32_t)(((uint64_t)L.n + tile - 1) / tile);
     a.q_out = L.q_out;
@@ -176,8 +208,8 @@ static hipError_t launch_fm(const PlainLaunch& L, hipStream_t stream) {
     if ((uint32_t)g > a.tiles) g = (int)a.tiles;
     dim3 grid((unsigned)g, (unsigned)L.nsets);
     hipLaunchKernelGGL((lattice_sum_kernel<F, M, kSumBlock>), grid, dim3(kSumBlock), 0, stream,
-                       a.z, a.params, a.shift, a.inv_n, a.n, a.d, a.P, a.tiles, a.q_out, a.tickets,
-                       a.scratch, a.scratch_stride, a.slot_stride);
+                       a.z, a.params, a.shift, a.inv_n, a.n, a.d, a.param_stride, a.shift_stride,
+                       a.tiles, a.q_out, a.tickets, a.scratch, a.scratch_stride, a.slot_stride);
     return hipGetLastError();
 }
 

@@ -59,6 +59,7 @@ def lib() -> ctypes.CDLL:
         L.qmc_workspace_size.argtypes = [i32, i64, i32, vp]
         L.qmc_lattice_sum.argtypes = [i32, i64, dp, dp, i32, dp, i32, i32, dp, vp, sz, vp]
         L.qmc_lattice_sum_ex.argtypes = [i32, i64, dp, dp, i32, dp, i32, i32, dp, vp, sz, vp, vp]
+        L.qmc_lattice_sum_shifts.argtypes = [i32, i64, dp, dp, i32, i32, dp, i32, dp, dp, vp, sz, vp]
         L.qmc_lattice_points.argtypes = [i32, i64, dp, i64, i64, dp, vp]
         L.qmc_mdi_lr.argtypes = [i32, dp, i32, dp, i32, i32, dp, vp, sz, vp]
         L.qmc_lattice_sum_adjoint.argtypes = [i32, i64, dp, dp, i32, dp, i32, i32, dp, dp, dp, vp, sz, vp]
@@ -212,6 +213,35 @@ def lattice_sum(z, n: int, family: int, params, precision: int = FP64, shift=Non
     if out is not None:
         return out
     return q[0] if squeeze else q
+
+
+def lattice_sum_shifts(z, n: int, family: int, params, shifts, precision: int = FP64,
+                       ws: Workspace | None = None, device="cuda", out=None, stats_out=None):
+    """Randomly shifted rule (qmc_lattice_sum_shifts): Q_r for each shift row r of
+    `shifts` ([R, d], drawn by the caller) with one shared parameter set, and
+    (mean, standard error of the mean).  Returns (q [R], stats [2]) device tensors."""
+    torch = _torch()
+    zt = _dev(z, torch.int64, device)
+    pt = _dev(params, torch.float64, device)
+    st = _dev(shifts, torch.float64, device)
+    d = int(zt.numel())
+    if st.dim() == 1:
+        st = st.unsqueeze(0)
+    if st.dim() != 2 or st.shape[1] != d:
+        raise QmcError(ERR_INVALID_ARG, "shifts must have shape [R, d]")
+    R = int(st.shape[0])
+    if pt.dim() != 1:
+        raise QmcError(ERR_INVALID_ARG, "params must be one parameter row")
+    q = out if out is not None else torch.empty(R, dtype=torch.float64, device=device)
+    stats = stats_out if stats_out is not None else torch.empty(2, dtype=torch.float64, device=device)
+    for t, m in ((q, R), (stats, 2)):
+        if t.dtype != torch.float64 or t.numel() < m or not t.is_contiguous():
+            raise QmcError(ERR_INVALID_ARG, "outputs must be contiguous float64 tensors")
+    w = _workspace(d, n, R, device, ws)
+    _check(lib().qmc_lattice_sum_shifts(d, n, _ptr(zt), _ptr(st), R, family, _ptr(pt), precision,
+                                        _ptr(q), _ptr(stats), w.ptr, w.nbytes, _stream()),
+           "qmc_lattice_sum_shifts")
+    return q, stats
 
 
 def lattice_points(z, n: int, i0: int, count: int, device="cuda"):

@@ -25,6 +25,8 @@ Workloads (k = 0..4):
                          {exp-sum, product-peak, Gaussian} with the parameter laws above
   4 adjoint_d50_osc      d=50, n=16777213, one a shared by 64 oscillatory sets,
                          u ~ U[0,1], c ~ U[0,2]
+  5 shifts_d20_peak      the plain_d20_peak problem (its own seed) with R = 64
+                         shifts Delta_r ~ U[0,1)^20 (random-shift ensemble)
 """
 from __future__ import annotations
 
@@ -115,6 +117,18 @@ class Batch:
 
 
 @dataclass
+class ShiftEnsemble:
+    """A plain problem evaluated on R shifted copies of its lattice."""
+    name: str
+    d: int
+    n: int
+    a: int
+    family: int
+    params: np.ndarray
+    shifts: np.ndarray  # [R, d]
+
+
+@dataclass
 class AdjointSets:
     name: str
     d: int
@@ -173,6 +187,19 @@ def adjoint_d50_osc(nsets: int = 64) -> AdjointSets:
     c = 2.0 * r[:, :d]
     u = r[:, d:]
     return AdjointSets("adjoint_d50_osc", d, n, a, OSCILLATORY, np.concatenate([u, c], axis=1))
+
+
+def shifts_d20_peak(nshifts: int = 64) -> ShiftEnsemble:
+    """Shift r does not depend on nshifts (row r of one draw)."""
+    base = plain_d20_peak()
+    rng = np.random.default_rng(SEED_BASE + 5)
+    shifts = rng.random((nshifts, base.d))
+    return ShiftEnsemble("shifts_d20_peak", base.d, base.n, base.a, base.family, base.params, shifts)
+
+
+def random_shifts(seed: int, nshifts: int, d: int) -> np.ndarray:
+    """R uniform shifts in [0,1)^d for a small test case."""
+    return np.random.default_rng(seed).random((nshifts, d))
 
 
 def random_plain(seed: int, family: int, d: int, n: int, shift: bool = False) -> Plain:

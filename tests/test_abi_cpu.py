@@ -86,6 +86,14 @@ def test_invalid_arguments_fail_before_launch():
                              None) == qmc.ERR_WORKSPACE
     assert L.qmc_lattice_sum(4, 100, fake, None, 0, fake, 1, 0, fake, ws, 16, None) == qmc.ERR_WORKSPACE
     assert b"needed" in L.qmc_last_error()
+    # shift ensembles: R out of range, null shifts or params, short workspace
+    big = 1 << 23
+    assert L.qmc_lattice_sum_shifts(4, 100, fake, fake, 0, 0, fake, 0, fake, None, ws, big, None) == qmc.ERR_INVALID_ARG
+    assert L.qmc_lattice_sum_shifts(4, 100, fake, fake, 4097, 0, fake, 0, fake, None, ws, big,
+                                    None) == qmc.ERR_INVALID_ARG
+    assert L.qmc_lattice_sum_shifts(4, 100, fake, None, 3, 0, fake, 0, fake, fake, ws, big, None) == qmc.ERR_INVALID_ARG
+    assert L.qmc_lattice_sum_shifts(4, 100, fake, fake, 3, 0, None, 0, fake, fake, ws, big, None) == qmc.ERR_INVALID_ARG
+    assert L.qmc_lattice_sum_shifts(4, 100, fake, fake, 3, 0, fake, 0, fake, fake, ws, 16, None) == qmc.ERR_WORKSPACE
     # MDI-LR and the index export
     assert L.qmc_mdi_lr(0, fake, 0, fake, 1, 0, fake, None, 0, None) == qmc.ERR_INVALID_ARG
     assert L.qmc_mdi_lr(4, None, 0, fake, 1, 0, fake, None, 0, None) == qmc.ERR_INVALID_ARG

@@ -1,0 +1,102 @@
+"""Parity of the randomly shifted rule (qmc_lattice_sum_shifts) with the FP64 oracle.
+
+Tolerances as for the plain rule: each Q_r within 1e-12 (QMC_FP64) or 1e-6
+(QMC_FP32_COMPENSATED) of the oracle relative to max(|Q_r|, A_r), A_r the oracle's
+mean |f| on that shifted lattice.  The mean and the standard error get the same
+bound against the oracle's, scaled by the largest A_r; and, independently of the
+precision of the sums, they must equal the mean and standard error of the GPU's own
+Q_r (recomputed here in FP64) to rounding.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2404_08867_amd import qmc
+from paper_2404_08867_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+TOL = {qmc.FP64: 1e-12, qmc.FP32_COMPENSATED: 1e-6}
+PRECS = [qmc.FP64, qmc.FP32_COMPENSATED]
+
+
+def _host_stats(q):
+    q = np.asarray(q, dtype=np.float64)
+    R = q.size
+    mean = math.fsum(q) / R
+    se = math.sqrt(math.fsum((q - mean) ** 2) / (R * (R - 1))) if R > 1 else 0.0
+    return mean, se
+
+
+def _check_stats_against_own_q(q, stats):
+    mean, se = _host_stats(q)
+    scale = max(np.max(np.abs(q)), 1e-300)
+    assert abs(stats[0] - mean) <= 1e-14 * scale
+    assert abs(stats[1] - se) <= 1e-12 * max(se, 1e-14 * scale)
+
+
+# (d, n, R): several tiles with a ragged tail, two direction chunks (d > 64),
+# one shift, one direction, R above one wave.
+CASES = [(3, 10007, 5), (20, 4099, 17), (65, 3001, 3), (1, 997, 70), (8, 1009, 1)]
+
+
+@pytest.mark.parametrize("precision", PRECS)
+@pytest.mark.parametrize("family", [0, 1, 2, 3])
+@pytest.mark.parametrize("d,n,R", CASES)
+def test_shift_ensemble_matches_oracle(precision, family, d, n, R):
+    prob = W.random_plain(7000 + 31 * d + n + family, family, d, n)
+    shifts = W.random_shifts(900 + d + R, R, d)
+    z = O.korobov(d, n, prob.a)
+    qo, mo, seo = O.shift_ensemble(z, n, family, prob.params, shifts)
+    ao = np.array([O.lattice_sum(z, n, family, prob.params, shifts[r])[1] for r in range(R)])
+    q, stats = qmc.lattice_sum_shifts(qmc.korobov(d, n, prob.a), n, family, prob.params, shifts,
+                                      precision)
+    q = q.cpu().numpy()
+    stats = stats.cpu().numpy()
+    for r in range(R):
+        assert abs(q[r] - qo[r]) <= TOL[precision] * max(abs(qo[r]), ao[r]), (r, q[r], qo[r])
+    scale = float(np.max(ao))
+    assert abs(stats[0] - mo) <= TOL[precision] * scale
+    assert abs(stats[1] - seo) <= 2 * TOL[precision] * scale
+    _check_stats_against_own_q(q, stats)
+
+
+@pytest.mark.parametrize("precision", PRECS)
+@pytest.mark.parametrize("family", [0, 1, 3])
+def test_single_shift_equals_shifted_plain_sum(precision, family):
+    d, n = 12, 65537
+    prob = W.random_plain(4242 + family, family, d, n, shift=True)
+    z = qmc.korobov(d, n, prob.a)
+    q1, stats = qmc.lattice_sum_shifts(z, n, family, prob.params, prob.shift[None, :], precision)
+    q2 = qmc.lattice_sum(z, n, family, prob.params, precision, shift=prob.shift)
+    assert float(q1[0].item()) == float(q2.item())  # same kernel, same fixed order
+    st = stats.cpu().numpy()
+    assert st[0] == float(q2.item()) and st[1] == 0.0
+
+
+@pytest.mark.parametrize("precision", PRECS)
+def test_shifts_d20_peak_full_size(precision):
+    """The benchmark's workload (n = 1048573, R = 64): sampled shifts against the
+    oracle, the statistics against the GPU's own values, the spread across shifts
+    against the oracle's."""
+    w = W.shifts_d20_peak()
+    z = qmc.korobov(w.d, w.n, w.a)
+    q, stats = qmc.lattice_sum_shifts(z, w.n, w.family, w.params, w.shifts, precision)
+    q = q.cpu().numpy()
+    stats = stats.cpu().numpy()
+    zo = O.korobov(w.d, w.n, w.a)
+    for r in (0, 37, 63):
+        qo, ao = O.lattice_sum(zo, w.n, w.family, w.params, w.shifts[r])
+        assert abs(q[r] - qo) <= TOL[precision] * max(abs(qo), ao), (r, q[r], qo)
+    _check_stats_against_own_q(q, stats)
+    assert stats[1] > 0 and np.all(np.isfinite(q))
+
+
+def test_shift_ensemble_rejects_bad_shapes():
+    z = qmc.korobov(3, 101, 7)
+    with pytest.raises(qmc.QmcError):
+        qmc.lattice_sum_shifts(z, 101, 0, [1.0, 1.0, 1.0], np.zeros((2, 4)))
+    with pytest.raises(qmc.QmcError):
+        qmc.lattice_sum_shifts(z, 101, 0, [1.0, 1.0, 1.0], np.zeros((4097, 3)))
