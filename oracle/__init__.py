@@ -55,6 +55,13 @@ def _load():
     lib.oracle_lattice_partial.argtypes = [i32, i64, dp, dp, i32, dp, i64, i64, dp]
     lib.oracle_lattice_grad.argtypes = [i32, i64, dp, dp, i32, dp, dp, dp]
     lib.oracle_shift_ensemble.argtypes = [i32, i64, dp, i32, dp, dp, i32, dp, dp, dp]
+    lib.oracle_bernoulli.argtypes = [i32, ctypes.c_double]
+    lib.oracle_bernoulli.restype = ctypes.c_double
+    lib.oracle_lattice_kernel_sum.argtypes = [i32, i64, dp, i32, dp, dp, dp]
+    lib.oracle_p_alpha.argtypes = [i32, i64, dp, i32, dp]
+    lib.oracle_shift_avg_wce2.argtypes = [i32, i64, dp, dp, ctypes.c_double, dp]
+    lib.oracle_korobov_search.argtypes = [i32, i64, i32, i64, i64, dp, dp]
+    lib.oracle_cbc.argtypes = [i32, i64, dp, ctypes.c_double, dp, dp]
     lib.oracle_mdi_dims.argtypes = [i32, dp, i64, dp]
     lib.oracle_mdi_lr_brute.argtypes = [i32, dp, i32, dp, dp]
     lib.oracle_mdi_lr_sweep.argtypes = [i32, dp, i32, dp, dp]
@@ -152,6 +159,58 @@ def shift_ensemble(z, n: int, family: int, params, shifts):
     _check(_load().oracle_shift_ensemble(z.size, n, _ptr(z), family, _ptr(params), _ptr(shifts), R,
                                          _ptr(q), _ptr(mean), _ptr(se)), "shift_ensemble")
     return q, float(mean[0]), float(se[0])
+
+
+def bernoulli(alpha: int, x: float) -> float:
+    """Bernoulli polynomial B_alpha(x), alpha in {2, 4}."""
+    return float(_load().oracle_bernoulli(alpha, float(x)))
+
+
+def lattice_kernel_sum(z, n: int, alpha: int, a):
+    """(S, A): S = (1/n) sum_k [prod_j (1 + a_j B_alpha({k z_j/n})) - 1], A its mean |term|."""
+    z = _i64(z)
+    a = _f64(a)
+    out = np.zeros(2)
+    _check(_load().oracle_lattice_kernel_sum(z.size, n, _ptr(z), alpha, _ptr(a), _ptr(out[0:]),
+                                             _ptr(out[1:])), "lattice_kernel_sum")
+    return float(out[0]), float(out[1])
+
+
+def p_alpha(z, n: int, alpha: int) -> float:
+    """P_alpha(z) by eq. 2.4."""
+    z = _i64(z)
+    out = np.zeros(1)
+    _check(_load().oracle_p_alpha(z.size, n, _ptr(z), alpha, _ptr(out)), "p_alpha")
+    return float(out[0])
+
+
+def shift_avg_wce2(z, n: int, gamma, beta: float) -> float:
+    """Squared shift-averaged worst-case error by eq. 2.12 (product weights)."""
+    z = _i64(z)
+    gamma = _f64(gamma)
+    out = np.zeros(1)
+    _check(_load().oracle_shift_avg_wce2(z.size, n, _ptr(z), _ptr(gamma), float(beta), _ptr(out)),
+           "shift_avg_wce2")
+    return float(out[0])
+
+
+def korobov_search(d: int, n: int, alpha: int, a0: int = 1, count: int | None = None):
+    """P_alpha(z(a)) for a = a0 .. a0+count-1 and the best a (first minimum)."""
+    count = n - a0 if count is None else count
+    vals = np.zeros(count)
+    best = np.zeros(1, dtype=np.int64)
+    _check(_load().oracle_korobov_search(d, n, alpha, a0, count, _ptr(vals), _ptr(best)),
+           "korobov_search")
+    return vals, int(best[0])
+
+
+def cbc(d: int, n: int, gamma, beta: float):
+    """CBC generating vector (z[d]) and the criterion after each component (e2[d])."""
+    gamma = _f64(gamma)
+    z = np.zeros(d, dtype=np.int64)
+    e2 = np.zeros(d)
+    _check(_load().oracle_cbc(d, n, _ptr(gamma), float(beta), _ptr(z), _ptr(e2)), "cbc")
+    return z, e2
 
 
 def mdi_dims(z, n: int) -> np.ndarray:

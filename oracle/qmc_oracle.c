@@ -316,6 +316,179 @@ int oracle_shift_ensemble(int d, int64_t n, const int64_t* z, int family, const 
 }
 
 /* ------------------------------------------------------------------------- */
+/* Lattice-quality criteria (Sec. 2.1, eq. 2.4 and eq. 2.12) and the two      */
+/* constructions built on them (Sec. 2.2: Korobov search, CBC lattice).        */
+/* ------------------------------------------------------------------------- */
+
+static int64_t gcd64(int64_t a, int64_t b);
+
+/* Bernoulli polynomials on [0,1] in their polynomial form; the paper defines
+ * B_alpha by its Fourier series (Sec. 2.1), which the tests compare against. */
+double oracle_bernoulli(int alpha, double x) {
+    if (alpha == 2) return x * x - x + 1.0 / 6.0;
+    if (alpha == 4) return x * x * x * x - 2.0 * x * x * x + x * x - 1.0 / 30.0;
+    return NAN;
+}
+
+/* zeta(alpha) for the even orders used here. */
+static double zeta_even(int alpha) {
+    if (alpha == 2) return OR_PI * OR_PI / 6.0;
+    return OR_PI * OR_PI * OR_PI * OR_PI / 90.0;
+}
+
+/* (-1)^{alpha/2 + 1} (2 pi)^alpha / alpha!, the factor in front of B_alpha in eq. 2.4. */
+static double p_alpha_coeff(int alpha) {
+    double f = 1.0;
+    for (int i = 2; i <= alpha; ++i) f *= (double)i;
+    return ((alpha / 2) % 2 == 1 ? 1.0 : -1.0) * pow(2.0 * OR_PI, (double)alpha) / f;
+}
+
+/* The fractional part {k z / n} by exact integer arithmetic. */
+static double frac_kz(int64_t k, int64_t z, int64_t n) { return (double)((k * z) % n) / (double)n; }
+
+/* Generic product-form lattice sum of the criteria:
+ *   S = (1/n) sum_{k=0}^{n-1} [ prod_j (1 + a_j B_alpha({k z_j / n})) - 1 ].
+ * Also returns A = (1/n) sum_k |prod_j (...) - 1|, the scale of this mixed-sign sum. */
+int oracle_lattice_kernel_sum(int d, int64_t n, const int64_t* z, int alpha, const double* a,
+                              double* s_out, double* abs_out) {
+    if (check_lattice_args(d, n, z, NULL) != OR_OK || (alpha != 2 && alpha != 4) || !a)
+        return OR_BAD_ARG;
+    neu_t acc = {0.0, 0.0}, aacc = {0.0, 0.0};
+    for (int64_t k = 0; k < n; ++k) {
+        double prod = 1.0;
+        for (int j = 0; j < d; ++j) prod *= 1.0 + a[j] * oracle_bernoulli(alpha, frac_kz(k, z[j], n));
+        neu_add(&acc, prod - 1.0);
+        neu_add(&aacc, fabs(prod - 1.0));
+    }
+    *s_out = neu_value(&acc) / (double)n;
+    if (abs_out) *abs_out = neu_value(&aacc) / (double)n;
+    return OR_OK;
+}
+
+/* eq. 2.4, second line, term by term: the k = 0 term (1 + 2 zeta(alpha))^d / n
+ * separately, then the terms k = 1..n-1, then -1. */
+int oracle_p_alpha(int d, int64_t n, const int64_t* z, int alpha, double* p_out) {
+    if (check_lattice_args(d, n, z, NULL) != OR_OK || (alpha != 2 && alpha != 4)) return OR_BAD_ARG;
+    const double c = p_alpha_coeff(alpha);
+    neu_t acc = {0.0, 0.0};
+    neu_add(&acc, -1.0);
+    neu_add(&acc, pow(1.0 + 2.0 * zeta_even(alpha), (double)d) / (double)n);
+    for (int64_t k = 1; k < n; ++k) {
+        double prod = 1.0;
+        for (int j = 0; j < d; ++j) prod *= 1.0 + c * oracle_bernoulli(alpha, frac_kz(k, z[j], n));
+        neu_add(&acc, prod / (double)n);
+    }
+    *p_out = neu_value(&acc);
+    return OR_OK;
+}
+
+/* eq. 2.12, second line (product weights gamma_nu = prod_{j in nu} gamma_j):
+ *   e^2 = -prod_j (1 + gamma_j beta)
+ *         + (1/n) sum_{k=0}^{n-1} prod_j (1 + gamma_j [B_2({k z_j / n}) + beta]),
+ * beta = c^2 - c + 1/3 (anchored Sobolev space, anchor c) or 0 (unanchored). */
+int oracle_shift_avg_wce2(int d, int64_t n, const int64_t* z, const double* gamma, double beta,
+                          double* e2_out) {
+    if (check_lattice_args(d, n, z, NULL) != OR_OK || !gamma) return OR_BAD_ARG;
+    double c0 = 1.0;
+    for (int j = 0; j < d; ++j) c0 *= 1.0 + gamma[j] * beta;
+    neu_t acc = {0.0, 0.0};
+    neu_add(&acc, -c0);
+    for (int64_t k = 0; k < n; ++k) {
+        double prod = 1.0;
+        for (int j = 0; j < d; ++j)
+            prod *= 1.0 + gamma[j] * (oracle_bernoulli(2, frac_kz(k, z[j], n)) + beta);
+        neu_add(&acc, prod / (double)n);
+    }
+    *e2_out = neu_value(&acc);
+    return OR_OK;
+}
+
+/* Candidates whose criteria agree to this relative tolerance count as tied:
+ * mathematically equal criteria (a and n - a, or in two dimensions z and its
+ * inverse mod n) come out of FP64 sums that differ in their last bits. */
+#define OR_TIE_REL 1e-10
+
+/* Index of the first value within OR_TIE_REL of the minimum of v[0..m), or -1. */
+static int64_t first_near_min(const double* v, int64_t m) {
+    double lo = INFINITY;
+    for (int64_t i = 0; i < m; ++i)
+        if (v[i] < lo) lo = v[i];
+    if (!(lo < INFINITY)) return -1;
+    for (int64_t i = 0; i < m; ++i)
+        if (v[i] <= lo + OR_TIE_REL * fabs(lo)) return i;
+    return -1;
+}
+
+/* Korobov search (Sec. 2.2): P_alpha(z(a)) for a = a0 .. a0 + count - 1, and the
+ * smallest a whose value is within OR_TIE_REL of the smallest value.  Candidates
+ * with gcd(a, n) != 1 are not generating vectors of the Korobov example; their
+ * value is reported as +infinity and never chosen. */
+int oracle_korobov_search(int d, int64_t n, int alpha, int64_t a0, int64_t count, double* p_out,
+                          int64_t* best_a) {
+    if (d < 1 || n < 2 || a0 < 1 || count < 1 || a0 + count > n || !p_out) return OR_BAD_ARG;
+    int64_t* z = (int64_t*)malloc(sizeof(int64_t) * (size_t)d);
+    if (!z) return OR_TOO_BIG;
+    for (int64_t i = 0; i < count; ++i) {
+        const int64_t a = a0 + i;
+        if (gcd64(a, n) != 1) {
+            p_out[i] = INFINITY;
+            continue;
+        }
+        oracle_korobov(d, n, a, z);
+        int rc = oracle_p_alpha(d, n, z, alpha, &p_out[i]);
+        if (rc != OR_OK) {
+            free(z);
+            return rc;
+        }
+    }
+    free(z);
+    const int64_t i = first_near_min(p_out, count);
+    if (best_a) *best_a = i < 0 ? -1 : a0 + i;
+    return OR_OK;
+}
+
+/* CBC construction (Sec. 2.2, CBC-lattice example) with product weights:
+ * z_1 = 1; for j = 2..d, with z_1..z_{j-1} fixed, z_j is the z in
+ * N_n = {1 <= z <= n-1 : gcd(z, n) = 1} that minimises the j-dimensional e^2 of
+ * eq. 2.12.  B_2(1 - x) = B_2(x) makes the criterion of z and n - z equal, so
+ * the search takes the representatives z <= n/2.
+ * Among candidates within OR_TIE_REL of the smallest criterion the smallest z is
+ * taken.  e2_out[j-1] is the criterion of the chosen (z_1..z_j).  Every candidate
+ * is evaluated by oracle_shift_avg_wce2. */
+int oracle_cbc(int d, int64_t n, const double* gamma, double beta, int64_t* z_out, double* e2_out) {
+    if (d < 1 || n < 2 || !gamma || !z_out) return OR_BAD_ARG;
+    z_out[0] = 1;
+    if (e2_out) {
+        int rc = oracle_shift_avg_wce2(1, n, z_out, gamma, beta, &e2_out[0]);
+        if (rc != OR_OK) return rc;
+    }
+    const int64_t half = n / 2;
+    double* vals = (double*)malloc(sizeof(double) * (size_t)half);
+    if (!vals) return OR_TOO_BIG;
+    for (int j = 1; j < d; ++j) {
+        for (int64_t c = 1; c <= half; ++c) {
+            vals[c - 1] = INFINITY;
+            if (gcd64(c, n) != 1) continue;
+            z_out[j] = c;
+            int rc = oracle_shift_avg_wce2(j + 1, n, z_out, gamma, beta, &vals[c - 1]);
+            if (rc != OR_OK) {
+                free(vals);
+                return rc;
+            }
+        }
+        const int64_t i = first_near_min(vals, half);
+        if (i < 0) {
+            free(vals);
+            return OR_BAD_ARG;
+        }
+        z_out[j] = i + 1;
+        if (e2_out) e2_out[j] = vals[i];
+    }
+    free(vals);
+    return OR_OK;
+}
+
+/* ------------------------------------------------------------------------- */
 /* Per-direction node counts of the transformed grid (eq. 3.5):              */
 /*   n_i = lcm(z_i, z_{i+1}) / min(z_i, z_{i+1}),  i < d;   n_d = ceil(n / z_d). */
 /* ------------------------------------------------------------------------- */
