@@ -27,6 +27,8 @@ import statistics
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
@@ -80,6 +82,17 @@ def work_per_point_adjoint(d: int, family: int) -> int:
 # accumulation.
 WORK_PER_MDI_FACTOR = 3 * C32 + CT + ACCUM
 
+# Lattice-quality criteria (FP64): per point and direction the index step, the
+# conversion, x = k/n, y = x (1 - x), the factor 1 + a B(x) and the product; per
+# point the "- 1" and the FP64 add.
+def work_per_point_criterion(d: int) -> int:
+    return d * (INDEX + 5 * C64) + 2 * C64
+
+
+# CBC candidate evaluation, per (candidate, k): the residue update (modular add),
+# the conversion, x, y, the factor, p(k) * factor - 1 and the FP64 add.
+WORK_PER_CBC_TERM = INDEX + 6 * C64
+
 
 def parse():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
@@ -88,7 +101,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--workload", default="plain_d20_peak",
                     choices=["plain_d20_peak", "plain_d4_expsum", "mdi_d100_gauss", "batched_4096",
-                             "adjoint_d50_osc", "shifts_d20_peak"])
+                             "adjoint_d50_osc", "shifts_d20_peak", "korobov_search_d20",
+                             "cbc_d20"])
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
                     help="wall-clock budget of the oracle's CPU-baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -283,6 +297,95 @@ def oracle_shifts_baseline(w, r32, r64, seconds):
     return w.n * k / dt, k, e32, e64
 
 
+def bench_search(args, torch, qmc, W):
+    """Korobov search: one step is the whole search over a in [1, (n-1)/2]."""
+    w = W.korobov_search_d20()
+    ws = qmc.Workspace(qmc.criteria_workspace_size(w.d, w.n))
+    holder = {}
+
+    a, c = qmc.wce2_weights(w.gamma, w.beta)
+
+    def launch():
+        holder["r"] = qmc.korobov_search(w.d, w.n, w.alpha, a=a, a0=w.a0, count=w.count, ws=ws)
+
+    step_s, kern_s = time_eager(torch, launch, args.steps, args.warmup)
+    vals, best = holder["r"]
+    r = dict(step_s=step_s, kern_s=kern_s, lat_s=step_s, q=c * vals.cpu().numpy(),
+             best=best.cpu().numpy())
+    units = w.count * w.n
+    config = {"workload": w.name, "d": w.d, "n": w.n,
+              "criterion": "e^2 (eq. 2.12), gamma_j = j^-2, beta = 0",
+              "candidates": w.count, "best_a": int(r["best"][1]), "best_e2": c * float(r["best"][0]),
+              "precision": "fp64", "unit_of_work": "one d-dimensional lattice point of one candidate"}
+    return w, {"fp32c": r, "fp64": r}, units, work_per_point_criterion(w.d), config
+
+
+def bench_cbc(args, torch, qmc, W):
+    """CBC: one step is the whole d-component construction."""
+    w = W.cbc_d20()
+    ws = qmc.Workspace(qmc.criteria_workspace_size(w.d, w.n))
+    holder = {}
+
+    def launch():
+        holder["r"] = qmc.cbc(w.d, w.n, w.gamma, w.beta, ws=ws)
+
+    step_s, kern_s = time_eager(torch, launch, args.steps, args.warmup)
+    z, e2 = holder["r"]
+    r = dict(step_s=step_s, kern_s=kern_s, lat_s=step_s, z=z.cpu().numpy(), q=e2.cpu().numpy())
+    units = (1 + (w.d - 1) * (w.n // 2)) * w.n  # (candidate, k) terms over all components
+    config = {"workload": w.name, "d": w.d, "n": w.n, "criterion": "e^2 (eq. 2.12), gamma_j = j^-2, beta = 0",
+              "z": [int(v) for v in r["z"]], "e2_final": float(r["q"][-1]), "precision": "fp64",
+              "unit_of_work": "one (candidate, lattice index) term"}
+    return w, {"fp32c": r, "fp64": r}, units, WORK_PER_CBC_TERM, config
+
+
+def _wce2_with_scale(O, z, w):
+    """Oracle e^2 and the scale C * A of its terms (A: mean |term| of the sum S)."""
+    g = np.asarray(w.gamma[: len(z)])
+    c = float(np.prod(1.0 + g * w.beta))
+    _, a_scale = O.lattice_kernel_sum(z, w.n, 2, g / (1.0 + g * w.beta))
+    return O.shift_avg_wce2(z, w.n, g, w.beta), c * a_scale
+
+
+def oracle_search_baseline(w, vals, seconds):
+    """The oracle's e^2 of the first candidates until the time budget is spent (the
+    rate counts the oracle's own evaluation); the error uses the mixed-sign measure."""
+    import oracle as O
+    t0 = time.perf_counter()
+    k = 0
+    for i in range(w.count):
+        O.shift_avg_wce2(O.korobov(w.d, w.n, w.a0 + i), w.n, w.gamma, w.beta)
+        k += 1
+        if time.perf_counter() - t0 > seconds:
+            break
+    dt = time.perf_counter() - t0
+    err = 0.0
+    for i in range(min(k, 64)):
+        eo, scale = _wce2_with_scale(O, O.korobov(w.d, w.n, w.a0 + i), w)
+        err = max(err, abs(vals[i] - eo) / max(abs(eo), scale))
+    return w.n * k / dt, k, err
+
+
+def oracle_cbc_baseline(w, res, seconds):
+    """The oracle's criterion for the first candidates of the second component, and
+    the relative error of every component's criterion at the GPU's choices."""
+    import oracle as O
+    z, e2 = res["z"], res["q"]
+    err = 0.0
+    for j in range(w.d):
+        eo, scale = _wce2_with_scale(O, z[: j + 1], w)
+        err = max(err, abs(e2[j] - eo) / max(abs(eo), scale))
+    t0 = time.perf_counter()
+    k = 0
+    for c in range(1, w.n // 2 + 1):
+        O.shift_avg_wce2([1, c], w.n, w.gamma[:2], w.beta)
+        k += 1
+        if time.perf_counter() - t0 > seconds:
+            break
+    dt = time.perf_counter() - t0
+    return w.n * k / dt, k, err
+
+
 def bench_mdi(args, torch, qmc, W):
     nsets = 65536
     w = W.mdi_d100_gauss(nsets=nsets)
@@ -432,6 +535,10 @@ def main():
         prob, res, units, wpp, config = bench_adjoint(args, torch, qmc, W)
     elif args.workload == "shifts_d20_peak":
         prob, res, units, wpp, config = bench_shifts(args, torch, qmc, W)
+    elif args.workload == "korobov_search_d20":
+        prob, res, units, wpp, config = bench_search(args, torch, qmc, W)
+    elif args.workload == "cbc_d20":
+        prob, res, units, wpp, config = bench_cbc(args, torch, qmc, W)
     else:
         prob, res, units, wpp, config = bench_plain(args, torch, qmc, W)
 
@@ -443,7 +550,9 @@ def main():
         "value": value,
         "unit": {"mdi_d100_gauss": "factor evals/s",
                  "adjoint_d50_osc": "point-set evals (value + gradient)/s",
-                 "shifts_d20_peak": "shifted-lattice point evals/s"}.get(
+                 "shifts_d20_peak": "shifted-lattice point evals/s",
+                 "korobov_search_d20": "candidate lattice-point evals/s",
+                 "cbc_d20": "candidate-index terms/s"}.get(
                      args.workload, "lattice-point evals/s"),
         "n_gpus": 1,
         "steps": args.steps,
@@ -452,7 +561,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": "f64" if args.workload in ("korobov_search_d20", "cbc_d20") else "f32",
         "data": "synthetic",
         "config": config,
         "roofline": {
@@ -478,6 +587,16 @@ def main():
         elif args.workload == "adjoint_d50_osc":
             rate, e32, e64 = oracle_adjoint_baseline(prob, res["fp32c"], res["fp64"])
             sample = "parameter set 0 of 64, all n points, value and 51 gradient components"
+        elif args.workload == "korobov_search_d20":
+            rate, k, e32 = oracle_search_baseline(prob, res["fp64"]["q"], args.cpu_seconds)
+            e64 = e32
+            sample = (f"e^2 of the first {k} of {prob.count} candidates (n={prob.n} points each); "
+                      f"rel_err over the first {min(k, 64)}")
+        elif args.workload == "cbc_d20":
+            rate, k, e32 = oracle_cbc_baseline(prob, res["fp64"], args.cpu_seconds)
+            e64 = e32
+            sample = (f"the criterion of the first {k} candidates of the second component "
+                      f"(n={prob.n} terms each); rel_err over the {prob.d} chosen components")
         elif args.workload == "shifts_d20_peak":
             rate, k, e32, e64 = oracle_shifts_baseline(prob, res["fp32c"], res["fp64"], args.cpu_seconds)
             sample = f"the first {k} of {prob.shifts.shape[0]} shifted lattices (n={prob.n} points each)"

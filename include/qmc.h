@@ -151,6 +151,57 @@ qmc_status qmc_lattice_sum_shifts(int32_t d, int64_t n, const int64_t* z, const 
                                   int32_t precision, double* q_out, double* stats_out, void* ws,
                                   size_t ws_bytes, void* stream);
 
+/* ---- lattice-quality criteria (Sec. 2.1) and constructions (Sec. 2.2) ----
+ *
+ * Both criteria of the paper are product-form lattice sums with Bernoulli factors,
+ *   S(z) = (1/n) sum_{k=0}^{n-1} [ prod_j (1 + a_j B_alpha({k z_j / n})) - 1 ],
+ * B_2(x) = x^2 - x + 1/6, B_4(x) = x^4 - 2x^3 + x^2 - 1/30 (alpha = 2 or 4):
+ *   P_alpha(z) of eq. 2.4 is S with a_j = (-1)^{alpha/2+1} (2 pi)^alpha / alpha! for
+ *   every j (2 pi^2 for alpha = 2, -2 pi^4 / 3 for alpha = 4);
+ *   the squared shift-averaged worst-case error of eq. 2.12 with product weights
+ *   gamma_j is prod_j (1 + gamma_j beta) * S with a_j = gamma_j / (1 + gamma_j beta)
+ *   (beta = c^2 - c + 1/3 for the anchored space with anchor c, 0 unanchored).
+ * Everything runs in FP64: criteria are small differences of O(1) terms.
+ * Candidates whose values agree to 1e-10 relative count as tied; the smallest
+ * candidate is chosen (the criteria of c and n - c are always equal).  Candidates
+ * with gcd(c, n) != 1 get +infinity.  Values beyond the FP64 range (products that
+ * overflow for large d and weights) come out as +-infinity or NaN. */
+
+/* Workspace bytes of qmc_bernoulli_sum, qmc_korobov_search and qmc_cbc at d, n. */
+qmc_status qmc_criteria_workspace_size(int32_t d, int64_t n, size_t* bytes);
+
+/* S for nz generating vectors (rows of z) in one launch.
+ *   z      device int64[nz][d], 0 <= z_j < n;  nz in [1, 4096];  n in [2, 2^31)
+ *   a      device double[d]
+ *   s_out  device double[nz]
+ *   ws     device workspace of qmc_workspace_size(d, n, nz) bytes */
+qmc_status qmc_bernoulli_sum(int32_t d, int64_t n, const int64_t* z, int32_t nz, int32_t alpha,
+                             const double* a, double* s_out, void* ws, size_t ws_bytes,
+                             void* stream);
+
+/* Korobov search (Sec. 2.2): S(z(a)) for the Korobov vectors
+ * z(a) = (1, a, ..., a^{d-1}) mod n of a = a0 .. a0 + count - 1 (1 <= a0,
+ * a0 + count <= n), and the best: best_out[0] = S, best_out[1] = a (as a double).
+ * The search is O(count * n * d) work; it is asynchronous like every launch.
+ *   s_out     device double[count]
+ *   best_out  device double[2]
+ *   ws        device workspace of qmc_criteria_workspace_size(d, n) bytes */
+qmc_status qmc_korobov_search(int32_t d, int64_t n, int32_t alpha, const double* a, int64_t a0,
+                              int32_t count, double* s_out, double* best_out, void* ws,
+                              size_t ws_bytes, void* stream);
+
+/* CBC construction (Sec. 2.2, CBC lattice; product weights): z_1 = 1, then for
+ * j = 2..d the z_j in {1 <= c <= n/2 : gcd(c, n) = 1} minimising S of (z_1..z_j)
+ * with weights a_1..a_j (which minimises e^2 of eq. 2.12 when a_j = gamma_j /
+ * (1 + gamma_j beta)).  s_out[j-1] is S of the chosen (z_1..z_j).  O(d n^2) work,
+ * 3 launches per component, all on `stream`.
+ *   n       in [2, 2^26]
+ *   z_out   device int64[d]
+ *   s_out   device double[d]
+ *   ws      device workspace of qmc_criteria_workspace_size(d, n) bytes */
+qmc_status qmc_cbc(int32_t d, int64_t n, int32_t alpha, const double* a, int64_t* z_out,
+                   double* s_out, void* ws, size_t ws_bytes, void* stream);
+
 /* Launch configuration of the plain-sum kernel.  Zero fields mean "choose
  * automatically".  points_per_thread must be 0, 4, 8 or 16 (the tile is
  * 1024 * points_per_thread consecutive points); max_blocks caps the persistent

@@ -28,11 +28,11 @@ DEVICE_FLAGS = [
 
 
 # Per-source additions.  The plain-sum kernels take scalar arguments, the
-# prologue's nine first: preloaded into scalar registers at wave start (gfx950
+# prologue's ten first: preloaded into scalar registers at wave start (gfx950
 # supports kernel-argument preloading; the code object keeps a fallback
 # prologue that loads them for firmware without it).
 SOURCE_FLAGS = {
-    "lattice_sum.hip": ["-mllvm", "-amdgpu-kernarg-preload-count=9"],
+    "lattice_sum.hip": ["-mllvm", "-amdgpu-kernarg-preload-count=10"],
 }
 
 

@@ -49,6 +49,7 @@ constexpr int kMaxSets = qmc::kMaxSumSets;  // plain sums: one grid row and 33 c
 constexpr int kMaxMdiSets = 1 << 24;     // MDI-LR: sets are spread over workgroups
 constexpr int64_t kMaxNodes = (int64_t)1 << 20;
 constexpr int64_t kMaxExport = (int64_t)1 << 26;
+constexpr int64_t kMaxCbcN = (int64_t)1 << 26;   // CBC keeps n + n/2 doubles
 
 int param_count(int family, int d) {
     switch (family) {
@@ -265,6 +266,7 @@ qmc_status qmc_lattice_sum_ex(int32_t d, int64_t n, const int64_t* z, const doub
     L.nsets = nsets;
     L.param_stride = L.P;
     L.shift_stride = 0;
+    L.z_stride = 0;
     L.fp32 = precision == QMC_FP32_COMPENSATED;
     L.q_out = q_out;
     L.ws = ws;
@@ -305,12 +307,69 @@ qmc_status qmc_lattice_sum_shifts(int32_t d, int64_t n, const int64_t* z, const 
     L.nsets = nshifts;
     L.param_stride = 0;
     L.shift_stride = d;
+    L.z_stride = 0;
     L.fp32 = precision == QMC_FP32_COMPENSATED;
     L.q_out = q_out;
     L.ws = ws;
     hipError_t e = qmc::launch_lattice_sum(L, (hipStream_t)stream);
     if (e == hipSuccess && stats_out) e = qmc::launch_shift_stats(q_out, nshifts, stats_out, (hipStream_t)stream);
     return from_hip(e, "qmc_lattice_sum_shifts");
+}
+
+qmc_status qmc_criteria_workspace_size(int32_t d, int64_t n, size_t* bytes) {
+    if (d < 1 || d > kMaxD) return fail(QMC_ERR_INVALID_ARG, "d = %d outside [1, %d]", d, kMaxD);
+    if (n < 2 || n >= kMaxN) return fail(QMC_ERR_INVALID_ARG, "n = %lld outside [2, 2^31)", (long long)n);
+    if (!bytes) return fail(QMC_ERR_INVALID_ARG, "bytes must be non-NULL");
+    *bytes = qmc::criteria_workspace_bytes(d, n);
+    return ok();
+}
+
+static qmc_status check_criteria(int32_t d, int64_t n, int32_t alpha, const double* a) {
+    if (d < 1 || d > kMaxD) return fail(QMC_ERR_INVALID_ARG, "d = %d outside [1, %d]", d, kMaxD);
+    if (n < 2 || n >= kMaxN) return fail(QMC_ERR_INVALID_ARG, "n = %lld outside [2, 2^31)", (long long)n);
+    if (alpha != 2 && alpha != 4) return fail(QMC_ERR_INVALID_ARG, "alpha = %d is not 2 or 4", alpha);
+    if (!a) return fail(QMC_ERR_INVALID_ARG, "a must be non-NULL");
+    return QMC_OK;
+}
+
+qmc_status qmc_bernoulli_sum(int32_t d, int64_t n, const int64_t* z, int32_t nz, int32_t alpha,
+                             const double* a, double* s_out, void* ws, size_t ws_bytes,
+                             void* stream) {
+    qmc_status s = check_criteria(d, n, alpha, a);
+    if (s != QMC_OK) return s;
+    if (nz < 1 || nz > kMaxSets) return fail(QMC_ERR_INVALID_ARG, "nz = %d outside [1, %d]", nz, kMaxSets);
+    if (!z || !s_out) return fail(QMC_ERR_INVALID_ARG, "z and s_out must be non-NULL");
+    s = check_workspace(ws, ws_bytes, qmc::plain_workspace_bytes(nz));
+    if (s != QMC_OK) return s;
+    qmc::BernoulliLaunch L{d, (uint32_t)n, z, nz, alpha, a, s_out, ws};
+    return from_hip(qmc::launch_bernoulli_sum(L, (hipStream_t)stream), "qmc_bernoulli_sum");
+}
+
+qmc_status qmc_korobov_search(int32_t d, int64_t n, int32_t alpha, const double* a, int64_t a0,
+                              int32_t count, double* s_out, double* best_out, void* ws,
+                              size_t ws_bytes, void* stream) {
+    qmc_status s = check_criteria(d, n, alpha, a);
+    if (s != QMC_OK) return s;
+    if (a0 < 1 || count < 1 || a0 + (int64_t)count > n)
+        return fail(QMC_ERR_INVALID_ARG, "candidates [%lld, %lld) outside [1, n)", (long long)a0,
+                    (long long)(a0 + count));
+    if (!s_out || !best_out) return fail(QMC_ERR_INVALID_ARG, "s_out and best_out must be non-NULL");
+    s = check_workspace(ws, ws_bytes, qmc::criteria_workspace_bytes(d, n));
+    if (s != QMC_OK) return s;
+    qmc::SearchLaunch L{d, (uint32_t)n, alpha, a, a0, count, s_out, best_out, ws};
+    return from_hip(qmc::launch_korobov_search(L, (hipStream_t)stream), "qmc_korobov_search");
+}
+
+qmc_status qmc_cbc(int32_t d, int64_t n, int32_t alpha, const double* a, int64_t* z_out,
+                   double* s_out, void* ws, size_t ws_bytes, void* stream) {
+    qmc_status s = check_criteria(d, n, alpha, a);
+    if (s != QMC_OK) return s;
+    if (n > kMaxCbcN) return fail(QMC_ERR_INVALID_ARG, "n = %lld above the CBC limit 2^26", (long long)n);
+    if (!z_out || !s_out) return fail(QMC_ERR_INVALID_ARG, "z_out and s_out must be non-NULL");
+    s = check_workspace(ws, ws_bytes, qmc::criteria_workspace_bytes(d, n));
+    if (s != QMC_OK) return s;
+    qmc::CbcLaunch L{d, (uint32_t)n, alpha, a, z_out, s_out, ws};
+    return from_hip(qmc::launch_cbc(L, (hipStream_t)stream), "qmc_cbc");
 }
 
 qmc_status qmc_lattice_points(int32_t d, int64_t n, const int64_t* z, int64_t i0, int64_t count,

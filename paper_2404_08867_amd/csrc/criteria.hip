@@ -1,0 +1,269 @@
+// Lattice-quality criteria and the constructions built on them (Sec. 2.1, eq. 2.4
+// and eq. 2.12; Sec. 2.2: the Korobov search and the CBC lattice).
+//
+// All of them reduce to the product-form Bernoulli sum
+//   S(z) = (1/n) sum_{k=0}^{n-1} [ prod_j (1 + a_j B_alpha({k z_j / n})) - 1 ],
+// evaluated by the plain-sum kernel (family BernoulliProduct) for whole generating
+// vectors, and by cbc_eval_kernel for the one-component-at-a-time search of CBC.
+//
+// Selection among candidates is deterministic: non-candidates (gcd(c, n) != 1) get
+// +infinity; among the candidates whose S is within kTieRel of the smallest, the
+// smallest candidate wins (the criteria of c and n - c are equal, and FP64 sums of
+// equal criteria differ in their last bits).
+#include "common.hpp"
+#include "families.hpp"
+#include "kernels.hpp"
+
+namespace qmc {
+
+constexpr double kTieRel = 1e-10;
+
+__device__ __forceinline__ uint32_t gcd_u32(uint32_t a, uint32_t b) {
+    while (b) {
+        const uint32_t t = a % b;
+        a = b;
+        b = t;
+    }
+    return a;
+}
+
+// --------------------------------------------------------------------------
+// Korobov generating vectors z(a) = (1, a, a^2, ..., a^{d-1}) mod n (Sec. 2.2) for
+// a = a0 + i, i < count: one thread per candidate, row i of the table.
+// --------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void korobov_table_kernel(int d, uint32_t n, double inv_n,
+                                                           int64_t a0, int count, int64_t* z) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= count) return;
+    const uint64_t a = (uint64_t)(a0 + i) % n;
+    int64_t* row = z + (size_t)i * d;
+    uint64_t v = 1 % n;
+    for (int j = 0; j < d; ++j) {
+        row[j] = (int64_t)v;
+        v = mulmod(v, a, n, inv_n);
+    }
+}
+
+// --------------------------------------------------------------------------
+// Selection over v[0..count) for candidates c = c_first + i.  One workgroup.
+// Writes +infinity over the non-candidates in v, then
+//   *best_value = v[i*],  *best_cand_f64 = c_first + i*  (if not null),
+//   *best_cand_i64 = c_first + i*                        (if not null),
+// i* the smallest index within kTieRel of the minimum (i* = 0 and +infinity when
+// no candidate is coprime to n).
+// --------------------------------------------------------------------------
+constexpr int kSelectBlock = 1024;
+
+__global__ __launch_bounds__(kSelectBlock) void select_kernel(double* v, int count, int64_t c_first,
+                                                             uint32_t n, double* best_value,
+                                                             double* best_cand_f64,
+                                                             int64_t* best_cand_i64) {
+    __shared__ double s_min[kSelectBlock / kWave];
+    __shared__ int s_idx[kSelectBlock / kWave];
+    const int tid = threadIdx.x, lane = tid & (kWave - 1), wv = tid / kWave;
+    constexpr int W = kSelectBlock / kWave;
+
+    // Pass 1: filter and minimum (a minimum is exact, so its order does not matter).
+    double m = INFINITY;
+    for (int i = tid; i < count; i += kSelectBlock) {
+        double x = v[i];
+        if (gcd_u32((uint32_t)((c_first + i) % n), n) != 1) {
+            x = INFINITY;
+            v[i] = x;  // the same thread reads v[i] again in pass 2
+        }
+        m = fmin(m, x);
+    }
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) m = fmin(m, __shfl_xor(m, off, kWave));
+    if (lane == 0) s_min[wv] = m;
+    __syncthreads();
+    m = s_min[0];
+#pragma unroll
+    for (int w = 1; w < W; ++w) m = fmin(m, s_min[w]);
+    const double thr = m + kTieRel * fabs(m);
+
+    // Pass 2: the smallest index within the tolerance.
+    int first = count;
+    for (int i = tid; i < count; i += kSelectBlock) {
+        if (v[i] <= thr) {
+            first = i;
+            break;
+        }
+    }
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) first = min(first, __shfl_xor(first, off, kWave));
+    if (lane == 0) s_idx[wv] = first;
+    __syncthreads();
+    if (tid == 0) {
+        int f = s_idx[0];
+        for (int w = 1; w < W; ++w) f = min(f, s_idx[w]);
+        if (f >= count) f = 0;
+        *best_value = v[f];
+        if (best_cand_f64) *best_cand_f64 = (double)(c_first + f);
+        if (best_cand_i64) *best_cand_i64 = c_first + f;
+    }
+}
+
+// --------------------------------------------------------------------------
+// CBC (Sec. 2.2): with the running product p(k) = prod_{i<j} (1 + a_i B({k z_i/n}))
+// in memory, the criterion of candidate c for component j is
+//   S_j(c) = (1/n) sum_k [ p(k) (1 + a_j B_alpha({k c / n})) - 1 ].
+// A workgroup owns kCbcCand consecutive candidates and sweeps all k in chunks of
+// kCbcBlock * kCbcM: each thread keeps kCbcM values of p and of k in registers and,
+// from one candidate to the next, advances its residues k c mod n by k (one modular
+// add).  Per candidate and chunk each wave adds its wave total to an LDS slot, in
+// chunk order, so the result is reproducible.
+// --------------------------------------------------------------------------
+constexpr int kCbcBlock = 1024;
+constexpr int kCbcM = 16;
+constexpr int kCbcCand = 64;
+
+template <int ALPHA>
+__global__ __launch_bounds__(kCbcBlock) void cbc_eval_kernel(uint32_t n, double inv_n,
+                                                            const double* a, int j,
+                                                            const double* p, int64_t c_first,
+                                                            int ncand, double* s_cand) {
+    constexpr int W = kCbcBlock / kWave;
+    __shared__ double s_acc[kCbcCand * W];
+    const int tid = threadIdx.x, lane = tid & (kWave - 1), wv = tid / kWave;
+    const int g0 = blockIdx.x * kCbcCand;
+    const int gc = min(kCbcCand, ncand - g0);
+    const double aj = a[j];
+    const double c0 = ALPHA == 2 ? 1.0 + aj / 6.0 : 1.0 - aj / 30.0;
+    for (int i = tid; i < kCbcCand * W; i += kCbcBlock) s_acc[i] = 0.0;
+    __syncthreads();
+    const uint64_t cbeg = (uint64_t)(c_first + g0) % n;
+
+    for (uint32_t k0 = 0; k0 < n; k0 += kCbcBlock * kCbcM) {
+        uint32_t r[kCbcM], kk[kCbcM];
+        double pk[kCbcM];
+        double bias = 0.0;  // +1 for each k >= n, whose term below is exactly -1
+#pragma unroll
+        for (int m = 0; m < kCbcM; ++m) {
+            const uint32_t k = k0 + (uint32_t)(m * kCbcBlock + tid);
+            const bool ok = k < n;
+            kk[m] = ok ? k : 0u;
+            pk[m] = ok ? p[k] : 0.0;
+            bias += ok ? 0.0 : 1.0;
+            r[m] = ok ? mulmod((uint64_t)k, cbeg, n, inv_n) : 0u;
+        }
+        for (int c = 0; c < gc; ++c) {
+            double acc = bias;
+#pragma unroll
+            for (int m = 0; m < kCbcM; ++m) {
+                const double x = (double)r[m] * inv_n;
+                const double y = fma(-x, x, x);  // x (1 - x)
+                double g;
+                if constexpr (ALPHA == 2)
+                    g = fma(-aj, y, c0);  // 1 + a (1/6 - y) = 1 + a B_2(x)
+                else
+                    g = fma(aj * y, y, c0);  // 1 + a (y^2 - 1/30) = 1 + a B_4(x)
+                acc += fma(pk[m], g, -1.0);
+                r[m] = addmod(r[m], kk[m], n);
+            }
+            const double w = wave_total(acc);
+            if (lane == kWaveTotalLane) s_acc[c * W + wv] += w;
+        }
+    }
+    __syncthreads();
+    for (int c = tid; c < gc; c += kCbcBlock) {
+        double t = 0.0;
+#pragma unroll
+        for (int w = 0; w < W; ++w) t += s_acc[c * W + w];
+        s_cand[g0 + c] = t * inv_n;
+    }
+}
+
+// p(k) = 1 for all k.
+__global__ __launch_bounds__(256) void cbc_init_kernel(uint32_t n, double* p) {
+    const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < n) p[k] = 1.0;
+}
+
+// p(k) *= 1 + a_j B_alpha({k z_j / n}) with the z_j just chosen (read from device memory).
+template <int ALPHA>
+__global__ __launch_bounds__(256) void cbc_update_kernel(uint32_t n, double inv_n, const double* a,
+                                                        int j, const int64_t* z, double* p) {
+    const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    const double aj = a[j];
+    const uint32_t r = mulmod((uint64_t)k, (uint64_t)z[j] % n, n, inv_n);
+    const double x = (double)r * inv_n;
+    const double y = fma(-x, x, x);
+    const double g = ALPHA == 2 ? fma(-aj, y, 1.0 + aj / 6.0) : fma(aj * y, y, 1.0 - aj / 30.0);
+    p[k] *= g;
+}
+
+// --------------------------------------------------------------------------
+// Launchers
+// --------------------------------------------------------------------------
+size_t criteria_workspace_bytes(int d, int64_t n) {
+    const size_t table = (size_t)kMaxSumSets * (size_t)d * sizeof(int64_t);
+    const size_t cbc = ((size_t)n + (size_t)n / 2 + 2) * sizeof(double);
+    return kZeroBytes + ((table > cbc ? table : cbc) + 255) / 256 * 256;
+}
+
+hipError_t launch_bernoulli_sum(const BernoulliLaunch& L, hipStream_t stream) {
+    PlainLaunch P{};
+    P.d = L.d;
+    P.n = L.n;
+    P.z = L.z;
+    P.shift = nullptr;
+    P.family = L.alpha == 2 ? kBernoulli2 : kBernoulli4;
+    P.params = L.a;
+    P.P = L.d;
+    P.nsets = L.nz;
+    P.param_stride = 0;
+    P.shift_stride = 0;
+    P.z_stride = L.d;
+    P.fp32 = false;
+    P.q_out = L.s_out;
+    P.ws = L.ws;
+    return launch_lattice_sum(P, stream);
+}
+
+hipError_t launch_korobov_search(const SearchLaunch& L, hipStream_t stream) {
+    const double inv_n = 1.0 / (double)L.n;
+    int64_t* table = (int64_t*)((char*)L.ws + kZeroBytes);
+    for (int64_t c0 = 0; c0 < L.count; c0 += kMaxSumSets) {
+        const int cnt = (int)((L.count - c0) < kMaxSumSets ? (L.count - c0) : kMaxSumSets);
+        hipLaunchKernelGGL(korobov_table_kernel, dim3((cnt + 255) / 256), dim3(256), 0, stream, L.d,
+                           L.n, inv_n, L.a0 + c0, cnt, table);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        BernoulliLaunch B{L.d, L.n, table, cnt, L.alpha, L.a, L.s_out + c0, L.ws};
+        e = launch_bernoulli_sum(B, stream);
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(select_kernel, dim3(1), dim3(kSelectBlock), 0, stream, L.s_out, L.count,
+                       L.a0, L.n, L.best_out, L.best_out + 1, (int64_t*)nullptr);
+    return hipGetLastError();
+}
+
+template <int ALPHA>
+static hipError_t launch_cbc_a(const CbcLaunch& L, hipStream_t stream) {
+    const double inv_n = 1.0 / (double)L.n;
+    double* p = (double*)((char*)L.ws + kZeroBytes);
+    double* cand = p + L.n;
+    hipLaunchKernelGGL(cbc_init_kernel, dim3((L.n + 255) / 256), dim3(256), 0, stream, L.n, p);
+    hipError_t e = hipGetLastError();
+    for (int j = 0; j < L.d && e == hipSuccess; ++j) {
+        // z_1 = 1; later components range over 1 <= c <= n/2 (c and n - c tie).
+        const int ncand = j == 0 ? 1 : (int)(L.n / 2);
+        hipLaunchKernelGGL((cbc_eval_kernel<ALPHA>), dim3((ncand + kCbcCand - 1) / kCbcCand),
+                           dim3(kCbcBlock), 0, stream, L.n, inv_n, L.a, j, p, (int64_t)1, ncand,
+                           cand);
+        hipLaunchKernelGGL(select_kernel, dim3(1), dim3(kSelectBlock), 0, stream, cand, ncand,
+                           (int64_t)1, L.n, L.s_out + j, (double*)nullptr, L.z_out + j);
+        hipLaunchKernelGGL((cbc_update_kernel<ALPHA>), dim3((L.n + 255) / 256), dim3(256), 0, stream,
+                           L.n, inv_n, L.a, j, L.z_out, p);
+        e = hipGetLastError();
+    }
+    return e;
+}
+
+hipError_t launch_cbc(const CbcLaunch& L, hipStream_t stream) {
+    return L.alpha == 2 ? launch_cbc_a<2>(L, stream) : launch_cbc_a<4>(L, stream);
+}
+
+}  // namespace qmc

@@ -27,7 +27,15 @@ constexpr double kLog2e = 1.4426950408889634074;
 constexpr double kSqrtLog2e = 1.2011224087864497918;
 constexpr double kInv2Pi = 0.15915494309189533577;
 
-enum FamilyId { kExpSum = 0, kProductPeak = 1, kGaussian = 2, kOscillatory = 3 };
+enum FamilyId {
+    kExpSum = 0,
+    kProductPeak = 1,
+    kGaussian = 2,
+    kOscillatory = 3,
+    // Internal: the Bernoulli product sums behind the lattice-quality criteria.
+    kBernoulli2 = 16,
+    kBernoulli4 = 17,
+};
 
 // exp2 of a double argument: split off the nearest integer in double, take the
 // fractional power in single precision (|fr| <= 1/2) and rescale exactly.
@@ -227,6 +235,46 @@ struct ProductPeak {
         }
     }
     __device__ static double scale(double, int ie) { return ldexp(1.0, ie); }
+};
+
+// --------------------------------------------------- Bernoulli products (FP64)
+// The product-form sums behind the lattice-quality criteria (eq. 2.4, eq. 2.12):
+//   f(x) = prod_j (1 + a_j B_alpha(x_j)) - 1,   params a[d].
+// With y = x (1 - x):  B_2(x) = 1/6 - y  and  B_4(x) = y^2 - 1/30, so a factor is
+// one FMA on y: (1 + a/6) - a y, or (1 - a/30) + (a y) y.  Criteria are small
+// differences of O(1) terms, so everything runs in FP64 in both precisions.
+template <int ALPHA>
+struct BernoulliProduct {
+    struct Dim {
+        double inv_n, off, a, c0;  // x = k inv_n + off; factor constant c0
+    };
+    struct Acc {
+        double P;
+    };
+    static constexpr int kRenorm = 0;
+    static constexpr bool kBlockTerms = false;
+    __device__ static void block_terms(const double*, int, int, double, double, double&, double&,
+                                       int&) {}
+    __device__ static double extra(const double*) { return 0.0; }
+    __device__ static Dim dim(const double* p, int d, int j, double inv_n, double sfrac) {
+        (void)d;
+        const double a = p[j];
+        return Dim{inv_n, sfrac * inv_n, a, ALPHA == 2 ? 1.0 + a / 6.0 : 1.0 - a / 30.0};
+    }
+    __device__ static Acc init(double) { return Acc{1.0}; }
+    __device__ static void step(Acc& acc, uint32_t k, const Dim& c) {
+        const double x = fma((double)k, c.inv_n, c.off);
+        const double y = fma(-x, x, x);
+        double f;
+        if constexpr (ALPHA == 2)
+            f = fma(-c.a, y, c.c0);
+        else
+            f = fma(c.a * y, y, c.c0);
+        acc.P *= f;
+    }
+    __device__ static void renorm(Acc&) {}
+    __device__ static double finish(const Acc& acc) { return acc.P - 1.0; }
+    __device__ static double scale(double, int) { return 1.0; }
 };
 
 }  // namespace qmc

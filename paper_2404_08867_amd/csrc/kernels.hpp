@@ -31,6 +31,7 @@ struct PlainLaunch {
     // parameter sets sharing one shift, (0, d) for shifts sharing one parameter set.
     int param_stride;
     int shift_stride;
+    int z_stride;  // int64 between the generating vectors of two sets (0: shared z)
     bool fp32;
     double* q_out;
     void* ws;
@@ -83,6 +84,47 @@ struct AdjLaunch {
 int adjoint_blocks_per_set(int nsets);
 size_t adjoint_workspace_bytes(int P, int nsets);
 hipError_t launch_adjoint(const AdjLaunch& a, hipStream_t stream);
+
+// Bernoulli product sums behind the lattice-quality criteria (criteria.hip).
+struct BernoulliLaunch {
+    int d;
+    uint32_t n;
+    const int64_t* z;  // [nz][d]
+    int nz;            // <= kMaxSumSets
+    int alpha;         // 2 or 4
+    const double* a;   // [d]
+    double* s_out;     // [nz]
+    void* ws;
+};
+hipError_t launch_bernoulli_sum(const BernoulliLaunch& L, hipStream_t stream);
+
+struct SearchLaunch {
+    int d;
+    uint32_t n;
+    int alpha;
+    const double* a;
+    int64_t a0;
+    int count;
+    double* s_out;     // [count]
+    double* best_out;  // [2]
+    void* ws;
+};
+hipError_t launch_korobov_search(const SearchLaunch& L, hipStream_t stream);
+
+struct CbcLaunch {
+    int d;
+    uint32_t n;
+    int alpha;
+    const double* a;
+    int64_t* z_out;  // [d]
+    double* s_out;   // [d]
+    void* ws;
+};
+hipError_t launch_cbc(const CbcLaunch& L, hipStream_t stream);
+
+// Workspace of the criteria entry points: the zero region, then the larger of a
+// table of kMaxSumSets generating vectors and the CBC vectors (n + n/2 doubles).
+size_t criteria_workspace_bytes(int d, int64_t n);
 
 int device_cu_count();
 

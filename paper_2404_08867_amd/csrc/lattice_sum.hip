@@ -30,6 +30,7 @@ struct SumArgs {
     int d;
     int param_stride;     // doubles between the parameter rows of two sets (0: shared)
     int shift_stride;     // doubles between the shift rows of two sets (0: shared)
+    int z_stride;         // int64 between the generating vectors of two sets (0: shared)
     uint32_t tiles;
     double* q_out;
     uint32_t* tickets;    // counter region of the workspace
@@ -54,15 +55,16 @@ __device__ __forceinline__ GridSlots set_slots(double* scratch, uint32_t scratch
 template <class F, int M, int B>
 __global__ __launch_bounds__(B) void lattice_sum_kernel(
     const int64_t* z, const double* params, const double* shift, double inv_n, uint32_t n, int d,
-    int param_stride, int shift_stride, uint32_t tiles, double* q_out, uint32_t* tickets,
-    double* scratch, uint32_t scratch_stride, int slot_stride) {
+    int param_stride, int shift_stride, int z_stride, uint32_t tiles, double* q_out,
+    uint32_t* tickets, double* scratch, uint32_t scratch_stride, int slot_stride) {
     constexpr uint32_t kTile = B * M;
     __shared__ TileShared<F, B> s;
     __shared__ double s_red[3 * (B / kWave)];
 
     const int set = blockIdx.y;
     const ProblemView v =
-        make_view(d, n, inv_n, z, shift ? shift + (size_t)set * shift_stride : nullptr,
+        make_view(d, n, inv_n, z + (size_t)set * z_stride,
+                  shift ? shift + (size_t)set * shift_stride : nullptr,
                   params + (size_t)set * param_stride);
     double init0, ds1;
     int ie;
@@ -196,6 +198,7 @@ static hipError_t launch_fm(const PlainLaunch& L, hipStream_t stream) {
     a.d = L.d;
     a.param_stride = L.param_stride;
     a.shift_stride = L.shift_stride;
+    a.z_stride = L.z_stride;
     const uint64_t tile = (uint64_t)kSumBlock * M;
     a.tiles = (uint32_t)(((uint64_t)L.n + tile - 1) / tile);
     a.q_out = L.q_out;
@@ -209,7 +212,8 @@ static hipError_t launch_fm(const PlainLaunch& L, hipStream_t stream) {
     dim3 grid((unsigned)g, (unsigned)L.nsets);
     hipLaunchKernelGGL((lattice_sum_kernel<F, M, kSumBlock>), grid, dim3(kSumBlock), 0, stream,
                        a.z, a.params, a.shift, a.inv_n, a.n, a.d, a.param_stride, a.shift_stride,
-                       a.tiles, a.q_out, a.tickets, a.scratch, a.scratch_stride, a.slot_stride);
+                       a.z_stride, a.tiles, a.q_out, a.tickets, a.scratch, a.scratch_stride,
+                       a.slot_stride);
     return hipGetLastError();
 }
 
@@ -234,6 +238,9 @@ static hipError_t launch_f(const PlainLaunch& L, hipStream_t stream) {
 }
 
 hipError_t launch_lattice_sum(const PlainLaunch& L, hipStream_t stream) {
+    // The Bernoulli products behind the criteria run in FP64 in both precisions.
+    if (L.family == kBernoulli2) return launch_f<BernoulliProduct<2>>(L, stream);
+    if (L.family == kBernoulli4) return launch_f<BernoulliProduct<4>>(L, stream);
     if (L.fp32) {
         switch (L.family) {
             case kExpSum: return launch_f<ExpSum<true>>(L, stream);

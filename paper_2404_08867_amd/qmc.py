@@ -8,6 +8,7 @@ fallback.
 from __future__ import annotations
 
 import ctypes
+import math
 import os
 import threading
 
@@ -61,6 +62,10 @@ def lib() -> ctypes.CDLL:
         L.qmc_lattice_sum_ex.argtypes = [i32, i64, dp, dp, i32, dp, i32, i32, dp, vp, sz, vp, vp]
         L.qmc_lattice_sum_shifts.argtypes = [i32, i64, dp, dp, i32, i32, dp, i32, dp, dp, vp, sz, vp]
         L.qmc_lattice_points.argtypes = [i32, i64, dp, i64, i64, dp, vp]
+        L.qmc_criteria_workspace_size.argtypes = [i32, i64, vp]
+        L.qmc_bernoulli_sum.argtypes = [i32, i64, dp, i32, i32, dp, dp, vp, sz, vp]
+        L.qmc_korobov_search.argtypes = [i32, i64, i32, dp, i64, i32, dp, dp, vp, sz, vp]
+        L.qmc_cbc.argtypes = [i32, i64, i32, dp, dp, dp, vp, sz, vp]
         L.qmc_mdi_lr.argtypes = [i32, dp, i32, dp, i32, i32, dp, vp, sz, vp]
         L.qmc_lattice_sum_adjoint.argtypes = [i32, i64, dp, dp, i32, dp, i32, i32, dp, dp, dp, vp, sz, vp]
         L.qmc_batch_plan_create.argtypes = [i32, vp, i32, vp, vp]
@@ -242,6 +247,103 @@ def lattice_sum_shifts(z, n: int, family: int, params, shifts, precision: int = 
                                         _ptr(q), _ptr(stats), w.ptr, w.nbytes, _stream()),
            "qmc_lattice_sum_shifts")
     return q, stats
+
+
+# ----------------------------------------------------------- lattice criteria
+def criteria_workspace_size(d: int, n: int) -> int:
+    out = ctypes.c_size_t(0)
+    _check(lib().qmc_criteria_workspace_size(d, n, ctypes.byref(out)), "qmc_criteria_workspace_size")
+    return int(out.value)
+
+
+def _criteria_workspace(d, n, device, ws):
+    if ws is not None:
+        return ws
+    need = criteria_workspace_size(d, n)
+    key = ("criteria", str(device), _torch().cuda.current_stream(device).cuda_stream)
+    cur = _ws_cache.get(key)
+    if cur is None or cur.nbytes < need:
+        cur = Workspace(need, device)
+        _ws_cache[key] = cur
+    return cur
+
+
+def p_alpha_weight(alpha: int) -> float:
+    """(-1)^{alpha/2+1} (2 pi)^alpha / alpha!: the weight a_j that makes S equal P_alpha (eq. 2.4)."""
+    return (1.0 if (alpha // 2) % 2 == 1 else -1.0) * (2.0 * math.pi) ** alpha / math.factorial(alpha)
+
+
+def wce2_weights(gamma, beta: float):
+    """(a_j, C) with e^2 = C * S(a) for product weights gamma_j (eq. 2.12)."""
+    g = np.asarray(gamma, dtype=np.float64)
+    return g / (1.0 + g * beta), float(np.prod(1.0 + g * beta))
+
+
+def bernoulli_sum(z, n: int, alpha: int, a, ws: Workspace | None = None, device="cuda"):
+    """S for each row of z ([nz, d] or [d]): (1/n) sum_k [prod_j (1 + a_j B_alpha({k z_j/n})) - 1]."""
+    torch = _torch()
+    zt = _dev(z, torch.int64, device)
+    if zt.dim() == 1:
+        zt = zt.unsqueeze(0)
+    nz, d = int(zt.shape[0]), int(zt.shape[1])
+    at = _dev(a, torch.float64, device)
+    if at.numel() != d:
+        raise QmcError(ERR_INVALID_ARG, "a must hold d weights")
+    s = torch.empty(nz, dtype=torch.float64, device=device)
+    w = _workspace(d, n, nz, device, ws)
+    _check(lib().qmc_bernoulli_sum(d, n, _ptr(zt), nz, alpha, _ptr(at), _ptr(s), w.ptr, w.nbytes,
+                                   _stream()), "qmc_bernoulli_sum")
+    return s
+
+
+def p_alpha(z, n: int, alpha: int, device="cuda"):
+    """P_alpha(z) of eq. 2.4 for each row of z (device tensor)."""
+    d = int(np.asarray(z).shape[-1]) if not hasattr(z, "shape") else int(z.shape[-1])
+    return bernoulli_sum(z, n, alpha, np.full(d, p_alpha_weight(alpha)), device=device)
+
+
+def shift_avg_wce2(z, n: int, gamma, beta: float, device="cuda"):
+    """Squared shift-averaged worst-case error of eq. 2.12 (product weights) per row of z."""
+    a, c = wce2_weights(gamma, beta)
+    return c * bernoulli_sum(z, n, 2, a, device=device)
+
+
+def korobov_search(d: int, n: int, alpha: int = 2, a=None, a0: int = 1, count: int | None = None,
+                   ws: Workspace | None = None, device="cuda"):
+    """S(z(a)) for a = a0 .. a0+count-1 (qmc_korobov_search; a_j = P_alpha weights by default).
+    Returns (values [count] device tensor, best [2] device tensor: value, a)."""
+    torch = _torch()
+    count = (n - a0) if count is None else count
+    weights = np.full(d, p_alpha_weight(alpha)) if a is None else a
+    at = _dev(weights, torch.float64, device)
+    vals = torch.empty(count, dtype=torch.float64, device=device)
+    best = torch.empty(2, dtype=torch.float64, device=device)
+    w = _criteria_workspace(d, n, device, ws)
+    _check(lib().qmc_korobov_search(d, n, alpha, _ptr(at), a0, count, _ptr(vals), _ptr(best), w.ptr,
+                                    w.nbytes, _stream()), "qmc_korobov_search")
+    return vals, best
+
+
+def cbc(d: int, n: int, gamma, beta: float, alpha: int = 2, ws: Workspace | None = None,
+        device="cuda"):
+    """CBC generating vector (qmc_cbc) for product weights gamma_j and beta.
+    Returns (z [d] int64 device tensor, criterion after each component [d]:
+    e^2 of eq. 2.12 for alpha = 2, S for alpha = 4)."""
+    torch = _torch()
+    g = np.asarray(gamma, dtype=np.float64)
+    if g.size != d:
+        raise QmcError(ERR_INVALID_ARG, "gamma must hold d weights")
+    a, _ = wce2_weights(g, beta) if alpha == 2 else (g, 1.0)
+    at = _dev(a, torch.float64, device)
+    z = torch.empty(d, dtype=torch.int64, device=device)
+    sv = torch.empty(d, dtype=torch.float64, device=device)
+    w = _criteria_workspace(d, n, device, ws)
+    _check(lib().qmc_cbc(d, n, alpha, _ptr(at), _ptr(z), _ptr(sv), w.ptr, w.nbytes, _stream()),
+           "qmc_cbc")
+    if alpha == 2:
+        cj = torch.tensor(np.cumprod(1.0 + g * beta), dtype=torch.float64, device=device)
+        sv = sv * cj
+    return z, sv
 
 
 def lattice_points(z, n: int, i0: int, count: int, device="cuda"):

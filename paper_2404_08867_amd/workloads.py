@@ -27,6 +27,13 @@ Workloads (k = 0..4):
                          u ~ U[0,1], c ~ U[0,2]
   5 shifts_d20_peak      the plain_d20_peak problem (its own seed) with R = 64
                          shifts Delta_r ~ U[0,1)^20 (random-shift ensemble)
+Lattice constructions (no random draws):
+    korobov_search_d20   e^2 of eq. 2.12 for z(a), d=20, n=65521 (the largest
+                         prime below 2^16), product weights gamma_j = j^-2,
+                         unanchored (beta = 0), every a in [1, (n-1)/2] (a and
+                         n-a tie).  (Unit weights would make every candidate's
+                         P_2 about (1 + pi^2/3)^20 / n: the k = 0 term.)
+    cbc_d20              CBC for the same e^2, d=20, n=65521
 """
 from __future__ import annotations
 
@@ -195,6 +202,41 @@ def shifts_d20_peak(nshifts: int = 64) -> ShiftEnsemble:
     rng = np.random.default_rng(SEED_BASE + 5)
     shifts = rng.random((nshifts, base.d))
     return ShiftEnsemble("shifts_d20_peak", base.d, base.n, base.a, base.family, base.params, shifts)
+
+
+@dataclass
+class Search:
+    name: str
+    d: int
+    n: int
+    alpha: int
+    a0: int
+    count: int
+    gamma: np.ndarray
+    beta: float
+
+
+@dataclass
+class Cbc:
+    name: str
+    d: int
+    n: int
+    gamma: np.ndarray
+    beta: float
+
+
+def _inverse_square_weights(d: int) -> np.ndarray:
+    return 1.0 / np.arange(1, d + 1, dtype=np.float64) ** 2
+
+
+def korobov_search_d20() -> Search:
+    n, d = 65521, 20
+    return Search("korobov_search_d20", d, n, 2, 1, (n - 1) // 2, _inverse_square_weights(d), 0.0)
+
+
+def cbc_d20() -> Cbc:
+    d = 20
+    return Cbc("cbc_d20", d, 65521, _inverse_square_weights(d), 0.0)
 
 
 def random_shifts(seed: int, nshifts: int, d: int) -> np.ndarray:

@@ -94,6 +94,16 @@ def test_invalid_arguments_fail_before_launch():
     assert L.qmc_lattice_sum_shifts(4, 100, fake, None, 3, 0, fake, 0, fake, fake, ws, big, None) == qmc.ERR_INVALID_ARG
     assert L.qmc_lattice_sum_shifts(4, 100, fake, fake, 3, 0, None, 0, fake, fake, ws, big, None) == qmc.ERR_INVALID_ARG
     assert L.qmc_lattice_sum_shifts(4, 100, fake, fake, 3, 0, fake, 0, fake, fake, ws, 16, None) == qmc.ERR_WORKSPACE
+    # lattice criteria: alpha, n, candidate range, CBC size limit, workspace
+    assert L.qmc_bernoulli_sum(4, 100, fake, 1, 3, fake, fake, ws, big, None) == qmc.ERR_INVALID_ARG
+    assert L.qmc_bernoulli_sum(4, 1, fake, 1, 2, fake, fake, ws, big, None) == qmc.ERR_INVALID_ARG
+    assert L.qmc_bernoulli_sum(4, 100, fake, 0, 2, fake, fake, ws, big, None) == qmc.ERR_INVALID_ARG
+    assert L.qmc_bernoulli_sum(4, 100, fake, 1, 2, None, fake, ws, big, None) == qmc.ERR_INVALID_ARG
+    assert L.qmc_korobov_search(4, 100, 2, fake, 0, 10, fake, fake, ws, big, None) == qmc.ERR_INVALID_ARG
+    assert L.qmc_korobov_search(4, 100, 2, fake, 95, 10, fake, fake, ws, big, None) == qmc.ERR_INVALID_ARG
+    assert L.qmc_korobov_search(4, 100, 2, fake, 1, 10, fake, fake, ws, 16, None) == qmc.ERR_WORKSPACE
+    assert L.qmc_cbc(4, (1 << 26) + 1, 2, fake, fake, fake, ws, big, None) == qmc.ERR_INVALID_ARG
+    assert L.qmc_cbc(4, 100, 2, fake, None, fake, ws, big, None) == qmc.ERR_INVALID_ARG
     # MDI-LR and the index export
     assert L.qmc_mdi_lr(0, fake, 0, fake, 1, 0, fake, None, 0, None) == qmc.ERR_INVALID_ARG
     assert L.qmc_mdi_lr(4, None, 0, fake, 1, 0, fake, None, 0, None) == qmc.ERR_INVALID_ARG
@@ -107,6 +117,14 @@ def test_invalid_arguments_fail_before_launch():
     assert L.qmc_mdi_lr_dims(3, 1 << 21, 0, 0, N.ctypes.data) == qmc.ERR_INVALID_ARG
     # z(a) with a = n: z_2 = 0 makes eq. 3.5 undefined
     assert L.qmc_mdi_lr_dims(3, 7, qmc.N_EXPLICIT, 7, N.ctypes.data) == qmc.ERR_INVALID_ARG
+
+
+def test_criteria_workspace_size():
+    # zero region, then the larger of 4096 generating vectors and n + n/2 doubles
+    def expect(d, n):
+        return (4 << 20) + (max(4096 * d * 8, (n + n // 2 + 2) * 8) + 255) // 256 * 256
+    for d, n in [(20, 65521), (200, 1009), (2, 1 << 24), (1024, 3)]:
+        assert qmc.criteria_workspace_size(d, n) == expect(d, n)
 
 
 def test_last_error_is_cleared_by_success():

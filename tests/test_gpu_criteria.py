@@ -1,0 +1,135 @@
+"""Parity of the lattice-quality criteria and constructions (qmc_bernoulli_sum,
+qmc_korobov_search, qmc_cbc) with the FP64 oracle.
+
+Tolerance: criteria are FP64 sums of O(1) terms of both signs whose result is
+small, so |S - S_oracle| <= 1e-12 * max(|S_oracle|, A), A the oracle's mean |term|
+(the measure used for every mixed-sign sum).  The chosen generating vectors are
+integers decided by floating point: both sides apply the same rule (smallest
+candidate within 1e-10 relative of the minimum), so they are compared exactly,
+and the GPU's choice is also checked to attain the oracle's minimum.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2404_08867_amd import qmc
+from paper_2404_08867_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-12
+
+
+def _close(s, so, ao):
+    return abs(s - so) <= TOL * max(abs(so), ao)
+
+
+@pytest.mark.parametrize("alpha", [2, 4])
+@pytest.mark.parametrize("d,n", [(3, 1009), (20, 4099), (65, 2003), (1, 997), (8, 64)])
+def test_bernoulli_sum_matches_oracle(alpha, d, n):
+    rng = np.random.default_rng(100 * d + n + alpha)
+    rows = [O.korobov(d, n, int(rng.integers(1, n))) for _ in range(5)]
+    a = rng.uniform(-2.0, 20.0, d) if alpha == 2 else rng.uniform(-20.0, 2.0, d)
+    s = qmc.bernoulli_sum(np.stack(rows), n, alpha, a).cpu().numpy()
+    for r, z in enumerate(rows):
+        so, ao = O.lattice_kernel_sum(z, n, alpha, a)
+        assert _close(s[r], so, ao), (r, s[r], so)
+
+
+@pytest.mark.parametrize("z,n", [([1, 3, 9, 27, 81], 1009), ([1, 40, 33, 19], 97)])
+def test_criterion_helpers(z, n):
+    for alpha in (2, 4):
+        p = float(qmc.p_alpha(np.array(z), n, alpha)[0].item())
+        assert p == pytest.approx(O.p_alpha(z, n, alpha), rel=1e-10)
+    gamma, beta = [1.0, 0.5, 0.25, 0.125, 0.0625][: len(z)], 0.3
+    e2 = float(qmc.shift_avg_wce2(np.array(z), n, gamma, beta)[0].item())
+    assert e2 == pytest.approx(O.shift_avg_wce2(z, n, gamma, beta), rel=1e-10)
+
+
+@pytest.mark.parametrize("d,n,alpha", [(8, 1009, 2), (5, 2003, 4), (4, 1000, 2), (4, 8191, 2)])
+def test_korobov_search_matches_oracle(d, n, alpha):
+    vals, best = qmc.korobov_search(d, n, alpha)
+    vals = vals.cpu().numpy()
+    best = best.cpu().numpy()
+    ov, ob = O.korobov_search(d, n, alpha)
+    assert np.array_equal(np.isinf(vals), np.isinf(ov))
+    c = qmc.p_alpha_weight(alpha)
+    for a in range(1, n):
+        if np.isfinite(ov[a - 1]):
+            _, ao = O.lattice_kernel_sum(O.korobov(d, n, a), n, alpha, np.full(d, c))
+            assert _close(vals[a - 1], ov[a - 1], ao), (a, vals[a - 1], ov[a - 1])
+    assert int(best[1]) == ob
+    assert best[0] == vals[ob - 1]
+
+
+@pytest.mark.parametrize("d,n,gamma,beta", [
+    (5, 1009, [1.0, 0.8, 0.64, 0.512, 0.41], 0.0),
+    (4, 2003, [0.5, 0.5, 0.5, 0.5], 0.25),
+    (6, 251, [1.0, 1.0, 0.5, 0.5, 0.25, 0.25], 1.0 / 3.0),
+    (3, 64, [0.9, 0.9, 0.9], 0.0),
+])
+def test_cbc_matches_oracle(d, n, gamma, beta):
+    z, e2 = qmc.cbc(d, n, gamma, beta)
+    z = z.cpu().numpy()
+    e2 = e2.cpu().numpy()
+    oz, oe2 = O.cbc(d, n, gamma, beta)
+    assert np.array_equal(z, oz), (z, oz)
+    assert np.allclose(e2, oe2, rtol=1e-9, atol=1e-13)
+
+
+def test_cbc_alpha4_against_exhaustive_oracle_search():
+    d, n = 3, 101
+    a = np.array([-1.5, -1.0, -0.5])
+    z, s = qmc.cbc(d, n, a, 0.0, alpha=4)  # alpha = 4 takes the weights as they are
+    z = z.cpu().numpy()
+    s = s.cpu().numpy()
+    prefix = [1]
+    so, _ = O.lattice_kernel_sum(prefix, n, 4, a[:1])
+    assert s[0] == pytest.approx(so, rel=1e-9, abs=1e-14)
+    for j in range(1, d):
+        cand = [c for c in range(1, n // 2 + 1) if math.gcd(c, n) == 1]
+        vals = [O.lattice_kernel_sum(prefix + [c], n, 4, a[: j + 1])[0] for c in cand]
+        m = min(vals)
+        pick = next(c for c, v in zip(cand, vals) if v <= m + 1e-10 * abs(m))
+        assert z[j] == pick
+        assert s[j] == pytest.approx(m, rel=1e-9, abs=1e-14)
+        prefix.append(pick)
+
+
+def test_korobov_search_d20_full_size_sampled():
+    """The benchmark's search (n = 65521, d = 20, e^2 with gamma_j = j^-2, a in
+    [1, n/2]): sampled candidates against the oracle, the chosen a's value, and the
+    selection rule on the GPU's own values."""
+    w = W.korobov_search_d20()
+    a, c = qmc.wce2_weights(w.gamma, w.beta)
+    vals, best = qmc.korobov_search(w.d, w.n, w.alpha, a=a, a0=w.a0, count=w.count)
+    vals = vals.cpu().numpy()
+    best = best.cpu().numpy()
+    assert np.all(np.isfinite(vals)) and vals.size == w.count
+    for cand in (1, 2, 17, 4099, w.a0 + w.count - 1, int(best[1])):
+        z = O.korobov(w.d, w.n, cand)
+        eo = O.shift_avg_wce2(z, w.n, w.gamma, w.beta)
+        _, ao = O.lattice_kernel_sum(z, w.n, 2, a)
+        assert _close(c * vals[cand - w.a0], eo, c * ao), cand
+    m = np.min(vals)
+    assert best[0] <= m * (1 + 1e-10) and np.all(vals[: int(best[1]) - w.a0] > m * (1 + 1e-10))
+
+
+def test_cbc_d20_full_size_components():
+    """The benchmark's CBC (n = 65521, d = 20): each component's criterion at the
+    GPU's choices against the oracle; each choice beats the sampled alternatives."""
+    w = W.cbc_d20()
+    z, e2 = qmc.cbc(w.d, w.n, w.gamma, w.beta)
+    z = z.cpu().numpy()
+    e2 = e2.cpu().numpy()
+    assert z[0] == 1 and np.all((z >= 1) & (z <= w.n // 2))
+    a, _ = qmc.wce2_weights(w.gamma, w.beta)
+    for j in (0, 1, 2, 9, 19):
+        eo = O.shift_avg_wce2(z[: j + 1], w.n, w.gamma[: j + 1], w.beta)
+        _, ao = O.lattice_kernel_sum(z[: j + 1], w.n, 2, a[: j + 1])
+        assert _close(e2[j], eo, ao), j
+    for c in (1, 2, 1000, 20000, w.n // 2):
+        alt = O.shift_avg_wce2(np.concatenate([z[:1], [c]]), w.n, w.gamma[:2], w.beta)
+        assert e2[1] <= alt * (1 + 1e-10)
