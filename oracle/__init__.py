@@ -62,6 +62,8 @@ def _load():
     lib.oracle_shift_avg_wce2.argtypes = [i32, i64, dp, dp, ctypes.c_double, dp]
     lib.oracle_korobov_search.argtypes = [i32, i64, i32, i64, i64, dp, dp]
     lib.oracle_cbc.argtypes = [i32, i64, dp, ctypes.c_double, dp, dp]
+    lib.oracle_mdi_sum_brute.argtypes = [i32, i64, i64, i32, dp, dp]
+    lib.oracle_mdi_sum_sweep.argtypes = [i32, i64, i64, i32, dp, dp, dp]
     lib.oracle_mdi_dims.argtypes = [i32, dp, i64, dp]
     lib.oracle_mdi_lr_brute.argtypes = [i32, dp, i32, dp, dp]
     lib.oracle_mdi_lr_sweep.argtypes = [i32, dp, i32, dp, dp]
@@ -211,6 +213,24 @@ def cbc(d: int, n: int, gamma, beta: float):
     e2 = np.zeros(d)
     _check(_load().oracle_cbc(d, n, _ptr(gamma), float(beta), _ptr(z), _ptr(e2)), "cbc")
     return z, e2
+
+
+def mdi_sum_brute(d: int, N: int, N_last: int, gfam: int, gp) -> float:
+    """Tensor midpoint rule of g(sum x) by brute force over the grid."""
+    gp = _f64(gp)
+    q = np.zeros(1)
+    _check(_load().oracle_mdi_sum_brute(d, N, N_last, gfam, _ptr(gp), _ptr(q)), "mdi_sum_brute")
+    return float(q[0])
+
+
+def mdi_sum(d: int, N: int, N_last: int, gfam: int, gp, counts: bool = False):
+    """Tensor midpoint rule of g(sum x) by the merged-state dimension iteration;
+    with counts=True also the number of index tuples per state after d-1 directions."""
+    gp = _f64(gp)
+    q = np.zeros(1)
+    c = np.zeros((d - 1) * (N - 1) + 1) if counts else None
+    _check(_load().oracle_mdi_sum_sweep(d, N, N_last, gfam, _ptr(gp), _ptr(q), _ptr(c)), "mdi_sum")
+    return (float(q[0]), c) if counts else float(q[0])
 
 
 def mdi_dims(z, n: int) -> np.ndarray:

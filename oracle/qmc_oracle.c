@@ -489,6 +489,98 @@ int oracle_cbc(int d, int64_t n, const double* gamma, double beta, int64_t* z_ou
 }
 
 /* ------------------------------------------------------------------------- */
+/* MDI-LR for integrands of the coordinate sum (Test 7's f_6 = (1 + sum x)^-(d+1)) */
+/* on the improved tensor rule: N_k = N nodes (t + 1/2)/N for k < d and N_last   */
+/* for the last direction,                                                      */
+/*   Q = (1 / (N^{d-1} N_last)) sum_t g( sum_{k<d} (t_k + 1/2)/N + (t_d + 1/2)/N_last ).  */
+/* Outer functions g (params):                                                  */
+/*   0 SUM_POWER  g(s) = (b + c s)^(-p)          b, c, p                        */
+/*   1 SUM_GAUSS  g(s) = exp(-c^2 (s - w)^2)     c, w                           */
+/* ------------------------------------------------------------------------- */
+static double sum_g(int gfam, const double* gp, double s) {
+    if (gfam == 0) return pow(gp[0] + gp[1] * s, -gp[2]);
+    return exp(-gp[0] * gp[0] * (s - gp[1]) * (s - gp[1]));
+}
+
+/* Brute force over the full grid (small d and N only). */
+int oracle_mdi_sum_brute(int d, int64_t N, int64_t N_last, int gfam, const double* gp, double* q) {
+    if (d < 1 || N < 1 || N_last < 1 || (gfam != 0 && gfam != 1) || !gp || !q) return OR_BAD_ARG;
+    double total_pts = pow((double)N, (double)(d - 1)) * (double)N_last;
+    if (total_pts > 5e7) return OR_TOO_BIG;
+    int64_t* t = (int64_t*)calloc((size_t)d, sizeof(int64_t));
+    if (!t) return OR_TOO_BIG;
+    neu_t acc = {0.0, 0.0};
+    for (;;) {
+        double s = 0.0;
+        for (int k = 0; k < d; ++k) {
+            const int64_t Nk = k < d - 1 ? N : N_last;
+            s += ((double)t[k] + 0.5) / (double)Nk;
+        }
+        neu_add(&acc, sum_g(gfam, gp, s));
+        int k = 0;
+        while (k < d) {
+            const int64_t Nk = k < d - 1 ? N : N_last;
+            if (++t[k] < Nk) break;
+            t[k] = 0;
+            ++k;
+        }
+        if (k == d) break;
+    }
+    free(t);
+    *q = neu_value(&acc) / total_pts;
+    return OR_OK;
+}
+
+/* Dimension iteration with merged states: after k equal directions the partial
+ * sum is (T + k/2) / N for an integer T in [0, k (N - 1)], and c_k[T], the
+ * fraction of the N^k index tuples with sum T, is the previous fraction averaged
+ * over a window of N states (one step of the iteration of Algorithm 1, with the
+ * terms that share a partial sum combined).  counts_out, if not NULL, receives
+ * N^k c_k[T] (the number of tuples) for k = d - 1. */
+int oracle_mdi_sum_sweep(int d, int64_t N, int64_t N_last, int gfam, const double* gp, double* q,
+                         double* counts_out) {
+    if (d < 1 || N < 1 || N_last < 1 || (gfam != 0 && gfam != 1) || !gp || !q) return OR_BAD_ARG;
+    const int64_t L = (int64_t)(d - 1) * (N - 1) + 1;  /* states after d - 1 directions */
+    if (L > ((int64_t)1 << 26)) return OR_TOO_BIG;
+    double* c = (double*)calloc((size_t)L, sizeof(double));
+    double* nc = (double*)calloc((size_t)L, sizeof(double));
+    if (!c || !nc) {
+        free(c);
+        free(nc);
+        return OR_TOO_BIG;
+    }
+    c[0] = 1.0;
+    for (int k = 1; k < d; ++k) {
+        const int64_t Lk = (int64_t)k * (N - 1) + 1;
+        for (int64_t T = 0; T < Lk; ++T) {
+            neu_t w = {0.0, 0.0};
+            for (int64_t u = 0; u < N; ++u)
+                if (T - u >= 0 && T - u < (int64_t)(k - 1) * (N - 1) + 1) neu_add(&w, c[T - u]);
+            nc[T] = neu_value(&w) / (double)N;
+        }
+        double* tmp = c;
+        c = nc;
+        nc = tmp;
+    }
+    neu_t acc = {0.0, 0.0};
+    for (int64_t T = 0; T < L; ++T) {
+        const double s0 = ((double)T + 0.5 * (double)(d - 1)) / (double)N;
+        neu_t inner = {0.0, 0.0};
+        for (int64_t u = 0; u < N_last; ++u)
+            neu_add(&inner, sum_g(gfam, gp, s0 + ((double)u + 0.5) / (double)N_last));
+        neu_add(&acc, c[T] * neu_value(&inner) / (double)N_last);
+    }
+    *q = neu_value(&acc);
+    if (counts_out) {
+        const double scale = pow((double)N, (double)(d - 1));
+        for (int64_t T = 0; T < L; ++T) counts_out[T] = c[T] * scale;
+    }
+    free(c);
+    free(nc);
+    return OR_OK;
+}
+
+/* ------------------------------------------------------------------------- */
 /* Per-direction node counts of the transformed grid (eq. 3.5):              */
 /*   n_i = lcm(z_i, z_{i+1}) / min(z_i, z_{i+1}),  i < d;   n_d = ceil(n / z_d). */
 /* ------------------------------------------------------------------------- */
