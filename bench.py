@@ -82,6 +82,12 @@ def work_per_point_adjoint(d: int, family: int) -> int:
 # accumulation.
 WORK_PER_MDI_FACTOR = 3 * C32 + CT + ACCUM
 
+# MDI-LR of g(sum x), power g, QMC_FP32_COMPENSATED, per merged-state evaluation of
+# g: the node, b + c s, an FP64 log2 (a software sequence), the exponent and the
+# split exp2, the weighted FP64 add -- 88 VALU instructions in the compiled loop,
+# 80 of them FP64: 168 slots.
+WORK_PER_SUM_EVAL = 80 * C64 + 8 * C32
+
 # Lattice-quality criteria (FP64): per point and direction the index step, the
 # conversion, x = k/n, y = x (1 - x), the factor 1 + a B(x) and the product; per
 # point the "- 1" and the FP64 add.
@@ -102,7 +108,7 @@ def parse():
     ap.add_argument("--workload", default="plain_d20_peak",
                     choices=["plain_d20_peak", "plain_d4_expsum", "mdi_d100_gauss", "batched_4096",
                              "adjoint_d50_osc", "shifts_d20_peak", "korobov_search_d20",
-                             "cbc_d20"])
+                             "cbc_d20", "mdi_sum_d100"])
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
                     help="wall-clock budget of the oracle's CPU-baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -295,6 +301,51 @@ def oracle_shifts_baseline(w, r32, r64, seconds):
             break
     dt = time.perf_counter() - t0
     return w.n * k / dt, k, e32, e64
+
+
+def bench_mdi_sum(args, torch, qmc, W):
+    """MDI-LR of g(sum x): one step is the state iteration and the evaluation of
+    all 4096 parameter sets (two launches)."""
+    w = W.mdi_sum_d100()
+    params = torch.tensor(w.params, dtype=torch.float64, device="cuda")
+    nsets = params.shape[0]
+    ws = qmc.Workspace(qmc.mdi_lr_sum_workspace_size(w.d, w.N))
+    results = {}
+    for prec, name in ((qmc.FP32_COMPENSATED, "fp32c"), (qmc.FP64, "fp64")):
+        out = torch.zeros(nsets, dtype=torch.float64, device="cuda")
+
+        def launch(prec=prec, out=out):
+            qmc.mdi_lr_sum(w.d, w.N, w.N_last, w.gfamily, params, prec, ws=ws, out=out)
+
+        step_s, kern_s, lat_s, g = time_graph(torch, launch, args.steps, args.warmup)
+        results[name] = dict(step_s=step_s, kern_s=kern_s, lat_s=lat_s, q=out.cpu().numpy())
+        del g
+    merge = w.N_last == w.N
+    states = (w.d if merge else w.d - 1) * (w.N - 1) + 1
+    units = nsets * states * (1 if merge else w.N_last)
+    config = {"workload": w.name, "d": w.d, "N": w.N, "N_last": w.N_last, "nsets": nsets,
+              "family": "sum_power (set 0: f_6 = (1 + sum x)^-(d+1))", "precision": "fp32_compensated",
+              "merged_states": states, "tensor_grid_points": f"{w.N}^{w.d}",
+              "sets_per_s": nsets / results["fp32c"]["step_s"],
+              "unit_of_work": "one evaluation of g at a merged state"}
+    return w, results, units, WORK_PER_SUM_EVAL, config
+
+
+def oracle_mdi_sum_baseline(w, r32, r64, seconds):
+    import oracle as O
+    t0 = time.perf_counter()
+    e32 = e64 = 0.0
+    k = 0
+    for s in range(len(w.params)):
+        qo = O.mdi_sum(w.d, w.N, w.N_last, w.gfamily, w.params[s])
+        e32 = max(e32, abs(r32["q"][s] - qo) / abs(qo))
+        e64 = max(e64, abs(r64["q"][s] - qo) / abs(qo))
+        k += 1
+        if time.perf_counter() - t0 > seconds:
+            break
+    dt = time.perf_counter() - t0
+    states = (w.d - 1) * (w.N - 1) + 1  # the oracle evaluates g at (state, last node) pairs
+    return states * w.N_last * k / dt, k, e32, e64
 
 
 def bench_search(args, torch, qmc, W):
@@ -539,6 +590,8 @@ def main():
         prob, res, units, wpp, config = bench_search(args, torch, qmc, W)
     elif args.workload == "cbc_d20":
         prob, res, units, wpp, config = bench_cbc(args, torch, qmc, W)
+    elif args.workload == "mdi_sum_d100":
+        prob, res, units, wpp, config = bench_mdi_sum(args, torch, qmc, W)
     else:
         prob, res, units, wpp, config = bench_plain(args, torch, qmc, W)
 
@@ -552,7 +605,8 @@ def main():
                  "adjoint_d50_osc": "point-set evals (value + gradient)/s",
                  "shifts_d20_peak": "shifted-lattice point evals/s",
                  "korobov_search_d20": "candidate lattice-point evals/s",
-                 "cbc_d20": "candidate-index terms/s"}.get(
+                 "cbc_d20": "candidate-index terms/s",
+                 "mdi_sum_d100": "merged-state evaluations of g/s"}.get(
                      args.workload, "lattice-point evals/s"),
         "n_gpus": 1,
         "steps": args.steps,
@@ -597,6 +651,10 @@ def main():
             e64 = e32
             sample = (f"the criterion of the first {k} candidates of the second component "
                       f"(n={prob.n} terms each); rel_err over the {prob.d} chosen components")
+        elif args.workload == "mdi_sum_d100":
+            rate, k, e32, e64 = oracle_mdi_sum_baseline(prob, res["fp32c"], res["fp64"], args.cpu_seconds)
+            sample = (f"the first {k} of {len(prob.params)} parameter sets; the oracle evaluates g at "
+                      "every (state, last node) pair, so its rate is in those evaluations")
         elif args.workload == "shifts_d20_peak":
             rate, k, e32, e64 = oracle_shifts_baseline(prob, res["fp32c"], res["fp64"], args.cpu_seconds)
             sample = f"the first {k} of {prob.shifts.shape[0]} shifted lattices (n={prob.n} points each)"

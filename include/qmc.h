@@ -151,6 +151,35 @@ qmc_status qmc_lattice_sum_shifts(int32_t d, int64_t n, const int64_t* z, const 
                                   int32_t precision, double* q_out, double* stats_out, void* ws,
                                   size_t ws_bytes, void* stream);
 
+/* ---- MDI-LR for integrands of the coordinate sum ---------------------------
+ * f(x) = g(x_1 + ... + x_d), e.g. Test 7's f_6 = (1 + sum x)^-(d+1), on the
+ * improved tensor midpoint rule with N nodes (t + 1/2)/N in each of the first
+ * d - 1 directions and N_last in the last (eq. 3.5 gives N_last = a or
+ * ceil(n / a^{d-1}) with N = a):
+ *   Q = (1 / (N^{d-1} N_last)) sum_t g( sum_{k<d} (t_k + 1/2)/N + (t_d + 1/2)/N_last ).
+ * Partial sums after k equal directions take k (N - 1) + 1 values, so the
+ * dimension iteration merges terms and carries their weights (one window
+ * average per direction); the result is evaluated for every parameter set of g.
+ * Outer functions (params per set, FP64):
+ *   QMC_SUM_POWER  g(s) = (b + c s)^(-p)         b, c, p   (b + c s > 0 on [0, d])
+ *   QMC_SUM_GAUSS  g(s) = exp(-c^2 (s - w)^2)    c, w
+ * QMC_FP32_COMPENSATED takes the exponent in FP64 and its fractional power in FP32. */
+typedef enum { QMC_SUM_POWER = 0, QMC_SUM_GAUSS = 1 } qmc_sum_family;
+
+/* Workspace bytes of qmc_mdi_lr_sum at d, N: 35 vectors of d (N - 1) + 1 doubles
+ * (weights and convolution partials; when N_last = N the last direction merges
+ * into the states too). */
+qmc_status qmc_mdi_lr_sum_workspace_size(int32_t d, int32_t N, size_t* bytes);
+
+/* Q for nsets parameter sets of g (two launches on `stream`).
+ *   d in [1, 1024]; N, N_last in [1, 2^20]; d (N - 1) + 1 <= 2^20
+ *   params  device double[nsets][3] (power) or [nsets][2] (Gaussian)
+ *   q_out   device double[nsets];  nsets in [1, 2^24]
+ *   ws      device workspace of qmc_mdi_lr_sum_workspace_size(d, N) bytes */
+qmc_status qmc_mdi_lr_sum(int32_t d, int32_t N, int32_t N_last, int32_t gfamily, const double* params,
+                          int32_t nsets, int32_t precision, double* q_out, void* ws, size_t ws_bytes,
+                          void* stream);
+
 /* ---- lattice-quality criteria (Sec. 2.1) and constructions (Sec. 2.2) ----
  *
  * Both criteria of the paper are product-form lattice sums with Bernoulli factors,

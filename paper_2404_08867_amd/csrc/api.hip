@@ -50,6 +50,8 @@ constexpr int kMaxMdiSets = 1 << 24;     // MDI-LR: sets are spread over workgro
 constexpr int64_t kMaxNodes = (int64_t)1 << 20;
 constexpr int64_t kMaxExport = (int64_t)1 << 26;
 constexpr int64_t kMaxCbcN = (int64_t)1 << 26;   // CBC keeps n + n/2 doubles
+constexpr int32_t kMaxSumNodes = 1 << 20;
+constexpr int64_t kMaxSumStates = (int64_t)1 << 20;
 
 int param_count(int family, int d) {
     switch (family) {
@@ -370,6 +372,43 @@ qmc_status qmc_cbc(int32_t d, int64_t n, int32_t alpha, const double* a, int64_t
     if (s != QMC_OK) return s;
     qmc::CbcLaunch L{d, (uint32_t)n, alpha, a, z_out, s_out, ws};
     return from_hip(qmc::launch_cbc(L, (hipStream_t)stream), "qmc_cbc");
+}
+
+static qmc_status check_mdi_sum(int32_t d, int32_t N, int32_t N_last, int32_t gfamily) {
+    if (d < 1 || d > kMaxD) return fail(QMC_ERR_INVALID_ARG, "d = %d outside [1, %d]", d, kMaxD);
+    if (N < 1 || N > kMaxSumNodes) return fail(QMC_ERR_INVALID_ARG, "N = %d outside [1, %d]", N, kMaxSumNodes);
+    if (N_last < 1 || N_last > kMaxSumNodes)
+        return fail(QMC_ERR_INVALID_ARG, "N_last = %d outside [1, %d]", N_last, kMaxSumNodes);
+    if ((int64_t)d * (N - 1) + 1 > kMaxSumStates)
+        return fail(QMC_ERR_INVALID_ARG, "d (N - 1) + 1 states above 2^20");
+    if (gfamily != QMC_SUM_POWER && gfamily != QMC_SUM_GAUSS)
+        return fail(QMC_ERR_INVALID_ARG, "unknown sum family %d", gfamily);
+    return QMC_OK;
+}
+
+qmc_status qmc_mdi_lr_sum_workspace_size(int32_t d, int32_t N, size_t* bytes) {
+    qmc_status s = check_mdi_sum(d, N, 1, QMC_SUM_POWER);
+    if (s != QMC_OK) return s;
+    if (!bytes) return fail(QMC_ERR_INVALID_ARG, "bytes must be non-NULL");
+    *bytes = qmc::mdi_sum_workspace_bytes(d, N);
+    return ok();
+}
+
+qmc_status qmc_mdi_lr_sum(int32_t d, int32_t N, int32_t N_last, int32_t gfamily, const double* params,
+                          int32_t nsets, int32_t precision, double* q_out, void* ws, size_t ws_bytes,
+                          void* stream) {
+    qmc_status s = check_mdi_sum(d, N, N_last, gfamily);
+    if (s != QMC_OK) return s;
+    if (nsets < 1 || nsets > kMaxMdiSets)
+        return fail(QMC_ERR_INVALID_ARG, "nsets = %d outside [1, %d]", nsets, kMaxMdiSets);
+    if (precision != QMC_FP64 && precision != QMC_FP32_COMPENSATED)
+        return fail(QMC_ERR_INVALID_ARG, "unknown precision %d", precision);
+    if (!params || !q_out) return fail(QMC_ERR_INVALID_ARG, "params and q_out must be non-NULL");
+    s = check_workspace(ws, ws_bytes, qmc::mdi_sum_workspace_bytes(d, N));
+    if (s != QMC_OK) return s;
+    qmc::MdiSumLaunch L{d, N, N_last, gfamily, params, gfamily == QMC_SUM_POWER ? 3 : 2, nsets,
+                        precision == QMC_FP32_COMPENSATED, q_out, ws};
+    return from_hip(qmc::launch_mdi_sum(L, (hipStream_t)stream), "qmc_mdi_lr_sum");
 }
 
 qmc_status qmc_lattice_points(int32_t d, int64_t n, const int64_t* z, int64_t i0, int64_t count,

@@ -126,6 +126,21 @@ hipError_t launch_cbc(const CbcLaunch& L, hipStream_t stream);
 // table of kMaxSumSets generating vectors and the CBC vectors (n + n/2 doubles).
 size_t criteria_workspace_bytes(int d, int64_t n);
 
+// MDI-LR for integrands of the coordinate sum (mdi_sum.hip).
+struct MdiSumLaunch {
+    int d, N, N_last;
+    int gfamily;           // 0 power (b, c, p), 1 Gaussian (c, w)
+    const double* params;  // [nsets][P]
+    int P;
+    int nsets;
+    bool fp32;
+    double* q_out;
+    void* ws;
+};
+hipError_t launch_mdi_sum(const MdiSumLaunch& L, hipStream_t stream);
+// The states after d - 1 directions and two buffers of the same size.
+size_t mdi_sum_workspace_bytes(int d, int N);
+
 int device_cu_count();
 
 }  // namespace qmc

@@ -1,0 +1,217 @@
+// MDI-LR for integrands of the coordinate sum, f(x) = g(x_1 + ... + x_d) (Test 7's
+// f_6 = (1 + sum x)^-(d+1)), on the improved tensor midpoint rule with N nodes
+// (t + 1/2)/N in each of the first d - 1 directions and N_last in the last.
+//
+// After k equal directions the partial sum is (T + k/2)/N for an integer T in
+// [0, k (N - 1)]: the terms of the dimension iteration that share T merge, and
+// the iteration carries c_k[T], the fraction of index tuples with sum T.  Each
+// direction replaces c by its average over a window of N states (Algorithm 1's
+// sweep with merged terms).  Then
+//   Q = sum_T c_{d-1}[T] (1/N_last) sum_u g((T + (d-1)/2)/N + (u + 1/2)/N_last).
+//
+// When N_last = N the last direction's nodes lie on the same grid, so the pairs
+// (T, u) merge into T + u as well: one more window step gives c_d, and
+//   Q = sum_T c_d[T] g((T + d/2)/N)
+// needs N times fewer evaluations of g.  The weights are built once for all
+// parameter sets; then one workgroup per set evaluates Q.
+#include "common.hpp"
+#include "families.hpp"
+#include "kernels.hpp"
+
+namespace qmc {
+
+// The weights after k equal directions are the k-fold self-convolution of the
+// N-point window (each direction averages the previous weights over N states).
+// Rather than k sequential window steps -- one short, serial pass per direction,
+// a poor fit for 256 CUs -- the launcher forms them by repeated squaring:
+// O(log k) convolutions, each parallel over its outputs.  Each output adds
+// positive terms in ascending order, so every state keeps full relative accuracy
+// and the result does not depend on the schedule.
+// A convolution out = a * b is split over (output tiles) x (segments of i):
+// conv_partial_kernel stages a segment of a and the matching window of b in LDS,
+// and each thread accumulates kConvR outputs kConvBlock apart (independent FMA
+// chains, conflict-free LDS reads, a[i] broadcast); conv_reduce_kernel adds the
+// segments in order.  Per output: i ascending within a segment, segments in order.
+constexpr int kConvBlock = 256;
+constexpr int kConvR = 4;
+constexpr int kConvOut = kConvBlock * kConvR;  // outputs per workgroup
+constexpr int kConvChunk = 1024;               // i values staged in LDS at once
+constexpr int kConvMaxSeg = 32;
+
+// partial[s][T] = sum over i in segment s of a[i] b[T - i], T < Lo = La + Lb - 1.
+__global__ __launch_bounds__(kConvBlock) void conv_partial_kernel(const double* a, int La,
+                                                                 const double* b, int Lb,
+                                                                 int seg_len, double* partial) {
+    __shared__ double sa[kConvChunk];
+    __shared__ double sb[kConvOut + kConvChunk - 1];
+    const int tid = threadIdx.x;
+    const int Lo = La + Lb - 1;
+    const int TB = blockIdx.x * kConvOut;
+    const int seg = blockIdx.y;
+    const int s0 = seg * seg_len, s1 = min(La, s0 + seg_len);
+    double acc[kConvR];
+#pragma unroll
+    for (int r = 0; r < kConvR; ++r) acc[r] = 0.0;
+    for (int c0 = s0; c0 < s1; c0 += kConvChunk) {
+        const int ni = min(kConvChunk, s1 - c0);
+        // a[c0 .. c0 + ni) and b[TB - (c0 + ni - 1) .. TB + kConvOut - 1 - c0]
+        const int blo = TB - (c0 + ni - 1);
+        const int nb = kConvOut + ni - 1;
+        __syncthreads();  // the previous chunk's reads are done
+        for (int k = tid; k < ni; k += kConvBlock) sa[k] = a[c0 + k];
+        for (int k = tid; k < nb; k += kConvBlock) {
+            const int idx = blo + k;
+            sb[k] = (idx >= 0 && idx < Lb) ? b[idx] : 0.0;
+        }
+        __syncthreads();
+        // output T = TB + tid + r kConvBlock needs b[T - i] = sb[tid + r kConvBlock + ni - 1 - k]
+        for (int k = 0; k < ni; ++k) {
+            const double ai = sa[k];
+#pragma unroll
+            for (int r = 0; r < kConvR; ++r)
+                acc[r] = fma(ai, sb[tid + r * kConvBlock + ni - 1 - k], acc[r]);
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < kConvR; ++r) {
+        const int T = TB + tid + r * kConvBlock;
+        if (T < Lo) partial[(size_t)seg * Lo + T] = acc[r];
+    }
+}
+
+// out[T] = sum_s partial[s][T], s ascending.
+__global__ __launch_bounds__(kConvBlock) void conv_reduce_kernel(const double* partial, int nseg,
+                                                                int Lo, double* out) {
+    const int T = blockIdx.x * kConvBlock + threadIdx.x;
+    if (T >= Lo) return;
+    double t = 0.0;
+    for (int s = 0; s < nseg; ++s) t += partial[(size_t)s * Lo + T];
+    out[T] = t;
+}
+
+// r = (1) and w = the window (1/N, ..., 1/N).
+__global__ __launch_bounds__(kConvBlock) void states_init_kernel(int N, double* r, double* w) {
+    const int t = blockIdx.x * kConvBlock + threadIdx.x;
+    if (t == 0) r[0] = 1.0;
+    if (t < N) w[t] = 1.0 / (double)N;
+}
+
+// g of the sum: power (b + c s)^-p, or Gaussian exp(-c^2 (s - w)^2).
+template <int GFAM, bool FP32>
+__device__ __forceinline__ double sum_g(const double* gp, double s) {
+    if constexpr (GFAM == 0) {
+        if constexpr (FP32) {
+            // 2^{-p log2(b + c s)}: the exponent in FP64, its fractional power in FP32
+            return exp2_split_f32(-gp[2] * log2(fma(gp[1], s, gp[0])));
+        } else {
+            return pow(fma(gp[1], s, gp[0]), -gp[2]);
+        }
+    } else {
+        const double y = gp[0] * (s - gp[1]);
+        if constexpr (FP32)
+            return exp2_split_f32(-kLog2e * y * y);
+        else
+            return exp(-y * y);
+    }
+}
+
+constexpr int kSumEvalBlock = 256;
+
+// Q of set blockIdx.x over `states` states and `nl` remaining nodes per state:
+//   Q = (1/nl) sum_T c[T] sum_{u < nl} g(T/N + off + u/nl).
+// Thread t owns the states T = t, t + kSumEvalBlock, ...; for each it sums g over
+// the nodes in order, weights by c[T], and the workgroup adds the thread sums in
+// the fixed order of block_sum.
+template <int GFAM, bool FP32>
+__global__ __launch_bounds__(kSumEvalBlock) void sum_eval_kernel(int states, int N, int nl, double off,
+                                                                const double* c,
+                                                                const double* params, int P,
+                                                                double* q_out) {
+    __shared__ double s_red[kSumEvalBlock / kWave];
+    const double* gp = params + (size_t)blockIdx.x * P;
+    const double invN = 1.0 / (double)N, invNl = 1.0 / (double)nl;
+    double acc = 0.0;
+    for (int T = threadIdx.x; T < states; T += kSumEvalBlock) {
+        const double s0 = fma((double)T, invN, off);
+        double inner = 0.0;
+        for (int u = 0; u < nl; ++u) inner += sum_g<GFAM, FP32>(gp, fma((double)u, invNl, s0));
+        acc = fma(c[T], inner, acc);
+    }
+    const double t = block_sum(acc, s_red);
+    if (threadIdx.x == 0) q_out[blockIdx.x] = t * invNl;
+}
+
+size_t mdi_sum_workspace_bytes(int d, int N) {
+    const size_t L = (size_t)d * (size_t)(N - 1) + 1;  // enough for both forms
+    // three rotating weight vectors and the convolution's segment partials
+    return ((3 + kConvMaxSeg) * L * sizeof(double) + 255) / 256 * 256;
+}
+
+template <int GFAM, bool FP32>
+static hipError_t launch_eval(const MdiSumLaunch& L, int states, int nl, double off, const double* c,
+                              hipStream_t stream) {
+    hipLaunchKernelGGL((sum_eval_kernel<GFAM, FP32>), dim3((unsigned)L.nsets), dim3(kSumEvalBlock), 0,
+                       stream, states, L.N, nl, off, c, L.params, L.P, L.q_out);
+    return hipGetLastError();
+}
+
+// out = a * b through `partial` (kConvMaxSeg * (La + Lb - 1) doubles).
+static hipError_t launch_conv(const double* a, int La, const double* b, int Lb, double* out,
+                              double* partial, hipStream_t stream) {
+    const int Lo = La + Lb - 1;
+    int nseg = (La + 63) / 64;
+    if (nseg > kConvMaxSeg) nseg = kConvMaxSeg;
+    const int seg_len = (La + nseg - 1) / nseg;
+    nseg = (La + seg_len - 1) / seg_len;
+    hipLaunchKernelGGL(conv_partial_kernel, dim3((Lo + kConvOut - 1) / kConvOut, nseg), dim3(kConvBlock),
+                       0, stream, a, La, b, Lb, seg_len, partial);
+    hipLaunchKernelGGL(conv_reduce_kernel, dim3((Lo + kConvBlock - 1) / kConvBlock), dim3(kConvBlock), 0,
+                       stream, partial, nseg, Lo, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_mdi_sum(const MdiSumLaunch& L, hipStream_t stream) {
+    // Equal node counts merge the last direction too.
+    const bool merge = L.N_last == L.N;
+    const int steps = merge ? L.d : L.d - 1;
+    const int nl = merge ? 1 : L.N_last;
+    const double off = merge ? 0.5 * (double)L.d / (double)L.N
+                             : 0.5 * (double)(L.d - 1) / (double)L.N + 0.5 / (double)L.N_last;
+    // Three buffers of d (N - 1) + 1 doubles rotate between the running result R,
+    // the running square B and the output of each convolution.
+    const size_t cap = (size_t)L.d * (size_t)(L.N - 1) + 1;
+    double* buf[3] = {(double*)L.ws, (double*)L.ws + cap, (double*)L.ws + 2 * cap};
+    double* partial = (double*)L.ws + 3 * cap;
+    double *R = buf[0], *B = buf[1], *T = buf[2];
+    int LR = 1, LB = L.N;
+    hipLaunchKernelGGL(states_init_kernel, dim3((L.N + kConvBlock - 1) / kConvBlock), dim3(kConvBlock),
+                       0, stream, L.N, R, B);
+    hipError_t e = hipGetLastError();
+    for (int bits = steps; bits > 0 && e == hipSuccess; bits >>= 1) {
+        if (bits & 1) {
+            // the shorter operand is staged as a (the convolution is symmetric)
+            e = LR <= LB ? launch_conv(R, LR, B, LB, T, partial, stream)
+                         : launch_conv(B, LB, R, LR, T, partial, stream);
+            double* t = R;
+            R = T;
+            T = t;
+            LR += LB - 1;
+        }
+        if ((bits >> 1) > 0 && e == hipSuccess) {
+            e = launch_conv(B, LB, B, LB, T, partial, stream);
+            double* t = B;
+            B = T;
+            T = t;
+            LB = 2 * LB - 1;
+        }
+    }
+    if (e != hipSuccess) return e;
+    // LR = steps (N - 1) + 1 states.
+    if (L.gfamily == 0)
+        return L.fp32 ? launch_eval<0, true>(L, LR, nl, off, R, stream)
+                      : launch_eval<0, false>(L, LR, nl, off, R, stream);
+    return L.fp32 ? launch_eval<1, true>(L, LR, nl, off, R, stream)
+                  : launch_eval<1, false>(L, LR, nl, off, R, stream);
+}
+
+}  // namespace qmc

@@ -63,6 +63,8 @@ def lib() -> ctypes.CDLL:
         L.qmc_lattice_sum_shifts.argtypes = [i32, i64, dp, dp, i32, i32, dp, i32, dp, dp, vp, sz, vp]
         L.qmc_lattice_points.argtypes = [i32, i64, dp, i64, i64, dp, vp]
         L.qmc_criteria_workspace_size.argtypes = [i32, i64, vp]
+        L.qmc_mdi_lr_sum_workspace_size.argtypes = [i32, i32, vp]
+        L.qmc_mdi_lr_sum.argtypes = [i32, i32, i32, i32, dp, i32, i32, dp, vp, sz, vp]
         L.qmc_bernoulli_sum.argtypes = [i32, i64, dp, i32, i32, dp, dp, vp, sz, vp]
         L.qmc_korobov_search.argtypes = [i32, i64, i32, dp, i64, i32, dp, dp, vp, sz, vp]
         L.qmc_cbc.argtypes = [i32, i64, i32, dp, dp, dp, vp, sz, vp]
@@ -247,6 +249,39 @@ def lattice_sum_shifts(z, n: int, family: int, params, shifts, precision: int = 
                                         _ptr(q), _ptr(stats), w.ptr, w.nbytes, _stream()),
            "qmc_lattice_sum_shifts")
     return q, stats
+
+
+# --------------------------------------------- MDI-LR of the coordinate sum
+SUM_POWER, SUM_GAUSS = 0, 1
+
+
+def mdi_lr_sum_workspace_size(d: int, N: int) -> int:
+    out = ctypes.c_size_t(0)
+    _check(lib().qmc_mdi_lr_sum_workspace_size(d, N, ctypes.byref(out)), "qmc_mdi_lr_sum_workspace_size")
+    return int(out.value)
+
+
+def mdi_lr_sum(d: int, N: int, N_last: int, gfamily: int, params, precision: int = FP64,
+               ws: Workspace | None = None, device="cuda", out=None):
+    """Tensor midpoint rule of g(x_1 + ... + x_d) (qmc_mdi_lr_sum) for each parameter
+    row of g: (b, c, p) for SUM_POWER, (c, w) for SUM_GAUSS."""
+    torch = _torch()
+    pt = _dev(params, torch.float64, device)
+    squeeze = pt.dim() == 1
+    if squeeze:
+        pt = pt.unsqueeze(0)
+    nsets = int(pt.shape[0])
+    q = out if out is not None else torch.empty(nsets, dtype=torch.float64, device=device)
+    if ws is None:
+        need = mdi_lr_sum_workspace_size(d, N)
+        key = ("mdi_sum", str(device), _torch().cuda.current_stream(device).cuda_stream)
+        ws = _ws_cache.get(key)
+        if ws is None or ws.nbytes < need:
+            ws = Workspace(need, device)
+            _ws_cache[key] = ws
+    _check(lib().qmc_mdi_lr_sum(d, N, N_last, gfamily, _ptr(pt), nsets, precision, _ptr(q), ws.ptr,
+                                ws.nbytes, _stream()), "qmc_mdi_lr_sum")
+    return q[0] if squeeze and out is None else q
 
 
 # ----------------------------------------------------------- lattice criteria

@@ -27,6 +27,10 @@ Workloads (k = 0..4):
                          u ~ U[0,1], c ~ U[0,2]
   5 shifts_d20_peak      the plain_d20_peak problem (its own seed) with R = 64
                          shifts Delta_r ~ U[0,1)^20 (random-shift ensemble)
+  6 mdi_sum_d100         MDI-LR of g(sum x), d=100, N=64 nodes in every direction,
+                         power g(s) = (b + c s)^-p; set 0 is Test 7's f_6
+                         (b = c = 1, p = d + 1), sets s >= 1 draw b ~ U[0.5,2],
+                         c ~ U[0.5,1.5], p ~ U[1, d+1]
 Lattice constructions (no random draws):
     korobov_search_d20   e^2 of eq. 2.12 for z(a), d=20, n=65521 (the largest
                          prime below 2^16), product weights gamma_j = j^-2,
@@ -202,6 +206,26 @@ def shifts_d20_peak(nshifts: int = 64) -> ShiftEnsemble:
     rng = np.random.default_rng(SEED_BASE + 5)
     shifts = rng.random((nshifts, base.d))
     return ShiftEnsemble("shifts_d20_peak", base.d, base.n, base.a, base.family, base.params, shifts)
+
+
+@dataclass
+class MdiSum:
+    name: str
+    d: int
+    N: int
+    N_last: int
+    gfamily: int
+    params: np.ndarray  # [nsets, 3]
+
+
+def mdi_sum_d100(nsets: int = 4096) -> MdiSum:
+    """Set s does not depend on nsets (row s of one draw); row 0 is f_6."""
+    d, N = 100, 64
+    rng = np.random.default_rng(SEED_BASE + 6)
+    r = rng.random((nsets, 3))
+    params = np.stack([0.5 + 1.5 * r[:, 0], 0.5 + r[:, 1], 1.0 + d * r[:, 2]], axis=1)
+    params[0] = (1.0, 1.0, d + 1.0)
+    return MdiSum("mdi_sum_d100", d, N, N, 0, params)
 
 
 @dataclass

@@ -1,0 +1,46 @@
+"""Parity of MDI-LR for integrands of the coordinate sum (qmc_mdi_lr_sum) with the
+FP64 oracle.  Every term is positive, so the bar is relative: 1e-12 (QMC_FP64)
+and 1e-6 (QMC_FP32_COMPENSATED)."""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2404_08867_amd import qmc
+from paper_2404_08867_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+TOL = {qmc.FP64: 1e-12, qmc.FP32_COMPENSATED: 1e-6}
+PRECS = [qmc.FP64, qmc.FP32_COMPENSATED]
+
+
+# (d, N, N_last): one direction; N = 1 (every state merges); a last count of
+# a + 1 (eq. 3.5 with n = 1 + a^d); states past one pass of the window loop;
+# Test 7's shape; more states than LDS holds (workspace buffers).
+SHAPES = [(1, 1, 17), (5, 1, 3), (4, 10, 11), (12, 9, 9), (100, 64, 64), (300, 64, 65)]
+PARAMS = {qmc.SUM_POWER: [[1.0, 1.0, 5.0], [0.7, 1.3, 2.5], [2.0, 0.4, 0.5]],
+          qmc.SUM_GAUSS: [[0.9, 0.3], [0.2, 1.7], [1.5, 4.0]]}
+
+
+@pytest.mark.parametrize("precision", PRECS)
+@pytest.mark.parametrize("gfam", [qmc.SUM_POWER, qmc.SUM_GAUSS])
+@pytest.mark.parametrize("d,N,N_last", SHAPES)
+def test_mdi_sum_matches_oracle(precision, gfam, d, N, N_last):
+    params = np.array(PARAMS[gfam], dtype=np.float64)
+    if gfam == qmc.SUM_GAUSS:
+        params[:, 1] *= d / 2  # centre the Gaussians where the sum lives
+    q = qmc.mdi_lr_sum(d, N, N_last, gfam, params, precision).cpu().numpy()
+    for s in range(len(params)):
+        qo = O.mdi_sum(d, N, N_last, gfam, params[s])
+        assert abs(q[s] - qo) <= TOL[precision] * abs(qo), (s, q[s], qo)
+
+
+@pytest.mark.parametrize("precision", PRECS)
+def test_mdi_sum_d100_full_size_sampled(precision):
+    """The benchmark's workload (4096 sets, set 0 = f_6): sampled sets."""
+    w = W.mdi_sum_d100()
+    q = qmc.mdi_lr_sum(w.d, w.N, w.N_last, w.gfamily, w.params, precision).cpu().numpy()
+    assert q.size == len(w.params) and np.all(q > 0) and np.all(np.isfinite(q))
+    for s in (0, 1, 2047, 4095):
+        qo = O.mdi_sum(w.d, w.N, w.N_last, w.gfamily, w.params[s])
+        assert abs(q[s] - qo) <= TOL[precision] * abs(qo), (s, q[s], qo)
