@@ -29,13 +29,16 @@ __device__ __forceinline__ uint32_t gcd_u32(uint32_t a, uint32_t b) {
 
 // --------------------------------------------------------------------------
 // Korobov generating vectors z(a) = (1, a, a^2, ..., a^{d-1}) mod n (Sec. 2.2) for
-// a = a0 + i, i < count: one thread per candidate, row i of the table.
+// a = a0 + i, i < count: one thread per candidate, row i of the table, and
+// coprime[i] = (gcd(a, n) == 1) for the selection.
 // --------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void korobov_table_kernel(int d, uint32_t n, double inv_n,
-                                                           int64_t a0, int count, int64_t* z) {
+                                                           int64_t a0, int count, int64_t* z,
+                                                           uint8_t* coprime) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= count) return;
     const uint64_t a = (uint64_t)(a0 + i) % n;
+    coprime[i] = gcd_u32((uint32_t)a, n) == 1 ? 1 : 0;
     int64_t* row = z + (size_t)i * d;
     uint64_t v = 1 % n;
     for (int j = 0; j < d; ++j) {
@@ -46,16 +49,18 @@ __global__ __launch_bounds__(256) void korobov_table_kernel(int d, uint32_t n, d
 
 // --------------------------------------------------------------------------
 // Selection over v[0..count) for candidates c = c_first + i.  One workgroup.
-// Writes +infinity over the non-candidates in v, then
+// If `coprime` is not null, writes +infinity over the entries it marks 0; then
 //   *best_value = v[i*],  *best_cand_f64 = c_first + i*  (if not null),
 //   *best_cand_i64 = c_first + i*                        (if not null),
 // i* the smallest index within kTieRel of the minimum (i* = 0 and +infinity when
-// no candidate is coprime to n).
+// no candidate is coprime to n).  The coprimality test itself runs where the
+// candidates are spread over many workgroups (the table and CBC kernels).
 // --------------------------------------------------------------------------
 constexpr int kSelectBlock = 1024;
 
 __global__ __launch_bounds__(kSelectBlock) void select_kernel(double* v, int count, int64_t c_first,
-                                                             uint32_t n, double* best_value,
+                                                             const uint8_t* coprime,
+                                                             double* best_value,
                                                              double* best_cand_f64,
                                                              int64_t* best_cand_i64) {
     __shared__ double s_min[kSelectBlock / kWave];
@@ -67,7 +72,7 @@ __global__ __launch_bounds__(kSelectBlock) void select_kernel(double* v, int cou
     double m = INFINITY;
     for (int i = tid; i < count; i += kSelectBlock) {
         double x = v[i];
-        if (gcd_u32((uint32_t)((c_first + i) % n), n) != 1) {
+        if (coprime && !coprime[i]) {
             x = INFINITY;
             v[i] = x;  // the same thread reads v[i] again in pass 2
         }
@@ -170,7 +175,8 @@ __global__ __launch_bounds__(kCbcBlock) void cbc_eval_kernel(uint32_t n, double 
         double t = 0.0;
 #pragma unroll
         for (int w = 0; w < W; ++w) t += s_acc[c * W + w];
-        s_cand[g0 + c] = t * inv_n;
+        const bool ok = gcd_u32((uint32_t)((cbeg + c) % n), n) == 1;
+        s_cand[g0 + c] = ok ? t * inv_n : INFINITY;
     }
 }
 
@@ -198,7 +204,9 @@ __global__ __launch_bounds__(256) void cbc_update_kernel(uint32_t n, double inv_
 // Launchers
 // --------------------------------------------------------------------------
 size_t criteria_workspace_bytes(int d, int64_t n) {
-    const size_t table = (size_t)kMaxSumSets * (size_t)d * sizeof(int64_t);
+    // search: a table of kMaxSumSets vectors and one coprimality byte per
+    // candidate (< n); CBC: the running product and the candidates' values
+    const size_t table = (size_t)kMaxSumSets * (size_t)d * sizeof(int64_t) + (size_t)n;
     const size_t cbc = ((size_t)n + (size_t)n / 2 + 2) * sizeof(double);
     return kZeroBytes + ((table > cbc ? table : cbc) + 255) / 256 * 256;
 }
@@ -225,10 +233,11 @@ hipError_t launch_bernoulli_sum(const BernoulliLaunch& L, hipStream_t stream) {
 hipError_t launch_korobov_search(const SearchLaunch& L, hipStream_t stream) {
     const double inv_n = 1.0 / (double)L.n;
     int64_t* table = (int64_t*)((char*)L.ws + kZeroBytes);
+    uint8_t* coprime = (uint8_t*)(table + (size_t)kMaxSumSets * L.d);
     for (int64_t c0 = 0; c0 < L.count; c0 += kMaxSumSets) {
         const int cnt = (int)((L.count - c0) < kMaxSumSets ? (L.count - c0) : kMaxSumSets);
         hipLaunchKernelGGL(korobov_table_kernel, dim3((cnt + 255) / 256), dim3(256), 0, stream, L.d,
-                           L.n, inv_n, L.a0 + c0, cnt, table);
+                           L.n, inv_n, L.a0 + c0, cnt, table, coprime + c0);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
         BernoulliLaunch B{L.d, L.n, table, cnt, L.alpha, L.a, L.s_out + c0, L.ws};
@@ -236,7 +245,7 @@ hipError_t launch_korobov_search(const SearchLaunch& L, hipStream_t stream) {
         if (e != hipSuccess) return e;
     }
     hipLaunchKernelGGL(select_kernel, dim3(1), dim3(kSelectBlock), 0, stream, L.s_out, L.count,
-                       L.a0, L.n, L.best_out, L.best_out + 1, (int64_t*)nullptr);
+                       L.a0, (const uint8_t*)coprime, L.best_out, L.best_out + 1, (int64_t*)nullptr);
     return hipGetLastError();
 }
 
@@ -254,7 +263,8 @@ static hipError_t launch_cbc_a(const CbcLaunch& L, hipStream_t stream) {
                            dim3(kCbcBlock), 0, stream, L.n, inv_n, L.a, j, p, (int64_t)1, ncand,
                            cand);
         hipLaunchKernelGGL(select_kernel, dim3(1), dim3(kSelectBlock), 0, stream, cand, ncand,
-                           (int64_t)1, L.n, L.s_out + j, (double*)nullptr, L.z_out + j);
+                           (int64_t)1, (const uint8_t*)nullptr, L.s_out + j, (double*)nullptr,
+                           L.z_out + j);
         hipLaunchKernelGGL((cbc_update_kernel<ALPHA>), dim3((L.n + 255) / 256), dim3(256), 0, stream,
                            L.n, inv_n, L.a, j, L.z_out, p);
         e = hipGetLastError();

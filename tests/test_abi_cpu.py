@@ -120,9 +120,9 @@ def test_invalid_arguments_fail_before_launch():
 
 
 def test_criteria_workspace_size():
-    # zero region, then the larger of 4096 generating vectors and n + n/2 doubles
+    # zero region, then the larger of (4096 generating vectors + n mask bytes) and n + n/2 doubles
     def expect(d, n):
-        return (4 << 20) + (max(4096 * d * 8, (n + n // 2 + 2) * 8) + 255) // 256 * 256
+        return (4 << 20) + (max(4096 * d * 8 + n, (n + n // 2 + 2) * 8) + 255) // 256 * 256
     for d, n in [(20, 65521), (200, 1009), (2, 1 << 24), (1024, 3)]:
         assert qmc.criteria_workspace_size(d, n) == expect(d, n)
 
