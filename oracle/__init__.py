@@ -64,6 +64,8 @@ def _load():
     lib.oracle_cbc.argtypes = [i32, i64, dp, ctypes.c_double, dp, dp]
     lib.oracle_mdi_sum_brute.argtypes = [i32, i64, i64, i32, dp, dp]
     lib.oracle_mdi_sum_sweep.argtypes = [i32, i64, i64, i32, dp, dp, dp]
+    lib.oracle_implr_coords.argtypes = [i32, i64, dp, dp]
+    lib.oracle_implr_grid.argtypes = [i32, i64, dp, dp, dp, dp]
     lib.oracle_mdi_dims.argtypes = [i32, dp, i64, dp]
     lib.oracle_mdi_lr_brute.argtypes = [i32, dp, i32, dp, dp]
     lib.oracle_mdi_lr_sweep.argtypes = [i32, dp, i32, dp, dp]
@@ -231,6 +233,24 @@ def mdi_sum(d: int, N: int, N_last: int, gfam: int, gp, counts: bool = False):
     c = np.zeros((d - 1) * (N - 1) + 1) if counts else None
     _check(_load().oracle_mdi_sum_sweep(d, N, N_last, gfam, _ptr(gp), _ptr(q), _ptr(c)), "mdi_sum")
     return (float(q[0]), c) if counts else float(q[0])
+
+
+def implr_coords(z, n: int) -> np.ndarray:
+    """Integer numerators [n, d] of the transformed coordinates of Theorem 3.1."""
+    z = _i64(z)
+    u = np.zeros((n, z.size), dtype=np.int64)
+    _check(_load().oracle_implr_coords(z.size, n, _ptr(z), _ptr(u)), "implr_coords")
+    return u
+
+
+def implr_grid(z, n: int):
+    """(counts per direction, n*, distinct transformed points) of the improved rule."""
+    z = _i64(z)
+    counts = np.zeros(z.size, dtype=np.int64)
+    out = np.zeros(2, dtype=np.int64)
+    _check(_load().oracle_implr_grid(z.size, n, _ptr(z), _ptr(counts), _ptr(out[0:]), _ptr(out[1:])),
+           "implr_grid")
+    return counts, int(out[0]), int(out[1])
 
 
 def mdi_dims(z, n: int) -> np.ndarray:

@@ -581,6 +581,96 @@ int oracle_mdi_sum_sweep(int d, int64_t N, int64_t N_last, int gfam, const doubl
 }
 
 /* ------------------------------------------------------------------------- */
+/* The affine transformation of Theorem 3.1 and the improved lattice rule's   */
+/* point count (Sec. 3.2).  By the theorem's proof (its eq. 13) the transformed */
+/* coordinates of lattice point j are                                          */
+/*   y_{j,i} = | floor(j z_{i+1}/n)/z_{i+1} - floor(j z_i/n)/z_i |,  i < d,      */
+/*   y_{j,d} = (z_d/n) floor(j - (n/z_d) floor(j z_d/n)),                       */
+/* all rationals with a fixed denominator per direction: z_i z_{i+1} (i < d)   */
+/* and n (i = d).  The oracle keeps the integer numerators                     */
+/*   u_{j,i} = | floor(j z_{i+1}/n) z_i - floor(j z_i/n) z_{i+1} |,              */
+/*   u_{j,d} = z_d floor(((j z_d) mod n) / z_d),                               */
+/* so every comparison is exact.  The tensor grid of the improved rule is the   */
+/* product of the per-direction value sets; n* is the number of its points that */
+/* no lattice point reaches (the ghost points).                                 */
+/* ------------------------------------------------------------------------- */
+int oracle_implr_coords(int d, int64_t n, const int64_t* z, int64_t* u_out) {
+    if (d < 1 || n < 1 || !z || !u_out) return OR_BAD_ARG;
+    for (int i = 0; i < d; ++i)
+        if (z[i] < 1 || z[i] >= n) return OR_BAD_ARG;
+    for (int64_t j = 0; j < n; ++j) {
+        for (int i = 0; i + 1 < d; ++i) {
+            const int64_t fi = (j * z[i]) / n, fi1 = (j * z[i + 1]) / n;
+            const int64_t v = fi1 * z[i] - fi * z[i + 1];
+            u_out[j * d + i] = v < 0 ? -v : v;
+        }
+        u_out[j * d + d - 1] = z[d - 1] * (((j * z[d - 1]) % n) / z[d - 1]);
+    }
+    return OR_OK;
+}
+
+static int cmp_i64(const void* a, const void* b) {
+    const int64_t x = *(const int64_t*)a, y = *(const int64_t*)b;
+    return x < y ? -1 : (x > y ? 1 : 0);
+}
+
+static const int64_t* g_rows;  /* qsort context: rows of d numerators */
+static int g_d;
+static int cmp_row(const void* a, const void* b) {
+    const int64_t ra = *(const int64_t*)a, rb = *(const int64_t*)b;
+    for (int i = 0; i < g_d; ++i) {
+        const int64_t x = g_rows[ra * g_d + i], y = g_rows[rb * g_d + i];
+        if (x != y) return x < y ? -1 : 1;
+    }
+    return 0;
+}
+
+/* counts_out[i] = number of distinct values of direction i; *nstar = product of
+ * the counts minus the number of distinct transformed points; *distinct = that
+ * number (n when the transformation is one-to-one on the lattice). */
+int oracle_implr_grid(int d, int64_t n, const int64_t* z, int64_t* counts_out, int64_t* nstar,
+                      int64_t* distinct) {
+    if (d < 1 || n < 1 || n > ((int64_t)1 << 24) || !z || !counts_out) return OR_BAD_ARG;
+    int64_t* u = (int64_t*)malloc(sizeof(int64_t) * (size_t)n * (size_t)d);
+    int64_t* col = (int64_t*)malloc(sizeof(int64_t) * (size_t)n);
+    int64_t* idx = (int64_t*)malloc(sizeof(int64_t) * (size_t)n);
+    if (!u || !col || !idx) {
+        free(u);
+        free(col);
+        free(idx);
+        return OR_TOO_BIG;
+    }
+    int rc = oracle_implr_coords(d, n, z, u);
+    if (rc != OR_OK) {
+        free(u);
+        free(col);
+        free(idx);
+        return rc;
+    }
+    double grid = 1.0;
+    for (int i = 0; i < d; ++i) {
+        for (int64_t j = 0; j < n; ++j) col[j] = u[j * d + i];
+        qsort(col, (size_t)n, sizeof(int64_t), cmp_i64);
+        int64_t c = 1;
+        for (int64_t j = 1; j < n; ++j) c += col[j] != col[j - 1];
+        counts_out[i] = c;
+        grid *= (double)c;
+    }
+    for (int64_t j = 0; j < n; ++j) idx[j] = j;
+    g_rows = u;
+    g_d = d;
+    qsort(idx, (size_t)n, sizeof(int64_t), cmp_row);
+    int64_t dist = 1;
+    for (int64_t j = 1; j < n; ++j) dist += cmp_row(&idx[j], &idx[j - 1]) != 0;
+    if (distinct) *distinct = dist;
+    if (nstar) *nstar = grid < 9.0e18 ? (int64_t)grid - dist : -1;
+    free(u);
+    free(col);
+    free(idx);
+    return OR_OK;
+}
+
+/* ------------------------------------------------------------------------- */
 /* Per-direction node counts of the transformed grid (eq. 3.5):              */
 /*   n_i = lcm(z_i, z_{i+1}) / min(z_i, z_{i+1}),  i < d;   n_d = ceil(n / z_d). */
 /* ------------------------------------------------------------------------- */
