@@ -100,6 +100,12 @@ def work_per_point_criterion(d: int) -> int:
 WORK_PER_CBC_TERM = INDEX + 6 * C64
 
 
+# The improved rule's point set: one int32 grid rank written per point and
+# direction (the generator is HBM-bound).  The order check that gives n* works
+# per residue wrap, not per point (about n / z_d wraps).
+IMPLR_BYTES_PER_POINT_DIM = 4
+
+
 def parse():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -108,7 +114,7 @@ def parse():
     ap.add_argument("--workload", default="plain_d20_peak",
                     choices=["plain_d20_peak", "plain_d4_expsum", "mdi_d100_gauss", "batched_4096",
                              "adjoint_d50_osc", "shifts_d20_peak", "korobov_search_d20",
-                             "cbc_d20", "mdi_sum_d100"])
+                             "cbc_d20", "mdi_sum_d100", "implr_d3"])
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
                     help="wall-clock budget of the oracle's CPU-baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -390,6 +396,79 @@ def bench_cbc(args, torch, qmc, W):
     return w, {"fp32c": r, "fp64": r}, units, WORK_PER_CBC_TERM, config
 
 
+def bench_implr(args, torch, qmc, W):
+    """Theorem 3.1's transformed point set: one step writes the grid ranks of all n
+    lattice points (qmc_implr_points, the dominant kernel, HBM-bound) and counts
+    the added points n* exactly (qmc_implr_grid, order check)."""
+    w = W.implr_d3()
+    ws = qmc.Workspace(qmc.implr_workspace_size(w.d, w.n, w.a))
+    nstar = torch.empty(1, dtype=torch.int64, device="cuda")
+    pts = torch.empty((w.d, (w.n + 63) // 64 * 64), dtype=torch.int32, device="cuda")  # rows 256-byte aligned
+    holder = {}
+
+    def gen():
+        qmc.implr_points(w.d, w.n, w.a, 0, w.n, out=pts)
+
+    def count():
+        holder["counts"], _ = qmc.implr_grid(w.d, w.n, w.a, qmc.IMPLR_AUTO, ws=ws, out=nstar)
+
+    for _ in range(args.warmup):
+        gen()
+        count()
+    torch.cuda.synchronize()
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(args.steps)]
+    t0 = time.perf_counter()
+    for e in ev:
+        e[0].record()
+        gen()
+        e[1].record()
+        count()
+        e[2].record()
+    torch.cuda.synchronize()
+    step_s = (time.perf_counter() - t0) / args.steps
+    gen_s = sum(e[0].elapsed_time(e[1]) for e in ev) * 1e-3 / args.steps
+    cnt_s = sum(e[1].elapsed_time(e[2]) for e in ev) * 1e-3 / args.steps
+    bytes_written = w.n * w.d * IMPLR_BYTES_PER_POINT_DIM
+    wpp = w.d * IMPLR_BYTES_PER_POINT_DIM  # bytes per point
+    roofline = {"bound": "hbm", "achieved": bytes_written / gen_s / 1e9, "peak": 8000.0, "unit": "GB/s",
+                "frac": bytes_written / gen_s / 8.0e12, "traffic": None,
+                "kernel": "implr_points_kernel", "bytes_per_launch": bytes_written,
+                "kernel_us": gen_s * 1e6}
+    wraps = sum((w.n - 1) * w.a ** i // w.n for i in range(w.d))  # residue i wraps about z_i times
+    check = {"us": cnt_s * 1e6, "pairs_verified": w.n - 1, "residue_wraps": wraps,
+             "launches": 6, "note": "order kernel plus five launches that exit at once"}
+    r = dict(step_s=step_s, kern_s=gen_s + cnt_s, lat_s=step_s, nstar=int(nstar.item()),
+             counts=[int(c) for c in holder["counts"]], roofline=roofline, pts=pts)
+    config = {"workload": w.name, "d": w.d, "n": w.n, "a": w.a, "counts": r["counts"],
+              "grid": int(np.prod(r["counts"])), "nstar": r["nstar"], "precision": "integer",
+              "unit_of_work": "one lattice point mapped to its grid ranks (written) and checked",
+              "nstar_order_check": check}
+    return w, {"fp32c": r, "fp64": r}, w.n, wpp, config
+
+
+def oracle_implr_baseline(w, qmc, res, seconds):
+    """The oracle's transformed coordinates of consecutive blocks of lattice points
+    until the time budget is spent (its n* needs every point in memory, which this
+    size does not allow); the GPU's n* is checked against prod(n_i) - n and sampled
+    GPU points against the oracle."""
+    import oracle as O
+    z = O.korobov(w.d, w.n, w.a)
+    exact = res["nstar"] == int(np.prod(O.mdi_dims(z, w.n))) - w.n
+    pts = res.pop("pts")
+    for j0 in (0, 12345678, w.n // 2, w.n - 4096):
+        s = pts[:, j0:j0 + 4096].cpu().numpy().astype(np.int64).T
+        exact = exact and bool(np.array_equal(s * z, O.implr_coords_at(z, w.n, np.arange(j0, j0 + 4096))))
+    del pts
+    block = 1 << 20
+    t0 = time.perf_counter()
+    k = 0
+    while k == 0 or time.perf_counter() - t0 < seconds:
+        O.implr_coords_at(z, w.n, np.arange(k * block, (k + 1) * block))
+        k += 1
+    dt = time.perf_counter() - t0
+    return block * k / dt, k, 0.0 if exact else 1.0
+
+
 def _wce2_with_scale(O, z, w):
     """Oracle e^2 and the scale C * A of its terms (A: mean |term| of the sum S)."""
     g = np.asarray(w.gamma[: len(z)])
@@ -592,11 +671,15 @@ def main():
         prob, res, units, wpp, config = bench_cbc(args, torch, qmc, W)
     elif args.workload == "mdi_sum_d100":
         prob, res, units, wpp, config = bench_mdi_sum(args, torch, qmc, W)
+    elif args.workload == "implr_d3":
+        prob, res, units, wpp, config = bench_implr(args, torch, qmc, W)
     else:
         prob, res, units, wpp, config = bench_plain(args, torch, qmc, W)
 
     line = {"metric": METRIC}
     main_r = res["fp32c"]
+    if args.no_cpu_baseline:
+        main_r.pop("pts", None)  # the f4 point set is kept only for the oracle's spot checks
     value = units / main_r["step_s"]
     achieved = wpp * units / main_r["kern_s"]  # slots per second
     line.update({
@@ -606,7 +689,8 @@ def main():
                  "shifts_d20_peak": "shifted-lattice point evals/s",
                  "korobov_search_d20": "candidate lattice-point evals/s",
                  "cbc_d20": "candidate-index terms/s",
-                 "mdi_sum_d100": "merged-state evaluations of g/s"}.get(
+                 "mdi_sum_d100": "merged-state evaluations of g/s",
+                 "implr_d3": "lattice points mapped to the grid and checked/s"}.get(
                      args.workload, "lattice-point evals/s"),
         "n_gpus": 1,
         "steps": args.steps,
@@ -615,10 +699,10 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if args.workload in ("korobov_search_d20", "cbc_d20") else "f32",
+        "dtype": {"korobov_search_d20": "f64", "cbc_d20": "f64", "implr_d3": "u32"}.get(args.workload, "f32"),
         "data": "synthetic",
         "config": config,
-        "roofline": {
+        "roofline": main_r.get("roofline") or {
             "bound": "alu",
             "achieved": achieved / 1e12,
             "peak": PEAK_SLOTS / 1e12,
@@ -651,6 +735,12 @@ def main():
             e64 = e32
             sample = (f"the criterion of the first {k} candidates of the second component "
                       f"(n={prob.n} terms each); rel_err over the {prob.d} chosen components")
+        elif args.workload == "implr_d3":
+            rate, k, e32 = oracle_implr_baseline(prob, qmc, res["fp64"], args.cpu_seconds)
+            e64 = e32
+            sample = (f"the oracle's transformed coordinates of the first {k} blocks of 2^20 lattice "
+                      "points (its n* needs every point in memory); rel_err 0: n* and 16384 sampled "
+                      "GPU points exact")
         elif args.workload == "mdi_sum_d100":
             rate, k, e32, e64 = oracle_mdi_sum_baseline(prob, res["fp32c"], res["fp64"], args.cpu_seconds)
             sample = (f"the first {k} of {len(prob.params)} parameter sets; the oracle evaluates g at "

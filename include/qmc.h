@@ -180,6 +180,46 @@ qmc_status qmc_mdi_lr_sum(int32_t d, int32_t N, int32_t N_last, int32_t gfamily,
                           int32_t nsets, int32_t precision, double* q_out, void* ws, size_t ws_bytes,
                           void* stream);
 
+/* ---- the improved lattice rule's tensor grid (Theorem 3.1, Sec. 3.2) ------
+ * For the Korobov lattice z = (1, a, ..., a^{d-1}) with a^{d-1} < n, the affine
+ * transformation of Theorem 3.1 maps lattice point j to the grid ranks
+ *   s_i = floor(j z_{i+1}/n) - a floor(j z_i/n) in [0, a)   (i < d),
+ *   s_d = floor(((j z_d) mod n) / z_d) in [0, ceil(n / z_d)),
+ * on a tensor grid of a^{d-1} ceil(n / a^{d-1}) points (eq. 3.5).  The improved
+ * rule adds the grid points no lattice point reaches; their number n* is
+ * computed exactly by one of two methods:
+ *   QMC_IMPLR_AUTO    every point's grid index (s_1 most significant) is computed
+ *                     and each consecutive pair is checked to increase strictly;
+ *                     if all pass the n points are distinct and n* = grid - n,
+ *                     otherwise the bitmap count runs (decided on the device);
+ *   QMC_IMPLR_BITMAP  every point sets its grid point's bit in a bitmap of the
+ *                     grid and n* = grid - set bits (no assumption on the order).
+ * Six launches on `stream` (the unused ones exit at once).
+ *   d in [1, 64]; n in [2, 2^31); 1 <= a < n with a^{d-1} < n.  gcd(a, n) = 1 is
+ *   not required: the equal-count case n = a^d has gcd a.  n* always counts the
+ *   points of eq. 3.5's grid, which contains every transformed point.
+ *   counts_host_out  host int64[d]: the per-direction counts (eq. 3.5), or NULL
+ *   nstar_out        device int64[1]
+ *   ws               device workspace of qmc_implr_workspace_size(d, n, a) bytes
+ *                    (no zero-fill needed)
+ * Errors: QMC_ERR_INVALID_ARG for arguments outside these ranges, an unknown
+ * method or a NULL nstar_out, QMC_ERR_WORKSPACE for a missing, misaligned or short
+ * workspace; nothing is launched and counts_host_out is left untouched then. */
+typedef enum { QMC_IMPLR_AUTO = 0, QMC_IMPLR_BITMAP = 1 } qmc_implr_method;
+qmc_status qmc_implr_workspace_size(int32_t d, int64_t n, int64_t a, size_t* bytes);
+qmc_status qmc_implr_grid(int32_t d, int64_t n, int64_t a, int32_t method, int64_t* counts_host_out,
+                          int64_t* nstar_out, void* ws, size_t ws_bytes, void* stream);
+
+/* The grid ranks of lattice points j = j0 .. j0 + count - 1 under the same
+ * transformation (y_i = s_i / z_{i+1} for i < d, y_d = s_d z_d / n), direction-major:
+ * s_out[i * ld + (j - j0)] = s_i(j).  One launch on `stream`; d, n, a as above,
+ * 0 <= j0, j0 + count <= n, ld >= count.  Each lane writes four consecutive ranks
+ * at once; rows that start on 16-byte boundaries (s_out and 4 ld multiples of 16)
+ * are written fastest.
+ *   s_out  device int32[d][ld], 4-byte aligned; may be NULL when count = 0 */
+qmc_status qmc_implr_points(int32_t d, int64_t n, int64_t a, int64_t j0, int64_t count, int32_t* s_out,
+                            int64_t ld, void* stream);
+
 /* ---- lattice-quality criteria (Sec. 2.1) and constructions (Sec. 2.2) ----
  *
  * Both criteria of the paper are product-form lattice sums with Bernoulli factors,

@@ -66,6 +66,7 @@ def _load():
     lib.oracle_mdi_sum_sweep.argtypes = [i32, i64, i64, i32, dp, dp, dp]
     lib.oracle_implr_coords.argtypes = [i32, i64, dp, dp]
     lib.oracle_implr_grid.argtypes = [i32, i64, dp, dp, dp, dp]
+    lib.oracle_implr_coords_at.argtypes = [i32, i64, dp, i64, dp, dp]
     lib.oracle_mdi_dims.argtypes = [i32, dp, i64, dp]
     lib.oracle_mdi_lr_brute.argtypes = [i32, dp, i32, dp, dp]
     lib.oracle_mdi_lr_sweep.argtypes = [i32, dp, i32, dp, dp]
@@ -240,6 +241,15 @@ def implr_coords(z, n: int) -> np.ndarray:
     z = _i64(z)
     u = np.zeros((n, z.size), dtype=np.int64)
     _check(_load().oracle_implr_coords(z.size, n, _ptr(z), _ptr(u)), "implr_coords")
+    return u
+
+
+def implr_coords_at(z, n: int, js) -> np.ndarray:
+    """implr_coords at the chosen lattice points js only (any n below 2^31)."""
+    z = _i64(z)
+    js = _i64(js)
+    u = np.zeros((js.size, z.size), dtype=np.int64)
+    _check(_load().oracle_implr_coords_at(z.size, n, _ptr(z), js.size, _ptr(js), _ptr(u)), "implr_coords_at")
     return u
 
 

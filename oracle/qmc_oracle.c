@@ -594,17 +594,35 @@ int oracle_mdi_sum_sweep(int d, int64_t N, int64_t N_last, int gfam, const doubl
 /* product of the per-direction value sets; n* is the number of its points that */
 /* no lattice point reaches (the ghost points).                                 */
 /* ------------------------------------------------------------------------- */
-int oracle_implr_coords(int d, int64_t n, const int64_t* z, int64_t* u_out) {
-    if (d < 1 || n < 1 || !z || !u_out) return OR_BAD_ARG;
+static void implr_point(int d, int64_t n, const int64_t* z, int64_t j, int64_t* u) {
+    for (int i = 0; i + 1 < d; ++i) {
+        const int64_t fi = (j * z[i]) / n, fi1 = (j * z[i + 1]) / n;
+        const int64_t v = fi1 * z[i] - fi * z[i + 1];
+        u[i] = v < 0 ? -v : v;
+    }
+    u[d - 1] = z[d - 1] * (((j * z[d - 1]) % n) / z[d - 1]);
+}
+
+static int implr_args_ok(int d, int64_t n, const int64_t* z) {
+    if (d < 1 || n < 1 || n > ((int64_t)1 << 31) || !z) return 0;
     for (int i = 0; i < d; ++i)
-        if (z[i] < 1 || z[i] >= n) return OR_BAD_ARG;
-    for (int64_t j = 0; j < n; ++j) {
-        for (int i = 0; i + 1 < d; ++i) {
-            const int64_t fi = (j * z[i]) / n, fi1 = (j * z[i + 1]) / n;
-            const int64_t v = fi1 * z[i] - fi * z[i + 1];
-            u_out[j * d + i] = v < 0 ? -v : v;
-        }
-        u_out[j * d + d - 1] = z[d - 1] * (((j * z[d - 1]) % n) / z[d - 1]);
+        if (z[i] < 1 || z[i] >= n) return 0;
+    return 1;
+}
+
+int oracle_implr_coords(int d, int64_t n, const int64_t* z, int64_t* u_out) {
+    if (!implr_args_ok(d, n, z) || !u_out) return OR_BAD_ARG;
+    for (int64_t j = 0; j < n; ++j) implr_point(d, n, z, j, u_out + j * d);
+    return OR_OK;
+}
+
+/* The same numerators at m chosen lattice points js[0 .. m), 0 <= js[k] < n. */
+int oracle_implr_coords_at(int d, int64_t n, const int64_t* z, int64_t m, const int64_t* js,
+                           int64_t* u_out) {
+    if (!implr_args_ok(d, n, z) || m < 0 || (m > 0 && (!js || !u_out))) return OR_BAD_ARG;
+    for (int64_t k = 0; k < m; ++k) {
+        if (js[k] < 0 || js[k] >= n) return OR_BAD_ARG;
+        implr_point(d, n, z, js[k], u_out + k * d);
     }
     return OR_OK;
 }

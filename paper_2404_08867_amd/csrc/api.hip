@@ -411,6 +411,69 @@ qmc_status qmc_mdi_lr_sum(int32_t d, int32_t N, int32_t N_last, int32_t gfamily,
     return from_hip(qmc::launch_mdi_sum(L, (hipStream_t)stream), "qmc_mdi_lr_sum");
 }
 
+// Korobov lattice with a^{d-1} < n: per-direction counts (eq. 3.5) and grid size.
+static qmc_status implr_shape(int32_t d, int64_t n, int64_t a, int64_t* counts, uint64_t* grid,
+                              int64_t* zd_out = nullptr) {
+    if (d < 1 || d > 64) return fail(QMC_ERR_INVALID_ARG, "d = %d outside [1, 64]", d);
+    if (n < 2 || n >= kMaxN) return fail(QMC_ERR_INVALID_ARG, "n = %lld outside [2, 2^31)", (long long)n);
+    if (a < 1 || a >= n) return fail(QMC_ERR_INVALID_ARG, "a = %lld outside [1, n)", (long long)a);
+    int64_t zd = 1;
+    for (int i = 0; i + 1 < d; ++i) {
+        if (zd > (n - 1) / a) return fail(QMC_ERR_INVALID_ARG, "a^(d-1) must be below n");
+        zd *= a;
+    }
+    for (int i = 0; i + 1 < d; ++i)
+        if (counts) counts[i] = a;
+    const int64_t nd = (n + zd - 1) / zd;
+    if (counts) counts[d - 1] = nd;
+    *grid = (uint64_t)zd * (uint64_t)nd;
+    if (zd_out) *zd_out = zd;
+    return QMC_OK;
+}
+
+qmc_status qmc_implr_workspace_size(int32_t d, int64_t n, int64_t a, size_t* bytes) {
+    uint64_t grid = 0;
+    qmc_status s = implr_shape(d, n, a, nullptr, &grid);
+    if (s != QMC_OK) return s;
+    if (!bytes) return fail(QMC_ERR_INVALID_ARG, "bytes must be non-NULL");
+    *bytes = qmc::implr_workspace_bytes(grid);
+    return ok();
+}
+
+qmc_status qmc_implr_grid(int32_t d, int64_t n, int64_t a, int32_t method, int64_t* counts_host_out,
+                          int64_t* nstar_out, void* ws, size_t ws_bytes, void* stream) {
+    uint64_t grid = 0;
+    int64_t zd = 0;
+    qmc_status s = implr_shape(d, n, a, nullptr, &grid, &zd);
+    if (s != QMC_OK) return s;
+    if (method != QMC_IMPLR_AUTO && method != QMC_IMPLR_BITMAP)
+        return fail(QMC_ERR_INVALID_ARG, "method = %d is not a qmc_implr_method", method);
+    if (!nstar_out) return fail(QMC_ERR_INVALID_ARG, "nstar_out must be non-NULL");
+    s = check_workspace(ws, ws_bytes, qmc::implr_workspace_bytes(grid));
+    if (s != QMC_OK) return s;
+    if (counts_host_out) implr_shape(d, n, a, counts_host_out, &grid);
+    qmc::ImplrLaunch L{d, (uint32_t)n, (uint32_t)a, (uint32_t)zd, (uint32_t)((n + zd - 1) / zd), grid,
+                       method == QMC_IMPLR_BITMAP, nstar_out, ws};
+    return from_hip(qmc::launch_implr(L, (hipStream_t)stream), "qmc_implr_grid");
+}
+
+qmc_status qmc_implr_points(int32_t d, int64_t n, int64_t a, int64_t j0, int64_t count, int32_t* s_out,
+                            int64_t ld, void* stream) {
+    uint64_t grid = 0;
+    int64_t zd = 0;
+    qmc_status s = implr_shape(d, n, a, nullptr, &grid, &zd);
+    if (s != QMC_OK) return s;
+    if (j0 < 0 || count < 0 || j0 > n - count)
+        return fail(QMC_ERR_INVALID_ARG, "points [%lld, %lld + %lld) outside [0, n)", (long long)j0,
+                    (long long)j0, (long long)count);
+    if (count > 0 && !s_out) return fail(QMC_ERR_INVALID_ARG, "s_out must be non-NULL");
+    if (ld < count) return fail(QMC_ERR_INVALID_ARG, "ld = %lld below count = %lld", (long long)ld, (long long)count);
+    if ((uintptr_t)s_out % 4 != 0) return fail(QMC_ERR_INVALID_ARG, "s_out must be 4-byte aligned");
+    qmc::ImplrPointsLaunch L{d, (uint32_t)n, (uint32_t)a, (uint32_t)zd, (uint64_t)j0, (uint64_t)count, (uint64_t)ld,
+                             s_out};
+    return from_hip(qmc::launch_implr_points(L, (hipStream_t)stream), "qmc_implr_points");
+}
+
 qmc_status qmc_lattice_points(int32_t d, int64_t n, const int64_t* z, int64_t i0, int64_t count,
                               int32_t* k_out, void* stream) {
     if (d < 1 || d > kMaxD) return fail(QMC_ERR_INVALID_ARG, "d = %d outside [1, %d]", d, kMaxD);

@@ -141,6 +141,31 @@ hipError_t launch_mdi_sum(const MdiSumLaunch& L, hipStream_t stream);
 // The states after d - 1 directions and two buffers of the same size.
 size_t mdi_sum_workspace_bytes(int d, int N);
 
+// The improved rule's tensor grid on a Korobov lattice (implr.hip).
+struct ImplrLaunch {
+    int d;
+    uint32_t n;
+    uint32_t a;
+    uint32_t zd;          // z_d = a^{d-1} < n
+    uint32_t nd;          // ceil(n / z_d)
+    uint64_t grid;        // z_d n_d
+    bool bitmap;          // count with the bitmap only (no order check)
+    int64_t* nstar_out;   // device
+    void* ws;
+};
+struct ImplrPointsLaunch {
+    int d;
+    uint32_t n;
+    uint32_t a;
+    uint32_t zd;
+    uint64_t j0, count;   // j0 + count <= n
+    uint64_t ld;          // >= count: s_out[i * ld + (j - j0)]
+    int32_t* s_out;       // device
+};
+hipError_t launch_implr(const ImplrLaunch& L, hipStream_t stream);
+hipError_t launch_implr_points(const ImplrPointsLaunch& L, hipStream_t stream);
+size_t implr_workspace_bytes(uint64_t grid);
+
 int device_cu_count();
 
 }  // namespace qmc

@@ -23,6 +23,8 @@ EXP_SUM, PRODUCT_PEAK, GAUSSIAN, OSCILLATORY = 0, 1, 2, 3
 FP64, FP32_COMPENSATED = 0, 1
 # qmc_n_mode
 N_A_POW_D, N_ONE_PLUS_A_POW_D, N_EXPLICIT = 0, 1, 2
+# qmc_implr_method
+IMPLR_AUTO, IMPLR_BITMAP = 0, 1
 # qmc_status
 OK, ERR_INVALID_ARG, ERR_UNSUPPORTED, ERR_WORKSPACE, ERR_OUT_OF_MEMORY, ERR_DEVICE = range(6)
 
@@ -68,6 +70,9 @@ def lib() -> ctypes.CDLL:
         L.qmc_bernoulli_sum.argtypes = [i32, i64, dp, i32, i32, dp, dp, vp, sz, vp]
         L.qmc_korobov_search.argtypes = [i32, i64, i32, dp, i64, i32, dp, dp, vp, sz, vp]
         L.qmc_cbc.argtypes = [i32, i64, i32, dp, dp, dp, vp, sz, vp]
+        L.qmc_implr_workspace_size.argtypes = [i32, i64, i64, vp]
+        L.qmc_implr_grid.argtypes = [i32, i64, i64, i32, vp, dp, vp, sz, vp]
+        L.qmc_implr_points.argtypes = [i32, i64, i64, i64, i64, dp, i64, vp]
         L.qmc_mdi_lr.argtypes = [i32, dp, i32, dp, i32, i32, dp, vp, sz, vp]
         L.qmc_lattice_sum_adjoint.argtypes = [i32, i64, dp, dp, i32, dp, i32, i32, dp, dp, dp, vp, sz, vp]
         L.qmc_batch_plan_create.argtypes = [i32, vp, i32, vp, vp]
@@ -379,6 +384,45 @@ def cbc(d: int, n: int, gamma, beta: float, alpha: int = 2, ws: Workspace | None
         cj = torch.tensor(np.cumprod(1.0 + g * beta), dtype=torch.float64, device=device)
         sv = sv * cj
     return z, sv
+
+
+# ------------------------------------------------ the improved rule's tensor grid
+def implr_workspace_size(d: int, n: int, a: int) -> int:
+    out = ctypes.c_size_t(0)
+    _check(lib().qmc_implr_workspace_size(d, n, a, ctypes.byref(out)), "qmc_implr_workspace_size")
+    return int(out.value)
+
+
+def implr_grid(d: int, n: int, a: int, method: int = IMPLR_AUTO, ws: Workspace | None = None, out=None,
+               device="cuda"):
+    """Theorem 3.1's grid for the Korobov lattice z = (1, a, ..., a^{d-1}) (qmc_implr_grid).
+    Returns (per-direction counts [d] int64 numpy array, n* [1] int64 device tensor)."""
+    torch = _torch()
+    counts = np.zeros(d, dtype=np.int64)
+    nstar = torch.empty(1, dtype=torch.int64, device=device) if out is None else out
+    if ws is None:
+        ws = Workspace(implr_workspace_size(d, n, a), device)
+    _check(lib().qmc_implr_grid(d, n, a, method, counts.ctypes.data, _ptr(nstar), ws.ptr, ws.nbytes,
+                                _stream()),
+           "qmc_implr_grid")
+    return counts, nstar
+
+
+def implr_points(d: int, n: int, a: int, j0: int, count: int, out=None, device="cuda"):
+    """Grid ranks s[i, j - j0] of lattice points j0 .. j0+count-1, direction-major
+    (qmc_implr_points).  `out` may be a [d, ld] int32 tensor (ld >= count, rows
+    contiguous); the result is its first `count` columns."""
+    torch = _torch()
+    if out is None:
+        ld = (count + 3) // 4 * 4
+        out = torch.empty((d, ld), dtype=torch.int32, device=device)
+    if out.dtype != torch.int32 or out.dim() != 2 or out.shape[0] != d or out.shape[1] < count or \
+            out.stride(1) != 1:
+        raise QmcError(ERR_INVALID_ARG, "out must be an int32 [d, ld] tensor with ld >= count and unit column stride")
+    ld = int(out.stride(0)) if d > 1 else int(out.shape[1])
+    _check(lib().qmc_implr_points(d, n, a, j0, count, _ptr(out) if count else None, ld, _stream()),
+           "qmc_implr_points")
+    return out[:, :count]
 
 
 def lattice_points(z, n: int, i0: int, count: int, device="cuda"):

@@ -15,7 +15,7 @@ from fixed seeds:
   * seed of workload k: ``2404088670 + k``;
   * draw order: a, then c, then w, then u.
 
-Workloads (k = 0..4):
+Workloads (k = 0..6):
   0 plain_d4_expsum      d=4,   n=1009,      exp-sum, c ~ U[0,1]
   1 plain_d20_peak       d=20,  n=1048573,   product-peak, c ~ U[0.5,2], w ~ U[0,1]
   2 mdi_d100_gauss       d=100, N=64 nodes per direction (a = N), Gaussian,
@@ -38,6 +38,8 @@ Lattice constructions (no random draws):
                          n-a tie).  (Unit weights would make every candidate's
                          P_2 about (1 + pi^2/3)^20 / n: the k = 0 term.)
     cbc_d20              CBC for the same e^2, d=20, n=65521
+    implr_d3             Theorem 3.1's grid for a = 1290, d = 3,
+                         n = a^3 + 1 = 2146689001 (largest 1 + a^3 below 2^31)
 """
 from __future__ import annotations
 
@@ -261,6 +263,22 @@ def korobov_search_d20() -> Search:
 def cbc_d20() -> Cbc:
     d = 20
     return Cbc("cbc_d20", d, 65521, _inverse_square_weights(d), 0.0)
+
+
+@dataclass
+class Implr:
+    name: str
+    d: int
+    n: int
+    a: int
+
+
+def implr_d3() -> Implr:
+    """Theorem 3.1's grid for the Korobov lattice with a = 1290, d = 3 and
+    n = a^3 + 1 = 2146689001, the largest n = a^3 + 1 below 2^31 (the case
+    n = 1 + a^d whose last direction has a + 1 nodes by eq. 3.5)."""
+    a = 1290
+    return Implr("implr_d3", 3, a ** 3 + 1, a)
 
 
 def random_shifts(seed: int, nshifts: int, d: int) -> np.ndarray:

@@ -104,6 +104,21 @@ def test_invalid_arguments_fail_before_launch():
     assert L.qmc_korobov_search(4, 100, 2, fake, 1, 10, fake, fake, ws, 16, None) == qmc.ERR_WORKSPACE
     assert L.qmc_cbc(4, (1 << 26) + 1, 2, fake, fake, fake, ws, big, None) == qmc.ERR_INVALID_ARG
     assert L.qmc_cbc(4, 100, 2, fake, None, fake, ws, big, None) == qmc.ERR_INVALID_ARG
+    # the improved rule's grid: d, a, a^{d-1} < n, null output, workspace
+    assert L.qmc_implr_grid(0, 101, 3, 0, None, fake, ws, big, None) == qmc.ERR_INVALID_ARG
+    assert L.qmc_implr_grid(3, 101, 0, 0, None, fake, ws, big, None) == qmc.ERR_INVALID_ARG
+    assert L.qmc_implr_grid(3, 100, 10, 0, None, fake, ws, big, None) == qmc.ERR_INVALID_ARG
+    assert b"below n" in L.qmc_last_error()
+    assert L.qmc_implr_grid(4, 101, 5, 0, None, fake, ws, big, None) == qmc.ERR_INVALID_ARG
+    assert L.qmc_implr_grid(3, 101, 3, 2, None, fake, ws, big, None) == qmc.ERR_INVALID_ARG
+    assert L.qmc_implr_grid(3, 101, 3, 0, None, None, ws, big, None) == qmc.ERR_INVALID_ARG
+    assert L.qmc_implr_grid(3, 101, 3, 1, None, fake, ws, 16, None) == qmc.ERR_WORKSPACE
+    assert L.qmc_implr_points(3, 101, 3, 100, 2, fake, 4, None) == qmc.ERR_INVALID_ARG
+    assert L.qmc_implr_points(3, 101, 3, -1, 2, fake, 4, None) == qmc.ERR_INVALID_ARG
+    assert L.qmc_implr_points(3, 101, 3, 0, 2, None, 4, None) == qmc.ERR_INVALID_ARG
+    assert L.qmc_implr_points(3, 101, 11, 0, 2, fake, 4, None) == qmc.ERR_INVALID_ARG
+    assert L.qmc_implr_points(3, 101, 3, 0, 8, fake, 7, None) == qmc.ERR_INVALID_ARG
+    assert L.qmc_implr_points(3, 101, 3, 0, 8, ctypes.c_void_p(0x1002), 8, None) == qmc.ERR_INVALID_ARG
     # MDI-LR and the index export
     assert L.qmc_mdi_lr(0, fake, 0, fake, 1, 0, fake, None, 0, None) == qmc.ERR_INVALID_ARG
     assert L.qmc_mdi_lr(4, None, 0, fake, 1, 0, fake, None, 0, None) == qmc.ERR_INVALID_ARG
@@ -125,6 +140,15 @@ def test_criteria_workspace_size():
         return (4 << 20) + (max(4096 * d * 8 + n, (n + n // 2 + 2) * 8) + 255) // 256 * 256
     for d, n in [(20, 65521), (200, 1009), (2, 1 << 24), (1024, 3)]:
         assert qmc.criteria_workspace_size(d, n) == expect(d, n)
+
+
+@pytest.mark.parametrize("d,n,a", [(3, 101, 3), (3, 1290**3 + 1, 1290), (1, 97, 5), (5, 1 << 30, 181),
+                                   (2, 2147483647, 16807)])
+def test_implr_workspace_size(d, n, a):
+    # counter, then one bit per point of the a^{d-1} ceil(n / a^{d-1}) grid (eq. 3.5)
+    zd = a ** (d - 1)
+    grid = zd * -(-n // zd)
+    assert qmc.implr_workspace_size(d, n, a) == 256 + ((grid + 31) // 32 * 4 + 255) // 256 * 256
 
 
 def test_last_error_is_cleared_by_success():

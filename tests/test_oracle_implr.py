@@ -6,7 +6,10 @@ improved rule's point count (Sec. 3.2).
   * Fig. 5: the 81-point lattice with z = (1, 7) needs 3 added points;
   * the per-direction counts are those of eq. 3.5 (Theorem 3.1);
   * Lemma 3.2: for a Korobov lattice with n = a^d every direction has a values and
-    the transformation is one-to-one onto the grid (no added point).
+    the transformation is one-to-one onto the grid (no added point);
+  * for a Korobov lattice with a^{d-1} < n the grid ranks (s_1, ..., s_d),
+    s_i = u_i / z_i, grow strictly in lexicographic order with j (so the map is
+    one-to-one and n* = prod(n_i) - n), brute force over every point.
 """
 from __future__ import annotations
 
@@ -77,3 +80,22 @@ def test_grid_counts_by_brute_force_sets(z, n):
     assert distinct == len(set(map(tuple, u)))
     assert list(counts) == [len(set(u[:, i])) for i in range(len(z))]
     assert nstar == int(np.prod(counts)) - distinct
+
+
+@pytest.mark.parametrize("d,n,a", [(2, 81, 7), (3, 1200, 6), (3, 1000, 10), (4, 10007, 21), (5, 1025, 4),
+                                   (2, 4099, 64), (1, 97, 5), (6, 733, 3)])
+def test_korobov_grid_ranks_increase_lexicographically(d, n, a):
+    z = O.korobov(d, n, a)
+    s = O.implr_coords(z, n) // z
+    assert np.array_equal(s * z, O.implr_coords(z, n))
+    for j in range(1, n):
+        assert tuple(s[j - 1]) < tuple(s[j]), j
+    counts, nstar, distinct = O.implr_grid(z, n)
+    assert distinct == n and nstar == int(np.prod(counts)) - n
+
+
+def test_coords_at_matches_the_full_table():
+    z, n = O.korobov(4, 10007, 21), 10007
+    u = O.implr_coords(z, n)
+    js = np.array([0, 1, 5000, 9999, 10006, 17])
+    assert np.array_equal(O.implr_coords_at(z, n, js), u[js])
