@@ -78,6 +78,21 @@ def work_per_point_adjoint(d: int, family: int) -> int:
     return work_per_point(d, family) + d * (INDEX + 3 * C64) + CT
 
 
+# Set-batched adjoint (exp-sum and oscillatory with many sets sharing the lattice):
+# the indices of a point are generated once for all sets of a 64-set group
+# (index step, conversion), then per point, set and direction one FP64 FMA into
+# the argument and one into the index-weighted sum; per point and set the
+# transcendental(s) (cos and sin, or exp2 split), the reduction to a fraction
+# (oscillatory) and two FP64 adds.
+def work_per_point_adjoint_sets(d: int, family: int, group: int = 64) -> float:
+    per_set = d * 2 * C64 + (2 * CT + 2 * C64 if family == 3 else CT + 2 * C64) + 2 * C64
+    return per_set + d * (INDEX + C64) / group
+
+
+def uses_adjoint_sets(d: int, family: int, nsets: int) -> bool:
+    return family in (0, 3) and d <= 56 and nsets >= 16
+
+
 # MDI-LR factor evaluation (Gaussian, FP32c): node, argument, square, exp2, FP64
 # accumulation.
 WORK_PER_MDI_FACTOR = 3 * C32 + CT + ACCUM
@@ -596,7 +611,8 @@ def bench_adjoint(args, torch, qmc, W):
         results[name] = dict(step_s=step_s, kern_s=kern_s, lat_s=step_s, q=q.cpu().numpy(),
                              g=g.cpu().numpy())
     units = w.n * nsets  # point-set evaluations of f and all its parameter derivatives
-    wpp = work_per_point_adjoint(w.d, w.family)
+    wpp = (work_per_point_adjoint_sets(w.d, w.family) if uses_adjoint_sets(w.d, w.family, nsets)
+           else work_per_point_adjoint(w.d, w.family))
     config = {"workload": w.name, "d": w.d, "n": w.n, "nsets": nsets, "a": w.a,
               "family": W.FAMILY_NAMES[w.family], "precision": "fp32_compensated",
               "unit_of_work": "one point of one parameter set, value and full gradient"}

@@ -302,6 +302,278 @@ __global__ __launch_bounds__(kBlock) void adjoint_kernel(const AdjArgs a) {
 }
 
 // --------------------------------------------------------------------------
+// Set-batched form for the linear-argument families (exp-sum, oscillatory) with
+// d <= kSetsMaxDims and many parameter sets sharing the lattice.  A wave serves
+// kSetsPerWave = 32 parameter sets (group g = blockIdx.y): lanes l and l + 32 both
+// belong to set 32 g + l, each owning half of the directions, so a point's indices
+// are generated once for all 32 sets instead of once per set.  With
+// x_j = (k_j + phi_j) / n (k_j the shifted index, phi_j the shift's fraction
+// times n) the argument is
+//   t_s = t0_s + sum_j a_sj k_j   (a_sj = c_sj / (2 pi n) in turns, or c_sj log2(e) / n),
+// and the derivative sums need only
+//   K_sj = sum_i k_ij w_si,   W_s = sum_i w_si,   sum_i x_ij w_si = (K_sj + phi_j W_s) / n,
+// so a point costs two FP64 FMAs per direction and set plus one transcendental
+// per set (evaluated by both lanes of the set, which hold the same argument: the
+// two halves are added as t_lo + t_hi in both).  Each wave takes a contiguous
+// range of points in chunks of kSetChunk: the chunk's indices k_ij (exact, as
+// doubles) go to LDS, then the points are taken in order, every lane reading the
+// same k_ij (an LDS broadcast).  Per-lane sums run over the wave's points in
+// order, waves are added in order, and workgroups by the vector grid sum:
+// bit-reproducible.
+constexpr int kSetsMaxDims = kAdjSetsMaxParams - 1;
+constexpr int kSetsPerWave = kWave / 2;
+constexpr int kSetChunk = 16;                         // points per chunk
+constexpr int kSetLanesPerPoint = kWave / kSetChunk;  // lanes generating one point's indices
+
+struct AdjSetsArgs {
+    int d;
+    uint32_t n;
+    double inv_n;
+    const int64_t* z;
+    const double* shift;
+    const double* params;
+    int P;
+    int nsets;
+    uint64_t points_per_wave;
+    const double* gq;
+    double* q_out;
+    double* grad_out;
+    uint32_t* tickets;
+    double* scratch;
+    size_t scratch_stride;  // doubles per group of kSetsPerWave sets
+};
+
+// LDS doubles: the chunks of the kWaves waves, later the block totals.
+__host__ __device__ constexpr int sets_lds_doubles(int DM) {
+    return kWaves * kSetChunk * DM > kSetsPerWave * (DM + 2) ? kWaves * kSetChunk * DM
+                                                              : kSetsPerWave * (DM + 2);
+}
+
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <int FAM, bool FP32, int DM>
+__global__ __launch_bounds__(kBlock) void adjoint_sets_kernel(const AdjSetsArgs a) {
+    static_assert(DM % 2 == 0, "two lanes per set split the directions evenly");
+    constexpr int DH = DM / 2;         // directions per lane
+    extern __shared__ double s_buf[];  // [kWaves][kSetChunk][DM] chunks, then [32][DM + 2] totals
+    __shared__ double s_phi[DM];       // shift fraction * n per direction
+    __shared__ uint32_t s_step[DM];    // kSetChunk z_j mod n
+    __shared__ int s_flag;
+
+    const int tid = threadIdx.x, lane = tid & (kWave - 1), wv = tid / kWave;
+    const int d = a.d;
+    const int ls = lane % kSetsPerWave, half = lane / kSetsPerWave, jh = half * DH;
+    const int set = blockIdx.y * kSetsPerWave + ls;
+    const bool live = set < a.nsets;
+    const double* p = a.params + (size_t)(live ? set : 0) * a.P;
+    const int pc = FAM == kOscillatory ? 1 : 0;  // parameter offset of c_0
+    const double dn = (double)a.n;
+
+    for (int j = tid; j < DM; j += kBlock) {
+        uint32_t whole = 0;
+        double frac = 0.0;
+        if (j < d) split_shift(a.shift, j, a.n, whole, frac);
+        s_phi[j] = frac;
+        s_step[j] = j < d ? mulmod_small((uint32_t)kSetChunk, (uint32_t)a.z[j], dn, a.inv_n) : 0u;
+    }
+    __syncthreads();
+
+    // this lane's coefficients (directions jh .. jh + DH) and its part of the constant
+    double coef[DH], K[DH];
+    double t0 = (FAM == kOscillatory && half == 0) ? p[0] : 0.0;
+#pragma unroll
+    for (int q = 0; q < DH; ++q) {
+        const int j = jh + q;
+        const double c = j < d ? p[pc + j] : 0.0;
+        const double aj = FAM == kOscillatory ? c * kInv2Pi * a.inv_n : c * kLog2e * a.inv_n;
+        coef[q] = aj;
+        // exp-sum: centred by sum_j c_j log2(e) / 2 (restored by the final scale)
+        t0 += aj * s_phi[j] - (FAM == kExpSum ? 0.5 * kLog2e * c : 0.0);
+        K[q] = 0.0;
+    }
+    double qs = 0.0, ws = 0.0;
+
+    // this wave's points [p0, p1); lane -> point (lane % kSetChunk) of each chunk and
+    // the directions jb, jb + kSetLanesPerPoint, ... (jb = lane / kSetChunk)
+    const uint64_t p0 = ((uint64_t)blockIdx.x * kWaves + wv) * a.points_per_wave;
+    const uint64_t p1 = min(p0 + a.points_per_wave, (uint64_t)a.n);
+    const int pt = lane % kSetChunk, jb = lane / kSetChunk;
+    constexpr int kJ = (DM + kSetLanesPerPoint - 1) / kSetLanesPerPoint;
+    uint32_t kst[kJ];  // (i z_j + whole_j) mod n of this lane's point in the current chunk
+    if (p0 < p1) {
+#pragma unroll
+        for (int q = 0; q < kJ; ++q) {
+            const int j = jb + q * kSetLanesPerPoint;
+            uint32_t whole = 0;
+            double frac = 0.0;
+            if (j < d) split_shift(a.shift, j, a.n, whole, frac);
+            kst[q] = j < d ? addmod(mulmod(p0 + (uint64_t)pt, (uint64_t)a.z[j], a.n, a.inv_n), whole, a.n) : 0u;
+        }
+    }
+    double* chunk = s_buf + (size_t)wv * kSetChunk * DM;
+    for (uint64_t c0 = p0; c0 < p1; c0 += kSetChunk) {
+#pragma unroll
+        for (int q = 0; q < kJ; ++q) {
+            const int j = jb + q * kSetLanesPerPoint;
+            if (j < DM) {
+                chunk[pt * DM + j] = (double)kst[q];
+                kst[q] = addmod(kst[q], s_step[j], a.n);
+            }
+        }
+        wave_lds_sync();
+        const int cnt = (int)min((uint64_t)kSetChunk, p1 - c0);
+        for (int r = 0; r < cnt; ++r) {
+            const double* kr = chunk + r * DM + jh;
+            // four interleaved partial sums keep four independent FMA chains in flight
+            double tp[4] = {t0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int q = 0; q < DH; ++q) tp[q & 3] = fma(coef[q], kr[q], tp[q & 3]);
+            const double th = (tp[0] + tp[1]) + (tp[2] + tp[3]);
+            const double tother = __shfl_xor(th, kSetsPerWave, kWave);
+            const double t = half == 0 ? th + tother : tother + th;  // t_lo + t_hi in both lanes
+            double val, w;
+            if constexpr (FAM == kOscillatory) {
+                const double fr = t - rint(t);
+                if constexpr (FP32) {
+                    val = (double)__builtin_amdgcn_cosf((float)fr);
+                    w = -(double)__builtin_amdgcn_sinf((float)fr);
+                } else {
+                    double sn, cs;
+                    sincospi(2.0 * fr, &sn, &cs);
+                    val = cs;
+                    w = -sn;
+                }
+            } else {
+                val = FP32 ? exp2_split_f32(t) : exp2(t);
+                w = val;
+            }
+            qs += val;
+            ws += w;
+            // read the indices again (an LDS broadcast) rather than keep them live
+            // across the transcendental
+            asm volatile("" ::: "memory");
+#pragma unroll
+            for (int q = 0; q < DH; ++q) K[q] = fma(kr[q], w, K[q]);
+        }
+        wave_lds_sync();
+    }
+
+    // block totals, waves in order (per set: K_0 .. K_{DM-1}, W, Q); the buffer of
+    // the chunks is reused once every wave is past its last chunk
+    constexpr int L = DM + 2;
+    double* tot = s_buf;
+    __syncthreads();
+    for (int w = 0; w < kWaves; ++w) {
+        if (wv == w) {
+#pragma unroll
+            for (int q = 0; q < DH; ++q) tot[ls * L + jh + q] = (w == 0 ? 0.0 : tot[ls * L + jh + q]) + K[q];
+            if (half == 0) {
+                tot[ls * L + DM] = (w == 0 ? 0.0 : tot[ls * L + DM]) + ws;
+                tot[ls * L + DM + 1] = (w == 0 ? 0.0 : tot[ls * L + DM + 1]) + qs;
+            }
+        }
+        __syncthreads();
+    }
+    const int G = (int)gridDim.x;
+    double* part = a.scratch + (size_t)blockIdx.y * a.scratch_stride;
+    if (!grid_sum_vec(tot, kSetsPerWave * L, (int)blockIdx.x, G, part, part + (size_t)G * kSetsPerWave * L,
+                      a.tickets + (size_t)blockIdx.y * kTicketsPerReduction, &s_flag))
+        return;
+    // one thread per (set, output)
+    const double inv_n2 = a.inv_n * a.inv_n;
+    for (int e = tid; e < kSetsPerWave * (a.P + 1); e += kBlock) {
+        const int es = e / (a.P + 1), o = e % (a.P + 1);
+        const int st = blockIdx.y * kSetsPerWave + es;
+        if (st >= a.nsets) continue;
+        const double* ps = a.params + (size_t)st * a.P;
+        double scale = 1.0;
+        if constexpr (FAM == kExpSum) {
+            double h = 0.0;
+            for (int j = 0; j < d; ++j) h += 0.5 * kLog2e * ps[j];
+            scale = exp2(h);
+        }
+        const double g = a.gq ? a.gq[st] : 1.0;
+        const double* v = tot + es * L;
+        if (o == a.P) {
+            a.q_out[st] = scale * v[DM + 1] * a.inv_n;
+        } else if (FAM == kOscillatory && o == 0) {
+            a.grad_out[(size_t)st * a.P] = g * kTwoPi * v[DM] * a.inv_n;
+        } else {
+            const int j = o - pc;
+            a.grad_out[(size_t)st * a.P + o] = g * scale * (v[j] + s_phi[j] * v[DM]) * inv_n2;
+        }
+    }
+}
+
+static int sets_blocks(int groups) {
+    int g = 512 / groups;
+    return g < 1 ? 1 : g;
+}
+
+// Doubles per group of kSetsPerWave sets: one vector of kSetsPerWave (DM + 2) per
+// workgroup and per group.
+static size_t sets_group_stride(int DM, int groups) {
+    const size_t G = (size_t)sets_blocks(groups);
+    return (G + (G < (size_t)kReduceGroups ? G : (size_t)kReduceGroups)) * (size_t)kSetsPerWave *
+           (size_t)(DM + 2);
+}
+
+static size_t sets_workspace_bytes(int d, int nsets) {
+    const int groups = (nsets + kSetsPerWave - 1) / kSetsPerWave;
+    const int DM = d <= 48 ? (d + 7) / 8 * 8 : (d + 3) / 4 * 4;  // the kernel's bucket for d
+    return kZeroBytes + ((size_t)groups * sets_group_stride(DM, groups) * sizeof(double) + 255) / 256 * 256;
+}
+
+static bool use_sets_kernel(const AdjLaunch& L) {
+    return (L.family == kExpSum || L.family == kOscillatory) && L.d <= kSetsMaxDims && L.nsets >= 16;
+}
+
+template <int FAM, bool FP32, int DM>
+static hipError_t launch_sets_dm(const AdjLaunch& L, hipStream_t stream) {
+    AdjSetsArgs a;
+    a.d = L.d;
+    a.n = L.n;
+    a.inv_n = 1.0 / (double)L.n;
+    a.z = L.z;
+    a.shift = L.shift;
+    a.params = L.params;
+    a.P = L.P;
+    a.nsets = L.nsets;
+    const int groups = (L.nsets + kSetsPerWave - 1) / kSetsPerWave;
+    int G = sets_blocks(groups);
+    const uint64_t waves_min = ((uint64_t)L.n + kSetChunk - 1) / kSetChunk;  // at least one chunk per wave
+    if ((uint64_t)G * kWaves > waves_min) G = (int)((waves_min + kWaves - 1) / kWaves);
+    a.points_per_wave = (((uint64_t)L.n + (uint64_t)G * kWaves - 1) / ((uint64_t)G * kWaves) + kSetChunk - 1) /
+                        kSetChunk * kSetChunk;
+    a.gq = L.gq;
+    a.q_out = L.q_out;
+    a.grad_out = L.grad_out;
+    a.tickets = (uint32_t*)L.ws;
+    a.scratch = (double*)((char*)L.ws + kZeroBytes);
+    a.scratch_stride = sets_group_stride(DM, groups);
+    const size_t lds = (size_t)sets_lds_doubles(DM) * sizeof(double);
+    hipLaunchKernelGGL((adjoint_sets_kernel<FAM, FP32, DM>), dim3((unsigned)G, (unsigned)groups), dim3(kBlock),
+                       lds, stream, a);
+    return hipGetLastError();
+}
+
+template <int FAM, bool FP32>
+static hipError_t launch_sets(const AdjLaunch& L, hipStream_t stream) {
+    if (L.d <= 8) return launch_sets_dm<FAM, FP32, 8>(L, stream);
+    if (L.d <= 16) return launch_sets_dm<FAM, FP32, 16>(L, stream);
+    if (L.d <= 24) return launch_sets_dm<FAM, FP32, 24>(L, stream);
+    if (L.d <= 32) return launch_sets_dm<FAM, FP32, 32>(L, stream);
+    if (L.d <= 40) return launch_sets_dm<FAM, FP32, 40>(L, stream);
+    if (L.d <= 48) return launch_sets_dm<FAM, FP32, 48>(L, stream);
+    if (L.d <= 52) return launch_sets_dm<FAM, FP32, 52>(L, stream);
+    return launch_sets_dm<FAM, FP32, 56>(L, stream);
+}
+
+// --------------------------------------------------------------------------
 int adjoint_blocks_per_set(int nsets) {
     int g = kMaxAdjBlocks / (nsets > 0 ? nsets : 1);
     if (g < 1) g = 1;
@@ -315,7 +587,13 @@ static size_t adjoint_set_stride(int P, int nsets) {
 }
 
 size_t adjoint_workspace_bytes(int P, int nsets) {
-    return kZeroBytes + ((size_t)nsets * adjoint_set_stride(P, nsets) * sizeof(double) + 255) / 256 * 256;
+    const size_t per_set =
+        kZeroBytes + ((size_t)nsets * adjoint_set_stride(P, nsets) * sizeof(double) + 255) / 256 * 256;
+    // the set-batched form (d = P or P - 1 <= kSetsMaxDims) lays its scratch out per
+    // group of 64 sets; d <= min(P, kSetsMaxDims) bounds its size
+    const size_t batched = P <= kSetsMaxDims + 1 ? sets_workspace_bytes(P < kSetsMaxDims ? P : kSetsMaxDims, nsets)
+                                                 : 0;
+    return per_set > batched ? per_set : batched;
 }
 
 template <int FAM, bool FP32, class A, int M>
@@ -356,6 +634,11 @@ static hipError_t launch_adj_f(const AdjLaunch& L, hipStream_t stream) {
 }
 
 hipError_t launch_adjoint(const AdjLaunch& L, hipStream_t stream) {
+    if (use_sets_kernel(L)) {
+        if (L.family == kExpSum)
+            return L.fp32 ? launch_sets<kExpSum, true>(L, stream) : launch_sets<kExpSum, false>(L, stream);
+        return L.fp32 ? launch_sets<kOscillatory, true>(L, stream) : launch_sets<kOscillatory, false>(L, stream);
+    }
     if (L.fp32) {
         switch (L.family) {
             case kExpSum: return launch_adj_f<kExpSum, true, AdjFam<kExpSum, true>>(L, stream);

@@ -196,13 +196,20 @@ qmc_status qmc_workspace_size(int32_t max_d, int64_t max_n, int32_t max_sets, si
     }
     const size_t b = qmc::plain_workspace_bytes(max_sets);
     if (b > need) need = b;
-    // The adjoint keeps one vector of P + 1 doubles per workgroup and group.
+    // The adjoint keeps one vector of P + 1 doubles per workgroup and group; its
+    // set-batched form (small d) one vector per group of 64 sets, evaluated at the
+    // largest P it serves.
     const int pmax = 2 * (max_d < qmc::kMaxAdjDims ? max_d : qmc::kMaxAdjDims) + 1;
+    const int pset = pmax < qmc::kAdjSetsMaxParams ? pmax : qmc::kAdjSetsMaxParams;
     for (int s = 1; s <= max_sets; s = (s < 64 ? s + 1 : s * 2)) {
-        const size_t a = qmc::adjoint_workspace_bytes(pmax, s);
+        size_t a = qmc::adjoint_workspace_bytes(pmax, s);
+        if (a > need) need = a;
+        a = qmc::adjoint_workspace_bytes(pset, s);
         if (a > need) need = a;
     }
-    const size_t a = qmc::adjoint_workspace_bytes(pmax, max_sets);
+    size_t a = qmc::adjoint_workspace_bytes(pmax, max_sets);
+    if (a > need) need = a;
+    a = qmc::adjoint_workspace_bytes(pset, max_sets);
     if (a > need) need = a;
     *bytes = need;
     return ok();

@@ -132,3 +132,52 @@ def test_adjoint_rejects_large_d():
     with pytest.raises(qmc.QmcError) as e:
         qmc.lattice_sum_adjoint(z, 7, qmc.EXP_SUM, np.ones(513), qmc.FP64)
     assert e.value.status == qmc.ERR_UNSUPPORTED
+
+
+# The set-batched form (exp-sum and oscillatory, d <= 56, at least 16 sets: lane =
+# parameter set) against the oracle set by set, and against the per-set form.
+@pytest.mark.parametrize("precision", [qmc.FP64, qmc.FP32_COMPENSATED])
+@pytest.mark.parametrize("family", [0, 3])
+@pytest.mark.parametrize("d,n,nsets", [(3, 10007, 16), (20, 65537, 64), (56, 3001, 70), (1, 997, 130),
+                                       (9, 1009, 17)])
+def test_adjoint_set_batched_matches_oracle(precision, family, d, n, nsets):
+    rng = np.random.default_rng(11 * d + n + family + nsets)
+    z = qmc.korobov(d, n, W.draw_coprime(rng, n))
+    shift = rng.uniform(0, 1, d) if (d + nsets) % 2 else None
+    params = np.stack([W.draw_params(rng, family, d) for _ in range(nsets)])
+    gq = rng.uniform(-2.0, 2.0, nsets)
+    q, g = qmc.lattice_sum_adjoint(z, n, family, params, precision, shift=shift, gq=gq)
+    q, g = q.cpu().numpy(), g.cpu().numpy()
+    for s in sorted({0, 1, nsets // 2, nsets - 1, min(63, nsets - 1), min(64, nsets - 1)}):
+        qo, go = O.lattice_grad(z, n, family, params[s], shift)
+        _, ao = O.lattice_sum(z, n, family, params[s], shift)
+        _check_set(q[s], g[s], qo, ao, gq[s] * go, TOL[precision])
+
+
+@pytest.mark.parametrize("family", [0, 3])
+def test_adjoint_set_batched_agrees_with_per_set_form(family):
+    rng = np.random.default_rng(42 + family)
+    d, n, nsets = 24, 50021, 40
+    z = qmc.korobov(d, n, 20011)
+    shift = rng.uniform(0, 1, d)
+    params = np.stack([W.draw_params(rng, family, d) for _ in range(nsets)])
+    q, g = qmc.lattice_sum_adjoint(z, n, family, params, qmc.FP64, shift=shift)
+    q, g = q.cpu().numpy(), g.cpu().numpy()
+    for s in (0, 7, 39):
+        q1, g1 = qmc.lattice_sum_adjoint(z, n, family, params[s:s + 1], qmc.FP64, shift=shift)
+        q1, g1 = q1.cpu().numpy()[0], g1.cpu().numpy()[0]
+        assert abs(q[s] - q1) <= 1e-12 * max(abs(q1), 1e-3)
+        assert np.max(np.abs(g[s] - g1)) <= 1e-12 * max(np.max(np.abs(g1)), 1e-300)
+
+
+def test_adjoint_set_batched_workspace_from_workspace_size():
+    # a workspace sized by qmc_workspace_size serves the set-batched form
+    d, n, nsets = 50, 4099, 64
+    rng = np.random.default_rng(9)
+    z = qmc.korobov(d, n, 1234)
+    params = np.stack([W.draw_params(rng, 3, d) for _ in range(nsets)])
+    ws = qmc.Workspace(qmc.workspace_size(d, n, nsets))
+    q, g = qmc.lattice_sum_adjoint(z, n, 3, params, qmc.FP64, ws=ws)
+    qo, go = O.lattice_grad(z, n, 3, params[5])
+    _, ao = O.lattice_sum(z, n, 3, params[5])
+    _check_set(q.cpu().numpy()[5], g.cpu().numpy()[5], qo, ao, go, TOL[qmc.FP64])
