@@ -78,19 +78,19 @@ def work_per_point_adjoint(d: int, family: int) -> int:
     return work_per_point(d, family) + d * (INDEX + 3 * C64) + CT
 
 
-# Set-batched adjoint (exp-sum and oscillatory with many sets sharing the lattice):
-# the indices of a point are generated once for all sets of a 64-set group
-# (index step, conversion), then per point, set and direction one FP64 FMA into
-# the argument and one into the index-weighted sum; per point and set the
-# transcendental(s) (cos and sin, or exp2 split), the reduction to a fraction
-# (oscillatory) and two FP64 adds.
-def work_per_point_adjoint_sets(d: int, family: int, group: int = 64) -> float:
-    per_set = d * 2 * C64 + (2 * CT + 2 * C64 if family == 3 else CT + 2 * C64) + 2 * C64
-    return per_set + d * (INDEX + C64) / group
+# Set-batched adjoint (exp-sum and oscillatory, d <= 64, >= 16 sets sharing the
+# lattice): two dense FP64 contractions over the lattice indices, the arguments
+# T = k A and the index-weighted sums K = k^T W, on the FP64 matrix unit: 2 d
+# flops each per point and set (d unpadded), against the dense FP64 MFMA peak.
+PEAK_MFMA_F64 = 78.6e12
+
+
+def flops_per_point_adjoint_sets(d: int) -> int:
+    return 4 * d
 
 
 def uses_adjoint_sets(d: int, family: int, nsets: int) -> bool:
-    return family in (0, 3) and d <= 56 and nsets >= 16
+    return family in (0, 3) and d <= 64 and nsets >= 16
 
 
 # MDI-LR factor evaluation (Gaussian, FP32c): node, argument, square, exp2, FP64
@@ -611,8 +611,14 @@ def bench_adjoint(args, torch, qmc, W):
         results[name] = dict(step_s=step_s, kern_s=kern_s, lat_s=step_s, q=q.cpu().numpy(),
                              g=g.cpu().numpy())
     units = w.n * nsets  # point-set evaluations of f and all its parameter derivatives
-    wpp = (work_per_point_adjoint_sets(w.d, w.family) if uses_adjoint_sets(w.d, w.family, nsets)
-           else work_per_point_adjoint(w.d, w.family))
+    wpp = work_per_point_adjoint(w.d, w.family)
+    if uses_adjoint_sets(w.d, w.family, nsets):
+        fpp = flops_per_point_adjoint_sets(w.d)
+        kern = results["fp32c"]["kern_s"]
+        results["fp32c"]["roofline"] = {
+            "bound": "mfma", "achieved": fpp * units / kern / 1e12, "peak": PEAK_MFMA_F64 / 1e12,
+            "unit": "TFLOP/s (FP64 matrix)", "frac": fpp * units / kern / PEAK_MFMA_F64, "traffic": None,
+            "kernel": "adjoint_sets_kernel", "flops_per_unit": fpp, "kernel_us": kern * 1e6}
     config = {"workload": w.name, "d": w.d, "n": w.n, "nsets": nsets, "a": w.a,
               "family": W.FAMILY_NAMES[w.family], "precision": "fp32_compensated",
               "unit_of_work": "one point of one parameter set, value and full gradient"}

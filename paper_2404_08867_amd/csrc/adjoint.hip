@@ -303,27 +303,41 @@ __global__ __launch_bounds__(kBlock) void adjoint_kernel(const AdjArgs a) {
 
 // --------------------------------------------------------------------------
 // Set-batched form for the linear-argument families (exp-sum, oscillatory) with
-// d <= kSetsMaxDims and many parameter sets sharing the lattice.  A wave serves
-// kSetsPerWave = 32 parameter sets (group g = blockIdx.y): lanes l and l + 32 both
-// belong to set 32 g + l, each owning half of the directions, so a point's indices
-// are generated once for all 32 sets instead of once per set.  With
-// x_j = (k_j + phi_j) / n (k_j the shifted index, phi_j the shift's fraction
-// times n) the argument is
-//   t_s = t0_s + sum_j a_sj k_j   (a_sj = c_sj / (2 pi n) in turns, or c_sj log2(e) / n),
+// d <= kSetsMaxDims and many parameter sets sharing the lattice.  With
+// x_j = (k_j + phi_j) / n (k_j the shifted index, phi_j the shift's fraction times
+// n) the argument of set s at point i is
+//   t_is = t0_s + sum_j k_ij a_js   (a_js = c_sj / (2 pi n) in turns, or c_sj log2(e) / n)
 // and the derivative sums need only
-//   K_sj = sum_i k_ij w_si,   W_s = sum_i w_si,   sum_i x_ij w_si = (K_sj + phi_j W_s) / n,
-// so a point costs two FP64 FMAs per direction and set plus one transcendental
-// per set (evaluated by both lanes of the set, which hold the same argument: the
-// two halves are added as t_lo + t_hi in both).  Each wave takes a contiguous
-// range of points in chunks of kSetChunk: the chunk's indices k_ij (exact, as
-// doubles) go to LDS, then the points are taken in order, every lane reading the
-// same k_ij (an LDS broadcast).  Per-lane sums run over the wave's points in
-// order, waves are added in order, and workgroups by the vector grid sum:
-// bit-reproducible.
+//   K_js = sum_i k_ij w_is,   W_s = sum_i w_is,   sum_i x_ij w_is = (K_js + phi_j W_s) / n.
+// Both are dense contractions over the lattice indices, T = k A and K = k^T W, done
+// with the FP64 matrix instruction v_mfma_f64_16x16x4f64 (D[m][n] += sum_q
+// A[m][q] B[q][n] over a 16 x 4 by 4 x 16 block; lane l supplies A[l % 16][l / 16]
+// and B[l / 16][l % 16] and holds D[4 r + l / 16][l % 16] in register r -- the
+// layout as measured on gfx950).
+//
+// A wave serves the 64 sets of group blockIdx.y (four blocks of 16) over a
+// contiguous range of points, 16 points at a time:
+//  1. T[16 points][64 sets] = t0 + k[16][4 DQ] A[4 DQ][64]: the A operand is the
+//     lane's own index k(point c0 + l % 16, direction 4 q + l / 16), stepped by
+//     16 z_j mod n per block (exact integers, converted to double); the B operand
+//     is the coefficient a(direction 4 q + l / 16, set 16 b + l % 16), held in
+//     registers.
+//  2. the lane holds T for points c0 + 4 r + l / 16 (r < 4) of set 16 b + l % 16
+//     and evaluates f and the weight w there;
+//  3. K[16 e + m][16 b + n] += sum over the block's points of k(point, direction)
+//     w(point, set), with reduction step u pairing the lanes' register r = u with
+//     points c0 + 4 u + l / 16: the weights are already where the B operand needs
+//     them; the A operand is the lane's index k(point c0 + 4 u + l / 16,
+//     direction 16 e + l % 16), stepped like the first.
+// Partial points of the last block get w = 0 and f = 0.  The K accumulators (one
+// 16 x 16 block per 16 directions and 16 sets) stay in registers over the wave's
+// points; then waves are added in order and workgroups by the vector grid sum, so
+// the result is bit-reproducible.
 constexpr int kSetsMaxDims = kAdjSetsMaxParams - 1;
-constexpr int kSetsPerWave = kWave / 2;
-constexpr int kSetChunk = 16;                         // points per chunk
-constexpr int kSetLanesPerPoint = kWave / kSetChunk;  // lanes generating one point's indices
+constexpr int kSetsPerWave = kWave;  // four blocks of 16
+constexpr int kMfmaPoints = 16;      // points per block
+
+typedef double v4d __attribute__((ext_vector_type(4)));
 
 struct AdjSetsArgs {
     int d;
@@ -334,7 +348,7 @@ struct AdjSetsArgs {
     const double* params;
     int P;
     int nsets;
-    uint64_t points_per_wave;
+    uint64_t points_per_wave;  // a multiple of kMfmaPoints
     const double* gq;
     double* q_out;
     double* grad_out;
@@ -343,33 +357,31 @@ struct AdjSetsArgs {
     size_t scratch_stride;  // doubles per group of kSetsPerWave sets
 };
 
-// LDS doubles: the chunks of the kWaves waves, later the block totals.
+// LDS doubles: the coefficient table [DM][64] during the sweep, then the block
+// totals (per set K_0 .. K_{DM-1}, W, Q) and per-lane partials of W, Q.
 __host__ __device__ constexpr int sets_lds_doubles(int DM) {
-    return kWaves * kSetChunk * DM > kSetsPerWave * (DM + 2) ? kWaves * kSetChunk * DM
-                                                              : kSetsPerWave * (DM + 2);
+    return DM * kSetsPerWave > kSetsPerWave * (DM + 2) + 2 * kWave ? DM * kSetsPerWave
+                                                                    : kSetsPerWave * (DM + 2) + 2 * kWave;
 }
 
-__device__ __forceinline__ void wave_lds_sync() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+__device__ __forceinline__ uint32_t index_of(uint64_t i, uint32_t z, uint32_t whole, uint32_t n, double inv_n) {
+    return addmod(mulmod(i, (uint64_t)z, n, inv_n), whole, n);
 }
 
-template <int FAM, bool FP32, int DM>
+template <int FAM, bool FP32, int DQ>
 __global__ __launch_bounds__(kBlock) void adjoint_sets_kernel(const AdjSetsArgs a) {
-    static_assert(DM % 2 == 0, "two lanes per set split the directions evenly");
-    constexpr int DH = DM / 2;         // directions per lane
-    extern __shared__ double s_buf[];  // [kWaves][kSetChunk][DM] chunks, then [32][DM + 2] totals
-    __shared__ double s_phi[DM];       // shift fraction * n per direction
-    __shared__ uint32_t s_step[DM];    // kSetChunk z_j mod n
+    constexpr int NE = (DQ + 3) / 4;  // blocks of 16 directions in K
+    constexpr int DM = 4 * DQ;        // directions covered (>= d)
+    extern __shared__ double s_tot[];  // [DM][64] coefficients; later [64][DM + 2] totals, [2][64] partials
+    __shared__ double s_phi[DM];        // shift fraction * n per direction
+    __shared__ uint32_t s_whole[DM];    // shift whole part per direction
+    __shared__ uint32_t s_step[DM];     // 16 z_j mod n
+    __shared__ uint32_t s_z[DM];
     __shared__ int s_flag;
 
-    const int tid = threadIdx.x, lane = tid & (kWave - 1), wv = tid / kWave;
+    const int tid = threadIdx.x, l = tid & (kWave - 1), wv = tid / kWave;
+    const int lr = l % 16, lq = l / 16;
     const int d = a.d;
-    const int ls = lane % kSetsPerWave, half = lane / kSetsPerWave, jh = half * DH;
-    const int set = blockIdx.y * kSetsPerWave + ls;
-    const bool live = set < a.nsets;
-    const double* p = a.params + (size_t)(live ? set : 0) * a.P;
     const int pc = FAM == kOscillatory ? 1 : 0;  // parameter offset of c_0
     const double dn = (double)a.n;
 
@@ -378,109 +390,169 @@ __global__ __launch_bounds__(kBlock) void adjoint_sets_kernel(const AdjSetsArgs 
         double frac = 0.0;
         if (j < d) split_shift(a.shift, j, a.n, whole, frac);
         s_phi[j] = frac;
-        s_step[j] = j < d ? mulmod_small((uint32_t)kSetChunk, (uint32_t)a.z[j], dn, a.inv_n) : 0u;
+        s_whole[j] = whole;
+        s_z[j] = j < d ? (uint32_t)a.z[j] : 0u;
+        s_step[j] = j < d ? mulmod_small((uint32_t)kMfmaPoints, (uint32_t)a.z[j], dn, a.inv_n) : 0u;
     }
     __syncthreads();
 
-    // this lane's coefficients (directions jh .. jh + DH) and its part of the constant
-    double coef[DH], K[DH];
-    double t0 = (FAM == kOscillatory && half == 0) ? p[0] : 0.0;
-#pragma unroll
-    for (int q = 0; q < DH; ++q) {
-        const int j = jh + q;
-        const double c = j < d ? p[pc + j] : 0.0;
-        const double aj = FAM == kOscillatory ? c * kInv2Pi * a.inv_n : c * kLog2e * a.inv_n;
-        coef[q] = aj;
-        // exp-sum: centred by sum_j c_j log2(e) / 2 (restored by the final scale)
-        t0 += aj * s_phi[j] - (FAM == kExpSum ? 0.5 * kLog2e * c : 0.0);
-        K[q] = 0.0;
+    // coefficient table: s_coef[j * 64 + s] = a_js of set s of the group (0 beyond d
+    // and past the last set); the B operand of step 1 reads a(4 q + lq, 16 b + lr)
+    double* s_coef = s_tot;
+    for (int e = tid; e < DM * kSetsPerWave; e += kBlock) {
+        const int j = e / kSetsPerWave, set = blockIdx.y * kSetsPerWave + e % kSetsPerWave;
+        double c = 0.0;
+        if (j < d && set < a.nsets) c = a.params[(size_t)set * a.P + pc + j];
+        s_coef[e] = FAM == kOscillatory ? c * kInv2Pi * a.inv_n : c * kLog2e * a.inv_n;
     }
-    double qs = 0.0, ws = 0.0;
+    // t0 of set 16 b + lr
+    double t0[4];
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+        const int set = blockIdx.y * kSetsPerWave + 16 * b + lr;
+        const double* p = a.params + (size_t)(set < a.nsets ? set : 0) * a.P;
+        double c0 = FAM == kOscillatory ? p[0] : 0.0;
+        for (int j = 0; j < d; ++j) {
+            const double c = p[pc + j];
+            const double aj = FAM == kOscillatory ? c * kInv2Pi * a.inv_n : c * kLog2e * a.inv_n;
+            // exp-sum: centred by sum_j c_j log2(e) / 2 (restored by the final scale)
+            c0 += aj * s_phi[j] - (FAM == kExpSum ? 0.5 * kLog2e * c : 0.0);
+        }
+        t0[b] = c0;
+    }
+    __syncthreads();
 
-    // this wave's points [p0, p1); lane -> point (lane % kSetChunk) of each chunk and
-    // the directions jb, jb + kSetLanesPerPoint, ... (jb = lane / kSetChunk)
     const uint64_t p0 = ((uint64_t)blockIdx.x * kWaves + wv) * a.points_per_wave;
     const uint64_t p1 = min(p0 + a.points_per_wave, (uint64_t)a.n);
-    const int pt = lane % kSetChunk, jb = lane / kSetChunk;
-    constexpr int kJ = (DM + kSetLanesPerPoint - 1) / kSetLanesPerPoint;
-    uint32_t kst[kJ];  // (i z_j + whole_j) mod n of this lane's point in the current chunk
-    if (p0 < p1) {
+    // index states: step 1 (point p + lr, direction 4 q + lq), step 3 (point p + 4 u + lq, direction 16 e + lr)
+    uint32_t kt[DQ], kk[4][NE], st_t[DQ], st_k[NE];
 #pragma unroll
-        for (int q = 0; q < kJ; ++q) {
-            const int j = jb + q * kSetLanesPerPoint;
-            uint32_t whole = 0;
-            double frac = 0.0;
-            if (j < d) split_shift(a.shift, j, a.n, whole, frac);
-            kst[q] = j < d ? addmod(mulmod(p0 + (uint64_t)pt, (uint64_t)a.z[j], a.n, a.inv_n), whole, a.n) : 0u;
-        }
+    for (int q = 0; q < DQ; ++q) {
+        const int j = 4 * q + lq;
+        st_t[q] = s_step[j];
+        kt[q] = j < d ? index_of(p0 + lr, s_z[j], s_whole[j], a.n, a.inv_n) : 0u;
     }
-    double* chunk = s_buf + (size_t)wv * kSetChunk * DM;
-    for (uint64_t c0 = p0; c0 < p1; c0 += kSetChunk) {
 #pragma unroll
-        for (int q = 0; q < kJ; ++q) {
-            const int j = jb + q * kSetLanesPerPoint;
-            if (j < DM) {
-                chunk[pt * DM + j] = (double)kst[q];
-                kst[q] = addmod(kst[q], s_step[j], a.n);
-            }
+    for (int e = 0; e < NE; ++e) {
+        const int j = 16 * e + lr;
+        st_k[e] = j < DM ? s_step[j] : 0u;
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+            kk[u][e] = j < d ? index_of(p0 + 4 * u + lq, s_z[j], s_whole[j], a.n, a.inv_n) : 0u;
+    }
+    v4d acc[NE][4];
+#pragma unroll
+    for (int e = 0; e < NE; ++e)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) acc[e][b] = v4d{0.0, 0.0, 0.0, 0.0};
+    double qs[4] = {0.0, 0.0, 0.0, 0.0}, ws[4] = {0.0, 0.0, 0.0, 0.0};
+
+    for (uint64_t c0 = p0; c0 < p1; c0 += kMfmaPoints) {
+        // 1. arguments of the block's 16 points for the 64 sets
+        v4d t[4];
+#pragma unroll
+        for (int b = 0; b < 4; ++b) t[b] = v4d{t0[b], t0[b], t0[b], t0[b]};
+#pragma unroll
+        for (int q = 0; q < DQ; ++q) {
+            const double av = (double)kt[q];
+            const double* cr = s_coef + (4 * q + lq) * kSetsPerWave + lr;
+#pragma unroll
+            for (int b = 0; b < 4; ++b) t[b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, cr[16 * b], t[b], 0, 0, 0);
+            // at most 16 coefficient loads in flight: keeps them from all being
+            // hoisted into registers ahead of the matrix instructions
+            if ((q & 3) == 3) asm volatile("" ::: "memory");
         }
-        wave_lds_sync();
-        const int cnt = (int)min((uint64_t)kSetChunk, p1 - c0);
-        for (int r = 0; r < cnt; ++r) {
-            const double* kr = chunk + r * DM + jh;
-            // four interleaved partial sums keep four independent FMA chains in flight
-            double tp[4] = {t0, 0.0, 0.0, 0.0};
+        // 2. f and its weight at points c0 + 4 r + lq
+        double w[4][4];
 #pragma unroll
-            for (int q = 0; q < DH; ++q) tp[q & 3] = fma(coef[q], kr[q], tp[q & 3]);
-            const double th = (tp[0] + tp[1]) + (tp[2] + tp[3]);
-            const double tother = __shfl_xor(th, kSetsPerWave, kWave);
-            const double t = half == 0 ? th + tother : tother + th;  // t_lo + t_hi in both lanes
-            double val, w;
-            if constexpr (FAM == kOscillatory) {
-                const double fr = t - rint(t);
-                if constexpr (FP32) {
-                    val = (double)__builtin_amdgcn_cosf((float)fr);
-                    w = -(double)__builtin_amdgcn_sinf((float)fr);
+        for (int r = 0; r < 4; ++r) {
+            const bool live = c0 + (uint64_t)(4 * r + lq) < p1;
+#pragma unroll
+            for (int b = 0; b < 4; ++b) {
+                const double tt = t[b][r];
+                double val, wt;
+                if constexpr (FAM == kOscillatory) {
+                    const double fr = tt - rint(tt);
+                    if constexpr (FP32) {
+                        val = (double)__builtin_amdgcn_cosf((float)fr);
+                        wt = -(double)__builtin_amdgcn_sinf((float)fr);
+                    } else {
+                        double sn, cs;
+                        sincospi(2.0 * fr, &sn, &cs);
+                        val = cs;
+                        wt = -sn;
+                    }
                 } else {
-                    double sn, cs;
-                    sincospi(2.0 * fr, &sn, &cs);
-                    val = cs;
-                    w = -sn;
+                    val = FP32 ? exp2_split_f32(tt) : exp2(tt);
+                    wt = val;
                 }
-            } else {
-                val = FP32 ? exp2_split_f32(t) : exp2(t);
-                w = val;
+                val = live ? val : 0.0;
+                wt = live ? wt : 0.0;
+                qs[b] += val;
+                ws[b] += wt;
+                w[b][r] = wt;
             }
-            qs += val;
-            ws += w;
-            // read the indices again (an LDS broadcast) rather than keep them live
-            // across the transcendental
-            asm volatile("" ::: "memory");
-#pragma unroll
-            for (int q = 0; q < DH; ++q) K[q] = fma(kr[q], w, K[q]);
         }
-        wave_lds_sync();
+        // 3. K += k^T w over the block's points
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+#pragma unroll
+            for (int e = 0; e < NE; ++e) {
+                const double av = (double)kk[u][e];
+#pragma unroll
+                for (int b = 0; b < 4; ++b) acc[e][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, w[b][u], acc[e][b], 0, 0, 0);
+            }
+        }
+        // next block: 16 points on
+#pragma unroll
+        for (int q = 0; q < DQ; ++q) kt[q] = addmod(kt[q], st_t[q], a.n);
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int e = 0; e < NE; ++e) kk[u][e] = addmod(kk[u][e], st_k[e], a.n);
     }
 
-    // block totals, waves in order (per set: K_0 .. K_{DM-1}, W, Q); the buffer of
-    // the chunks is reused once every wave is past its last chunk
+    // block totals, waves in order: K from the accumulators (register r of block
+    // (e, b) is direction 16 e + 4 r + lq of set 16 b + lr); W and Q summed over lq
     constexpr int L = DM + 2;
-    double* tot = s_buf;
-    __syncthreads();
+    double* part = s_tot + kSetsPerWave * L;  // [2][64]: per-lane W, Q partials of one wave
+    __syncthreads();  // every wave is past the coefficient table
     for (int w = 0; w < kWaves; ++w) {
         if (wv == w) {
 #pragma unroll
-            for (int q = 0; q < DH; ++q) tot[ls * L + jh + q] = (w == 0 ? 0.0 : tot[ls * L + jh + q]) + K[q];
-            if (half == 0) {
-                tot[ls * L + DM] = (w == 0 ? 0.0 : tot[ls * L + DM]) + ws;
-                tot[ls * L + DM + 1] = (w == 0 ? 0.0 : tot[ls * L + DM + 1]) + qs;
-            }
+            for (int e = 0; e < NE; ++e)
+#pragma unroll
+                for (int b = 0; b < 4; ++b)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const int j = 16 * e + 4 * r + lq;
+                        if (j < DM) {
+                            double* slot = &s_tot[(16 * b + lr) * L + j];
+                            *slot = (w == 0 ? 0.0 : *slot) + acc[e][b][r];
+                        }
+                    }
         }
         __syncthreads();
+        for (int b = 0; b < 4; ++b) {
+            if (wv == w) {
+                part[l] = ws[b];
+                part[kWave + l] = qs[b];
+            }
+            __syncthreads();
+            if (wv == w && lq == 0) {
+                const double wsum = ((part[lr] + part[16 + lr]) + part[32 + lr]) + part[48 + lr];
+                const double qsum = ((part[kWave + lr] + part[kWave + 16 + lr]) + part[kWave + 32 + lr]) +
+                                    part[kWave + 48 + lr];
+                double* row = &s_tot[(16 * b + lr) * L];
+                row[DM] = (w == 0 ? 0.0 : row[DM]) + wsum;
+                row[DM + 1] = (w == 0 ? 0.0 : row[DM + 1]) + qsum;
+            }
+            __syncthreads();
+        }
     }
     const int G = (int)gridDim.x;
-    double* part = a.scratch + (size_t)blockIdx.y * a.scratch_stride;
-    if (!grid_sum_vec(tot, kSetsPerWave * L, (int)blockIdx.x, G, part, part + (size_t)G * kSetsPerWave * L,
+    double* gpart = a.scratch + (size_t)blockIdx.y * a.scratch_stride;
+    if (!grid_sum_vec(s_tot, kSetsPerWave * L, (int)blockIdx.x, G, gpart, gpart + (size_t)G * kSetsPerWave * L,
                       a.tickets + (size_t)blockIdx.y * kTicketsPerReduction, &s_flag))
         return;
     // one thread per (set, output)
@@ -497,7 +569,7 @@ __global__ __launch_bounds__(kBlock) void adjoint_sets_kernel(const AdjSetsArgs 
             scale = exp2(h);
         }
         const double g = a.gq ? a.gq[st] : 1.0;
-        const double* v = tot + es * L;
+        const double* v = s_tot + es * L;
         if (o == a.P) {
             a.q_out[st] = scale * v[DM + 1] * a.inv_n;
         } else if (FAM == kOscillatory && o == 0) {
@@ -522,9 +594,11 @@ static size_t sets_group_stride(int DM, int groups) {
            (size_t)(DM + 2);
 }
 
+static int sets_dims(int d) { return d <= 16 ? 16 : d <= 32 ? 32 : d <= 48 ? 48 : d <= 56 ? 56 : 64; }
+
 static size_t sets_workspace_bytes(int d, int nsets) {
     const int groups = (nsets + kSetsPerWave - 1) / kSetsPerWave;
-    const int DM = d <= 48 ? (d + 7) / 8 * 8 : (d + 3) / 4 * 4;  // the kernel's bucket for d
+    const int DM = sets_dims(d);
     return kZeroBytes + ((size_t)groups * sets_group_stride(DM, groups) * sizeof(double) + 255) / 256 * 256;
 }
 
@@ -532,8 +606,9 @@ static bool use_sets_kernel(const AdjLaunch& L) {
     return (L.family == kExpSum || L.family == kOscillatory) && L.d <= kSetsMaxDims && L.nsets >= 16;
 }
 
-template <int FAM, bool FP32, int DM>
-static hipError_t launch_sets_dm(const AdjLaunch& L, hipStream_t stream) {
+template <int FAM, bool FP32, int DQ>
+static hipError_t launch_sets_dq(const AdjLaunch& L, hipStream_t stream) {
+    constexpr int DM = 4 * DQ;
     AdjSetsArgs a;
     a.d = L.d;
     a.n = L.n;
@@ -545,10 +620,10 @@ static hipError_t launch_sets_dm(const AdjLaunch& L, hipStream_t stream) {
     a.nsets = L.nsets;
     const int groups = (L.nsets + kSetsPerWave - 1) / kSetsPerWave;
     int G = sets_blocks(groups);
-    const uint64_t waves_min = ((uint64_t)L.n + kSetChunk - 1) / kSetChunk;  // at least one chunk per wave
+    const uint64_t waves_min = ((uint64_t)L.n + kMfmaPoints - 1) / kMfmaPoints;  // at least one block per wave
     if ((uint64_t)G * kWaves > waves_min) G = (int)((waves_min + kWaves - 1) / kWaves);
-    a.points_per_wave = (((uint64_t)L.n + (uint64_t)G * kWaves - 1) / ((uint64_t)G * kWaves) + kSetChunk - 1) /
-                        kSetChunk * kSetChunk;
+    a.points_per_wave = (((uint64_t)L.n + (uint64_t)G * kWaves - 1) / ((uint64_t)G * kWaves) + kMfmaPoints - 1) /
+                        kMfmaPoints * kMfmaPoints;
     a.gq = L.gq;
     a.q_out = L.q_out;
     a.grad_out = L.grad_out;
@@ -556,21 +631,20 @@ static hipError_t launch_sets_dm(const AdjLaunch& L, hipStream_t stream) {
     a.scratch = (double*)((char*)L.ws + kZeroBytes);
     a.scratch_stride = sets_group_stride(DM, groups);
     const size_t lds = (size_t)sets_lds_doubles(DM) * sizeof(double);
-    hipLaunchKernelGGL((adjoint_sets_kernel<FAM, FP32, DM>), dim3((unsigned)G, (unsigned)groups), dim3(kBlock),
-                       lds, stream, a);
+    hipLaunchKernelGGL((adjoint_sets_kernel<FAM, FP32, DQ>), dim3((unsigned)G, (unsigned)groups), dim3(kBlock), lds,
+                       stream, a);
     return hipGetLastError();
 }
 
 template <int FAM, bool FP32>
 static hipError_t launch_sets(const AdjLaunch& L, hipStream_t stream) {
-    if (L.d <= 8) return launch_sets_dm<FAM, FP32, 8>(L, stream);
-    if (L.d <= 16) return launch_sets_dm<FAM, FP32, 16>(L, stream);
-    if (L.d <= 24) return launch_sets_dm<FAM, FP32, 24>(L, stream);
-    if (L.d <= 32) return launch_sets_dm<FAM, FP32, 32>(L, stream);
-    if (L.d <= 40) return launch_sets_dm<FAM, FP32, 40>(L, stream);
-    if (L.d <= 48) return launch_sets_dm<FAM, FP32, 48>(L, stream);
-    if (L.d <= 52) return launch_sets_dm<FAM, FP32, 52>(L, stream);
-    return launch_sets_dm<FAM, FP32, 56>(L, stream);
+    switch (sets_dims(L.d)) {
+        case 16: return launch_sets_dq<FAM, FP32, 4>(L, stream);
+        case 32: return launch_sets_dq<FAM, FP32, 8>(L, stream);
+        case 48: return launch_sets_dq<FAM, FP32, 12>(L, stream);
+        case 56: return launch_sets_dq<FAM, FP32, 14>(L, stream);
+        default: return launch_sets_dq<FAM, FP32, 16>(L, stream);
+    }
 }
 
 // --------------------------------------------------------------------------

@@ -64,7 +64,7 @@ hipError_t launch_mdi_lr(const MdiLaunch& a, hipStream_t stream);
 // Adjoint of the plain rule for nsets parameter sets sharing the lattice.
 constexpr int kMaxAdjBlocks = 1024;
 constexpr int kMaxAdjDims = 512;
-constexpr int kAdjSetsMaxParams = 57;  // parameters per set served by the set-batched adjoint (d <= 56)
+constexpr int kAdjSetsMaxParams = 65;  // parameters per set served by the set-batched adjoint (d <= 64)
 
 struct AdjLaunch {
     int d;

@@ -134,12 +134,13 @@ def test_adjoint_rejects_large_d():
     assert e.value.status == qmc.ERR_UNSUPPORTED
 
 
-# The set-batched form (exp-sum and oscillatory, d <= 56, at least 16 sets: lane =
-# parameter set) against the oracle set by set, and against the per-set form.
+# The set-batched form (exp-sum and oscillatory, d <= 64, at least 16 sets: FP64
+# matrix instructions over 64 sets per wave) against the oracle set by set, and
+# against the per-set form.
 @pytest.mark.parametrize("precision", [qmc.FP64, qmc.FP32_COMPENSATED])
 @pytest.mark.parametrize("family", [0, 3])
 @pytest.mark.parametrize("d,n,nsets", [(3, 10007, 16), (20, 65537, 64), (56, 3001, 70), (1, 997, 130),
-                                       (9, 1009, 17)])
+                                       (9, 1009, 17), (64, 4099, 65), (57, 2003, 128), (33, 101, 20)])
 def test_adjoint_set_batched_matches_oracle(precision, family, d, n, nsets):
     rng = np.random.default_rng(11 * d + n + family + nsets)
     z = qmc.korobov(d, n, W.draw_coprime(rng, n))
