@@ -98,10 +98,11 @@ def uses_adjoint_sets(d: int, family: int, nsets: int) -> bool:
 WORK_PER_MDI_FACTOR = 3 * C32 + CT + ACCUM
 
 # MDI-LR of g(sum x), power g, QMC_FP32_COMPENSATED, per merged-state evaluation of
-# g: the node, b + c s, an FP64 log2 (a software sequence), the exponent and the
-# split exp2, the weighted FP64 add -- 88 VALU instructions in the compiled loop,
-# 80 of them FP64: 168 slots.
-WORK_PER_SUM_EVAL = 80 * C64 + 8 * C32
+# g (FP64 operations): the node and b + c s (2); log2 by the atanh series (22: the
+# mantissa and exponent, the reduction to [sqrt(1/2), sqrt(2)), the reciprocal with
+# two Newton steps, the eight-term polynomial, the exponent added back); the
+# exponent -p log2 (1); the split exp2 (5, plus one v_exp_f32); the weighted add (1).
+WORK_PER_SUM_EVAL = 31 * C64 + CT
 
 # Lattice-quality criteria (FP64): per point and direction the index step, the
 # conversion, x = k/n, y = x (1 - x), the factor 1 + a B(x) and the product; per

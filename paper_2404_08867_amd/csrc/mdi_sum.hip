@@ -96,13 +96,44 @@ __global__ __launch_bounds__(kConvBlock) void states_init_kernel(int N, double* 
     if (t < N) w[t] = 1.0 / (double)N;
 }
 
+// log2(x) for finite x > 0 to about 1e-13 absolute: x = m 2^e with m in
+// [sqrt(1/2), sqrt(2)), and log2(m) = (2 / ln 2) atanh(s) with s = (m - 1) / (m + 1),
+// |s| <= 3 - 2 sqrt(2) < 0.172, atanh(s) = s sum_k s^{2k} / (2k + 1) (the first
+// eight terms; the ninth is below 2e-14 s).  The reciprocal of m + 1 in [1.7, 2.5]
+// is the hardware estimate refined by two Newton steps.  Other x take the
+// library log2.
+__device__ __forceinline__ double log2_atanh(double x) {
+    if (!(x > 0.0 && x < __builtin_huge_val())) return log2(x);
+    int e = __builtin_amdgcn_frexp_exp(x);
+    double m = __builtin_amdgcn_frexp_mant(x);  // [1/2, 1)
+    if (m < 0.70710678118654752440) {
+        m *= 2.0;
+        e -= 1;
+    }
+    const double den = m + 1.0;
+    double rc = __builtin_amdgcn_rcp(den);
+    rc = fma(rc, fma(-den, rc, 1.0), rc);
+    rc = fma(rc, fma(-den, rc, 1.0), rc);
+    const double sv = (m - 1.0) * rc;
+    const double s2 = sv * sv;
+    double poly = 1.0 / 15.0;
+    poly = fma(poly, s2, 1.0 / 13.0);
+    poly = fma(poly, s2, 1.0 / 11.0);
+    poly = fma(poly, s2, 1.0 / 9.0);
+    poly = fma(poly, s2, 1.0 / 7.0);
+    poly = fma(poly, s2, 1.0 / 5.0);
+    poly = fma(poly, s2, 1.0 / 3.0);
+    poly = fma(poly, s2, 1.0);
+    return fma(2.0 * kLog2e * sv, poly, (double)e);
+}
+
 // g of the sum: power (b + c s)^-p, or Gaussian exp(-c^2 (s - w)^2).
 template <int GFAM, bool FP32>
 __device__ __forceinline__ double sum_g(const double* gp, double s) {
     if constexpr (GFAM == 0) {
         if constexpr (FP32) {
             // 2^{-p log2(b + c s)}: the exponent in FP64, its fractional power in FP32
-            return exp2_split_f32(-gp[2] * log2(fma(gp[1], s, gp[0])));
+            return exp2_split_f32(-gp[2] * log2_atanh(fma(gp[1], s, gp[0])));
         } else {
             return pow(fma(gp[1], s, gp[0]), -gp[2]);
         }
