@@ -182,3 +182,32 @@ def test_adjoint_set_batched_workspace_from_workspace_size():
     qo, go = O.lattice_grad(z, n, 3, params[5])
     _, ao = O.lattice_sum(z, n, 3, params[5])
     _check_set(q.cpu().numpy()[5], g.cpu().numpy()[5], qo, ao, go, TOL[qmc.FP64])
+
+
+def test_adjoint_set_batched_replays_in_a_graph():
+    # the set-batched form's tickets reset themselves: every replay of a captured
+    # call matches the eager result bit for bit, with eager calls in between
+    torch = _torch()
+    rng = np.random.default_rng(77)
+    d, n, nsets = 30, 50021, 64
+    z = torch.tensor(qmc.korobov(d, n, 4321), device="cuda")
+    params = torch.tensor(np.stack([W.draw_params(rng, 3, d) for _ in range(nsets)]), device="cuda")
+    ws = qmc.Workspace(qmc.workspace_size(d, n, nsets))
+    q0, g0 = qmc.lattice_sum_adjoint(z, n, 3, params, qmc.FP32_COMPENSATED, ws=ws)
+    q0, g0 = q0.clone(), g0.clone()
+    holder = {}
+    g = torch.cuda.CUDAGraph()
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        with torch.cuda.graph(g):
+            holder["r"] = qmc.lattice_sum_adjoint(z, n, 3, params, qmc.FP32_COMPENSATED, ws=ws)
+    torch.cuda.current_stream().wait_stream(side)
+    for rep in range(3):
+        holder["r"][0].fill_(0.0)
+        holder["r"][1].fill_(0.0)
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(holder["r"][0], q0) and torch.equal(holder["r"][1], g0), rep
+        qmc.lattice_sum_adjoint(z, n, 0, params[:20, :d], qmc.FP64, ws=ws)  # other work in between
+        torch.cuda.synchronize()

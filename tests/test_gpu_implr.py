@@ -113,3 +113,30 @@ def test_points_unaligned_output_rows():
         assert np.array_equal(s * z, want), (ld, off)
         rest = big[:, off + count:].cpu().numpy()
         assert np.all(rest == -1)  # nothing written past count
+
+
+def test_grid_count_replays_in_a_graph():
+    # all counters are reset by the launches themselves (no memset): a captured
+    # call gives the same n* on every replay, with eager calls in between
+    import torch
+    d, n, a = 4, 1048573, 100
+    ws = qmc.Workspace(qmc.implr_workspace_size(d, n, a))
+    out = torch.zeros(1, dtype=torch.int64, device="cuda")
+    want = int(np.prod(O.mdi_dims(O.korobov(d, n, a), n))) - n
+    for method in METHODS:
+        qmc.implr_grid(d, n, a, method, ws=ws, out=out)
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            with torch.cuda.graph(g):
+                qmc.implr_grid(d, n, a, method, ws=ws, out=out)
+        torch.cuda.current_stream().wait_stream(side)
+        for rep in range(3):
+            out.fill_(-1)
+            g.replay()
+            torch.cuda.synchronize()
+            assert int(out.item()) == want, (method, rep)
+            _, eager = qmc.implr_grid(3, 1332, 11, method, ws=ws)  # other work in between
+            assert int(eager.item()) == 11 * 11 * 12 - 1332
