@@ -256,3 +256,43 @@ def test_one_workspace_serves_every_call_shape():
         for s in range(nsets):
             qo, ao = O.lattice_sum(z, n, fam, params[s])
             assert _rel(q[s], qo, ao) <= 1e-12, (i, s, q[s], qo)
+
+
+def test_plain_and_mdi_graph_replays_match_eager():
+    # the plain sum's tickets and tagged slots return to zero by themselves, and
+    # MDI-LR uses no workspace: captured calls replay bit for bit, with eager calls
+    # (other sizes, other set counts) in between
+    import torch
+    prob = W.plain_d20_peak()
+    z = torch.tensor(qmc.korobov(prob.d, prob.n, prob.a), device="cuda")
+    params = torch.tensor(prob.params, dtype=torch.float64, device="cuda")
+    ws = qmc.Workspace(qmc.workspace_size(prob.d, prob.n, 8))
+    wm = W.mdi_d100_gauss(nsets=256)
+    N = torch.tensor(wm.N.astype("int32"), device="cuda")
+    mp = torch.tensor(wm.params, dtype=torch.float64, device="cuda")
+    outs = {}
+    for prec in (qmc.FP32_COMPENSATED, qmc.FP64):
+        q_eager = qmc.lattice_sum(z, prob.n, prob.family, params, prec, ws=ws).clone()
+        m_eager = qmc.mdi_lr(N, wm.family, mp, prec).clone()
+        q_out = torch.zeros(1, dtype=torch.float64, device="cuda")
+        m_out = torch.zeros(256, dtype=torch.float64, device="cuda")
+        g = torch.cuda.CUDAGraph()
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            with torch.cuda.graph(g):
+                qmc.lattice_sum(z, prob.n, prob.family, params, prec, ws=ws, out=q_out)
+                qmc.mdi_lr(N, wm.family, mp, prec, out=m_out)
+        torch.cuda.current_stream().wait_stream(side)
+        for rep in range(3):
+            q_out.zero_()
+            m_out.zero_()
+            g.replay()
+            torch.cuda.synchronize()
+            assert torch.equal(q_out.reshape(-1), q_eager.reshape(-1)), (prec, rep)
+            assert torch.equal(m_out, m_eager), (prec, rep)
+            many = torch.stack([params, params * 0.5])  # two sets: other slot layout
+            qmc.lattice_sum(z, prob.n, prob.family, many, prec, ws=ws)
+            torch.cuda.synchronize()
+        outs[prec] = float(q_eager.reshape(-1)[0])
+    assert abs(outs[qmc.FP32_COMPENSATED] - outs[qmc.FP64]) <= 1e-6 * abs(outs[qmc.FP64])
