@@ -663,8 +663,8 @@ def oracle_adjoint_baseline(w, r32, r64):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
-              "the multi-GPU sharding is described in DESIGN.md but not implemented.", file=sys.stderr)
+        print(f"bench.py: runs on one GPU only (asked for --gpus {args.gpus}); "
+              "sharding the lattice over several GPUs is not implemented.", file=sys.stderr)
         sys.exit(2)
     import numpy as np
     import torch
