@@ -59,6 +59,20 @@ __device__ __forceinline__ uint32_t stepmod(uint32_t k, uint32_t st, uint32_t st
     return min(k + st, k + stm);
 }
 
+// The same step on an index held as a float, for n <= kFloatIndexMaxN = 2^24:
+// k < n, st and stm = st - n are exact in single precision.  If k + st < n, that
+// sum is exact and the other one negative, and a negative float's sign bit makes
+// its bit pattern the larger one.  Otherwise k + st - n lies in [0, n) and is
+// exact, and k + st (rounded when above 2^24) is not smaller; non-negative floats
+// order like their patterns (an exact zero is +0.0, pattern 0).  Either way the
+// unsigned minimum of the two patterns is the residue, as a float: three VALU
+// operations and no integer-to-float conversion per point.
+constexpr uint32_t kFloatIndexMaxN = 1u << 24;
+
+__device__ __forceinline__ float stepmod_f(float k, float st, float stm) {
+    return __uint_as_float(min(__float_as_uint(k + st), __float_as_uint(k + stm)));
+}
+
 // ---------------------------------------------------------------------------
 // Deterministic reductions (fixed order within the wave, waves in index order
 // across the workgroup).

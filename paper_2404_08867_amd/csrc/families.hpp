@@ -214,6 +214,13 @@ struct ProductPeak {
         const T y = fma((T)k, c.a, c.b);
         acc.D *= fma(y, y, c.g);
     }
+    // FP32 factors can take the index as an exact float (stepmod_f): the same y
+    // as step() without the conversion.
+    static constexpr bool kFloatIndex = FP32_DIMS;
+    __device__ static void step_f(Acc& acc, float k, const Dim& c) {
+        const T y = fma((T)k, c.a, c.b);
+        acc.D *= fma(y, y, c.g);
+    }
     __device__ static void renorm(Acc& acc) {
         if constexpr (FP32_DIMS) {
             acc.E += __builtin_amdgcn_frexp_expf(acc.D);

@@ -52,7 +52,7 @@ __device__ __forceinline__ GridSlots set_slots(double* scratch, uint32_t scratch
     return s;
 }
 
-template <class F, int M, int B>
+template <class F, int M, int B, bool FI>
 __global__ __launch_bounds__(B) void lattice_sum_kernel(
     const int64_t* z, const double* params, const double* shift, double inv_n, uint32_t n, int d,
     int param_stride, int shift_stride, int z_stride, uint32_t tiles, double* q_out,
@@ -74,11 +74,11 @@ __global__ __launch_bounds__(B) void lattice_sum_kernel(
         // residues are built with them.
         setup_one_chunk<F, M, B>(v, s, s_red, blockIdx.x * kTile, init0, ds1, ie);
         for (uint32_t tile = blockIdx.x; tile < tiles; tile += gridDim.x)
-            tacc += tile_points_one_chunk<F, M, B>(v, s, tile * kTile, init0, tile == blockIdx.x);
+            tacc += tile_points_one_chunk<F, M, B, FI>(v, s, tile * kTile, init0, tile == blockIdx.x);
     } else {
         block_constants<F, B>(v, s_red, init0, ds1, ie);
         for (uint32_t tile = blockIdx.x; tile < tiles; tile += gridDim.x)
-            tacc += tile_points<F, M, B>(v, s, tile * kTile, init0);
+            tacc += tile_points<F, M, B, FI>(v, s, tile * kTile, init0);
     }
 
     // Workgroup total to wave 0 (red[B / kWave ..) is untouched by the setup), then
@@ -187,7 +187,7 @@ int device_cu_count() {
     return cus;
 }
 
-template <class F, int M>
+template <class F, int M, bool FI>
 static hipError_t launch_fm(const PlainLaunch& L, hipStream_t stream) {
     SumArgs a;
     a.z = L.z;
@@ -210,11 +210,20 @@ static hipError_t launch_fm(const PlainLaunch& L, hipStream_t stream) {
     if (L.max_blocks > 0 && L.max_blocks < g) g = L.max_blocks;
     if ((uint32_t)g > a.tiles) g = (int)a.tiles;
     dim3 grid((unsigned)g, (unsigned)L.nsets);
-    hipLaunchKernelGGL((lattice_sum_kernel<F, M, kSumBlock>), grid, dim3(kSumBlock), 0, stream,
+    hipLaunchKernelGGL((lattice_sum_kernel<F, M, kSumBlock, FI>), grid, dim3(kSumBlock), 0, stream,
                        a.z, a.params, a.shift, a.inv_n, a.n, a.d, a.param_stride, a.shift_stride,
                        a.z_stride, a.tiles, a.q_out, a.tickets, a.scratch, a.scratch_stride,
                        a.slot_stride);
     return hipGetLastError();
+}
+
+// Families with an exact-float index step use it whenever n allows.
+template <class F, int M>
+static hipError_t launch_fi(const PlainLaunch& L, hipStream_t stream) {
+    if constexpr (float_index<F>::value) {
+        if (L.n <= kFloatIndexMaxN) return launch_fm<F, M, true>(L, stream);
+    }
+    return launch_fm<F, M, false>(L, stream);
 }
 
 template <class F>
@@ -230,9 +239,9 @@ static hipError_t launch_f(const PlainLaunch& L, hipStream_t stream) {
             M /= 2;
     }
     switch (M) {
-        case 4: return launch_fm<F, 4>(L, stream);
-        case 8: return launch_fm<F, 8>(L, stream);
-        case 16: return launch_fm<F, 16>(L, stream);
+        case 4: return launch_fi<F, 4>(L, stream);
+        case 8: return launch_fi<F, 8>(L, stream);
+        case 16: return launch_fi<F, 16>(L, stream);
         default: return hipErrorInvalidValue;
     }
 }

@@ -12,10 +12,18 @@
 // at a time.  One step is two 32-bit adds and a min.
 #pragma once
 
+#include <type_traits>
+
 #include "common.hpp"
 #include "families.hpp"
 
 namespace qmc {
+
+// Families whose step can take the index as an exact float (F::kFloatIndex).
+template <class F, class = void>
+struct float_index : std::false_type {};
+template <class F>
+struct float_index<F, std::void_t<decltype(F::kFloatIndex)>> : std::bool_constant<F::kFloatIndex> {};
 
 // A problem as seen by the device: lattice, shift and one parameter row.
 struct ProblemView {
@@ -64,6 +72,7 @@ struct TileShared {
     uint32_t lz[kDimChunk * kWave];   // [j][lane]
     uint32_t kw[kDimChunk * (B / kWave)];  // [j][wave]
     uint2 st[kDimChunk];              // (D_j, D_j - n)
+    float2 stf[kDimChunk];            // the same as exact floats (n <= kFloatIndexMaxN)
     uint32_t sh[kDimChunk];           // whole part of the shift
     typename F::Dim c[kDimChunk];     // family constants
 };
@@ -135,6 +144,7 @@ __device__ __forceinline__ void fill_dims(const ProblemView& v, TileShared<F, B>
         split_shift(v.shift, j, v.n, whole, frac);
         const uint32_t st = mulmod_small((uint32_t)kWave, (uint32_t)v.z[j], v.dn, v.inv_n);
         s.st[e] = make_uint2(st, st - v.n);
+        if constexpr (float_index<F>::value) s.stf[e] = make_float2((float)st, (float)st - (float)v.n);
         s.sh[e] = whole;
         s.c[e] = F::dim(v.p, v.d, j, v.inv_n, frac);
     }
@@ -153,19 +163,31 @@ __device__ __forceinline__ void fill_tile(const ProblemView& v, TileShared<F, B>
 
 // Accumulates directions [j0, j0 + dc) into the thread's M point states, from
 // the direction tables (fill_dims) and the tile's start residues (fill_tile) in s.
-template <class F, int M, int B>
+// FI (families with kFloatIndex, n <= kFloatIndexMaxN): the thread's M indices
+// of a direction are stepped as exact floats (stepmod_f), converted once.
+template <class F, int M, int B, bool FI = false>
 __device__ __forceinline__ void chunk_points(typename F::Acc (&acc)[M], const TileShared<F, B>& s, int j0,
                                              int dc, uint32_t n) {
     using Dim = typename F::Dim;
     const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
     for (int jj = 0; jj < dc; ++jj) {
         uint32_t k = addmod(s.kw[jj * (B / kWave) + wv], s.lz[jj * kWave + lane], n);
-        const uint2 stp = s.st[jj];
         const Dim c = s.c[jj];
+        if constexpr (FI) {
+            const float2 stp = s.stf[jj];
+            float kf = (float)k;
 #pragma unroll
-        for (int m = 0; m < M; ++m) {
-            F::step(acc[m], k, c);
-            k = stepmod(k, stp.x, stp.y);
+            for (int m = 0; m < M; ++m) {
+                F::step_f(acc[m], kf, c);
+                kf = stepmod_f(kf, stp.x, stp.y);
+            }
+        } else {
+            const uint2 stp = s.st[jj];
+#pragma unroll
+            for (int m = 0; m < M; ++m) {
+                F::step(acc[m], k, c);
+                k = stepmod(k, stp.x, stp.y);
+            }
         }
         if constexpr (F::kRenorm > 0) {
             if ((j0 + jj + 1) % F::kRenorm == 0) {
@@ -194,7 +216,7 @@ __device__ __forceinline__ double finish_points(const typename F::Acc (&acc)[M],
 // The thread's sum of f / scale over its M points of the tile, any d: the
 // tables are rebuilt chunk by chunk.  Begins with a barrier; the caller may
 // reuse s afterwards only after another barrier.
-template <class F, int M, int B>
+template <class F, int M, int B, bool FI = false>
 __device__ __forceinline__ double tile_points(const ProblemView& v, TileShared<F, B>& s,
                                               uint32_t tile_base, double init0) {
     typename F::Acc acc[M];
@@ -207,7 +229,7 @@ __device__ __forceinline__ double tile_points(const ProblemView& v, TileShared<F
         __syncthreads();
         fill_tile<F, M, B>(v, s, j0, dc, tile_base);
         __syncthreads();
-        chunk_points<F, M, B>(acc, s, j0, dc, v.n);
+        chunk_points<F, M, B, FI>(acc, s, j0, dc, v.n);
     }
     return finish_points<F, M>(acc, tile_base, v.n);
 }
@@ -236,6 +258,8 @@ __device__ __forceinline__ void setup_one_chunk(const ProblemView& v, TileShared
             if constexpr (F::kBlockTerms) F::block_terms(v.p, d, j, v.inv_n, frac, t0, t1, te);
             const uint32_t st = mulmod_small((uint32_t)kWave, (uint32_t)v.z[j], v.dn, v.inv_n);
             s.st[j] = make_uint2(st, st - v.n);
+            if constexpr (float_index<F>::value)
+                s.stf[j] = make_float2((float)st, (float)st - (float)v.n);
             s.sh[j] = whole;
             s.c[j] = F::dim(v.p, d, j, v.inv_n, frac);
         }
@@ -272,7 +296,7 @@ __device__ __forceinline__ void setup_one_chunk(const ProblemView& v, TileShared
 // One tile of a problem set up by setup_one_chunk.  With `kw_ready` the start
 // residues of this tile are already in s; otherwise they are rebuilt between two
 // barriers.  The caller may overwrite s afterwards only after a barrier.
-template <class F, int M, int B>
+template <class F, int M, int B, bool FI = false>
 __device__ __forceinline__ double tile_points_one_chunk(const ProblemView& v, TileShared<F, B>& s,
                                                         uint32_t tile_base, double init0,
                                                         bool kw_ready) {
@@ -284,7 +308,7 @@ __device__ __forceinline__ double tile_points_one_chunk(const ProblemView& v, Ti
     typename F::Acc acc[M];
 #pragma unroll
     for (int m = 0; m < M; ++m) acc[m] = F::init(init0);
-    chunk_points<F, M, B>(acc, s, 0, v.d, v.n);
+    chunk_points<F, M, B, FI>(acc, s, 0, v.d, v.n);
     return finish_points<F, M>(acc, tile_base, v.n);
 }
 

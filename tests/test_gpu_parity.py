@@ -97,6 +97,19 @@ def test_plain_sum_tiny_n(n):
             assert _rel(_gpu_sum(prob, precision), qo, ao) <= TOL[precision]
 
 
+@pytest.mark.parametrize("n", [8388593, 16777213, 1 << 24, 16777259])
+@pytest.mark.parametrize("shift", [False, True])
+def test_plain_sum_float_index_boundary(n, shift):
+    """FP32 product-peak sums step their indices as exact floats for n <= 2^24 and
+    as integers above; both sides of the bound against the oracle, FP32c and FP64."""
+    prob = W.random_plain(n + int(shift), 1, 4, n, shift=shift)
+    qo, ao = _oracle_sum(prob)
+    for precision in PRECS:
+        for ppt in (4, 8, 16):
+            q = _gpu_sum(prob, precision, points_per_thread=ppt)
+            assert _rel(q, qo, ao) <= TOL[precision], (n, precision, ppt, q, qo)
+
+
 def test_plain_sum_max_dimension():
     for family in range(4):
         prob = W.random_plain(5 + family, family, 1024, 257, shift=True)
