@@ -113,15 +113,29 @@ __global__ __launch_bounds__(kSelectBlock) void select_kernel(double* v, int cou
 // CBC (Sec. 2.2): with the running product p(k) = prod_{i<j} (1 + a_i B({k z_i/n}))
 // in memory, the criterion of candidate c for component j is
 //   S_j(c) = (1/n) sum_k [ p(k) (1 + a_j B_alpha({k c / n})) - 1 ].
-// A workgroup owns kCbcCand consecutive candidates and sweeps all k in chunks of
-// kCbcBlock * kCbcM: each thread keeps kCbcM values of p and of k in registers and,
-// from one candidate to the next, advances its residues k c mod n by k (one modular
-// add).  Per candidate and chunk each wave adds its wave total to an LDS slot, in
-// chunk order, so the result is reproducible.
+// Index k and n - k give mirrored points ({(n - k) z / n} = 1 - {k z / n} or both
+// 0) and B_alpha(1 - x) = B_alpha(x) for even alpha, so p and every term are equal
+// at k and n - k: the sum is T(0) + 2 sum_{k=1}^{h} T(k) + [n even] T(n/2) with
+// h = (n - 1) / 2, and p is kept for k <= n/2 only.
+// A workgroup owns kCbcCand consecutive candidates and sweeps k = 1..h in chunks
+// of kCbcBlock * kCbcM: each thread keeps kCbcM values of p and of k in registers
+// and, from one candidate to the next, advances its residues k c mod n by k (one
+// modular add).  Per candidate and chunk each wave adds its wave total to an LDS
+// slot, in chunk order; thread c then adds T(0) and T(n/2) in a fixed order, so the
+// result is reproducible.
 // --------------------------------------------------------------------------
 constexpr int kCbcBlock = 1024;
 constexpr int kCbcM = 16;
 constexpr int kCbcCand = 64;
+
+// 1 + a B_alpha(x) from y = x (1 - x), with c0 = 1 + a B_alpha(0).
+template <int ALPHA>
+__device__ __forceinline__ double bernoulli_factor(double aj, double c0, double y) {
+    if constexpr (ALPHA == 2)
+        return fma(-aj, y, c0);  // 1 + a (1/6 - y) = 1 + a B_2(x)
+    else
+        return fma(aj * y, y, c0);  // 1 + a (y^2 - 1/30) = 1 + a B_4(x)
+}
 
 template <int ALPHA>
 __global__ __launch_bounds__(kCbcBlock) void cbc_eval_kernel(uint32_t n, double inv_n,
@@ -135,18 +149,19 @@ __global__ __launch_bounds__(kCbcBlock) void cbc_eval_kernel(uint32_t n, double 
     const int gc = min(kCbcCand, ncand - g0);
     const double aj = a[j];
     const double c0 = ALPHA == 2 ? 1.0 + aj / 6.0 : 1.0 - aj / 30.0;
+    const uint32_t h = (n - 1) / 2;  // paired indices 1..h
     for (int i = tid; i < kCbcCand * W; i += kCbcBlock) s_acc[i] = 0.0;
     __syncthreads();
     const uint64_t cbeg = (uint64_t)(c_first + g0) % n;
 
-    for (uint32_t k0 = 0; k0 < n; k0 += kCbcBlock * kCbcM) {
+    for (uint32_t k0 = 1; k0 <= h; k0 += kCbcBlock * kCbcM) {
         uint32_t r[kCbcM], kk[kCbcM];
         double pk[kCbcM];
-        double bias = 0.0;  // +1 for each k >= n, whose term below is exactly -1
+        double bias = 0.0;  // +1 for each k > h, whose term below is exactly -1
 #pragma unroll
         for (int m = 0; m < kCbcM; ++m) {
             const uint32_t k = k0 + (uint32_t)(m * kCbcBlock + tid);
-            const bool ok = k < n;
+            const bool ok = k <= h;
             kk[m] = ok ? k : 0u;
             pk[m] = ok ? p[k] : 0.0;
             bias += ok ? 0.0 : 1.0;
@@ -158,12 +173,7 @@ __global__ __launch_bounds__(kCbcBlock) void cbc_eval_kernel(uint32_t n, double 
             for (int m = 0; m < kCbcM; ++m) {
                 const double x = (double)r[m] * inv_n;
                 const double y = fma(-x, x, x);  // x (1 - x)
-                double g;
-                if constexpr (ALPHA == 2)
-                    g = fma(-aj, y, c0);  // 1 + a (1/6 - y) = 1 + a B_2(x)
-                else
-                    g = fma(aj * y, y, c0);  // 1 + a (y^2 - 1/30) = 1 + a B_4(x)
-                acc += fma(pk[m], g, -1.0);
+                acc += fma(pk[m], bernoulli_factor<ALPHA>(aj, c0, y), -1.0);
                 r[m] = addmod(r[m], kk[m], n);
             }
             const double w = wave_total(acc);
@@ -175,29 +185,36 @@ __global__ __launch_bounds__(kCbcBlock) void cbc_eval_kernel(uint32_t n, double 
         double t = 0.0;
 #pragma unroll
         for (int w = 0; w < W; ++w) t += s_acc[c * W + w];
-        const bool ok = gcd_u32((uint32_t)((cbeg + c) % n), n) == 1;
-        s_cand[g0 + c] = ok ? t * inv_n : INFINITY;
+        const uint32_t cand = (uint32_t)((cbeg + c) % n);
+        // T(0): x = 0.  T(n/2) for even n: x = {c / 2}, 0 or 1/2.
+        double total = fma(p[0], c0, -1.0) + 2.0 * t;
+        if ((n & 1u) == 0) {
+            const double y = (cand & 1u) ? 0.25 : 0.0;
+            total += fma(p[n / 2], bernoulli_factor<ALPHA>(aj, c0, y), -1.0);
+        }
+        const bool ok = gcd_u32(cand, n) == 1;
+        s_cand[g0 + c] = ok ? total * inv_n : INFINITY;
     }
 }
 
-// p(k) = 1 for all k.
+// p(k) = 1 for k <= n/2.
 __global__ __launch_bounds__(256) void cbc_init_kernel(uint32_t n, double* p) {
     const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k < n) p[k] = 1.0;
+    if (k <= n / 2) p[k] = 1.0;
 }
 
-// p(k) *= 1 + a_j B_alpha({k z_j / n}) with the z_j just chosen (read from device memory).
+// p(k) *= 1 + a_j B_alpha({k z_j / n}) for k <= n/2, with the z_j just chosen (read
+// from device memory).
 template <int ALPHA>
 __global__ __launch_bounds__(256) void cbc_update_kernel(uint32_t n, double inv_n, const double* a,
                                                         int j, const int64_t* z, double* p) {
     const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= n) return;
+    if (k > n / 2) return;
     const double aj = a[j];
     const uint32_t r = mulmod((uint64_t)k, (uint64_t)z[j] % n, n, inv_n);
     const double x = (double)r * inv_n;
     const double y = fma(-x, x, x);
-    const double g = ALPHA == 2 ? fma(-aj, y, 1.0 + aj / 6.0) : fma(aj * y, y, 1.0 - aj / 30.0);
-    p[k] *= g;
+    p[k] *= bernoulli_factor<ALPHA>(aj, ALPHA == 2 ? 1.0 + aj / 6.0 : 1.0 - aj / 30.0, y);
 }
 
 // --------------------------------------------------------------------------
@@ -254,7 +271,8 @@ static hipError_t launch_cbc_a(const CbcLaunch& L, hipStream_t stream) {
     const double inv_n = 1.0 / (double)L.n;
     double* p = (double*)((char*)L.ws + kZeroBytes);
     double* cand = p + L.n;
-    hipLaunchKernelGGL(cbc_init_kernel, dim3((L.n + 255) / 256), dim3(256), 0, stream, L.n, p);
+    const unsigned half_blocks = (unsigned)((L.n / 2 + 1 + 255) / 256);
+    hipLaunchKernelGGL(cbc_init_kernel, dim3(half_blocks), dim3(256), 0, stream, L.n, p);
     hipError_t e = hipGetLastError();
     for (int j = 0; j < L.d && e == hipSuccess; ++j) {
         // z_1 = 1; later components range over 1 <= c <= n/2 (c and n - c tie).
@@ -265,7 +283,7 @@ static hipError_t launch_cbc_a(const CbcLaunch& L, hipStream_t stream) {
         hipLaunchKernelGGL(select_kernel, dim3(1), dim3(kSelectBlock), 0, stream, cand, ncand,
                            (int64_t)1, (const uint8_t*)nullptr, L.s_out + j, (double*)nullptr,
                            L.z_out + j);
-        hipLaunchKernelGGL((cbc_update_kernel<ALPHA>), dim3((L.n + 255) / 256), dim3(256), 0, stream,
+        hipLaunchKernelGGL((cbc_update_kernel<ALPHA>), dim3(half_blocks), dim3(256), 0, stream,
                            L.n, inv_n, L.a, j, L.z_out, p);
         e = hipGetLastError();
     }

@@ -79,6 +79,29 @@ def test_cbc_matches_oracle(d, n, gamma, beta):
     assert np.allclose(e2, oe2, rtol=1e-9, atol=1e-13)
 
 
+@pytest.mark.parametrize("n", [2, 3, 4, 6, 8, 30, 1024, 1025])
+@pytest.mark.parametrize("alpha", [2, 4])
+def test_cbc_small_and_even_n(n, alpha):
+    """The device sums each criterion over the mirrored half of the indices (k and
+    n - k give mirrored points); odd and even n, down to n = 2, against the oracle's
+    full sums."""
+    d = 3
+    if alpha == 2:
+        gamma = np.array([1.0, 0.7, 0.3])
+        z, e2 = qmc.cbc(d, n, gamma, 0.2)
+        oz, oe2 = O.cbc(d, n, gamma, 0.2)
+        assert np.array_equal(z.cpu().numpy(), oz)
+        assert np.allclose(e2.cpu().numpy(), oe2, rtol=1e-9, atol=1e-13)
+    else:
+        a = np.array([-1.5, -1.0, -0.5])
+        z, s = qmc.cbc(d, n, a, 0.0, alpha=4)
+        z = z.cpu().numpy()
+        s = s.cpu().numpy()
+        for j in range(d):
+            so, _ = O.lattice_kernel_sum(list(z[: j + 1]), n, 4, a[: j + 1])
+            assert s[j] == pytest.approx(so, rel=1e-9, abs=1e-14), (n, j)
+
+
 def test_cbc_alpha4_against_exhaustive_oracle_search():
     d, n = 3, 101
     a = np.array([-1.5, -1.0, -0.5])
