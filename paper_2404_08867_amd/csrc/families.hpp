@@ -260,6 +260,8 @@ struct BernoulliProduct {
     };
     static constexpr int kRenorm = 0;
     static constexpr bool kBlockTerms = false;
+    // B_alpha(1 - x) = B_alpha(x) for even alpha.
+    static constexpr bool kMirror = true;
     __device__ static void block_terms(const double*, int, int, double, double, double&, double&,
                                        int&) {}
     __device__ static double extra(const double*) { return 0.0; }

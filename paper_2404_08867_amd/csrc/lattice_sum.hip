@@ -7,6 +7,10 @@
 // direction's constants are loaded once per M points and the per-point state is M
 // registers whatever d is; no 64-bit arithmetic runs per point.
 //
+// The Bernoulli products behind the lattice-quality criteria satisfy
+// f(x) = f(1 - x) in every coordinate; on an unshifted lattice point n - i mirrors
+// point i, so those sums evaluate i <= n/2 only (finish_points).
+//
 // Reduction: per-thread FP64 sums, a DPP wave reduction, waves in order, one
 // FP64 partial per workgroup, then the two-level fixed-order grid sum of
 // common.hpp, run by wave 0 (tickets and tagged slots in the workspace's zero
@@ -52,7 +56,7 @@ __device__ __forceinline__ GridSlots set_slots(double* scratch, uint32_t scratch
     return s;
 }
 
-template <class F, int M, int B, bool FI>
+template <class F, int M, int B, bool FI, bool MIRROR>
 __global__ __launch_bounds__(B) void lattice_sum_kernel(
     const int64_t* z, const double* params, const double* shift, double inv_n, uint32_t n, int d,
     int param_stride, int shift_stride, int z_stride, uint32_t tiles, double* q_out,
@@ -74,11 +78,11 @@ __global__ __launch_bounds__(B) void lattice_sum_kernel(
         // residues are built with them.
         setup_one_chunk<F, M, B>(v, s, s_red, blockIdx.x * kTile, init0, ds1, ie);
         for (uint32_t tile = blockIdx.x; tile < tiles; tile += gridDim.x)
-            tacc += tile_points_one_chunk<F, M, B, FI>(v, s, tile * kTile, init0, tile == blockIdx.x);
+            tacc += tile_points_one_chunk<F, M, B, FI, MIRROR>(v, s, tile * kTile, init0, tile == blockIdx.x);
     } else {
         block_constants<F, B>(v, s_red, init0, ds1, ie);
         for (uint32_t tile = blockIdx.x; tile < tiles; tile += gridDim.x)
-            tacc += tile_points<F, M, B, FI>(v, s, tile * kTile, init0);
+            tacc += tile_points<F, M, B, FI, MIRROR>(v, s, tile * kTile, init0);
     }
 
     // Workgroup total to wave 0 (red[B / kWave ..) is untouched by the setup), then
@@ -187,7 +191,12 @@ int device_cu_count() {
     return cus;
 }
 
-template <class F, int M, bool FI>
+// Points a launch evaluates: n, or n/2 + 1 for a mirrored sum (finish_points).
+static uint64_t evaluated_points(const PlainLaunch& L, bool mirror) {
+    return mirror ? (uint64_t)L.n / 2 + 1 : (uint64_t)L.n;
+}
+
+template <class F, int M, bool FI, bool MIRROR>
 static hipError_t launch_fm(const PlainLaunch& L, hipStream_t stream) {
     SumArgs a;
     a.z = L.z;
@@ -200,7 +209,7 @@ static hipError_t launch_fm(const PlainLaunch& L, hipStream_t stream) {
     a.shift_stride = L.shift_stride;
     a.z_stride = L.z_stride;
     const uint64_t tile = (uint64_t)kSumBlock * M;
-    a.tiles = (uint32_t)(((uint64_t)L.n + tile - 1) / tile);
+    a.tiles = (uint32_t)((evaluated_points(L, MIRROR) + tile - 1) / tile);
     a.q_out = L.q_out;
     a.tickets = (uint32_t*)L.ws;
     a.scratch = (double*)((char*)L.ws + kTicketBytes);  // tagged-slot part of the zero region
@@ -210,20 +219,24 @@ static hipError_t launch_fm(const PlainLaunch& L, hipStream_t stream) {
     if (L.max_blocks > 0 && L.max_blocks < g) g = L.max_blocks;
     if ((uint32_t)g > a.tiles) g = (int)a.tiles;
     dim3 grid((unsigned)g, (unsigned)L.nsets);
-    hipLaunchKernelGGL((lattice_sum_kernel<F, M, kSumBlock, FI>), grid, dim3(kSumBlock), 0, stream,
+    hipLaunchKernelGGL((lattice_sum_kernel<F, M, kSumBlock, FI, MIRROR>), grid, dim3(kSumBlock), 0, stream,
                        a.z, a.params, a.shift, a.inv_n, a.n, a.d, a.param_stride, a.shift_stride,
                        a.z_stride, a.tiles, a.q_out, a.tickets, a.scratch, a.scratch_stride,
                        a.slot_stride);
     return hipGetLastError();
 }
 
-// Families with an exact-float index step use it whenever n allows.
+// Families with an exact-float index step use it whenever n allows; mirror-
+// symmetric families on an unshifted lattice sum half of the points.
 template <class F, int M>
 static hipError_t launch_fi(const PlainLaunch& L, hipStream_t stream) {
     if constexpr (float_index<F>::value) {
-        if (L.n <= kFloatIndexMaxN) return launch_fm<F, M, true>(L, stream);
+        if (L.n <= kFloatIndexMaxN) return launch_fm<F, M, true, false>(L, stream);
     }
-    return launch_fm<F, M, false>(L, stream);
+    if constexpr (mirror_family<F>::value) {
+        if (!L.shift) return launch_fm<F, M, false, true>(L, stream);
+    }
+    return launch_fm<F, M, false, false>(L, stream);
 }
 
 template <class F>
@@ -234,8 +247,9 @@ static hipError_t launch_f(const PlainLaunch& L, hipStream_t stream) {
         // per-direction setup is amortised over M points, the latency over the
         // workgroups resident on a CU).
         const uint64_t want_tiles = 3ull * device_cu_count() / 2;
+        const uint64_t pts = evaluated_points(L, mirror_family<F>::value && !L.shift);
         M = 16;
-        while (M > 4 && ((uint64_t)L.n + kSumBlock * M - 1) / ((uint64_t)kSumBlock * M) < want_tiles)
+        while (M > 4 && (pts + kSumBlock * M - 1) / ((uint64_t)kSumBlock * M) < want_tiles)
             M /= 2;
     }
     switch (M) {

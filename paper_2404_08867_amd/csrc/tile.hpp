@@ -25,6 +25,13 @@ struct float_index : std::false_type {};
 template <class F>
 struct float_index<F, std::void_t<decltype(F::kFloatIndex)>> : std::bool_constant<F::kFloatIndex> {};
 
+// Families with f(x) = f(1 - x) in every coordinate (F::kMirror): on an unshifted
+// lattice their sum needs only the points i <= n/2 (finish_points).
+template <class F, class = void>
+struct mirror_family : std::false_type {};
+template <class F>
+struct mirror_family<F, std::void_t<decltype(F::kMirror)>> : std::bool_constant<F::kMirror> {};
+
 // A problem as seen by the device: lattice, shift and one parameter row.
 struct ProblemView {
     int d;
@@ -199,7 +206,10 @@ __device__ __forceinline__ void chunk_points(typename F::Acc (&acc)[M], const Ti
 }
 
 // The thread's sum of f / scale over its M points (points >= n contribute zero).
-template <class F, int M>
+// MIRROR (unshifted lattices, integrands with f(x) = f(1 - x) in every coordinate):
+// point n - i is the mirror image of point i, so only i <= n/2 is evaluated, with
+// weight 2 except for i = 0 and, for even n, i = n/2 (their own mirrors).
+template <class F, int M, bool MIRROR = false>
 __device__ __forceinline__ double finish_points(const typename F::Acc (&acc)[M], uint32_t tile_base,
                                                 uint32_t n) {
     const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
@@ -208,7 +218,13 @@ __device__ __forceinline__ double finish_points(const typename F::Acc (&acc)[M],
 #pragma unroll
     for (int m = 0; m < M; ++m) {
         const double f = F::finish(acc[m]);
-        t += (i0 + (uint32_t)(kWave * m) < n) ? f : 0.0;
+        const uint32_t i = i0 + (uint32_t)(kWave * m);
+        if constexpr (MIRROR) {
+            const double w = (i == 0 || 2 * i == n) ? 1.0 : 2.0;
+            t += (i <= n / 2) ? w * f : 0.0;
+        } else {
+            t += (i < n) ? f : 0.0;
+        }
     }
     return t;
 }
@@ -216,7 +232,7 @@ __device__ __forceinline__ double finish_points(const typename F::Acc (&acc)[M],
 // The thread's sum of f / scale over its M points of the tile, any d: the
 // tables are rebuilt chunk by chunk.  Begins with a barrier; the caller may
 // reuse s afterwards only after another barrier.
-template <class F, int M, int B, bool FI = false>
+template <class F, int M, int B, bool FI = false, bool MIRROR = false>
 __device__ __forceinline__ double tile_points(const ProblemView& v, TileShared<F, B>& s,
                                               uint32_t tile_base, double init0) {
     typename F::Acc acc[M];
@@ -231,7 +247,7 @@ __device__ __forceinline__ double tile_points(const ProblemView& v, TileShared<F
         __syncthreads();
         chunk_points<F, M, B, FI>(acc, s, j0, dc, v.n);
     }
-    return finish_points<F, M>(acc, tile_base, v.n);
+    return finish_points<F, M, MIRROR>(acc, tile_base, v.n);
 }
 
 // ---------------------------------------------------------------------------
@@ -296,7 +312,7 @@ __device__ __forceinline__ void setup_one_chunk(const ProblemView& v, TileShared
 // One tile of a problem set up by setup_one_chunk.  With `kw_ready` the start
 // residues of this tile are already in s; otherwise they are rebuilt between two
 // barriers.  The caller may overwrite s afterwards only after a barrier.
-template <class F, int M, int B, bool FI = false>
+template <class F, int M, int B, bool FI = false, bool MIRROR = false>
 __device__ __forceinline__ double tile_points_one_chunk(const ProblemView& v, TileShared<F, B>& s,
                                                         uint32_t tile_base, double init0,
                                                         bool kw_ready) {
@@ -309,7 +325,7 @@ __device__ __forceinline__ double tile_points_one_chunk(const ProblemView& v, Ti
 #pragma unroll
     for (int m = 0; m < M; ++m) acc[m] = F::init(init0);
     chunk_points<F, M, B, FI>(acc, s, 0, v.d, v.n);
-    return finish_points<F, M>(acc, tile_base, v.n);
+    return finish_points<F, M, MIRROR>(acc, tile_base, v.n);
 }
 
 }  // namespace qmc

@@ -38,6 +38,23 @@ def test_bernoulli_sum_matches_oracle(alpha, d, n):
         assert _close(s[r], so, ao), (r, s[r], so)
 
 
+@pytest.mark.parametrize("n", [2, 3, 4, 5, 6, 64, 65, 4096, 4097, 65521, 65536, 1048573])
+def test_bernoulli_sum_mirrored_half_for_any_z(n):
+    """The device sums Bernoulli products over i <= n/2 only, with weight 2 for the
+    mirrored pairs (i, n - i); odd and even n, generating vectors with any entries
+    (zeros and repeats included), against the oracle's sums over all n points."""
+    rng = np.random.default_rng(n)
+    d = 6
+    rows = [rng.integers(0, n, d) for _ in range(3)] + [np.zeros(d, dtype=np.int64),
+                                                          np.full(d, n // 2, dtype=np.int64)]
+    for alpha in (2, 4):
+        a = rng.uniform(-2.0, 5.0, d)
+        s = qmc.bernoulli_sum(np.stack(rows), n, alpha, a).cpu().numpy()
+        for r, z in enumerate(rows):
+            so, ao = O.lattice_kernel_sum(z, n, alpha, a)
+            assert _close(s[r], so, ao), (n, alpha, r, s[r], so)
+
+
 @pytest.mark.parametrize("z,n", [([1, 3, 9, 27, 81], 1009), ([1, 40, 33, 19], 97)])
 def test_criterion_helpers(z, n):
     for alpha in (2, 4):
