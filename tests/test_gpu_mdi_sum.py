@@ -16,8 +16,10 @@ PRECS = [qmc.FP64, qmc.FP32_COMPENSATED]
 
 # (d, N, N_last): one direction; N = 1 (every state merges); a last count of
 # a + 1 (eq. 3.5 with n = 1 + a^d); states past one pass of the window loop;
-# Test 7's shape; more states than LDS holds (workspace buffers).
-SHAPES = [(1, 1, 17), (5, 1, 3), (4, 10, 11), (12, 9, 9), (100, 64, 64), (300, 64, 65)]
+# Test 7's shape; more states than LDS holds (workspace buffers); long windows
+# (N = 128, 600, 1500) with few directions, odd and even step counts.
+SHAPES = [(1, 1, 17), (5, 1, 3), (4, 10, 11), (12, 9, 9), (100, 64, 64), (300, 64, 65),
+          (9, 128, 128), (3, 600, 600), (2, 1500, 1500), (2, 1500, 7)]
 PARAMS = {qmc.SUM_POWER: [[1.0, 1.0, 5.0], [0.7, 1.3, 2.5], [2.0, 0.4, 0.5]],
           qmc.SUM_GAUSS: [[0.9, 0.3], [0.2, 1.7], [1.5, 4.0]]}
 
