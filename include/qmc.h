@@ -231,6 +231,9 @@ qmc_status qmc_implr_points(int32_t d, int64_t n, int64_t a, int64_t j0, int64_t
  *   gamma_j is prod_j (1 + gamma_j beta) * S with a_j = gamma_j / (1 + gamma_j beta)
  *   (beta = c^2 - c + 1/3 for the anchored space with anchor c, 0 unanchored).
  * Everything runs in FP64: criteria are small differences of O(1) terms.
+ * The terms of k and n - k are equal (the points are mirror images and
+ * B_alpha(1 - x) = B_alpha(x)), so the device evaluates k <= n/2 only, with
+ * weight 2 except for k = 0 and, for even n, k = n/2: half the terms above.
  * Candidates whose values agree to 1e-10 relative count as tied; the smallest
  * candidate is chosen (the criteria of c and n - c are always equal).  Candidates
  * with gcd(c, n) != 1 get +infinity.  Values beyond the FP64 range (products that
@@ -251,7 +254,7 @@ qmc_status qmc_bernoulli_sum(int32_t d, int64_t n, const int64_t* z, int32_t nz,
 /* Korobov search (Sec. 2.2): S(z(a)) for the Korobov vectors
  * z(a) = (1, a, ..., a^{d-1}) mod n of a = a0 .. a0 + count - 1 (1 <= a0,
  * a0 + count <= n), and the best: best_out[0] = S, best_out[1] = a (as a double).
- * The search is O(count * n * d) work; it is asynchronous like every launch.
+ * The search is O(count * n * d / 2) work; it is asynchronous like every launch.
  *   s_out     device double[count]
  *   best_out  device double[2]
  *   ws        device workspace of qmc_criteria_workspace_size(d, n) bytes */
@@ -262,7 +265,7 @@ qmc_status qmc_korobov_search(int32_t d, int64_t n, int32_t alpha, const double*
 /* CBC construction (Sec. 2.2, CBC lattice; product weights): z_1 = 1, then for
  * j = 2..d the z_j in {1 <= c <= n/2 : gcd(c, n) = 1} minimising S of (z_1..z_j)
  * with weights a_1..a_j (which minimises e^2 of eq. 2.12 when a_j = gamma_j /
- * (1 + gamma_j beta)).  s_out[j-1] is S of the chosen (z_1..z_j).  O(d n^2) work,
+ * (1 + gamma_j beta)).  s_out[j-1] is S of the chosen (z_1..z_j).  O(d n^2 / 4) work,
  * 3 launches per component, all on `stream`.
  *   n       in [2, 2^26]
  *   z_out   device int64[d]
