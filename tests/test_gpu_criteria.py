@@ -173,3 +173,51 @@ def test_cbc_d20_full_size_components():
     for c in (1, 2, 1000, 20000, w.n // 2):
         alt = O.shift_avg_wce2(np.concatenate([z[:1], [c]]), w.n, w.gamma[:2], w.beta)
         assert e2[1] <= alt * (1 + 1e-10)
+
+
+def test_criteria_graph_replays_match_eager():
+    """The Korobov search (table, mirrored Bernoulli sums, selection) and CBC (init,
+    then evaluation, selection and product update per component) captured in one
+    graph through the C ABI: every replay reproduces the eager results bit for bit,
+    with eager calls of other sizes on the same workspace in between."""
+    import torch
+    L = qmc.lib()
+    d, n, count = 6, 1031, 515
+    gamma = np.array([1.0, 0.8, 0.6, 0.4, 0.3, 0.2])
+    a_np, _ = qmc.wce2_weights(gamma, 0.1)
+    a = torch.tensor(a_np, dtype=torch.float64, device="cuda")
+    ws = qmc.Workspace(qmc.criteria_workspace_size(d, 4099))
+    vals = torch.zeros(count, dtype=torch.float64, device="cuda")
+    best = torch.zeros(2, dtype=torch.float64, device="cuda")
+    z = torch.zeros(d, dtype=torch.int64, device="cuda")
+    s = torch.zeros(d, dtype=torch.float64, device="cuda")
+
+    def calls():
+        qmc._check(L.qmc_korobov_search(d, n, 2, qmc._ptr(a), 1, count, qmc._ptr(vals), qmc._ptr(best),
+                                        ws.ptr, ws.nbytes, qmc._stream()), "qmc_korobov_search")
+        qmc._check(L.qmc_cbc(d, n, 2, qmc._ptr(a), qmc._ptr(z), qmc._ptr(s), ws.ptr, ws.nbytes,
+                             qmc._stream()), "qmc_cbc")
+
+    calls()
+    torch.cuda.synchronize()
+    ref = [t.clone() for t in (vals, best, z, s)]
+    g = torch.cuda.CUDAGraph()
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        with torch.cuda.graph(g):
+            calls()
+    torch.cuda.current_stream().wait_stream(side)
+    for rep in range(3):
+        for t in (vals, best, z, s):
+            t.zero_()
+        g.replay()
+        torch.cuda.synchronize()
+        for t, r in zip((vals, best, z, s), ref):
+            assert torch.equal(t, r), rep
+        qmc.cbc(4, 4099, gamma[:4], 0.0, ws=ws)  # other sizes on the same workspace
+        qmc.korobov_search(3, 2048, 2, a=a_np[:3], a0=1, count=100, ws=ws)
+        torch.cuda.synchronize()
+    # the eager results themselves against the oracle
+    oz, oe2 = O.cbc(d, n, gamma, 0.1)
+    assert np.array_equal(z.cpu().numpy(), oz)

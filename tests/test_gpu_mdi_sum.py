@@ -46,3 +46,41 @@ def test_mdi_sum_d100_full_size_sampled(precision):
     for s in (0, 1, 2047, 4095):
         qo = O.mdi_sum(w.d, w.N, w.N_last, w.gfamily, w.params[s])
         assert abs(q[s] - qo) <= TOL[precision] * abs(qo), (s, q[s], qo)
+
+
+def test_mdi_sum_graph_replays_match_eager():
+    """The state convolutions and the evaluation captured in one graph through the
+    C ABI replay bit for bit, with eager calls of other shapes on the same
+    workspace in between."""
+    import torch
+    L = qmc.lib()
+    d, N, N_last = 100, 64, 64
+    w = W.mdi_sum_d100()
+    params = torch.tensor(w.params[:64], dtype=torch.float64, device="cuda")
+    ws = qmc.Workspace(qmc.mdi_lr_sum_workspace_size(300, 64))
+    for prec in PRECS:
+        q = torch.zeros(64, dtype=torch.float64, device="cuda")
+
+        def call():
+            qmc._check(L.qmc_mdi_lr_sum(d, N, N_last, w.gfamily, qmc._ptr(params), 64, prec, qmc._ptr(q),
+                                        ws.ptr, ws.nbytes, qmc._stream()), "qmc_mdi_lr_sum")
+
+        call()
+        torch.cuda.synchronize()
+        ref = q.clone()
+        g = torch.cuda.CUDAGraph()
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            with torch.cuda.graph(g):
+                call()
+        torch.cuda.current_stream().wait_stream(side)
+        for rep in range(3):
+            q.zero_()
+            g.replay()
+            torch.cuda.synchronize()
+            assert torch.equal(q, ref), (prec, rep)
+            qmc.mdi_lr_sum(300, 64, 65, w.gfamily, w.params[:3], prec, ws=ws)  # another shape
+            torch.cuda.synchronize()
+        qo = O.mdi_sum(d, N, N_last, w.gfamily, w.params[0])
+        assert abs(float(ref[0]) - qo) <= TOL[prec] * abs(qo)
