@@ -33,6 +33,10 @@ DEVICE_FLAGS = [
 # prologue that loads them for firmware without it).
 SOURCE_FLAGS = {
     "lattice_sum.hip": ["-mllvm", "-amdgpu-kernarg-preload-count=10"],
+    # The set-batched adjoint keeps its FP64 matrix accumulators in ordinary
+    # VGPRs: in the AGPR form the compiler moved them between the two register
+    # files every block of points.
+    "adjoint.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form=1"],
 }
 
 

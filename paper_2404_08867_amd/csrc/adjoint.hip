@@ -315,9 +315,9 @@ __global__ __launch_bounds__(kBlock) void adjoint_kernel(const AdjArgs a) {
 // and B[l / 16][l % 16] and holds D[4 r + l / 16][l % 16] in register r -- the
 // layout as measured on gfx950).
 //
-// A wave serves the 64 sets of group blockIdx.y (four blocks of 16) over a
-// contiguous range of points, 16 points at a time:
-//  1. T[16 points][64 sets] = t0 + k[16][4 DQ] A[4 DQ][64]: the A operand is the
+// A wave serves the kSetsPerWave = 32 sets of group blockIdx.y (two blocks of 16)
+// over a contiguous range of points, 16 points at a time:
+//  1. T[16 points][32 sets] = t0 + k[16][4 DQ] A[4 DQ][32]: the A operand is the
 //     lane's own index k(point c0 + l % 16, direction 4 q + l / 16), stepped by
 //     16 z_j mod n per block (exact integers, converted to double); the B operand
 //     is the coefficient a(direction 4 q + l / 16, set 16 b + l % 16), held in
@@ -333,8 +333,12 @@ __global__ __launch_bounds__(kBlock) void adjoint_kernel(const AdjArgs a) {
 // 16 x 16 block per 16 directions and 16 sets) stay in registers over the wave's
 // points; then waves are added in order and workgroups by the vector grid sum, so
 // the result is bit-reproducible.
+// Two blocks of 16 sets per wave keep the state at about 230 registers (two
+// waves per SIMD); four needed 476 and one wave per SIMD, and moved accumulators
+// between the register files every block.
 constexpr int kSetsMaxDims = kAdjSetsMaxParams - 1;
-constexpr int kSetsPerWave = kWave;  // four blocks of 16
+constexpr int kSetBlocks = 2;                    // blocks of 16 sets per wave
+constexpr int kSetsPerWave = 16 * kSetBlocks;
 constexpr int kMfmaPoints = 16;      // points per block
 
 typedef double v4d __attribute__((ext_vector_type(4)));
@@ -357,7 +361,7 @@ struct AdjSetsArgs {
     size_t scratch_stride;  // doubles per group of kSetsPerWave sets
 };
 
-// LDS doubles: the coefficient table [DM][64] during the sweep, then the block
+// LDS doubles: the coefficient table [DM][kSetsPerWave] during the sweep, then the block
 // totals (per set K_0 .. K_{DM-1}, W, Q) and per-lane partials of W, Q.
 __host__ __device__ constexpr int sets_lds_doubles(int DM) {
     return DM * kSetsPerWave > kSetsPerWave * (DM + 2) + 2 * kWave ? DM * kSetsPerWave
@@ -372,7 +376,7 @@ template <int FAM, bool FP32, int DQ>
 __global__ __launch_bounds__(kBlock) void adjoint_sets_kernel(const AdjSetsArgs a) {
     constexpr int NE = (DQ + 3) / 4;  // blocks of 16 directions in K
     constexpr int DM = 4 * DQ;        // directions covered (>= d)
-    extern __shared__ double s_tot[];  // [DM][64] coefficients; later [64][DM + 2] totals, [2][64] partials
+    extern __shared__ double s_tot[];  // [DM][sets] coefficients; later [sets][DM + 2] totals, [2][64] partials
     __shared__ double s_phi[DM];        // shift fraction * n per direction
     __shared__ uint32_t s_whole[DM];    // shift whole part per direction
     __shared__ uint32_t s_step[DM];     // 16 z_j mod n
@@ -396,7 +400,7 @@ __global__ __launch_bounds__(kBlock) void adjoint_sets_kernel(const AdjSetsArgs 
     }
     __syncthreads();
 
-    // coefficient table: s_coef[j * 64 + s] = a_js of set s of the group (0 beyond d
+    // coefficient table: s_coef[j * kSetsPerWave + s] = a_js of set s of the group (0 beyond d
     // and past the last set); the B operand of step 1 reads a(4 q + lq, 16 b + lr)
     double* s_coef = s_tot;
     for (int e = tid; e < DM * kSetsPerWave; e += kBlock) {
@@ -406,9 +410,9 @@ __global__ __launch_bounds__(kBlock) void adjoint_sets_kernel(const AdjSetsArgs 
         s_coef[e] = FAM == kOscillatory ? c * kInv2Pi * a.inv_n : c * kLog2e * a.inv_n;
     }
     // t0 of set 16 b + lr
-    double t0[4];
+    double t0[kSetBlocks];
 #pragma unroll
-    for (int b = 0; b < 4; ++b) {
+    for (int b = 0; b < kSetBlocks; ++b) {
         const int set = blockIdx.y * kSetsPerWave + 16 * b + lr;
         const double* p = a.params + (size_t)(set < a.nsets ? set : 0) * a.P;
         double c0 = FAM == kOscillatory ? p[0] : 0.0;
@@ -440,35 +444,36 @@ __global__ __launch_bounds__(kBlock) void adjoint_sets_kernel(const AdjSetsArgs 
         for (int u = 0; u < 4; ++u)
             kk[u][e] = j < d ? index_of(p0 + 4 * u + lq, s_z[j], s_whole[j], a.n, a.inv_n) : 0u;
     }
-    v4d acc[NE][4];
+    v4d acc[NE][kSetBlocks];
 #pragma unroll
     for (int e = 0; e < NE; ++e)
 #pragma unroll
-        for (int b = 0; b < 4; ++b) acc[e][b] = v4d{0.0, 0.0, 0.0, 0.0};
-    double qs[4] = {0.0, 0.0, 0.0, 0.0}, ws[4] = {0.0, 0.0, 0.0, 0.0};
+        for (int b = 0; b < kSetBlocks; ++b) acc[e][b] = v4d{0.0, 0.0, 0.0, 0.0};
+    double qs[kSetBlocks] = {}, ws[kSetBlocks] = {};
 
     for (uint64_t c0 = p0; c0 < p1; c0 += kMfmaPoints) {
-        // 1. arguments of the block's 16 points for the 64 sets
-        v4d t[4];
+        // 1. arguments of the block's 16 points for the wave's sets
+        v4d t[kSetBlocks];
 #pragma unroll
-        for (int b = 0; b < 4; ++b) t[b] = v4d{t0[b], t0[b], t0[b], t0[b]};
+        for (int b = 0; b < kSetBlocks; ++b) t[b] = v4d{t0[b], t0[b], t0[b], t0[b]};
 #pragma unroll
         for (int q = 0; q < DQ; ++q) {
             const double av = (double)kt[q];
             const double* cr = s_coef + (4 * q + lq) * kSetsPerWave + lr;
 #pragma unroll
-            for (int b = 0; b < 4; ++b) t[b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, cr[16 * b], t[b], 0, 0, 0);
-            // at most 16 coefficient loads in flight: keeps them from all being
-            // hoisted into registers ahead of the matrix instructions
+            for (int b = 0; b < kSetBlocks; ++b)
+                t[b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, cr[16 * b], t[b], 0, 0, 0);
+            // at most 4 kSetBlocks coefficient loads in flight: keeps them from all
+            // being hoisted into registers ahead of the matrix instructions
             if ((q & 3) == 3) asm volatile("" ::: "memory");
         }
         // 2. f and its weight at points c0 + 4 r + lq
-        double w[4][4];
+        double w[kSetBlocks][4];
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             const bool live = c0 + (uint64_t)(4 * r + lq) < p1;
 #pragma unroll
-            for (int b = 0; b < 4; ++b) {
+            for (int b = 0; b < kSetBlocks; ++b) {
                 const double tt = t[b][r];
                 double val, wt;
                 if constexpr (FAM == kOscillatory) {
@@ -500,7 +505,8 @@ __global__ __launch_bounds__(kBlock) void adjoint_sets_kernel(const AdjSetsArgs 
             for (int e = 0; e < NE; ++e) {
                 const double av = (double)kk[u][e];
 #pragma unroll
-                for (int b = 0; b < 4; ++b) acc[e][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, w[b][u], acc[e][b], 0, 0, 0);
+                for (int b = 0; b < kSetBlocks; ++b)
+                    acc[e][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, w[b][u], acc[e][b], 0, 0, 0);
             }
         }
         // next block: 16 points on
@@ -522,7 +528,7 @@ __global__ __launch_bounds__(kBlock) void adjoint_sets_kernel(const AdjSetsArgs 
 #pragma unroll
             for (int e = 0; e < NE; ++e)
 #pragma unroll
-                for (int b = 0; b < 4; ++b)
+                for (int b = 0; b < kSetBlocks; ++b)
 #pragma unroll
                     for (int r = 0; r < 4; ++r) {
                         const int j = 16 * e + 4 * r + lq;
@@ -533,7 +539,7 @@ __global__ __launch_bounds__(kBlock) void adjoint_sets_kernel(const AdjSetsArgs 
                     }
         }
         __syncthreads();
-        for (int b = 0; b < 4; ++b) {
+        for (int b = 0; b < kSetBlocks; ++b) {
             if (wv == w) {
                 part[l] = ws[b];
                 part[kWave + l] = qs[b];
@@ -664,7 +670,7 @@ size_t adjoint_workspace_bytes(int P, int nsets) {
     const size_t per_set =
         kZeroBytes + ((size_t)nsets * adjoint_set_stride(P, nsets) * sizeof(double) + 255) / 256 * 256;
     // the set-batched form (d = P or P - 1 <= kSetsMaxDims) lays its scratch out per
-    // group of 64 sets; d <= min(P, kSetsMaxDims) bounds its size
+    // group of kSetsPerWave sets; d <= min(P, kSetsMaxDims) bounds its size
     const size_t batched = P <= kSetsMaxDims + 1 ? sets_workspace_bytes(P < kSetsMaxDims ? P : kSetsMaxDims, nsets)
                                                  : 0;
     return per_set > batched ? per_set : batched;
