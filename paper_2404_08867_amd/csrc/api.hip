@@ -197,7 +197,7 @@ qmc_status qmc_workspace_size(int32_t max_d, int64_t max_n, int32_t max_sets, si
     const size_t b = qmc::plain_workspace_bytes(max_sets);
     if (b > need) need = b;
     // The adjoint keeps one vector of P + 1 doubles per workgroup and group; its
-    // set-batched form (small d) one vector per group of 64 sets, evaluated at the
+    // set-batched form (small d) one vector per group of 32 sets, evaluated at the
     // largest P it serves.
     const int pmax = 2 * (max_d < qmc::kMaxAdjDims ? max_d : qmc::kMaxAdjDims) + 1;
     const int pset = pmax < qmc::kAdjSetsMaxParams ? pmax : qmc::kAdjSetsMaxParams;
