@@ -600,7 +600,9 @@ static size_t sets_group_stride(int DM, int groups) {
            (size_t)(DM + 2);
 }
 
-static int sets_dims(int d) { return d <= 16 ? 16 : d <= 32 ? 32 : d <= 48 ? 48 : d <= 56 ? 56 : 64; }
+static int sets_dims(int d) {
+    return d <= 16 ? 16 : d <= 32 ? 32 : d <= 48 ? 48 : d <= 52 ? 52 : d <= 56 ? 56 : 64;
+}
 
 static size_t sets_workspace_bytes(int d, int nsets) {
     const int groups = (nsets + kSetsPerWave - 1) / kSetsPerWave;
@@ -648,6 +650,7 @@ static hipError_t launch_sets(const AdjLaunch& L, hipStream_t stream) {
         case 16: return launch_sets_dq<FAM, FP32, 4>(L, stream);
         case 32: return launch_sets_dq<FAM, FP32, 8>(L, stream);
         case 48: return launch_sets_dq<FAM, FP32, 12>(L, stream);
+        case 52: return launch_sets_dq<FAM, FP32, 13>(L, stream);
         case 56: return launch_sets_dq<FAM, FP32, 14>(L, stream);
         default: return launch_sets_dq<FAM, FP32, 16>(L, stream);
     }
