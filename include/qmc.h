@@ -213,7 +213,7 @@ qmc_status qmc_implr_grid(int32_t d, int64_t n, int64_t a, int32_t method, int64
 /* The grid ranks of lattice points j = j0 .. j0 + count - 1 under the same
  * transformation (y_i = s_i / z_{i+1} for i < d, y_d = s_d z_d / n), direction-major:
  * s_out[i * ld + (j - j0)] = s_i(j).  One launch on `stream`; d, n, a as above,
- * 0 <= j0, j0 + count <= n, ld >= count.  Each lane writes four consecutive ranks
+ * 0 <= j0, j0 + count <= n, count <= ld <= 2^40.  Each lane writes four consecutive ranks
  * at once; rows that start on 16-byte boundaries (s_out and 4 ld multiples of 16)
  * are written fastest.
  *   s_out  device int32[d][ld], 4-byte aligned; may be NULL when count = 0 */

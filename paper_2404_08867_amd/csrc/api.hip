@@ -52,6 +52,7 @@ constexpr int64_t kMaxExport = (int64_t)1 << 26;
 constexpr int64_t kMaxCbcN = (int64_t)1 << 26;   // CBC keeps n + n/2 doubles
 constexpr int32_t kMaxSumNodes = 1 << 20;
 constexpr int64_t kMaxSumStates = (int64_t)1 << 20;
+constexpr int64_t kMaxImplrLd = (int64_t)1 << 40;  // elements between rows of qmc_implr_points
 
 int param_count(int family, int d) {
     switch (family) {
@@ -475,6 +476,8 @@ qmc_status qmc_implr_points(int32_t d, int64_t n, int64_t a, int64_t j0, int64_t
                     (long long)j0, (long long)count);
     if (count > 0 && !s_out) return fail(QMC_ERR_INVALID_ARG, "s_out must be non-NULL");
     if (ld < count) return fail(QMC_ERR_INVALID_ARG, "ld = %lld below count = %lld", (long long)ld, (long long)count);
+    // (d - 1) ld + count elements must be addressable; no device buffer comes near 2^40
+    if (ld > kMaxImplrLd) return fail(QMC_ERR_INVALID_ARG, "ld = %lld above 2^40", (long long)ld);
     if ((uintptr_t)s_out % 4 != 0) return fail(QMC_ERR_INVALID_ARG, "s_out must be 4-byte aligned");
     qmc::ImplrPointsLaunch L{d, (uint32_t)n, (uint32_t)a, (uint32_t)zd, (uint64_t)j0, (uint64_t)count, (uint64_t)ld,
                              s_out};

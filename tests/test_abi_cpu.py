@@ -118,6 +118,7 @@ def test_invalid_arguments_fail_before_launch():
     assert L.qmc_implr_points(3, 101, 3, 0, 2, None, 4, None) == qmc.ERR_INVALID_ARG
     assert L.qmc_implr_points(3, 101, 11, 0, 2, fake, 4, None) == qmc.ERR_INVALID_ARG
     assert L.qmc_implr_points(3, 101, 3, 0, 8, fake, 7, None) == qmc.ERR_INVALID_ARG
+    assert L.qmc_implr_points(3, 101, 3, 0, 8, fake, (1 << 40) + 1, None) == qmc.ERR_INVALID_ARG
     assert L.qmc_implr_points(3, 101, 3, 0, 8, ctypes.c_void_p(0x1002), 8, None) == qmc.ERR_INVALID_ARG
     # MDI-LR and the index export
     assert L.qmc_mdi_lr(0, fake, 0, fake, 1, 0, fake, None, 0, None) == qmc.ERR_INVALID_ARG
