@@ -42,6 +42,7 @@ __device__ __forceinline__ void direction_sum(const double* p, int d, int k, int
         if constexpr (FP32) {
             const float Af = (float)A, Bf = (float)B;
             float tf = 0.0f;
+#pragma unroll 4
             for (int t = 0; t < Nk; ++t, tf += 1.0f) sr += (double)__builtin_amdgcn_exp2f(fmaf(tf, Af, Bf));
         } else {
             for (int t = 0; t < Nk; ++t) sr += exp2(fma((double)t, A, B));
@@ -53,6 +54,7 @@ __device__ __forceinline__ void direction_sum(const double* p, int d, int k, int
         if constexpr (FP32) {
             const float Af = (float)A, Bf = (float)B;
             float tf = 0.0f;
+#pragma unroll 4
             for (int t = 0; t < Nk; ++t, tf += 1.0f) {
                 const float y = fmaf(tf, Af, Bf);
                 sr += (double)__builtin_amdgcn_exp2f(-y * y);
@@ -70,6 +72,7 @@ __device__ __forceinline__ void direction_sum(const double* p, int d, int k, int
         if constexpr (FP32) {
             const float Af = (float)A, Bf = (float)B, gf = (float)g;
             float tf = 0.0f;
+#pragma unroll 4
             for (int t = 0; t < Nk; ++t, tf += 1.0f) {
                 const float y = fmaf(tf, Af, Bf);
                 sr += (double)__builtin_amdgcn_rcpf(fmaf(y, y, gf));
