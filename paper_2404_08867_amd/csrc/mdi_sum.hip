@@ -79,12 +79,14 @@ __global__ __launch_bounds__(kConvBlock) void conv_partial_kernel(const double* 
     }
 }
 
-// out[T] = sum_s partial[s][T], s ascending.
+// out[T] = sum_s partial[s][T], s ascending.  Unrolled by eight so that the loads
+// of eight segments are in flight together (the additions keep their order).
 __global__ __launch_bounds__(kConvBlock) void conv_reduce_kernel(const double* partial, int nseg,
                                                                 int Lo, double* out) {
     const int T = blockIdx.x * kConvBlock + threadIdx.x;
     if (T >= Lo) return;
     double t = 0.0;
+#pragma unroll 8
     for (int s = 0; s < nseg; ++s) t += partial[(size_t)s * Lo + T];
     out[T] = t;
 }
@@ -186,14 +188,24 @@ static hipError_t launch_eval(const MdiSumLaunch& L, int states, int nl, double 
     return hipGetLastError();
 }
 
-// out = a * b through `partial` (kConvMaxSeg * (La + Lb - 1) doubles).
+// out = a * b through `partial` (kConvMaxSeg * (La + Lb - 1) doubles).  An operand a
+// of at most kConvOneSeg states is one segment: its partial sums are the output and
+// no reduction launch follows.  (Longer single segments make each thread's FMA chain
+// long enough to cost more than the reduction launch saves.)
+constexpr int kConvOneSeg = 64;
+
 static hipError_t launch_conv(const double* a, int La, const double* b, int Lb, double* out,
                               double* partial, hipStream_t stream) {
     const int Lo = La + Lb - 1;
-    int nseg = (La + 63) / 64;
+    int nseg = La <= kConvOneSeg ? 1 : (La + 63) / 64;
     if (nseg > kConvMaxSeg) nseg = kConvMaxSeg;
     const int seg_len = (La + nseg - 1) / nseg;
     nseg = (La + seg_len - 1) / seg_len;
+    if (nseg == 1) {
+        hipLaunchKernelGGL(conv_partial_kernel, dim3((Lo + kConvOut - 1) / kConvOut, 1), dim3(kConvBlock), 0,
+                           stream, a, La, b, Lb, seg_len, out);
+        return hipGetLastError();
+    }
     hipLaunchKernelGGL(conv_partial_kernel, dim3((Lo + kConvOut - 1) / kConvOut, nseg), dim3(kConvBlock),
                        0, stream, a, La, b, Lb, seg_len, partial);
     hipLaunchKernelGGL(conv_reduce_kernel, dim3((Lo + kConvBlock - 1) / kConvBlock), dim3(kConvBlock), 0,
