@@ -69,7 +69,9 @@ __global__ __launch_bounds__(kSelectBlock) void select_kernel(double* v, int cou
     constexpr int W = kSelectBlock / kWave;
 
     // Pass 1: filter and minimum (a minimum is exact, so its order does not matter).
+    // Both passes are unrolled so that several loads are in flight per thread.
     double m = INFINITY;
+#pragma unroll 8
     for (int i = tid; i < count; i += kSelectBlock) {
         double x = v[i];
         if (coprime && !coprime[i]) {
@@ -89,6 +91,7 @@ __global__ __launch_bounds__(kSelectBlock) void select_kernel(double* v, int cou
 
     // Pass 2: the smallest index within the tolerance.
     int first = count;
+#pragma unroll 8
     for (int i = tid; i < count; i += kSelectBlock) {
         if (v[i] <= thr) {
             first = i;
