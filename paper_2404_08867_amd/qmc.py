@@ -151,6 +151,24 @@ def _ptr(t) -> int | None:
     return None if t is None else int(t.data_ptr())
 
 
+class _on:
+    """Makes the device of tensor `t` current around a library call: the library
+    launches on the current device, and _stream() is that device's current stream."""
+
+    def __init__(self, t):
+        self._ctx = _torch().cuda.device(t.device) if t is not None and t.is_cuda else None
+
+    def __enter__(self):
+        if self._ctx is not None:
+            self._ctx.__enter__()
+        return self
+
+    def __exit__(self, *exc):
+        if self._ctx is not None:
+            self._ctx.__exit__(*exc)
+        return False
+
+
 def _dev(x, dtype, device):
     torch = _torch()
     if isinstance(x, torch.Tensor):
@@ -219,9 +237,10 @@ def lattice_sum(z, n: int, family: int, params, precision: int = FP64, shift=Non
         q = torch.empty(nsets, dtype=torch.float64, device=device)
     w = _workspace(d, n, nsets, device, ws)
     cfg = LaunchConfig(points_per_thread, max_blocks)
-    _check(lib().qmc_lattice_sum_ex(d, n, _ptr(zt), _ptr(st), family, _ptr(pt), nsets, precision,
-                                    _ptr(q), w.ptr, w.nbytes, _stream(), ctypes.byref(cfg)),
-           "qmc_lattice_sum")
+    with _on(q):
+        _check(lib().qmc_lattice_sum_ex(d, n, _ptr(zt), _ptr(st), family, _ptr(pt), nsets, precision,
+                                        _ptr(q), w.ptr, w.nbytes, _stream(), ctypes.byref(cfg)),
+               "qmc_lattice_sum")
     if out is not None:
         return out
     return q[0] if squeeze else q
@@ -250,9 +269,10 @@ def lattice_sum_shifts(z, n: int, family: int, params, shifts, precision: int = 
         if t.dtype != torch.float64 or t.numel() < m or not t.is_contiguous():
             raise QmcError(ERR_INVALID_ARG, "outputs must be contiguous float64 tensors")
     w = _workspace(d, n, R, device, ws)
-    _check(lib().qmc_lattice_sum_shifts(d, n, _ptr(zt), _ptr(st), R, family, _ptr(pt), precision,
-                                        _ptr(q), _ptr(stats), w.ptr, w.nbytes, _stream()),
-           "qmc_lattice_sum_shifts")
+    with _on(q):
+        _check(lib().qmc_lattice_sum_shifts(d, n, _ptr(zt), _ptr(st), R, family, _ptr(pt), precision,
+                                            _ptr(q), _ptr(stats), w.ptr, w.nbytes, _stream()),
+               "qmc_lattice_sum_shifts")
     return q, stats
 
 
@@ -284,8 +304,9 @@ def mdi_lr_sum(d: int, N: int, N_last: int, gfamily: int, params, precision: int
         if ws is None or ws.nbytes < need:
             ws = Workspace(need, device)
             _ws_cache[key] = ws
-    _check(lib().qmc_mdi_lr_sum(d, N, N_last, gfamily, _ptr(pt), nsets, precision, _ptr(q), ws.ptr,
-                                ws.nbytes, _stream()), "qmc_mdi_lr_sum")
+    with _on(q):
+        _check(lib().qmc_mdi_lr_sum(d, N, N_last, gfamily, _ptr(pt), nsets, precision, _ptr(q), ws.ptr,
+                                    ws.nbytes, _stream()), "qmc_mdi_lr_sum")
     return q[0] if squeeze and out is None else q
 
 
@@ -331,8 +352,9 @@ def bernoulli_sum(z, n: int, alpha: int, a, ws: Workspace | None = None, device=
         raise QmcError(ERR_INVALID_ARG, "a must hold d weights")
     s = torch.empty(nz, dtype=torch.float64, device=device)
     w = _workspace(d, n, nz, device, ws)
-    _check(lib().qmc_bernoulli_sum(d, n, _ptr(zt), nz, alpha, _ptr(at), _ptr(s), w.ptr, w.nbytes,
-                                   _stream()), "qmc_bernoulli_sum")
+    with _on(s):
+        _check(lib().qmc_bernoulli_sum(d, n, _ptr(zt), nz, alpha, _ptr(at), _ptr(s), w.ptr, w.nbytes,
+                                       _stream()), "qmc_bernoulli_sum")
     return s
 
 
@@ -359,8 +381,9 @@ def korobov_search(d: int, n: int, alpha: int = 2, a=None, a0: int = 1, count: i
     vals = torch.empty(count, dtype=torch.float64, device=device)
     best = torch.empty(2, dtype=torch.float64, device=device)
     w = _criteria_workspace(d, n, device, ws)
-    _check(lib().qmc_korobov_search(d, n, alpha, _ptr(at), a0, count, _ptr(vals), _ptr(best), w.ptr,
-                                    w.nbytes, _stream()), "qmc_korobov_search")
+    with _on(vals):
+        _check(lib().qmc_korobov_search(d, n, alpha, _ptr(at), a0, count, _ptr(vals), _ptr(best), w.ptr,
+                                        w.nbytes, _stream()), "qmc_korobov_search")
     return vals, best
 
 
@@ -378,8 +401,9 @@ def cbc(d: int, n: int, gamma, beta: float, alpha: int = 2, ws: Workspace | None
     z = torch.empty(d, dtype=torch.int64, device=device)
     sv = torch.empty(d, dtype=torch.float64, device=device)
     w = _criteria_workspace(d, n, device, ws)
-    _check(lib().qmc_cbc(d, n, alpha, _ptr(at), _ptr(z), _ptr(sv), w.ptr, w.nbytes, _stream()),
-           "qmc_cbc")
+    with _on(z):
+        _check(lib().qmc_cbc(d, n, alpha, _ptr(at), _ptr(z), _ptr(sv), w.ptr, w.nbytes, _stream()),
+               "qmc_cbc")
     if alpha == 2:
         cj = torch.tensor(np.cumprod(1.0 + g * beta), dtype=torch.float64, device=device)
         sv = sv * cj
@@ -402,9 +426,10 @@ def implr_grid(d: int, n: int, a: int, method: int = IMPLR_AUTO, ws: Workspace |
     nstar = torch.empty(1, dtype=torch.int64, device=device) if out is None else out
     if ws is None:
         ws = Workspace(implr_workspace_size(d, n, a), device)
-    _check(lib().qmc_implr_grid(d, n, a, method, counts.ctypes.data, _ptr(nstar), ws.ptr, ws.nbytes,
-                                _stream()),
-           "qmc_implr_grid")
+    with _on(nstar):
+        _check(lib().qmc_implr_grid(d, n, a, method, counts.ctypes.data, _ptr(nstar), ws.ptr, ws.nbytes,
+                                    _stream()),
+               "qmc_implr_grid")
     return counts, nstar
 
 
@@ -420,8 +445,9 @@ def implr_points(d: int, n: int, a: int, j0: int, count: int, out=None, device="
             out.stride(1) != 1:
         raise QmcError(ERR_INVALID_ARG, "out must be an int32 [d, ld] tensor with ld >= count and unit column stride")
     ld = int(out.stride(0)) if d > 1 else int(out.shape[1])
-    _check(lib().qmc_implr_points(d, n, a, j0, count, _ptr(out) if count else None, ld, _stream()),
-           "qmc_implr_points")
+    with _on(out):
+        _check(lib().qmc_implr_points(d, n, a, j0, count, _ptr(out) if count else None, ld, _stream()),
+               "qmc_implr_points")
     return out[:, :count]
 
 
@@ -431,8 +457,9 @@ def lattice_points(z, n: int, i0: int, count: int, device="cuda"):
     zt = _dev(z, torch.int64, device)
     d = int(zt.numel())
     k = torch.empty((count, d), dtype=torch.int32, device=device)
-    _check(lib().qmc_lattice_points(d, n, _ptr(zt), i0, count, _ptr(k) if count else None,
-                                    _stream()), "qmc_lattice_points")
+    with _on(k):
+        _check(lib().qmc_lattice_points(d, n, _ptr(zt), i0, count, _ptr(k) if count else None,
+                                        _stream()), "qmc_lattice_points")
     return k
 
 
@@ -447,8 +474,9 @@ def mdi_lr(N, family: int, params, precision: int = FP64, device="cuda", out=Non
     d = int(Nt.numel())
     nsets = int(pt.shape[0])
     q = out if out is not None else torch.empty(nsets, dtype=torch.float64, device=device)
-    _check(lib().qmc_mdi_lr(d, _ptr(Nt), family, _ptr(pt), nsets, precision, _ptr(q), None, 0,
-                            _stream()), "qmc_mdi_lr")
+    with _on(q):
+        _check(lib().qmc_mdi_lr(d, _ptr(Nt), family, _ptr(pt), nsets, precision, _ptr(q), None, 0,
+                                _stream()), "qmc_mdi_lr")
     if out is not None:
         return out
     return q[0] if squeeze else q
@@ -509,9 +537,10 @@ class BatchPlan:
             cfg = BatchConfig(config.get("points_per_thread", 0), config.get("workgroups_per_cu", 0),
                               config.get("order", 0))
         self._plan = ctypes.c_void_p()
-        _check(lib().qmc_batch_plan_create(self.count, ctypes.byref(arr), precision,
-                                           ctypes.byref(cfg) if cfg is not None else None,
-                                           ctypes.byref(self._plan)), "qmc_batch_plan_create")
+        with _on(self.z):  # the plan's device arrays live on the problems' device
+            _check(lib().qmc_batch_plan_create(self.count, ctypes.byref(arr), precision,
+                                               ctypes.byref(cfg) if cfg is not None else None,
+                                               ctypes.byref(self._plan)), "qmc_batch_plan_create")
         b = ctypes.c_size_t(0)
         _check(lib().qmc_batch_workspace_size(self._plan, ctypes.byref(b)), "qmc_batch_workspace_size")
         self.ws = Workspace(int(b.value), device)
@@ -535,16 +564,18 @@ class BatchPlan:
     def run(self, out=None):
         torch = _torch()
         q = out if out is not None else torch.empty(self.count, dtype=torch.float64, device=self.device)
-        _check(lib().qmc_lattice_sum_batched(self._plan, _ptr(q), self.ws.ptr, self.ws.nbytes, _stream()),
-               "qmc_lattice_sum_batched")
+        with _on(q):
+            _check(lib().qmc_lattice_sum_batched(self._plan, _ptr(q), self.ws.ptr, self.ws.nbytes, _stream()),
+                   "qmc_lattice_sum_batched")
         return q
 
     def autotune(self, reps: int = 2, out=None) -> dict:
         torch = _torch()
         q = out if out is not None else torch.empty(self.count, dtype=torch.float64, device=self.device)
         best = BatchConfig()
-        _check(lib().qmc_batch_autotune(self._plan, _ptr(q), self.ws.ptr, self.ws.nbytes, _stream(), reps,
-                                        ctypes.byref(best)), "qmc_batch_autotune")
+        with _on(q):
+            _check(lib().qmc_batch_autotune(self._plan, _ptr(q), self.ws.ptr, self.ws.nbytes, _stream(), reps,
+                                            ctypes.byref(best)), "qmc_batch_autotune")
         return best.as_dict()
 
     def graph(self, out):
@@ -561,11 +592,13 @@ class Graph:
     def __init__(self, plan: BatchPlan, out):
         self._keep = (plan, out)
         self._g = ctypes.c_void_p()
-        _check(lib().qmc_batch_graph_create(plan._plan, _ptr(out), plan.ws.ptr, plan.ws.nbytes,
-                                            ctypes.byref(self._g)), "qmc_batch_graph_create")
+        with _on(out):
+            _check(lib().qmc_batch_graph_create(plan._plan, _ptr(out), plan.ws.ptr, plan.ws.nbytes,
+                                                ctypes.byref(self._g)), "qmc_batch_graph_create")
 
     def launch(self):
-        _check(lib().qmc_graph_launch(self._g, _stream()), "qmc_graph_launch")
+        with _on(self._keep[1]):
+            _check(lib().qmc_graph_launch(self._g, _stream()), "qmc_graph_launch")
 
     def __del__(self):
         if getattr(self, "_g", None) and _lib is not None:
@@ -595,9 +628,10 @@ def lattice_sum_adjoint(z, n: int, family: int, params, precision: int = FP64, s
     q = torch.empty(nsets, dtype=torch.float64, device=device)
     g = torch.empty((nsets, P), dtype=torch.float64, device=device)
     w = _workspace(d, n, nsets, device, ws)
-    _check(lib().qmc_lattice_sum_adjoint(d, n, _ptr(zt), _ptr(st), family, _ptr(pt), nsets, precision,
-                                         _ptr(gt), _ptr(q), _ptr(g), w.ptr, w.nbytes, _stream()),
-           "qmc_lattice_sum_adjoint")
+    with _on(q):
+        _check(lib().qmc_lattice_sum_adjoint(d, n, _ptr(zt), _ptr(st), family, _ptr(pt), nsets, precision,
+                                             _ptr(gt), _ptr(q), _ptr(g), w.ptr, w.nbytes, _stream()),
+               "qmc_lattice_sum_adjoint")
     if squeeze:
         return q[0], g[0]
     return q, g
