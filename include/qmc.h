@@ -38,6 +38,12 @@
  *       1 <= d <= 1024, 1 <= n < 2^31, 1 <= nsets <= 4096 (qmc_mdi_lr: 2^24),
  *       valid family and precision.  z_j in [0, n) and Delta_j in [0, 1) are the
  *       caller's contract for device arrays (not read back on the host).
+ *   - Debug mode: with QMC_VALIDATE=1 in the environment, the entry points that take
+ *     z or shift arrays (the plain sum, its shifts and adjoint, the Bernoulli sums,
+ *     the point export, batch plan creation) read them back on their stream
+ *     (synchronously, into host buffers) and return QMC_ERR_INVALID_ARG for an entry
+ *     out of range, before launching anything.  While the stream is being captured
+ *     into a graph the read-back is skipped.
  *   - Results are deterministic: every reduction runs in a fixed order, so a
  *     given call on given inputs returns bit-identical values on every run.
  */

@@ -2,8 +2,10 @@
 // kernel launchers.  Nothing here allocates device memory; see include/qmc.h.
 #include <stdarg.h>
 #include <stdio.h>
+#include <stdlib.h>
 
 #include <string>
+#include <vector>
 
 #include "qmc.h"
 #include "kernels.hpp"
@@ -35,6 +37,55 @@ qmc_status from_hip(hipError_t e, const char* where) {
     return fail(QMC_ERR_DEVICE, "%s: HIP error %d (%s)", where, (int)e, hipGetErrorString(e));
 }
 
+// Debug mode: with QMC_VALIDATE=1 in the environment, the device arrays whose
+// ranges are the caller's contract (z_j in [0, n), shift_j in [0, 1)) are read back
+// on the call's stream -- synchronously, after the work already queued there -- and
+// checked before anything is launched.  A stream that is being captured into a
+// graph cannot be synchronised, so there the check is skipped.
+static bool validate_mode() {
+    const char* v = getenv("QMC_VALIDATE");
+    return v && v[0] == '1';
+}
+
+static bool capturing(hipStream_t stream) {
+    hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
+    return hipStreamIsCapturing(stream, &st) == hipSuccess && st != hipStreamCaptureStatusNone;
+}
+
+template <class T>
+static qmc_status read_back(const T* dev, size_t count, hipStream_t stream, std::vector<T>& host, const char* what) {
+    host.resize(count);
+    hipError_t e = hipMemcpyAsync(host.data(), dev, count * sizeof(T), hipMemcpyDeviceToHost, stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) return from_hip(e, what);
+    return QMC_OK;
+}
+
+// z: `count` int64 entries, each in [0, n).
+qmc_status validate_z(const int64_t* z, size_t count, int64_t n, void* stream, const char* what) {
+    if (!validate_mode() || !z || capturing((hipStream_t)stream)) return QMC_OK;
+    std::vector<int64_t> h;
+    qmc_status s = read_back(z, count, (hipStream_t)stream, h, what);
+    if (s != QMC_OK) return s;
+    for (size_t i = 0; i < count; ++i)
+        if (h[i] < 0 || h[i] >= n)
+            return fail(QMC_ERR_INVALID_ARG, "%s: z[%zu] = %lld outside [0, %lld) (QMC_VALIDATE)", what, i,
+                        (long long)h[i], (long long)n);
+    return QMC_OK;
+}
+
+// shift: `count` doubles, each in [0, 1).
+qmc_status validate_shift(const double* sh, size_t count, void* stream, const char* what) {
+    if (!validate_mode() || !sh || capturing((hipStream_t)stream)) return QMC_OK;
+    std::vector<double> h;
+    qmc_status s = read_back(sh, count, (hipStream_t)stream, h, what);
+    if (s != QMC_OK) return s;
+    for (size_t i = 0; i < count; ++i)
+        if (!(h[i] >= 0.0 && h[i] < 1.0))
+            return fail(QMC_ERR_INVALID_ARG, "%s: shift[%zu] = %g outside [0, 1) (QMC_VALIDATE)", what, i, h[i]);
+    return QMC_OK;
+}
+
 }  // namespace qmc
 
 namespace {
@@ -42,6 +93,8 @@ namespace {
 using qmc::fail;
 using qmc::from_hip;
 using qmc::ok;
+using qmc::validate_shift;
+using qmc::validate_z;
 
 constexpr int kMaxD = 1024;
 constexpr int64_t kMaxN = (int64_t)1 << 31;  // exclusive
@@ -230,6 +283,8 @@ qmc_status qmc_lattice_sum_adjoint(int32_t d, int64_t n, const int64_t* z, const
     const int P = param_count(family, d);
     s = check_workspace(ws, ws_bytes, qmc::adjoint_workspace_bytes(P, nsets));
     if (s != QMC_OK) return s;
+    if ((s = validate_z(z, (size_t)d, n, stream, "qmc_lattice_sum_adjoint")) != QMC_OK) return s;
+    if ((s = validate_shift(shift, (size_t)d, stream, "qmc_lattice_sum_adjoint")) != QMC_OK) return s;
     qmc::AdjLaunch L{};
     L.d = d;
     L.n = (uint32_t)n;
@@ -265,6 +320,8 @@ qmc_status qmc_lattice_sum_ex(int32_t d, int64_t n, const int64_t* z, const doub
     if (!z || !params || !q_out) return fail(QMC_ERR_INVALID_ARG, "z, params and q_out must be non-NULL");
     s = check_workspace(ws, ws_bytes, qmc::plain_workspace_bytes(nsets));
     if (s != QMC_OK) return s;
+    if ((s = validate_z(z, (size_t)d, n, stream, "qmc_lattice_sum")) != QMC_OK) return s;
+    if ((s = validate_shift(shift, (size_t)d, stream, "qmc_lattice_sum")) != QMC_OK) return s;
     qmc::PlainLaunch L{};
     L.d = d;
     L.n = (uint32_t)n;
@@ -306,6 +363,9 @@ qmc_status qmc_lattice_sum_shifts(int32_t d, int64_t n, const int64_t* z, const 
         return fail(QMC_ERR_INVALID_ARG, "z, shifts, params and q_out must be non-NULL");
     s = check_workspace(ws, ws_bytes, qmc::plain_workspace_bytes(nshifts));
     if (s != QMC_OK) return s;
+    if ((s = validate_z(z, (size_t)d, n, stream, "qmc_lattice_sum_shifts")) != QMC_OK) return s;
+    if ((s = validate_shift(shifts, (size_t)nshifts * (size_t)d, stream, "qmc_lattice_sum_shifts")) != QMC_OK)
+        return s;
     qmc::PlainLaunch L{};
     L.d = d;
     L.n = (uint32_t)n;
@@ -351,6 +411,7 @@ qmc_status qmc_bernoulli_sum(int32_t d, int64_t n, const int64_t* z, int32_t nz,
     if (!z || !s_out) return fail(QMC_ERR_INVALID_ARG, "z and s_out must be non-NULL");
     s = check_workspace(ws, ws_bytes, qmc::plain_workspace_bytes(nz));
     if (s != QMC_OK) return s;
+    if ((s = validate_z(z, (size_t)nz * (size_t)d, n, stream, "qmc_bernoulli_sum")) != QMC_OK) return s;
     qmc::BernoulliLaunch L{d, (uint32_t)n, z, nz, alpha, a, s_out, ws};
     return from_hip(qmc::launch_bernoulli_sum(L, (hipStream_t)stream), "qmc_bernoulli_sum");
 }
@@ -491,6 +552,8 @@ qmc_status qmc_lattice_points(int32_t d, int64_t n, const int64_t* z, int64_t i0
     if (i0 < 0 || i0 >= kMaxN) return fail(QMC_ERR_INVALID_ARG, "i0 outside [0, 2^31)");
     if (count < 0 || count > kMaxExport) return fail(QMC_ERR_INVALID_ARG, "count outside [0, 2^26]");
     if (!z || (!k_out && count > 0)) return fail(QMC_ERR_INVALID_ARG, "z and k_out must be non-NULL");
+    qmc_status s = validate_z(z, (size_t)d, n, stream, "qmc_lattice_points");
+    if (s != QMC_OK) return s;
     return from_hip(qmc::launch_lattice_points(d, (uint32_t)n, z, i0, count, k_out, (hipStream_t)stream),
                     "qmc_lattice_points");
 }

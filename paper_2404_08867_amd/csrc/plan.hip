@@ -207,6 +207,13 @@ qmc_status qmc_batch_plan_create(int32_t count, const qmc_problem* problems, int
             return fail(QMC_ERR_INVALID_ARG, "problem %d: n = %lld outside [1, 2^31)", i, (long long)q.n);
         if (!q.z || !q.params) return fail(QMC_ERR_INVALID_ARG, "problem %d: z and params must be non-NULL", i);
     }
+    // QMC_VALIDATE=1: every problem's z and shift against their ranges (no-op otherwise)
+    for (int i = 0; i < count; ++i) {
+        const qmc_problem& q = problems[i];
+        qmc_status s = qmc::validate_z(q.z, (size_t)q.d, q.n, nullptr, "qmc_batch_plan_create");
+        if (s == QMC_OK) s = qmc::validate_shift(q.shift, (size_t)q.d, nullptr, "qmc_batch_plan_create");
+        if (s != QMC_OK) return s;
+    }
     qmc_batch_config c{kDefaultPoints, kDefaultWpc, 0};
     if (cfg) {
         c = *cfg;

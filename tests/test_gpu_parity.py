@@ -309,3 +309,58 @@ def test_plain_and_mdi_graph_replays_match_eager():
             torch.cuda.synchronize()
         outs[prec] = float(q_eager.reshape(-1)[0])
     assert abs(outs[qmc.FP32_COMPENSATED] - outs[qmc.FP64]) <= 1e-6 * abs(outs[qmc.FP64])
+
+
+def test_validate_mode_rejects_out_of_range_z_and_shift(monkeypatch):
+    """QMC_VALIDATE=1: entry points read z and shift back on their stream and reject
+    entries outside [0, n) and [0, 1) before launching anything; valid inputs give
+    the same results as without the check, and a capture still works (skipped)."""
+    import torch
+    prob = W.random_plain(11, 0, 5, 1009, shift=True)
+    z = qmc.korobov(prob.d, prob.n, prob.a)
+    qo, ao = _oracle_sum(prob)
+    q_plain = _gpu_sum(prob, qmc.FP64)
+    monkeypatch.setenv("QMC_VALIDATE", "1")
+    assert _gpu_sum(prob, qmc.FP64) == q_plain and _rel(q_plain, qo, ao) <= 1e-12
+
+    def rejected(call):
+        with pytest.raises(qmc.QmcError) as e:
+            call()
+        assert e.value.status == qmc.ERR_INVALID_ARG and "QMC_VALIDATE" in str(e.value), str(e.value)
+
+    for bad in (prob.n, -1, 1 << 40):
+        zb = z.copy()
+        zb[2] = bad
+        rejected(lambda: qmc.lattice_sum(zb, prob.n, 0, prob.params, qmc.FP64, shift=prob.shift))
+        rejected(lambda: qmc.lattice_sum_adjoint(zb, prob.n, 0, prob.params, qmc.FP64, shift=prob.shift))
+        rejected(lambda: qmc.lattice_points(zb, prob.n, 0, 10))
+        rejected(lambda: qmc.bernoulli_sum(np.stack([z, zb]), prob.n, 2, np.ones(prob.d)))
+        rejected(lambda: qmc.lattice_sum_shifts(zb, prob.n, 0, prob.params, np.full((3, prob.d), 0.25),
+                                                qmc.FP64))
+        rejected(lambda: qmc.BatchPlan([(0, z, prob.n, prob.params, None), (0, zb, prob.n, prob.params, None)]))
+    for bad in (1.0, -1e-300, float("nan")):
+        sb = prob.shift.copy()
+        sb[4] = bad
+        rejected(lambda: qmc.lattice_sum(z, prob.n, 0, prob.params, qmc.FP64, shift=sb))
+        shifts = np.full((3, prob.d), 0.25)
+        shifts[2, 1] = bad
+        rejected(lambda: qmc.lattice_sum_shifts(z, prob.n, 0, prob.params, shifts, qmc.FP64))
+    # valid calls captured in a graph under QMC_VALIDATE (the read-back is skipped there)
+    zt = torch.tensor(z, device="cuda")
+    pt = torch.tensor(prob.params, dtype=torch.float64, device="cuda")
+    st = torch.tensor(prob.shift, dtype=torch.float64, device="cuda")
+    ws = qmc.Workspace(qmc.workspace_size(prob.d, prob.n, 1))
+    out = torch.zeros(1, dtype=torch.float64, device="cuda")
+    qmc.lattice_sum(zt, prob.n, 0, pt, qmc.FP64, shift=st, ws=ws, out=out)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        with torch.cuda.graph(g):
+            qmc.lattice_sum(zt, prob.n, 0, pt, qmc.FP64, shift=st, ws=ws, out=out)
+    torch.cuda.current_stream().wait_stream(side)
+    out.zero_()
+    g.replay()
+    torch.cuda.synchronize()
+    assert float(out[0]) == q_plain
