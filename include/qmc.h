@@ -16,8 +16,12 @@
  *   QMC_PRODUCT_PEAK  f(x) = prod_j 1 / (c_j^-2 + (x_j - w_j)^2)   params: c[d], w[d]
  *   QMC_GAUSSIAN      f(x) = exp(-sum_j c_j^2 (x_j - w_j)^2)       params: c[d], w[d]
  *   QMC_OSCILLATORY   f(x) = cos(2 pi u + sum_j c_j x_j)           params: u, c[d]
+ *   QMC_EXP_QUADRATIC f(x) = exp(sum_j c_j (x_j - w_j)^2)         params: c[d], w[d]
+ *                     (c_j of either sign; c_j = -g_j^2 is the Gaussian, alternating
+ *                     signs with w = 0 are Test 7's f_5)
  * (the families of the paper's Tests 3-7: Gaussian, exp of a signed sum,
- *  product peak, cos of a sum -- with per-direction parameters).
+ *  product peak, cos of a sum, exp of a signed sum of squares -- with
+ *  per-direction parameters).
  *
  * Conventions for every entry point:
  *   - Every call returns a qmc_status; no C++ exception crosses the ABI.  On an
@@ -70,7 +74,8 @@ typedef enum {
     QMC_EXP_SUM = 0,
     QMC_PRODUCT_PEAK = 1,
     QMC_GAUSSIAN = 2,
-    QMC_OSCILLATORY = 3
+    QMC_OSCILLATORY = 3,
+    QMC_EXP_QUADRATIC = 4
 } qmc_family;
 
 /* QMC_FP64: every arithmetic step in IEEE double precision.

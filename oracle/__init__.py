@@ -21,7 +21,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "qmc_oracle.c")
 _LIB_PATH = os.path.join(_HERE, "liboracle.so")
 
-EXP_SUM, PRODUCT_PEAK, GAUSSIAN, OSCILLATORY = 0, 1, 2, 3
+EXP_SUM, PRODUCT_PEAK, GAUSSIAN, OSCILLATORY, EXP_QUADRATIC = 0, 1, 2, 3, 4
 TEST1_F, SIN_SQ = 100, 101
 
 _lib = None

@@ -17,6 +17,7 @@
  *   1 PRODUCT_PEAK  f(x) = prod_j 1 / (c_j^-2 + (x_j - w_j)^2)     params c[d], w[d]
  *   2 GAUSSIAN      f(x) = exp(-sum_j c_j^2 (x_j - w_j)^2)         params c[d], w[d]
  *   3 OSCILLATORY   f(x) = cos(2 pi u + sum_j c_j x_j)             params u, c[d]
+ *   4 EXP_QUADRATIC f(x) = exp(sum_j c_j (x_j - w_j)^2), c_j any sign  params c[d], w[d]
  * Oracle-only integrands used to pin the index map against the paper's tables:
  *   100 TEST1_F     f(x) = x_2 exp(x_1 x_2) / (e - 2)   (Test 1, d = 2)
  *   101 SIN_SQ      f(x) = sin(2 pi + sum_j x_j^2)       (Tests 1 and 2)
@@ -34,6 +35,7 @@
 #define OR_PRODUCT_PEAK 1
 #define OR_GAUSSIAN 2
 #define OR_OSCILLATORY 3
+#define OR_EXP_QUADRATIC 4
 #define OR_TEST1_F 100
 #define OR_SIN_SQ 101
 
@@ -96,6 +98,7 @@ int oracle_param_count(int family, int d) {
         case OR_PRODUCT_PEAK: return 2 * d;
         case OR_GAUSSIAN: return 2 * d;
         case OR_OSCILLATORY: return d + 1;
+        case OR_EXP_QUADRATIC: return 2 * d;
         case OR_TEST1_F: return 0;
         case OR_SIN_SQ: return 0;
         default: return -1;
@@ -131,6 +134,14 @@ double oracle_eval(int family, int d, const double* p, const double* x) {
             for (int j = 0; j < d; ++j) t += p[1 + j] * x[j];
             return cos(t);
         }
+        case OR_EXP_QUADRATIC: {
+            double s = 0.0;
+            for (int j = 0; j < d; ++j) {
+                double c = p[j], w = p[d + j];
+                s += c * (x[j] - w) * (x[j] - w);
+            }
+            return exp(s);
+        }
         case OR_TEST1_F:
             return x[1] * exp(x[0] * x[1]) / (exp(1.0) - 2.0);
         case OR_SIN_SQ: {
@@ -144,7 +155,7 @@ double oracle_eval(int family, int d, const double* p, const double* x) {
 }
 
 /* Gradient of the integrand with respect to its parameter vector (same layout
- * as params), accumulated as g += scale * df/dp.  Only the four families. */
+ * as params), accumulated as g += scale * df/dp.  Only the five families. */
 static void oracle_eval_grad(int family, int d, const double* p, const double* x, double scale,
                              double* g) {
     switch (family) {
@@ -170,6 +181,16 @@ static void oracle_eval_grad(int family, int d, const double* p, const double* x
                 double c = p[j], w = p[d + j];
                 g[j] += scale * f * (-2.0 * c * (x[j] - w) * (x[j] - w));
                 g[d + j] += scale * f * (2.0 * c * c * (x[j] - w));
+            }
+            break;
+        }
+        case OR_EXP_QUADRATIC: {
+            /* df/dc_j = f (x_j - w_j)^2 ; df/dw_j = -2 c_j (x_j - w_j) f */
+            double f = oracle_eval(family, d, p, x);
+            for (int j = 0; j < d; ++j) {
+                double c = p[j], w = p[d + j];
+                g[j] += scale * f * (x[j] - w) * (x[j] - w);
+                g[d + j] += scale * f * (-2.0 * c * (x[j] - w));
             }
             break;
         }
@@ -760,7 +781,8 @@ int oracle_mdi_lr_brute(int d, const int64_t* N, int family, const double* param
 
 /* One factor phi_k(y) of a product-form integrand, as a complex number
  * (re, im).  EXP_SUM: e^{c y}; GAUSSIAN: e^{-c^2 (y-w)^2};
- * PRODUCT_PEAK: 1 / (c^-2 + (y-w)^2); OSCILLATORY: e^{i c y}. */
+ * PRODUCT_PEAK: 1 / (c^-2 + (y-w)^2); OSCILLATORY: e^{i c y};
+ * EXP_QUADRATIC: e^{c (y-w)^2}. */
 static void factor(int family, int d, const double* p, int k, double y, double* re, double* im) {
     *im = 0.0;
     switch (family) {
@@ -773,6 +795,11 @@ static void factor(int family, int d, const double* p, int k, double y, double* 
         case OR_PRODUCT_PEAK: {
             double c = p[k], w = p[d + k];
             *re = 1.0 / (1.0 / (c * c) + (y - w) * (y - w));
+            break;
+        }
+        case OR_EXP_QUADRATIC: {
+            double c = p[k], w = p[d + k];
+            *re = exp(c * (y - w) * (y - w));
             break;
         }
         case OR_OSCILLATORY: {
@@ -795,7 +822,7 @@ static void factor(int family, int d, const double* p, int k, double y, double* 
  * is complex.  C is kept as a mantissa pair with a separate power-of-two
  * exponent so that d in the thousands cannot overflow. */
 int oracle_mdi_lr_sweep(int d, const int64_t* N, int family, const double* params, double* q_out) {
-    if (d < 1 || !N || family < 0 || family > 3) return OR_BAD_ARG;
+    if (d < 1 || !N || family < 0 || family > 4) return OR_BAD_ARG;
     double cre = 1.0, cim = 0.0;
     int cexp = 0;
     if (family == OR_OSCILLATORY) {
@@ -835,7 +862,7 @@ int oracle_mdi_lr_sweep(int d, const int64_t* N, int family, const double* param
  * for diagnostics of the sweep. */
 int oracle_mdi_lr_factors(int d, const int64_t* N, int family, const double* params, double* m_re,
                           double* m_im) {
-    if (d < 1 || !N || family < 0 || family > 3) return OR_BAD_ARG;
+    if (d < 1 || !N || family < 0 || family > 4) return OR_BAD_ARG;
     for (int k = 0; k < d; ++k) {
         if (N[k] < 1) return OR_BAD_ARG;
         neu_t mre = {0.0, 0.0}, mim = {0.0, 0.0};

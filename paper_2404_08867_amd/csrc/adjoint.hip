@@ -1,11 +1,12 @@
 // Adjoint of the plain lattice rule: Q_s and gq_s * dQ_s/d(params_s) for every
 // parameter set s sharing the lattice (derivative of eq. 1.2):
 //   dQ/dp = (1/n) sum_i df/dp (x_i).
-// For the four product- or sum-form families df/dp_j = w(x) * h_j(x_j): a per-point
+// For the product- or sum-form families df/dp_j = w(x) * h_j(x_j): a per-point
 // weight w times a function of one coordinate,
 //   exp-sum      w = f,        dc_j: h = x_j
 //   oscillatory  w = -sin(th), dc_j: h = x_j,  du: 2 pi w (per point)
 //   Gaussian     w = f,        dc_j: h = -2 c_j (x_j - w_j)^2,  dw_j: h = 2 c_j^2 (x_j - w_j)
+//   exp of a quadratic  w = f, dc_j: h = (x_j - w_j)^2,         dw_j: h = -2 c_j (x_j - w_j)
 //   product peak w = f,        dc_j: h = 2 c_j^-3 / q_j,        dw_j: h = 2 (x_j - w_j) / q_j
 // so a tile is processed in two sweeps over the directions: the first is the
 // forward accumulation of the sum kernel (giving f and w per point), the second
@@ -95,6 +96,24 @@ struct AdjFam<kGaussian, FP32> {
         const double y = x - c.w;
         ga = fma(wt, -2.0 * c.c * y * y, ga);
         gb = fma(wt, 2.0 * c.c * c.c * y, gb);
+    }
+    __device__ static int ia(int j, int) { return j; }
+    __device__ static int ib(int j, int d) { return d + j; }
+};
+
+template <bool FP32>
+struct AdjFam<kExpQuadratic, FP32> {
+    using F = ExpQuadratic<FP32>;
+    static constexpr bool kTwo = true;
+    __device__ static void point(const typename F::Acc& acc, double& val, double& wt, double& gu) {
+        val = F::finish(acc);
+        wt = val;
+        gu = 0.0;
+    }
+    __device__ static void dir(double x, const AdjDim& c, double wt, double& ga, double& gb) {
+        const double y = x - c.w;
+        ga = fma(wt, y * y, ga);
+        gb = fma(wt, -2.0 * c.c * y, gb);
     }
     __device__ static int ia(int j, int) { return j; }
     __device__ static int ib(int j, int d) { return d + j; }
@@ -727,6 +746,8 @@ hipError_t launch_adjoint(const AdjLaunch& L, hipStream_t stream) {
             case kExpSum: return launch_adj_f<kExpSum, true, AdjFam<kExpSum, true>>(L, stream);
             case kOscillatory: return launch_adj_f<kOscillatory, true, AdjFam<kOscillatory, true>>(L, stream);
             case kGaussian: return launch_adj_f<kGaussian, true, AdjFam<kGaussian, true>>(L, stream);
+            case kExpQuadratic:
+                return launch_adj_f<kExpQuadratic, true, AdjFam<kExpQuadratic, true>>(L, stream);
             case kProductPeak:
                 if (L.d <= kPeakF32MaxDims)
                     return launch_adj_f<kProductPeak, true, AdjPeak<ProductPeak<true, true>>>(L, stream);
@@ -737,6 +758,8 @@ hipError_t launch_adjoint(const AdjLaunch& L, hipStream_t stream) {
             case kExpSum: return launch_adj_f<kExpSum, false, AdjFam<kExpSum, false>>(L, stream);
             case kOscillatory: return launch_adj_f<kOscillatory, false, AdjFam<kOscillatory, false>>(L, stream);
             case kGaussian: return launch_adj_f<kGaussian, false, AdjFam<kGaussian, false>>(L, stream);
+            case kExpQuadratic:
+                return launch_adj_f<kExpQuadratic, false, AdjFam<kExpQuadratic, false>>(L, stream);
             case kProductPeak:
                 return launch_adj_f<kProductPeak, false, AdjPeak<ProductPeak<false, false>>>(L, stream);
         }

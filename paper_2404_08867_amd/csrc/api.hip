@@ -113,6 +113,7 @@ int param_count(int family, int d) {
         case QMC_PRODUCT_PEAK: return 2 * d;
         case QMC_GAUSSIAN: return 2 * d;
         case QMC_OSCILLATORY: return d + 1;
+        case QMC_EXP_QUADRATIC: return 2 * d;
         default: return -1;
     }
 }

@@ -32,6 +32,7 @@ struct BatchFamilies {
     using PD = ProductPeak<false, FP32>;  // FP64 factors
     using G = Gaussian<FP32>;
     using O = Oscillatory<FP32>;
+    using Q = ExpQuadratic<FP32>;
 };
 
 template <bool FP32>
@@ -41,6 +42,7 @@ union BatchShared {
     TileShared<typename BatchFamilies<FP32>::PD> pd;
     TileShared<typename BatchFamilies<FP32>::G> g;
     TileShared<typename BatchFamilies<FP32>::O> o;
+    TileShared<typename BatchFamilies<FP32>::Q> q;
 };
 
 template <class F, int M>
@@ -108,6 +110,7 @@ __global__ __launch_bounds__(kBlock) void batched_kernel(const BatchArgs a) {
                     run_tile<typename Fam::PD, M>(a, lo, pr, local, s.pd, red, &flag);
                 break;
             case kGaussian: run_tile<typename Fam::G, M>(a, lo, pr, local, s.g, red, &flag); break;
+            case kExpQuadratic: run_tile<typename Fam::Q, M>(a, lo, pr, local, s.q, red, &flag); break;
             default: run_tile<typename Fam::O, M>(a, lo, pr, local, s.o, red, &flag); break;
         }
         __syncthreads();  // shared tables and flag are free for the next tile

@@ -32,6 +32,7 @@ enum FamilyId {
     kProductPeak = 1,
     kGaussian = 2,
     kOscillatory = 3,
+    kExpQuadratic = 4,
     // Internal: the Bernoulli product sums behind the lattice-quality criteria.
     kBernoulli2 = 16,
     kBernoulli4 = 17,
@@ -122,6 +123,48 @@ struct Gaussian {
             return exp2_split_f32(-acc.s);
         else
             return exp2(-acc.s);
+    }
+    __device__ static double scale(double, int) { return 1.0; }
+};
+
+// ------------------------------------------------------ exp of a quadratic
+// f = exp(sum_j c_j (x_j - w_j)^2) with c_j of either sign = 2^{sum_j s_j y_j^2},
+// y_j = sqrt(|c_j| log2(e)) (x_j - w_j), s_j = sign(c_j).  Per point and direction
+// y and s_j y come from two FMAs on the same index (scaling by s_j = +-1 is exact),
+// and one more FMA adds their product.  c_j = -g_j^2 is the Gaussian; alternating
+// signs with w = 0 are Test 7's f_5.
+template <bool FP32>
+struct ExpQuadratic {
+    struct Dim {
+        double b, g, sb, sg;
+    };
+    struct Acc {
+        double s;
+    };
+    static constexpr int kRenorm = 0;
+    static constexpr bool kBlockTerms = false;
+    __device__ static void block_terms(const double*, int, int, double, double, double&, double&,
+                                       int&) {}
+    __device__ static double extra(const double*) { return 0.0; }
+    __device__ static Dim dim(const double* p, int d, int j, double inv_n, double sfrac) {
+        const double c = p[j], w = p[d + j];
+        const double m = sqrt(fabs(c) * kLog2e);
+        const double b = m * inv_n, g = fma(b, sfrac, -m * w);
+        const double sg = c < 0.0 ? -1.0 : 1.0;
+        return Dim{b, g, sg * b, sg * g};
+    }
+    __device__ static Acc init(double) { return Acc{0.0}; }
+    __device__ static void step(Acc& acc, uint32_t k, const Dim& c) {
+        const double kd = (double)k;
+        const double y = fma(kd, c.b, c.g), ys = fma(kd, c.sb, c.sg);
+        acc.s = fma(ys, y, acc.s);
+    }
+    __device__ static void renorm(Acc&) {}
+    __device__ static double finish(const Acc& acc) {
+        if constexpr (FP32)
+            return exp2_split_f32(acc.s);
+        else
+            return exp2(acc.s);
     }
     __device__ static double scale(double, int) { return 1.0; }
 };

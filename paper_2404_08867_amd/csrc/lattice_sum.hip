@@ -272,6 +272,7 @@ hipError_t launch_lattice_sum(const PlainLaunch& L, hipStream_t stream) {
                 return launch_f<ProductPeak<false, true>>(L, stream);
             case kGaussian: return launch_f<Gaussian<true>>(L, stream);
             case kOscillatory: return launch_f<Oscillatory<true>>(L, stream);
+            case kExpQuadratic: return launch_f<ExpQuadratic<true>>(L, stream);
         }
     } else {
         switch (L.family) {
@@ -279,6 +280,7 @@ hipError_t launch_lattice_sum(const PlainLaunch& L, hipStream_t stream) {
             case kProductPeak: return launch_f<ProductPeak<false, false>>(L, stream);
             case kGaussian: return launch_f<Gaussian<false>>(L, stream);
             case kOscillatory: return launch_f<Oscillatory<false>>(L, stream);
+            case kExpQuadratic: return launch_f<ExpQuadratic<false>>(L, stream);
         }
     }
     return hipErrorInvalidValue;

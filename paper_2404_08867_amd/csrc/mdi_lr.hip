@@ -65,6 +65,36 @@ __device__ __forceinline__ void direction_sum(const double* p, int d, int k, int
                 sr += exp2(-y * y);
             }
         }
+    } else if constexpr (FAM == kExpQuadratic) {
+        // phi = 2^{s y^2}, y = sqrt(|c| log2 e) ((t + 1/2)/N - w) = A t + B, s = sign(c)
+        const double cq = p[k], w = p[d + k];
+        const double m = sqrt(fabs(cq) * kLog2e);
+        const double A = m * invN, B = m * fma(0.5, invN, -w);
+        if constexpr (FP32) {
+            const float Af = (float)A, Bf = (float)B;
+            float tf = 0.0f;
+            if (cq < 0.0) {
+#pragma unroll 4
+                for (int t = 0; t < Nk; ++t, tf += 1.0f) {
+                    const float y = fmaf(tf, Af, Bf);
+                    sr += (double)__builtin_amdgcn_exp2f(-y * y);
+                }
+            } else {
+                // a positive exponent can leave the FP32 range: its integer part is
+                // split off in double
+#pragma unroll 4
+                for (int t = 0; t < Nk; ++t, tf += 1.0f) {
+                    const float y = fmaf(tf, Af, Bf);
+                    sr += exp2_split_f32((double)y * (double)y);
+                }
+            }
+        } else {
+            const double sg = cq < 0.0 ? -1.0 : 1.0;
+            for (int t = 0; t < Nk; ++t) {
+                const double y = fma((double)t, A, B);
+                sr += exp2(sg * y * y);
+            }
+        }
     } else if constexpr (FAM == kProductPeak) {
         // phi = 1 / (c^-2 + y^2), y = (t + 1/2)/N - w = A t + B
         const double c = p[k], w = p[d + k];
@@ -195,6 +225,8 @@ hipError_t launch_mdi_lr(const MdiLaunch& L, hipStream_t stream) {
         case kGaussian * 2 + 1: return launch_mdi_t<kGaussian, true>(L, stream);
         case kOscillatory * 2: return launch_mdi_t<kOscillatory, false>(L, stream);
         case kOscillatory * 2 + 1: return launch_mdi_t<kOscillatory, true>(L, stream);
+        case kExpQuadratic * 2: return launch_mdi_t<kExpQuadratic, false>(L, stream);
+        case kExpQuadratic * 2 + 1: return launch_mdi_t<kExpQuadratic, true>(L, stream);
     }
     return hipErrorInvalidValue;
 }

@@ -59,6 +59,7 @@ int param_count(int family, int d) {
         case QMC_PRODUCT_PEAK:
         case QMC_GAUSSIAN: return 2 * d;
         case QMC_OSCILLATORY: return d + 1;
+        case QMC_EXP_QUADRATIC: return 2 * d;
         default: return -1;
     }
 }
@@ -124,7 +125,7 @@ qmc_status build_tables(qmc_batch_plan* p) {
 
 std::string signature(const qmc_batch_plan* p) {
     double sn = 0, snd = 0;
-    int fam[4] = {0, 0, 0, 0}, maxd = 0;
+    int fam[5] = {0, 0, 0, 0, 0}, maxd = 0;
     int64_t maxn = 0;
     for (const auto& q : p->probs) {
         sn += (double)q.n;
@@ -134,8 +135,8 @@ std::string signature(const qmc_batch_plan* p) {
         maxn = std::max(maxn, (int64_t)q.n);
     }
     char buf[256];
-    snprintf(buf, sizeof(buf), "batch:c%d:p%d:sn%.6e:snd%.6e:f%d-%d-%d-%d:d%d:n%lld:cu%d", p->count,
-             p->precision, sn, snd, fam[0], fam[1], fam[2], fam[3], maxd, (long long)maxn,
+    snprintf(buf, sizeof(buf), "batch:c%d:p%d:sn%.6e:snd%.6e:f%d-%d-%d-%d-%d:d%d:n%lld:cu%d", p->count,
+             p->precision, sn, snd, fam[0], fam[1], fam[2], fam[3], fam[4], maxd, (long long)maxn,
              qmc::device_cu_count());
     return buf;
 }

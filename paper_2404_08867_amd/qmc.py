@@ -18,7 +18,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libqmc.so")
 
 # qmc_family
-EXP_SUM, PRODUCT_PEAK, GAUSSIAN, OSCILLATORY = 0, 1, 2, 3
+EXP_SUM, PRODUCT_PEAK, GAUSSIAN, OSCILLATORY, EXP_QUADRATIC = 0, 1, 2, 3, 4
 # qmc_precision
 FP64, FP32_COMPENSATED = 0, 1
 # qmc_n_mode

@@ -51,14 +51,15 @@ import numpy as np
 SEED_BASE = 2404088670
 
 # Family ids (the same numbering as the C ABI and the oracle).
-EXP_SUM, PRODUCT_PEAK, GAUSSIAN, OSCILLATORY = 0, 1, 2, 3
+EXP_SUM, PRODUCT_PEAK, GAUSSIAN, OSCILLATORY, EXP_QUADRATIC = 0, 1, 2, 3, 4
 FAMILY_NAMES = {EXP_SUM: "exp_sum", PRODUCT_PEAK: "product_peak", GAUSSIAN: "gaussian",
-                OSCILLATORY: "oscillatory"}
+                OSCILLATORY: "oscillatory", EXP_QUADRATIC: "exp_quadratic"}
 
 
 def param_count(family: int, d: int) -> int:
-    """Length of the FP64 parameter vector: c | c,w | c,w | u,c."""
-    return {EXP_SUM: d, PRODUCT_PEAK: 2 * d, GAUSSIAN: 2 * d, OSCILLATORY: d + 1}[family]
+    """Length of the FP64 parameter vector: c | c,w | c,w | u,c | c,w."""
+    return {EXP_SUM: d, PRODUCT_PEAK: 2 * d, GAUSSIAN: 2 * d, OSCILLATORY: d + 1,
+            EXP_QUADRATIC: 2 * d}[family]
 
 
 def draw_params(rng: np.random.Generator, family: int, d: int) -> np.ndarray:
@@ -77,6 +78,11 @@ def draw_params(rng: np.random.Generator, family: int, d: int) -> np.ndarray:
         c = rng.uniform(0.0, 2.0, d)
         u = rng.uniform(0.0, 1.0, 1)
         return np.concatenate([u, c])
+    if family == EXP_QUADRATIC:
+        # signed weights, as in Test 7's f_5 (alternating +-1, w = 0)
+        c = rng.uniform(-1.0, 1.0, d)
+        w = rng.uniform(0.0, 1.0, d)
+        return np.concatenate([c, w])
     raise ValueError(f"unknown family {family}")
 
 

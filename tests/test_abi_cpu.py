@@ -54,7 +54,7 @@ def test_mdi_dims_paper_cases():
 
 
 def test_param_count_and_workspace():
-    assert [qmc.param_count(f, 7) for f in range(4)] == [7, 14, 14, 8]
+    assert [qmc.param_count(f, 7) for f in range(5)] == [7, 14, 14, 8, 14]
     assert qmc.workspace_size(20, 1 << 20, 1) >= 8 * 2048
     assert qmc.workspace_size(50, 1 << 24, 64) >= 64 * 8
 

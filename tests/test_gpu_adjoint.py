@@ -29,7 +29,7 @@ def _check_set(q, g, qo, ao, go, tol):
 
 
 @pytest.mark.parametrize("precision", [qmc.FP64, qmc.FP32_COMPENSATED])
-@pytest.mark.parametrize("family", [0, 1, 2, 3])
+@pytest.mark.parametrize("family", [0, 1, 2, 3, 4])
 @pytest.mark.parametrize("d,n", [(3, 10007), (20, 65537), (65, 3001), (130, 1009), (1, 997)])
 def test_adjoint_matches_oracle(precision, family, d, n):
     rng = np.random.default_rng(7 * d + n + family)
@@ -48,7 +48,7 @@ def test_adjoint_value_equals_forward_and_gq_scales():
     rng = np.random.default_rng(3)
     d, n = 12, 50021
     z = qmc.korobov(d, n, 4321)
-    for family in range(4):
+    for family in range(5):
         params = np.stack([W.draw_params(rng, family, d) for _ in range(3)])
         q, g = qmc.lattice_sum_adjoint(z, n, family, params, qmc.FP64)
         qf = qmc.lattice_sum(z, n, family, params, qmc.FP64)
@@ -58,7 +58,7 @@ def test_adjoint_value_equals_forward_and_gq_scales():
         assert np.allclose(g2.cpu().numpy(), gq[:, None] * g.cpu().numpy(), rtol=1e-15, atol=0)
 
 
-@pytest.mark.parametrize("family", [0, 1, 2, 3])
+@pytest.mark.parametrize("family", [0, 1, 2, 3, 4])
 def test_adjoint_matches_finite_differences_of_device_forward(family):
     rng = np.random.default_rng(40 + family)
     d, n = 4, 4099
@@ -114,7 +114,7 @@ def test_autograd_function_gradcheck_and_chain_rule():
     d, n = 3, 2003
     z = qmc.korobov(d, n, 561)
     rng = np.random.default_rng(5)
-    for family in range(4):
+    for family in range(5):
         p = torch.tensor(np.stack([W.draw_params(rng, family, d) for _ in range(2)]), device="cuda",
                          requires_grad=True)
         f = lambda x: qmc.lattice_sum_autograd(x, z, n, family, qmc.FP64)

@@ -20,7 +20,7 @@ def _mixed_problems(seed, count, dmax=130, nmax=60000):
     rng = np.random.default_rng(seed)
     probs = []
     for b in range(count):
-        fam = b % 4
+        fam = b % 5
         d = int(rng.integers(1, dmax + 1))
         n = int(rng.choice([1, 2, 63, 1025, int(rng.integers(3, nmax))])) if b % 7 == 0 else int(rng.integers(3, nmax))
         a = W.draw_coprime(rng, n)

@@ -65,7 +65,7 @@ CASES = [  # (d, n): several tiles and a ragged tail; 2 and 3 direction chunks
 
 
 @pytest.mark.parametrize("precision", PRECS)
-@pytest.mark.parametrize("family", [0, 1, 2, 3])
+@pytest.mark.parametrize("family", [0, 1, 2, 3, 4])
 @pytest.mark.parametrize("d,n", CASES)
 @pytest.mark.parametrize("shift", [False, True])
 def test_plain_sum_matches_oracle(precision, family, d, n, shift):
@@ -77,7 +77,7 @@ def test_plain_sum_matches_oracle(precision, family, d, n, shift):
 
 @pytest.mark.parametrize("ppt", [4, 8, 16])
 @pytest.mark.parametrize("max_blocks", [1, 3, 0])
-@pytest.mark.parametrize("family", [0, 1, 2, 3])
+@pytest.mark.parametrize("family", [0, 1, 2, 3, 4])
 def test_plain_sum_every_launch_shape(ppt, max_blocks, family):
     """Each tile size, a single persistent workgroup looping over all tiles, and
     a ragged persistent distribution give the oracle's value."""
@@ -90,7 +90,7 @@ def test_plain_sum_every_launch_shape(ppt, max_blocks, family):
 
 @pytest.mark.parametrize("n", [1, 2, 3, 63, 64, 65, 1023, 1025])
 def test_plain_sum_tiny_n(n):
-    for family in range(4):
+    for family in range(5):
         prob = W.random_plain(n + 10 * family, family, 5, n, shift=(n % 2 == 1))
         qo, ao = _oracle_sum(prob)
         for precision in PRECS:
@@ -111,7 +111,7 @@ def test_plain_sum_float_index_boundary(n, shift):
 
 
 def test_plain_sum_max_dimension():
-    for family in range(4):
+    for family in range(5):
         prob = W.random_plain(5 + family, family, 1024, 257, shift=True)
         qo, ao = _oracle_sum(prob)
         for precision in PRECS:
@@ -125,7 +125,7 @@ def test_plain_sum_many_sets():
     d, n = 6, 30011
     z = qmc.korobov(d, n, 1234)
     shift = rng.uniform(0, 1, d)
-    for family in range(4):
+    for family in range(5):
         P = W.param_count(family, d)
         params = np.stack([W.draw_params(rng, family, d) for _ in range(5)])
         assert params.shape == (5, P)
@@ -188,7 +188,7 @@ def test_workload_plain_d20_peak(precision):
 
 # ------------------------------------------------------------------------ MDI-LR
 @pytest.mark.parametrize("precision", PRECS)
-@pytest.mark.parametrize("family", [0, 1, 2, 3])
+@pytest.mark.parametrize("family", [0, 1, 2, 3, 4])
 @pytest.mark.parametrize("N", [[7], [4, 9], [3, 1, 6], [5, 4, 3, 7], [12, 12, 12, 13]])
 def test_mdi_lr_small_grids_match_brute_force(precision, family, N):
     rng = np.random.default_rng(len(N) * 7 + family)
@@ -222,7 +222,7 @@ def test_mdi_lr_many_sets_sampled(precision):
 
 
 @pytest.mark.parametrize("precision", PRECS)
-@pytest.mark.parametrize("family", [0, 1, 2, 3])
+@pytest.mark.parametrize("family", [0, 1, 2, 3, 4])
 def test_mdi_lr_ragged_nodes_and_families(precision, family):
     rng = np.random.default_rng(50 + family)
     d = 37

@@ -43,7 +43,7 @@ CASES = [(3, 10007, 5), (20, 4099, 17), (65, 3001, 3), (1, 997, 70), (8, 1009, 1
 
 
 @pytest.mark.parametrize("precision", PRECS)
-@pytest.mark.parametrize("family", [0, 1, 2, 3])
+@pytest.mark.parametrize("family", [0, 1, 2, 3, 4])
 @pytest.mark.parametrize("d,n,R", CASES)
 def test_shift_ensemble_matches_oracle(precision, family, d, n, R):
     prob = W.random_plain(7000 + 31 * d + n + family, family, d, n)

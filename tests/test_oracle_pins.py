@@ -204,7 +204,7 @@ def test_midpoint_closed_forms(N):
     assert got == pytest.approx(z.real, rel=1e-12, abs=1e-14)
 
 
-@pytest.mark.parametrize("family", [0, 1, 2, 3])
+@pytest.mark.parametrize("family", [0, 1, 2, 3, 4])
 def test_half_shifted_1d_lattice_is_midpoint_rule(family):
     """d = 1, z = 1, Delta = 1/(2n): the lattice points are the midpoints (k + 1/2)/n,
     so the plain rule equals the MDI-LR tensor rule with N_1 = n."""
@@ -216,7 +216,7 @@ def test_half_shifted_1d_lattice_is_midpoint_rule(family):
 
 
 # ---- brute force for the MDI-LR sweep --------------------------------------------
-@pytest.mark.parametrize("family", [0, 1, 2, 3])
+@pytest.mark.parametrize("family", [0, 1, 2, 3, 4])
 @pytest.mark.parametrize("N", [[7], [4, 9], [3, 1, 6], [5, 4, 3, 7], [12, 12, 12, 12]])
 def test_mdi_sweep_matches_brute_force(family, N):
     rng = np.random.default_rng(len(N) * 10 + family)
@@ -237,8 +237,46 @@ def test_mdi_sweep_survives_d1000_underflow_range():
     assert math.log(got) == pytest.approx(lg, rel=1e-13)
 
 
+# ---- exp of a signed quadratic (Test 7's f_5) ------------------------------------
+def test_exp_quadratic_with_negative_weights_is_the_gaussian():
+    """c_j = -g_j^2 makes exp(sum_j c_j (x_j - w_j)^2) the Gaussian family with widths g."""
+    rng = np.random.default_rng(11)
+    d, n = 5, 1009
+    g, w = rng.uniform(0.2, 1.5, d), rng.uniform(0, 1, d)
+    z, shift = O.korobov(d, n, 389), rng.uniform(0, 1, d)
+    pq, pg = np.concatenate([-g * g, w]), np.concatenate([g, w])
+    q = O.lattice_sum(z, n, O.EXP_QUADRATIC, pq, shift)[0]
+    assert q == pytest.approx(O.lattice_sum(z, n, O.GAUSSIAN, pg, shift)[0], rel=1e-14)
+    N = [5, 8, 3, 7, 6]
+    assert O.mdi_lr(N, O.EXP_QUADRATIC, pq) == pytest.approx(O.mdi_lr(N, O.GAUSSIAN, pg), rel=1e-14)
+
+
+@pytest.mark.parametrize("N", [16, 64, 256])
+def test_f5_mdi_lr_against_erf_erfi_closed_form(N):
+    """f_5 = exp(sum_j (-1)^{j+1} x_j^2): MDI-LR is the tensor midpoint rule, a product of
+    1-D midpoint sums of exp(s x^2), s = +-1, whose integrals are (sqrt(pi)/2) erfi(1) and
+    (sqrt(pi)/2) erf(1).  The midpoint rule's Euler-Maclaurin expansion gives each factor
+    as I - (h^2/24) D1 + (7 h^4/5760) D3 + O(h^6), with h = 1/N and the end-point
+    differences D1 = f'(1) - f'(0) = 2 s e^s, D3 = f'''(1) - f'''(0) = (12 + 8 s) e^s."""
+    d = 6
+    s = np.array([(-1.0) ** j for j in range(d)])
+    p = np.concatenate([s, np.zeros(d)])
+    h = 1.0 / N
+    fac = []
+    for sj in s:
+        exact = math.sqrt(math.pi) / 2 * (float(mp.erfi(1)) if sj > 0 else math.erf(1.0))
+        e = math.exp(sj)
+        fac.append(exact - h * h / 24 * 2 * sj * e + 7 * h ** 4 / 5760 * (12 + 8 * sj) * e)
+    q = O.mdi_lr([N] * d, O.EXP_QUADRATIC, p)
+    assert q == pytest.approx(math.prod(fac), rel=max(d * h ** 6, 1e-13))
+    # the h^4 term is resolved: dropping it misses by more than the tolerance
+    if N == 16:
+        lead = math.prod(f - 7 * h ** 4 / 5760 * (12 + 8 * sj) * math.exp(sj) for f, sj in zip(fac, s))
+        assert abs(q - lead) > d * h ** 6 * abs(q)
+
+
 # ---- gradients --------------------------------------------------------------------
-@pytest.mark.parametrize("family", [0, 1, 2, 3])
+@pytest.mark.parametrize("family", [0, 1, 2, 3, 4])
 def test_gradient_matches_central_differences(family):
     rng = np.random.default_rng(100 + family)
     d, n = 3, 257

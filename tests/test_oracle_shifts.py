@@ -57,7 +57,7 @@ def test_two_shift_standard_error(n, c):
     assert se == pytest.approx(0.5 * abs(q1 - q0), rel=1e-10)
 
 
-@pytest.mark.parametrize("family", [0, 1, 2, 3])
+@pytest.mark.parametrize("family", [0, 1, 2, 3, 4])
 def test_identical_shifts_have_zero_standard_error(family):
     d, n = 3, 211
     z = O.korobov(d, n, 17)
