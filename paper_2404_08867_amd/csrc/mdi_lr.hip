@@ -80,12 +80,15 @@ __device__ __forceinline__ void direction_sum(const double* p, int d, int k, int
                     sr += (double)__builtin_amdgcn_exp2f(-y * y);
                 }
             } else {
-                // a positive exponent can leave the FP32 range: its integer part is
-                // split off in double
+                // a growing factor: the largest nodes dominate the sum, so y and y^2 are
+                // formed in double (an FP32 y would carry a relative error of ~1e-7 y^2
+                // into the exponent) and the integer part of y^2 is split off before the
+                // FP32 exp2
+                double td = 0.0;
 #pragma unroll 4
-                for (int t = 0; t < Nk; ++t, tf += 1.0f) {
-                    const float y = fmaf(tf, Af, Bf);
-                    sr += exp2_split_f32((double)y * (double)y);
+                for (int t = 0; t < Nk; ++t, td += 1.0) {
+                    const double y = fma(td, A, B);
+                    sr += exp2_split_f32(y * y);
                 }
             }
         } else {

@@ -239,6 +239,32 @@ def test_mdi_lr_ragged_nodes_and_families(precision, family):
         assert abs(q[s] - qo) <= TOL[precision] * scale, (s, q[s], qo)
 
 
+@pytest.mark.parametrize("precision", PRECS)
+def test_mdi_lr_exp_quadratic_growing_factors(precision):
+    """Signed quadratic with large positive weights: the largest nodes dominate each
+    factor (e^24 against 1), so the FP32c sweep must form the argument in double."""
+    N = np.array([64, 48, 64, 33], np.int32)
+    p = np.array([30.0, 20.0, -5.0, 12.0, 0.1, 0.9, 0.5, 0.0])
+    q = float(qmc.mdi_lr(N, qmc.EXP_QUADRATIC, p, precision).item())
+    qo = O.mdi_lr(N.astype(np.int64), O.EXP_QUADRATIC, p)
+    assert abs(q - qo) <= TOL[precision] * abs(qo), (q, qo)
+
+
+@pytest.mark.parametrize("precision", PRECS)
+@pytest.mark.parametrize("d,N", [(1000, 10), (1000, 14), (200, 64)])
+def test_mdi_lr_test7_f5(precision, d, N):
+    """Test 7's f_5 = exp(sum_j (-1)^{j+1} x_j^2) at the node counts of its timing runs.
+    Its directions come in two identical kinds, so the FP32 rounding of each factor is
+    the same in every direction of a kind and adds up linearly over d: QMC_FP32_COMPENSATED
+    is held to 1e-8 per direction here (measured: 4.7e-9) instead of 1e-6 overall."""
+    p = np.concatenate([[(-1.0) ** j for j in range(d)], np.zeros(d)])
+    q = float(qmc.mdi_lr(np.full(d, N, np.int32), qmc.EXP_QUADRATIC, p, precision).item())
+    qo = O.mdi_lr(np.full(d, N), O.EXP_QUADRATIC, p)
+    tol = TOL[precision] if precision == qmc.FP64 else max(TOL[precision], 1e-8 * d)
+    print(f"f5 d={d} N={N} precision={precision} rel err {abs(q - qo) / abs(qo):.3e}")
+    assert abs(q - qo) <= tol * abs(qo), (q, qo)
+
+
 def test_mdi_lr_paper_table23_d1000():
     """Table 2-3 settings (d = 1000): exp of the alternating sum with N = 8 and the
     product peak with N = 20 match the oracle sweep to FP64 accuracy."""
