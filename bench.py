@@ -537,6 +537,30 @@ def oracle_cbc_baseline(w, res, seconds):
     return (w.n // 2 + 1) * k / dt, k, err
 
 
+def gaussian_integral(c, w):
+    """Exact integral over [0,1]^d of exp(-sum_j c_j^2 (x_j - w_j)^2)."""
+    out = 1.0
+    for cj, wj in zip(c, w):
+        out *= math.sqrt(math.pi) / (2 * cj) * (math.erf(cj * (1 - wj)) + math.erf(cj * wj))
+    return out
+
+
+def mdi_beside_plain_rule(torch, qmc, W, w, results):
+    """Set 0 of the MDI-LR launch and the plain rule on the same Gaussian (n = 1048573,
+    seeded a), both against the exact integral (outside the timed region)."""
+    pr = W.mdi_d100_gauss_plain_rule()
+    exact = gaussian_integral(pr.params[:pr.d], pr.params[pr.d:])
+    z = torch.tensor(qmc.korobov(pr.d, pr.n, pr.a), device="cuda")
+    params = torch.tensor(pr.params, dtype=torch.float64, device="cuda")
+    out = {"exact_integral": exact, "mdi_lr": {"N": int(w.N[0]), "nodes": f"{int(w.N[0])}^{w.d}"},
+           "plain_rule": {"n": pr.n, "a": pr.a}}
+    for name, prec in (("fp32c", qmc.FP32_COMPENSATED), ("fp64", qmc.FP64)):
+        out["mdi_lr"][f"rel_err_{name}"] = float(results[name]["q"][0]) / exact - 1
+        q = float(qmc.lattice_sum(z, pr.n, pr.family, params, prec).item())
+        out["plain_rule"][f"rel_err_{name}"] = q / exact - 1
+    return out
+
+
 def bench_mdi(args, torch, qmc, W):
     nsets = 65536
     w = W.mdi_d100_gauss(nsets=nsets)
@@ -554,6 +578,7 @@ def bench_mdi(args, torch, qmc, W):
         del g
     units = int(w.N.sum()) * nsets  # one-dimensional factor evaluations per launch
     wpp = WORK_PER_MDI_FACTOR
+    results["vs_plain_rule"] = mdi_beside_plain_rule(torch, qmc, W, w, results)
     config = {"workload": w.name, "d": w.d, "N": int(w.N[0]), "nsets": nsets,
               "family": W.FAMILY_NAMES[w.family], "precision": "fp32_compensated",
               "unit_of_work": "one-dimensional factor evaluation"}
@@ -744,6 +769,8 @@ def main():
         "fp64": {"value": units / res["fp64"]["step_s"], "ms_per_step": res["fp64"]["step_s"] * 1e3,
                  "kernel_us": res["fp64"]["kern_s"] * 1e6},
     })
+    if "vs_plain_rule" in res:
+        line["vs_plain_rule"] = res["vs_plain_rule"]
 
     if not args.no_cpu_baseline:
         if args.workload == "batched_4096":

@@ -185,6 +185,15 @@ def mdi_d100_gauss(nsets: int = 1) -> MdiSets:
                    np.concatenate([c, w], axis=1))
 
 
+def mdi_d100_gauss_plain_rule() -> Plain:
+    """The plain rule beside the MDI-LR workload: set 0's Gaussian parameters on a
+    Korobov lattice with n = 1048573 and a seeded a (its own stream of the same seed)."""
+    w = mdi_d100_gauss(nsets=1)
+    n = 1048573
+    a = int(np.random.default_rng([SEED_BASE + 2, 1]).integers(2, n))
+    return Plain("mdi_d100_gauss_plain_rule", w.d, n, a, GAUSSIAN, w.params[0].copy())
+
+
 def batched_4096(count: int = 4096, d_range=(8, 200), n_range=(1 << 12, 1 << 22)) -> Batch:
     rng = np.random.default_rng(SEED_BASE + 3)
     primes = primes_between(*n_range)

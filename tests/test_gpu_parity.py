@@ -211,6 +211,37 @@ def test_mdi_lr_workload_d100(precision):
     assert abs(q - qo) <= TOL[precision] * abs(qo)
 
 
+def test_mdi_lr_beside_plain_rule_d100_gaussian():
+    """Set 0 of the MDI-LR workload (d = 100, N = 64) and the plain rule on the same
+    Gaussian at n = 1048573 with a seeded a: both device results against the oracle, and
+    the MDI-LR error against the exact integral equal to the midpoint rule's first
+    Euler-Maclaurin term (independent of the oracle)."""
+    m = W.mdi_d100_gauss(nsets=1)
+    pr = W.mdi_d100_gauss_plain_rule()
+    d = m.d
+    c, w = m.params[0][:d], m.params[0][d:]
+    h = 1.0 / 64
+    exact, pred = 1.0, 1.0
+    for cj, wj in zip(c, w):
+        Ij = math.sqrt(math.pi) / (2 * cj) * (math.erf(cj * (1 - wj)) + math.erf(cj * wj))
+        dphi = -2 * cj * cj * ((1 - wj) * math.exp(-cj * cj * (1 - wj) ** 2) + wj * math.exp(-cj * cj * wj * wj))
+        exact *= Ij
+        pred *= 1 - h * h / 24 * dphi / Ij
+    pred -= 1
+    err = {}
+    for precision, tol in ((qmc.FP64, 1e-4), (qmc.FP32_COMPENSATED, 2e-3)):
+        q = float(qmc.mdi_lr(m.N.astype(np.int32), m.family, m.params[0], precision).item())
+        err[precision] = q / exact - 1
+        assert abs(err[precision] / pred - 1) < tol, (precision, err[precision], pred)
+    z = qmc.korobov(d, pr.n, pr.a)
+    qo, ao = O.lattice_sum(z, pr.n, pr.family, pr.params)
+    for precision in PRECS:
+        q = float(qmc.lattice_sum(z, pr.n, pr.family, pr.params, precision).item())
+        assert _rel(q, qo, ao) <= TOL[precision], (precision, q, qo)
+    print(f"d=100 Gaussian: MDI-LR (N=64) rel err {err[qmc.FP64]:.3e}, plain rule (n={pr.n}, a={pr.a}) "
+          f"rel err {qo / exact - 1:.3e}")
+
+
 @pytest.mark.parametrize("precision", PRECS)
 def test_mdi_lr_many_sets_sampled(precision):
     """Throughput launch over 4099 sets; 40 sampled sets checked against the oracle."""

@@ -237,6 +237,31 @@ def test_mdi_sweep_survives_d1000_underflow_range():
     assert math.log(got) == pytest.approx(lg, rel=1e-13)
 
 
+def _gauss_integral_and_midpoint_error(c, w, N):
+    """Closed form of int_[0,1]^d exp(-sum c_j^2 (x_j - w_j)^2) dx and the relative error
+    of the tensor midpoint rule predicted by the first Euler-Maclaurin term of each
+    direction, -(h^2/24) (phi'(1) - phi'(0)) / I_j with phi'(x) = -2 c^2 (x - w) phi(x)."""
+    h = 1.0 / N
+    exact, pred = 1.0, 1.0
+    for cj, wj in zip(c, w):
+        Ij = math.sqrt(math.pi) / (2 * cj) * (math.erf(cj * (1 - wj)) + math.erf(cj * wj))
+        dphi = -2 * cj * cj * ((1 - wj) * math.exp(-cj * cj * (1 - wj) ** 2) + wj * math.exp(-cj * cj * wj * wj))
+        exact *= Ij
+        pred *= 1 - h * h / 24 * dphi / Ij
+    return exact, pred - 1
+
+
+def test_mdi_lr_d100_gaussian_against_closed_form():
+    """The MDI-LR workload's set 0 (d = 100, N = 64): the oracle's relative error against
+    the exact integral is the midpoint rule's Euler-Maclaurin prediction to 1e-4 of itself
+    (the next term is O(h^4))."""
+    m = W.mdi_d100_gauss(nsets=1)
+    d = m.d
+    exact, pred = _gauss_integral_and_midpoint_error(m.params[0][:d], m.params[0][d:], 64)
+    err = O.mdi_lr(m.N, m.family, m.params[0]) / exact - 1
+    assert abs(err / pred - 1) < 1e-4, (err, pred)
+
+
 # ---- exp of a signed quadratic (Test 7's f_5) ------------------------------------
 def test_exp_quadratic_with_negative_weights_is_the_gaussian():
     """c_j = -g_j^2 makes exp(sum_j c_j (x_j - w_j)^2) the Gaussian family with widths g."""
