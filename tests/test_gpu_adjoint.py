@@ -96,6 +96,22 @@ def test_adjoint_exact_u_derivative_of_character_sum():
     assert float(g[0].item()) == pytest.approx(-2 * math.pi * math.sin(arg), abs=1e-8)
 
 
+def test_adjoint_character_identity_at_largest_n():
+    """The adjoint at n = 2^31 - 1, z = (1, 2, 4), h = (-2, 1, 0) in the dual lattice: the
+    value is cos(2 pi u + 2 pi h.Delta) and its u-derivative -2 pi sin(...) exactly."""
+    n, d = 2147483647, 3
+    z = qmc.korobov(d, n, 2)
+    shift = np.random.default_rng(6).uniform(0, 1, d)
+    u = 0.37
+    h = np.array([-2.0, 1.0, 0.0])
+    params = np.concatenate([[u], 2 * math.pi * h])
+    arg = 2 * math.pi * u + 2 * math.pi * float(np.dot(h, shift))
+    for precision, tol in ((qmc.FP64, 1e-9), (qmc.FP32_COMPENSATED, 1e-6)):
+        q, g = qmc.lattice_sum_adjoint(z, n, qmc.OSCILLATORY, params, precision, shift=shift)
+        assert float(q.item()) == pytest.approx(math.cos(arg), abs=tol)
+        assert float(g[0].item()) == pytest.approx(-2 * math.pi * math.sin(arg), abs=10 * tol)
+
+
 @pytest.mark.parametrize("precision", [qmc.FP32_COMPENSATED, qmc.FP64])
 def test_adjoint_workload_d50_sampled(precision):
     """64 oscillatory sets, d = 50, n = 16777213 in one adjoint launch; set 0 is

@@ -161,6 +161,28 @@ def test_character_identity_on_device():
         assert abs(q - expect) < 1e-9, (h, q, expect)
 
 
+@pytest.mark.parametrize("shifted", [False, True])
+def test_character_identity_at_largest_n(shifted):
+    """n = 2^31 - 1 (the largest n the ABI accepts; prime), z = (1, 2, 4): h = (-2, 1, 0) and
+    (0, -2, 1) are in the dual lattice, (1, 0, 0) and (1, 1, 1) are not, so eq. 2.3 fixes
+    each sum exactly; a wrong index anywhere in the 2^31 - 1 points breaks it."""
+    n, d = 2147483647, 3
+    z = qmc.korobov(d, n, 2)
+    assert list(z) == [1, 2, 4]
+    shift = np.random.default_rng(5).uniform(0, 1, d) if shifted else np.zeros(d)
+    u = 0.3125
+    for h, in_dual in (((-2, 1, 0), True), ((0, -2, 1), True), ((1, 0, 0), False), ((1, 1, 1), False)):
+        h = np.array(h, dtype=float)
+        params = np.concatenate([[u], 2 * math.pi * h])
+        expect = math.cos(2 * math.pi * u + 2 * math.pi * float(np.dot(h, shift))) if in_dual else 0.0
+        for precision, tol in ((qmc.FP64, 1e-9), (qmc.FP32_COMPENSATED, 1e-6)):
+            for ppt in (4, 8, 16):
+                q = float(qmc.lattice_sum(z, n, qmc.OSCILLATORY, params, precision,
+                                          shift=shift if shifted else None,
+                                          points_per_thread=ppt).item())
+                assert abs(q - expect) < tol, (h, precision, ppt, q, expect)
+
+
 def test_results_are_deterministic_and_workspace_reusable():
     prob = W.plain_d20_peak()
     z = qmc.korobov(prob.d, prob.n, prob.a)
