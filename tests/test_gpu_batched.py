@@ -1,4 +1,6 @@
 """Batched plain sums (one persistent launch for many integrands) against the oracle."""
+import math
+
 import numpy as np
 import pytest
 
@@ -64,6 +66,25 @@ def test_batched_every_configuration_is_exact_and_reproducible():
                     q2 = plan.run().cpu().numpy()
                     assert np.array_equal(q1.view(np.int64), q2.view(np.int64))
                     _check(q1, ref, precision)
+
+
+def test_batched_with_a_largest_n_problem():
+    """A batch holding one n = 2^31 - 1 problem (z = (1, 2, 4), oscillatory with h =
+    (-2, 1, 0) in the dual lattice: exactly cos(2 pi u + 2 pi h.Delta), eq. 2.3) among small
+    random ones, which are checked against the oracle."""
+    n, d = 2147483647, 3
+    shift = np.random.default_rng(12).uniform(0, 1, d)
+    u = 0.3125
+    h = np.array([-2.0, 1.0, 0.0])
+    big = (qmc.OSCILLATORY, qmc.korobov(d, n, 2), n, np.concatenate([[u], 2 * math.pi * h]), shift)
+    small = _mixed_problems(9, 6, dmax=20, nmax=20000)
+    probs = small[:3] + [big] + small[3:]
+    expect = math.cos(2 * math.pi * u + 2 * math.pi * float(np.dot(h, shift)))
+    ref = _oracle(small[:3]) + [None] + _oracle(small[3:])
+    for precision, tol in ((qmc.FP64, 1e-9), (qmc.FP32_COMPENSATED, 1e-6)):
+        q = qmc.BatchPlan(probs, precision).run().cpu().numpy()
+        assert abs(q[3] - expect) < tol, (precision, q[3], expect)
+        _check(np.delete(q, 3), ref[:3] + ref[4:], precision)
 
 
 def test_batched_agrees_with_single_problem_kernel():

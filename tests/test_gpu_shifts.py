@@ -94,6 +94,23 @@ def test_shifts_d20_peak_full_size(precision):
     assert stats[1] > 0 and np.all(np.isfinite(q))
 
 
+def test_shift_ensemble_character_identity_at_largest_n():
+    """n = 2^31 - 1, z = (1, 2, 4), h = (-2, 1, 0) in the dual lattice: each shifted rule is
+    cos(2 pi u + 2 pi h.Delta_r) exactly (eq. 2.3), and the statistics follow from those."""
+    n, d, R = 2147483647, 3, 9
+    z = qmc.korobov(d, n, 2)
+    shifts = np.random.default_rng(8).uniform(0, 1, (R, d))
+    u = 0.3125
+    h = np.array([-2.0, 1.0, 0.0])
+    params = np.concatenate([[u], 2 * math.pi * h])
+    expect = np.cos(2 * math.pi * u + 2 * math.pi * shifts @ h)
+    for precision, tol in ((qmc.FP64, 1e-9), (qmc.FP32_COMPENSATED, 1e-6)):
+        q, stats = qmc.lattice_sum_shifts(z, n, qmc.OSCILLATORY, params, shifts, precision)
+        q, stats = q.cpu().numpy(), stats.cpu().numpy()
+        assert np.max(np.abs(q - expect)) < tol, (precision, q, expect)
+        _check_stats_against_own_q(q, stats)
+
+
 def test_shift_ensemble_rejects_bad_shapes():
     z = qmc.korobov(3, 101, 7)
     with pytest.raises(qmc.QmcError):
