@@ -93,9 +93,10 @@ def uses_adjoint_sets(d: int, family: int, nsets: int) -> bool:
     return family in (0, 3) and d <= 64 and nsets >= 16
 
 
-# MDI-LR factor evaluation (Gaussian, FP32c): node, argument, square, exp2, FP64
-# accumulation.
-WORK_PER_MDI_FACTOR = 3 * C32 + CT + ACCUM
+# MDI-LR factor evaluation (Gaussian): the node recurrence phi_{t+1} = phi_t r_t,
+# r_{t+1} = r_t q and the accumulation, two FP64 multiplies and one FP64 add per
+# node (the exp2 seeds of each run of nodes are not counted).
+WORK_PER_MDI_FACTOR = 3 * C64
 
 # MDI-LR of g(sum x), power g, QMC_FP32_COMPENSATED, per merged-state evaluation of
 # g (FP64 operations): the node and b + c s (2); log2 by the atanh series (22: the

@@ -293,6 +293,26 @@ def test_mdi_lr_ragged_nodes_and_families(precision, family):
 
 
 @pytest.mark.parametrize("precision", PRECS)
+def test_mdi_lr_gaussian_wide_and_narrow_in_one_launch(precision):
+    """Gaussian sets from wide (c = 0.1) to narrow (c = 80) in one launch: factors whose
+    node values all stay above 2^-1000 are summed by the multiplicative node recurrence,
+    the others node by node, and lanes of one wave take either branch."""
+    rng = np.random.default_rng(21)
+    d, nsets = 4, 200
+    N = np.array([64, 17, 64, 100], np.int32)
+    c = np.exp(rng.uniform(math.log(0.1), math.log(80.0), (nsets, d)))
+    w = rng.uniform(-0.2, 1.2, (nsets, d))
+    params = np.concatenate([c, w], axis=1)
+    q = qmc.mdi_lr(N, qmc.GAUSSIAN, params, precision).cpu().numpy()
+    for s in range(nsets):
+        qo = O.mdi_lr(N.astype(np.int64), O.GAUSSIAN, params[s])
+        if qo == 0.0:
+            assert q[s] == 0.0, s
+        else:
+            assert abs(q[s] - qo) <= TOL[precision] * abs(qo), (s, q[s], qo)
+
+
+@pytest.mark.parametrize("precision", PRECS)
 def test_mdi_lr_exp_quadratic_growing_factors(precision):
     """Signed quadratic with large positive weights: the largest nodes dominate each
     factor (e^24 against 1), so the FP32c sweep must form the argument in double."""
@@ -309,7 +329,7 @@ def test_mdi_lr_test7_f5(precision, d, N):
     """Test 7's f_5 = exp(sum_j (-1)^{j+1} x_j^2) at the node counts of its timing runs.
     Its directions come in two identical kinds, so the FP32 rounding of each factor is
     the same in every direction of a kind and adds up linearly over d: QMC_FP32_COMPENSATED
-    is held to 1e-8 per direction here (measured: 4.7e-9) instead of 1e-6 overall."""
+    is held to 1e-8 per direction here (measured: 1.4e-9) instead of 1e-6 overall."""
     p = np.concatenate([[(-1.0) ** j for j in range(d)], np.zeros(d)])
     q = float(qmc.mdi_lr(np.full(d, N, np.int32), qmc.EXP_QUADRATIC, p, precision).item())
     qo = O.mdi_lr(np.full(d, N), O.EXP_QUADRATIC, p)
