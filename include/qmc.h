@@ -85,8 +85,9 @@ typedef enum {
  * Its relative error against the FP64 rule is reported by the tests and the
  * benchmark for every workload (target <= 1e-6).  In the MDI-LR product the FP32
  * error of one factor repeats in every direction with the same parameters, so for
- * inputs with many identical directions it grows linearly in d (Test 7's f_5:
- * about 1.4e-9 per direction, 1.4e-6 at d = 1000); QMC_FP64 has no such growth. */
+ * inputs with many identical directions it can grow linearly in d; the Gaussian and
+ * signed-quadratic factors are summed in FP64 in both precisions (a node recurrence)
+ * and do not show it. */
 typedef enum { QMC_FP64 = 0, QMC_FP32_COMPENSATED = 1 } qmc_precision;
 
 /* How qmc_mdi_lr_dims obtains n for the Korobov lattice z(a) (Lemma 3.2, eq. 3.5). */

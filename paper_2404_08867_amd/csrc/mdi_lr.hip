@@ -28,26 +28,29 @@ struct MdiArgs {
     double* q_out;
 };
 
-// Sum over t = 0..Nk-1 of 2^{-y_t^2}, y_t = A t + B, by the exact recurrence of a
-// Gaussian on equispaced nodes: phi_{t+1} = phi_t r_t and r_{t+1} = r_t q with
-// r_t = 2^{-A (2 y_t + A)}, q = 2^{-2 A^2} -- two FP64 multiplies and one add per
-// node.  phi and r are recomputed with exp2 at every S-th node, which bounds the
-// compounded rounding of a run to S^2/2 units in the last place: S = 32 for QMC_FP64
-// (~1e-14 per factor), 64 for QMC_FP32_COMPENSATED (one run for N = 64).  The
-// recurrence is used only while every node value stays above 2^-1000 (max y^2 over
-// the nodes, taken at an end point, at most 1000), so no intermediate underflows;
-// otherwise each node is evaluated directly (FP32: FP64 argument, split FP32 exp2).
+// Sum over t = 0..Nk-1 of 2^{s y_t^2}, y_t = A t + B, s = -1 (a Gaussian) or +1 (a
+// growing factor of the signed quadratic), by the exact recurrence on equispaced
+// nodes: phi_{t+1} = phi_t r_t and r_{t+1} = r_t q with r_t = 2^{s A (2 y_t + A)},
+// q = 2^{2 s A^2} -- two FP64 multiplies and one add per node.  phi and r are
+// recomputed with exp2 at every S-th node, which bounds the compounded rounding of a
+// run to S^2/2 units in the last place: S = 8 for QMC_FP64 (< 1e-15 per factor, so
+// that a thousand identical directions stay within 1e-12), 64 for
+// QMC_FP32_COMPENSATED (one run for N = 64).  The recurrence is used only while
+// every node value, every ratio and q stay within 2^-1000..2^1000 (max y^2 over the
+// nodes, taken at an end point, and 2 A^2 at most 1000), so no intermediate value
+// underflows or overflows; otherwise each node is evaluated directly (FP32: FP64
+// argument, split FP32 exp2).
 template <bool FP32>
-__device__ __forceinline__ double gauss_node_sum(double A, double B, int Nk) {
-    constexpr int kGaussSeed = FP32 ? 64 : 32;
+__device__ __forceinline__ double quad_node_sum(double A, double B, int Nk, double s) {
+    constexpr int kSeed = FP32 ? 64 : 8;
     const double y_last = fma((double)(Nk - 1), A, B);
     double sr = 0.0;
-    if (fmax(B * B, y_last * y_last) <= 1000.0) {
-        const double q = exp2(-2.0 * A * A);
-        for (int t0 = 0; t0 < Nk; t0 += kGaussSeed) {
+    if (fmax(fmax(B * B, y_last * y_last), 2.0 * A * A) <= 1000.0) {
+        const double q = exp2(2.0 * s * A * A);
+        for (int t0 = 0; t0 < Nk; t0 += kSeed) {
             const double y = fma((double)t0, A, B);
-            double f = exp2(-y * y), r = exp2(-A * fma(2.0, y, A));
-            const int n1 = min(kGaussSeed, Nk - t0);
+            double f = exp2(s * y * y), r = exp2(s * A * fma(2.0, y, A));
+            const int n1 = min(kSeed, Nk - t0);
             sr += f;
 #pragma unroll 4
             for (int t = 1; t < n1; ++t) {
@@ -59,12 +62,12 @@ __device__ __forceinline__ double gauss_node_sum(double A, double B, int Nk) {
     } else if constexpr (FP32) {
         for (int t = 0; t < Nk; ++t) {
             const double y = fma((double)t, A, B);
-            sr += exp2_split_f32(-y * y);
+            sr += exp2_split_f32(s * y * y);
         }
     } else {
         for (int t = 0; t < Nk; ++t) {
             const double y = fma((double)t, A, B);
-            sr += exp2(-y * y);
+            sr += exp2(s * y * y);
         }
     }
     return sr;
@@ -93,30 +96,13 @@ __device__ __forceinline__ void direction_sum(const double* p, int d, int k, int
         // phi = 2^{-y^2}, y = c sqrt(log2 e) ((t + 1/2)/N - w) = A t + B
         const double c = p[k] * kSqrtLog2e, w = p[d + k];
         const double A = c * invN, B = c * fma(0.5, invN, -w);
-        sr = gauss_node_sum<FP32>(A, B, Nk);
+        sr = quad_node_sum<FP32>(A, B, Nk, -1.0);
     } else if constexpr (FAM == kExpQuadratic) {
         // phi = 2^{s y^2}, y = sqrt(|c| log2 e) ((t + 1/2)/N - w) = A t + B, s = sign(c)
         const double cq = p[k], w = p[d + k];
         const double m = sqrt(fabs(cq) * kLog2e);
         const double A = m * invN, B = m * fma(0.5, invN, -w);
-        if (cq < 0.0) {
-            sr = gauss_node_sum<FP32>(A, B, Nk);
-        } else if constexpr (FP32) {
-            // a growing factor: the largest nodes dominate the sum, so y and y^2 are
-            // formed in double (an FP32 y would carry a relative error of ~1e-7 y^2 into
-            // the exponent) and the integer part of y^2 is split off before the FP32 exp2
-            double td = 0.0;
-#pragma unroll 4
-            for (int t = 0; t < Nk; ++t, td += 1.0) {
-                const double y = fma(td, A, B);
-                sr += exp2_split_f32(y * y);
-            }
-        } else {
-            for (int t = 0; t < Nk; ++t) {
-                const double y = fma((double)t, A, B);
-                sr += exp2(y * y);
-            }
-        }
+        sr = quad_node_sum<FP32>(A, B, Nk, cq < 0.0 ? -1.0 : 1.0);
     } else if constexpr (FAM == kProductPeak) {
         // phi = 1 / (c^-2 + y^2), y = (t + 1/2)/N - w = A t + B
         const double c = p[k], w = p[d + k];
