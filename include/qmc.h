@@ -85,9 +85,10 @@ typedef enum {
  * Its relative error against the FP64 rule is reported by the tests and the
  * benchmark for every workload (target <= 1e-6).  In the MDI-LR product the FP32
  * error of one factor repeats in every direction with the same parameters, so for
- * inputs with many identical directions it can grow linearly in d; the Gaussian and
- * signed-quadratic factors are summed in FP64 in both precisions (a node recurrence)
- * and do not show it. */
+ * inputs with many identical directions it can grow linearly in d.  The exp-sum,
+ * Gaussian and signed-quadratic factors are summed by FP64 node recurrences and the
+ * product-peak reciprocals refined in FP64, so only the oscillatory family's FP32
+ * sin/cos can show it. */
 typedef enum { QMC_FP64 = 0, QMC_FP32_COMPENSATED = 1 } qmc_precision;
 
 /* How qmc_mdi_lr_dims obtains n for the Korobov lattice z(a) (Lemma 3.2, eq. 3.5). */

@@ -81,16 +81,21 @@ __device__ __forceinline__ void direction_sum(const double* p, int d, int k, int
     const double invN = 1.0 / (double)Nk;
     double sr = 0.0, si = 0.0;
     if constexpr (FAM == kExpSum) {
-        // phi = 2^{c log2e (t + 1/2)/N} = 2^{A t + B}
+        // phi = 2^{c log2e (t + 1/2)/N} = 2^{A t + B}: a geometric sequence, phi_{t+1} =
+        // phi_t 2^A, one FP64 multiply and one add per node in both precisions; phi is
+        // reseeded with exp2 every 64 nodes (the rounding of a run grows linearly).
         const double c = p[k] * kLog2e;
         const double A = c * invN, B = 0.5 * c * invN;
-        if constexpr (FP32) {
-            const float Af = (float)A, Bf = (float)B;
-            float tf = 0.0f;
+        const double R = exp2(A);
+        for (int t0 = 0; t0 < Nk; t0 += 64) {
+            double f = exp2(fma((double)t0, A, B));
+            const int n1 = min(64, Nk - t0);
+            sr += f;
 #pragma unroll 4
-            for (int t = 0; t < Nk; ++t, tf += 1.0f) sr += (double)__builtin_amdgcn_exp2f(fmaf(tf, Af, Bf));
-        } else {
-            for (int t = 0; t < Nk; ++t) sr += exp2(fma((double)t, A, B));
+            for (int t = 1; t < n1; ++t) {
+                f *= R;
+                sr += f;
+            }
         }
     } else if constexpr (FAM == kGaussian) {
         // phi = 2^{-y^2}, y = c sqrt(log2 e) ((t + 1/2)/N - w) = A t + B
@@ -108,12 +113,15 @@ __device__ __forceinline__ void direction_sum(const double* p, int d, int k, int
         const double c = p[k], w = p[d + k];
         const double g = 1.0 / (c * c), A = invN, B = fma(0.5, invN, -w);
         if constexpr (FP32) {
-            const float Af = (float)A, Bf = (float)B, gf = (float)g;
-            float tf = 0.0f;
+            // FP32 reciprocal refined by one Newton step in FP64 (relative error ~1e-15):
+            // an FP32 factor's rounding would repeat in every direction with the same
+            // parameters and grow linearly in d (3.4e-6 at d = 1000 for Table 2-3).
+            double td = 0.0;
 #pragma unroll 4
-            for (int t = 0; t < Nk; ++t, tf += 1.0f) {
-                const float y = fmaf(tf, Af, Bf);
-                sr += (double)__builtin_amdgcn_rcpf(fmaf(y, y, gf));
+            for (int t = 0; t < Nk; ++t, td += 1.0) {
+                const double y = fma(td, A, B), v = fma(y, y, g);
+                const double r = (double)__builtin_amdgcn_rcpf((float)v);
+                sr += fma(r, fma(-v, r, 1.0), r);
             }
         } else {
             for (int t = 0; t < Nk; ++t) {
