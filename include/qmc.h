@@ -87,8 +87,8 @@ typedef enum {
  * error of one factor repeats in every direction with the same parameters, so for
  * inputs with many identical directions it can grow linearly in d.  The exp-sum,
  * Gaussian and signed-quadratic factors are summed by FP64 node recurrences and the
- * product-peak reciprocals refined in FP64, so only the oscillatory family's FP32
- * sin/cos can show it. */
+ * product-peak reciprocals refined in FP64; the oscillatory family's FP32 sin/cos,
+ * and Gaussian factors too narrow for the recurrence, keep FP32 node values. */
 typedef enum { QMC_FP64 = 0, QMC_FP32_COMPENSATED = 1 } qmc_precision;
 
 /* How qmc_mdi_lr_dims obtains n for the Korobov lattice z(a) (Lemma 3.2, eq. 3.5). */
