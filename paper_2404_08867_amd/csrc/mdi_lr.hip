@@ -112,10 +112,14 @@ __device__ __forceinline__ void direction_sum(const double* p, int d, int k, int
         // phi = 1 / (c^-2 + y^2), y = (t + 1/2)/N - w = A t + B
         const double c = p[k], w = p[d + k];
         const double g = 1.0 / (c * c), A = invN, B = fma(0.5, invN, -w);
-        if constexpr (FP32) {
+        // v = g + y^2 lies in [g, g + max(B^2, y_last^2)] (y^2 is largest at an end node)
+        const double y_last = fma((double)(Nk - 1), A, B);
+        const bool f32_range = g >= 1e-36 && g + fmax(B * B, y_last * y_last) <= 1e36;
+        if (FP32 && f32_range) {
             // FP32 reciprocal refined by one Newton step in FP64 (relative error ~1e-15):
             // an FP32 factor's rounding would repeat in every direction with the same
-            // parameters and grow linearly in d (3.4e-6 at d = 1000 for Table 2-3).
+            // parameters and grow linearly in d (3.4e-6 at d = 1000 for Table 2-3).  Only
+            // where every denominator is a normal FP32 number.
             double td = 0.0;
 #pragma unroll 4
             for (int t = 0; t < Nk; ++t, td += 1.0) {

@@ -313,6 +313,25 @@ def test_mdi_lr_gaussian_wide_and_narrow_in_one_launch(precision):
 
 
 @pytest.mark.parametrize("precision", PRECS)
+def test_mdi_lr_product_peak_extreme_widths(precision):
+    """Product-peak factors whose denominators c^-2 + y^2 leave the normal FP32 range
+    (c = 1e-25: about 1e50; c = 1e25 with w on a node: down to 1e-50) are summed with FP64
+    divisions; ordinary ones in the same launch take the refined FP32 reciprocal."""
+    N = np.array([16, 16, 9], np.int32)
+    sets = [
+        [1e-25, 1.0, 2.0, 0.3, 0.7, 0.1],
+        [1e25, 0.5, 1.5, 0.5 / 16, 0.2, 0.9],
+        [3.0, 1e25, 1e-25, 0.4, 0.5 / 16, 0.6],
+        [1.1, 0.9, 2.0, 0.6, 0.6, 0.6],
+    ]
+    params = np.array(sets)
+    q = qmc.mdi_lr(N, qmc.PRODUCT_PEAK, params, precision).cpu().numpy()
+    for s in range(len(sets)):
+        qo = O.mdi_lr(N.astype(np.int64), O.PRODUCT_PEAK, params[s])
+        assert np.isfinite(q[s]) and abs(q[s] - qo) <= TOL[precision] * abs(qo), (s, q[s], qo)
+
+
+@pytest.mark.parametrize("precision", PRECS)
 def test_mdi_lr_exp_quadratic_growing_factors(precision):
     """Signed quadratic with large positive weights: the largest nodes dominate each
     factor (e^24 against 1), so the FP32c sweep must form the argument in double."""
