@@ -64,7 +64,7 @@ def work_per_point(d: int, family: int) -> int:
             per_dim = INDEX + C32 + 3 * C32
         else:
             per_dim = INDEX + C64 + 3 * C64
-    elif family == 2:  # Gaussian
+    elif family in (2, 4):  # Gaussian, exp of a signed quadratic (y, then s y^2 added)
         per_dim = INDEX + C64 + 2 * C64
     else:  # exp-sum, oscillatory
         per_dim = INDEX + C64 + C64
@@ -129,7 +129,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--workload", default="plain_d20_peak",
-                    choices=["plain_d20_peak", "plain_d4_expsum", "mdi_d100_gauss", "batched_4096",
+                    choices=["plain_d20_peak", "plain_d4_expsum", "plain_d20_f5", "mdi_d100_gauss", "batched_4096",
                              "adjoint_d50_osc", "shifts_d20_peak", "korobov_search_d20",
                              "cbc_d20", "mdi_sum_d100", "implr_d3"])
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
@@ -256,7 +256,8 @@ def time_graph(torch, launch, steps, warmup):
 
 
 def bench_plain(args, torch, qmc, W):
-    prob = W.plain_d20_peak() if args.workload == "plain_d20_peak" else W.plain_d4_expsum()
+    prob = {"plain_d20_peak": W.plain_d20_peak, "plain_d4_expsum": W.plain_d4_expsum,
+            "plain_d20_f5": W.plain_d20_f5}[args.workload]()
     z = torch.tensor(qmc.korobov(prob.d, prob.n, prob.a), device="cuda")
     params = torch.tensor(prob.params, dtype=torch.float64, device="cuda")
     ws = qmc.Workspace(qmc.workspace_size(prob.d, prob.n, 1))

@@ -15,7 +15,7 @@ from fixed seeds:
   * seed of workload k: ``2404088670 + k``;
   * draw order: a, then c, then w, then u.
 
-Workloads (k = 0..6):
+Workloads (k = 0..7):
   0 plain_d4_expsum      d=4,   n=1009,      exp-sum, c ~ U[0,1]
   1 plain_d20_peak       d=20,  n=1048573,   product-peak, c ~ U[0.5,2], w ~ U[0,1]
   2 mdi_d100_gauss       d=100, N=64 nodes per direction (a = N), Gaussian,
@@ -31,6 +31,8 @@ Workloads (k = 0..6):
                          power g(s) = (b + c s)^-p; set 0 is Test 7's f_6
                          (b = c = 1, p = d + 1), sets s >= 1 draw b ~ U[0.5,2],
                          c ~ U[0.5,1.5], p ~ U[1, d+1]
+  7 plain_d20_f5         d=20, n=1048573, Test 7's f_5 (exp of a signed quadratic,
+                         c = +-1 alternating, w = 0); only a is drawn
 Lattice constructions (no random draws):
     korobov_search_d20   e^2 of eq. 2.12 for z(a), d=20, n=65521 (the largest
                          prime below 2^16), product weights gamma_j = j^-2,
@@ -172,6 +174,16 @@ def plain_d20_peak() -> Plain:
     c = rng.uniform(0.5, 2.0, d)
     w = rng.uniform(0.0, 1.0, d)
     return Plain("plain_d20_peak", d, n, a, PRODUCT_PEAK, np.concatenate([c, w]))
+
+
+def plain_d20_f5() -> Plain:
+    """Test 7's f_5 = exp(sum_j (-1)^{j+1} x_j^2) on the plain_d20_peak lattice size, as
+    the exp of a signed quadratic (c = +1, -1, ..., w = 0); a from seed 7."""
+    rng = np.random.default_rng(SEED_BASE + 7)
+    n, d = 1048573, 20
+    a = int(rng.integers(2, n))
+    c = np.array([(-1.0) ** j for j in range(d)])
+    return Plain("plain_d20_f5", d, n, a, EXP_QUADRATIC, np.concatenate([c, np.zeros(d)]))
 
 
 def mdi_d100_gauss(nsets: int = 1) -> MdiSets:
