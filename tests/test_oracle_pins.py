@@ -189,6 +189,35 @@ def test_left_rectangle_geometric_sum(n, c):
     assert q == pytest.approx(expect, rel=1e-13)
 
 
+@pytest.mark.parametrize("n,c,i0,m", [(1, 0.7, 0, 1), (7, 1.3, 2, 4), (1009, 0.25, 0, 1009),
+                                       (1009, -0.8, 500, 1), (65537, -2.0, 1234, 40000)])
+def test_partial_sum_geometric_closed_form(n, c, i0, m):
+    """d = 1, z = 1: the indices i0 .. i0+m-1 (< n) are their own residues, so the
+    partial sum of e^{c k/n} is e^{c i0/n} (e^{c m/n} - 1) / (e^{c/n} - 1)."""
+    s = O.lattice_partial([1 % n], n, O.EXP_SUM, [c], i0, m)
+    expect = math.exp(c * i0 / n) * math.expm1(c * m / n) / math.expm1(c / n)
+    assert s == pytest.approx(expect, rel=1e-13)
+
+
+@pytest.mark.parametrize("family", [0, 1, 2, 3, 4])
+@pytest.mark.parametrize("shifted", [False, True])
+def test_partial_sums_over_a_split_add_up(family, shifted):
+    """Partial sums over any split of [0, n) add up to n Q of the full rule; the
+    whole range is the full rule's own sum (the same additions in the same order)."""
+    p = W.random_plain(40 + family, family, 5, 4099, shift=shifted)
+    z = O.korobov(p.d, p.n, p.a)
+    q, a = O.lattice_sum(z, p.n, p.family, p.params, p.shift)
+    cuts = np.sort(np.random.default_rng(family).choice(np.arange(1, p.n), 6, replace=False))
+    edges = [0, *cuts.tolist(), p.n]
+    parts = [O.lattice_partial(z, p.n, p.family, p.params, lo, hi - lo, p.shift)
+             for lo, hi in zip(edges[:-1], edges[1:])]
+    assert math.fsum(parts) == pytest.approx(p.n * q, abs=1e-14 * p.n * a)
+    assert O.lattice_partial(z, p.n, p.family, p.params, 0, p.n, p.shift) / p.n == q
+    assert O.lattice_partial(z, p.n, p.family, p.params, 17, 0, p.shift) == 0.0
+    with pytest.raises(ValueError):
+        O.lattice_partial(z, p.n, p.family, p.params, p.n - 3, 4, p.shift)
+
+
 @pytest.mark.parametrize("N", [1, 2, 5, 64, 1000])
 def test_midpoint_closed_forms(N):
     """M = (1/N) sum_s e^{c (s+1/2)/N} = (e^c - 1) / (2 N sinh(c / 2N)); the complex
