@@ -749,8 +749,8 @@ hipError_t launch_adjoint(const AdjLaunch& L, hipStream_t stream) {
             case kExpQuadratic:
                 return launch_adj_f<kExpQuadratic, true, AdjFam<kExpQuadratic, true>>(L, stream);
             case kProductPeak:
-                if (L.d <= kPeakF32MaxDims)
-                    return launch_adj_f<kProductPeak, true, AdjPeak<ProductPeak<true, true>>>(L, stream);
+                // double-precision factors (FP32 reciprocal per point): the FP32 factors'
+                // per-direction rounding would bias the gradient sums as it biases Q
                 return launch_adj_f<kProductPeak, true, AdjPeak<ProductPeak<false, true>>>(L, stream);
         }
     } else {

@@ -33,9 +33,12 @@ enum FamilyId {
     kGaussian = 2,
     kOscillatory = 3,
     kExpQuadratic = 4,
-    // Internal: the Bernoulli product sums behind the lattice-quality criteria.
+    // Internal: the Bernoulli product sums behind the lattice-quality criteria
+    // (weights a_j; the S forms also multiply the sum by the parameter a_d).
     kBernoulli2 = 16,
     kBernoulli4 = 17,
+    kBernoulli2S = 18,
+    kBernoulli4S = 19,
 };
 
 // exp2 of a double argument: split off the nearest integer in double, take the
@@ -220,13 +223,19 @@ __device__ __forceinline__ int peak_pow4(double c) {
     return __builtin_amdgcn_frexp_exp(q) >> 1;
 }
 
-// FP32_DIMS: per-direction factors in single precision (7 VALU ops per point and
-// direction).  Their constants a, b, g are rounded to FP32 once per direction, a
-// bias that is the same for every point and grows like sqrt(d) * 2^-24 over the
-// product; the launcher therefore uses single-precision factors only for
-// d <= kPeakF32MaxDims and double-precision factors beyond.
+// FP32_DIMS: per-direction factors in single precision (6 VALU ops per point and
+// direction with the exact-float index step).  Their constants a, b, g are rounded to
+// FP32 once per direction: a bias that is the same for every point of the direction,
+// so over the product it does not average out but grows like sqrt(d) * 2^-24 (up to
+// ~5e-7 at d = 64 for c_j in [1/2, 2]).  The launchers therefore take single-precision
+// factors only for d <= kPeakF32MaxDims, and the kernels themselves fall back to the
+// double-precision factors for the whole problem unless every direction passes
+// fp32_dim_ok: |c_j| <= kPeakF32MaxC (the rounding of the coordinate's offset moves a
+// factor by up to 2^-23 |c_j| of itself near its peak) and a factor range that keeps a
+// run of kRenorm = 16 factors well inside the FP32 exponent range.
 // FP32_FINISH: the per-point reciprocal by v_rcp_f32 instead of an IEEE divide.
-constexpr int kPeakF32MaxDims = 64;
+constexpr int kPeakF32MaxDims = 32;
+constexpr double kPeakF32MaxC = 4.0;
 
 template <bool FP32_DIMS, bool FP32_FINISH>
 struct ProductPeak {
@@ -240,6 +249,20 @@ struct ProductPeak {
     };
     static constexpr int kRenorm = FP32_DIMS ? 16 : 64;
     static constexpr bool kBlockTerms = true;
+    // The FP32-factor form runs only where every direction passes fp32_dim_ok; the
+    // double-precision factors serve the other problems (same scale, same constants).
+    static constexpr bool kGuarded = FP32_DIMS;
+    using Fallback = ProductPeak<false, FP32_FINISH>;
+    __device__ static bool fp32_dim_ok(const double* p, int d, int j) {
+        const double c = fabs(p[j]), w = p[d + j];
+        if (!(c > 0.0 && c <= kPeakF32MaxC)) return false;
+        const double s2 = ldexp(1.0, -2 * peak_pow4(c));
+        const double ymax = fmax(fabs(w), fabs(1.0 - w));  // |x - w| for x in [0, 1]
+        const double lo = s2 / (c * c), hi = s2 * (1.0 / (c * c) + ymax * ymax);
+        // a factor in [2^-7, 2^7]: 16 of them stay within 2^+-112 of the renormalised
+        // mantissa, inside FP32's normal range
+        return lo >= 0x1p-7 && hi <= 0x1p7;
+    }
     __device__ static void block_terms(const double* p, int d, int j, double, double, double&,
                                        double&, int& ie) {
         (void)d;
@@ -293,7 +316,9 @@ struct ProductPeak {
 // With y = x (1 - x):  B_2(x) = 1/6 - y  and  B_4(x) = y^2 - 1/30, so a factor is
 // one FMA on y: (1 + a/6) - a y, or (1 - a/30) + (a y) y.  Criteria are small
 // differences of O(1) terms, so everything runs in FP64 in both precisions.
-template <int ALPHA>
+// SCALED (internal criteria): the parameter row holds a_0 .. a_{d-1} and then a
+// positive constant C that multiplies the sum (eq. 2.12's prod_j (1 + gamma_j beta)).
+template <int ALPHA, bool SCALED = false>
 struct BernoulliProduct {
     struct Dim {
         double inv_n, off, a, c0;  // x = k inv_n + off; factor constant c0
@@ -305,6 +330,7 @@ struct BernoulliProduct {
     static constexpr bool kBlockTerms = false;
     // B_alpha(1 - x) = B_alpha(x) for even alpha.
     static constexpr bool kMirror = true;
+    static constexpr bool kParamScale = SCALED;
     __device__ static void block_terms(const double*, int, int, double, double, double&, double&,
                                        int&) {}
     __device__ static double extra(const double*) { return 0.0; }

@@ -32,6 +32,25 @@ struct mirror_family : std::false_type {};
 template <class F>
 struct mirror_family<F, std::void_t<decltype(F::kMirror)>> : std::bool_constant<F::kMirror> {};
 
+// Families whose result is multiplied by the parameter after the d weights
+// (F::kParamScale): p[d] scales the sum.
+template <class F, class = void>
+struct param_scaled : std::false_type {};
+template <class F>
+struct param_scaled<F, std::void_t<decltype(F::kParamScale)>> : std::bool_constant<F::kParamScale> {};
+
+// Families whose single-precision form is valid only for some parameters
+// (F::kGuarded): F::fp32_dim_ok decides per direction, and a problem with any
+// direction that fails is evaluated by F::Fallback (same constants and scale).
+template <class F, class = void>
+struct guarded_family : std::false_type {
+    using fallback_dim = char;
+};
+template <class F>
+struct guarded_family<F, std::void_t<decltype(F::kGuarded)>> : std::bool_constant<F::kGuarded> {
+    using fallback_dim = typename F::Fallback::Dim;
+};
+
 // A problem as seen by the device: lattice, shift and one parameter row.
 struct ProblemView {
     int d;
@@ -82,6 +101,9 @@ struct TileShared {
     float2 stf[kDimChunk];            // the same as exact floats (n <= kFloatIndexMaxN)
     uint32_t sh[kDimChunk];           // whole part of the shift
     typename F::Dim c[kDimChunk];     // family constants
+    // guarded families: the fallback's constants and whether the problem needs them
+    typename guarded_family<F>::fallback_dim c2[guarded_family<F>::value ? kDimChunk : 1];
+    int use_fallback;
 };
 
 // Workgroup constants of a problem: sums over all directions in a fixed order.
@@ -172,14 +194,16 @@ __device__ __forceinline__ void fill_tile(const ProblemView& v, TileShared<F, B>
 // the direction tables (fill_dims) and the tile's start residues (fill_tile) in s.
 // FI (families with kFloatIndex, n <= kFloatIndexMaxN): the thread's M indices
 // of a direction are stepped as exact floats (stepmod_f), converted once.
-template <class F, int M, int B, bool FI = false>
-__device__ __forceinline__ void chunk_points(typename F::Acc (&acc)[M], const TileShared<F, B>& s, int j0,
-                                             int dc, uint32_t n) {
+// `dims` holds F's constants of the chunk's directions (the tables' own c, or the
+// fallback constants c2 of a guarded family).
+template <class F, int M, int B, bool FI = false, class S>
+__device__ __forceinline__ void chunk_points(typename F::Acc (&acc)[M], const S& s,
+                                             const typename F::Dim* dims, int j0, int dc, uint32_t n) {
     using Dim = typename F::Dim;
     const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
     for (int jj = 0; jj < dc; ++jj) {
         uint32_t k = addmod(s.kw[jj * (B / kWave) + wv], s.lz[jj * kWave + lane], n);
-        const Dim c = s.c[jj];
+        const Dim c = dims[jj];
         if constexpr (FI) {
             const float2 stp = s.stf[jj];
             float kf = (float)k;
@@ -245,7 +269,7 @@ __device__ __forceinline__ double tile_points(const ProblemView& v, TileShared<F
         __syncthreads();
         fill_tile<F, M, B>(v, s, j0, dc, tile_base);
         __syncthreads();
-        chunk_points<F, M, B, FI>(acc, s, j0, dc, v.n);
+        chunk_points<F, M, B, FI>(acc, s, s.c, j0, dc, v.n);
     }
     return finish_points<F, M, MIRROR>(acc, tile_base, v.n);
 }
@@ -266,6 +290,8 @@ __device__ __forceinline__ void setup_one_chunk(const ProblemView& v, TileShared
     if (tid < kWave) {
         double t0 = 0.0, t1 = 0.0;
         int te = 0;
+        bool bad = false;  // a direction the guarded family's FP32 form cannot take
+        (void)bad;
         if (tid < d) {
             const int j = tid;
             uint32_t whole;
@@ -278,6 +304,14 @@ __device__ __forceinline__ void setup_one_chunk(const ProblemView& v, TileShared
                 s.stf[j] = make_float2((float)st, (float)st - (float)v.n);
             s.sh[j] = whole;
             s.c[j] = F::dim(v.p, d, j, v.inv_n, frac);
+            if constexpr (guarded_family<F>::value) {
+                s.c2[j] = F::Fallback::dim(v.p, d, j, v.inv_n, frac);
+                bad = !F::fp32_dim_ok(v.p, d, j);
+            }
+        }
+        if constexpr (guarded_family<F>::value) {
+            const bool any_bad = __builtin_amdgcn_ballot_w64(bad) != 0;
+            if (tid == 0) s.use_fallback = any_bad ? 1 : 0;
         }
         if constexpr (F::kBlockTerms) {
             const double x = wave_total(t0), y = wave_total(t1), w = wave_total((double)te);
@@ -321,10 +355,20 @@ __device__ __forceinline__ double tile_points_one_chunk(const ProblemView& v, Ti
         fill_tile<F, M, B>(v, s, 0, v.d, tile_base);
         __syncthreads();
     }
+    if constexpr (guarded_family<F>::value) {
+        if (s.use_fallback) {
+            using FB = typename F::Fallback;
+            typename FB::Acc acc[M];
+#pragma unroll
+            for (int m = 0; m < M; ++m) acc[m] = FB::init(init0);
+            chunk_points<FB, M, B, false>(acc, s, s.c2, 0, v.d, v.n);
+            return finish_points<FB, M, MIRROR>(acc, tile_base, v.n);
+        }
+    }
     typename F::Acc acc[M];
 #pragma unroll
     for (int m = 0; m < M; ++m) acc[m] = F::init(init0);
-    chunk_points<F, M, B, FI>(acc, s, 0, v.d, v.n);
+    chunk_points<F, M, B, FI>(acc, s, s.c, 0, v.d, v.n);
     return finish_points<F, M, MIRROR>(acc, tile_base, v.n);
 }
 

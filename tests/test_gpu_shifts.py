@@ -104,7 +104,7 @@ def test_shift_ensemble_character_identity_at_largest_n():
     h = np.array([-2.0, 1.0, 0.0])
     params = np.concatenate([[u], 2 * math.pi * h])
     expect = np.cos(2 * math.pi * u + 2 * math.pi * shifts @ h)
-    for precision, tol in ((qmc.FP64, 1e-9), (qmc.FP32_COMPENSATED, 1e-6)):
+    for precision, tol in ((qmc.FP64, 1e-12), (qmc.FP32_COMPENSATED, 1e-6)):
         q, stats = qmc.lattice_sum_shifts(z, n, qmc.OSCILLATORY, params, shifts, precision)
         q, stats = q.cpu().numpy(), stats.cpu().numpy()
         assert np.max(np.abs(q - expect)) < tol, (precision, q, expect)
