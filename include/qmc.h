@@ -43,8 +43,8 @@
  *       valid family and precision.  z_j in [0, n) and Delta_j in [0, 1) are the
  *       caller's contract for device arrays (not read back on the host).
  *   - Debug mode: with QMC_VALIDATE=1 in the environment, the entry points that take
- *     z or shift arrays (the plain sum, its shifts and adjoint, the Bernoulli sums,
- *     the point export, batch plan creation) read them back on their stream
+ *     z, shift, gamma or N arrays (the plain sum, its shifts and adjoint, the criteria,
+ *     the point export, batch plan creation, MDI-LR) read them back on their stream
  *     (synchronously, into host buffers) and return QMC_ERR_INVALID_ARG for an entry
  *     out of range, before launching anything.  While the stream is being captured
  *     into a graph the read-back is skipped.
@@ -246,6 +246,9 @@ qmc_status qmc_implr_points(int32_t d, int64_t n, int64_t a, int64_t j0, int64_t
  *   the squared shift-averaged worst-case error of eq. 2.12 with product weights
  *   gamma_j is prod_j (1 + gamma_j beta) * S with a_j = gamma_j / (1 + gamma_j beta)
  *   (beta = c^2 - c + 1/3 for the anchored space with anchor c, 0 unanchored).
+ * The library derives the weights a_j and the factor prod_j (1 + gamma_j beta) on the
+ * device: qmc_p_alpha, qmc_shift_avg_wce2, qmc_korobov_search and qmc_cbc return the
+ * criteria themselves; qmc_bernoulli_sum returns S for weights the caller chooses.
  * Everything runs in FP64: criteria are small differences of O(1) terms.
  * The terms of k and n - k are equal (the points are mirror images and
  * B_alpha(1 - x) = B_alpha(x)), so the device evaluates k <= n/2 only, with
@@ -255,8 +258,38 @@ qmc_status qmc_implr_points(int32_t d, int64_t n, int64_t a, int64_t j0, int64_t
  * with gcd(c, n) != 1 get +infinity.  Values beyond the FP64 range (products that
  * overflow for large d and weights) come out as +-infinity or NaN. */
 
-/* Workspace bytes of qmc_bernoulli_sum, qmc_korobov_search and qmc_cbc at d, n. */
+/* Which criterion a search or construction minimises. */
+typedef enum {
+    QMC_CRIT_P_ALPHA = 0, /* P_alpha of eq. 2.4 (alpha = 2 or 4; gamma and beta unused)      */
+    QMC_CRIT_WCE2 = 1     /* e^2 of eq. 2.12 with product weights gamma_j and beta (alpha 2) */
+} qmc_criterion_kind;
+
+typedef struct {
+    int32_t kind;          /* qmc_criterion_kind */
+    int32_t alpha;         /* QMC_CRIT_P_ALPHA: 2 or 4; ignored by QMC_CRIT_WCE2 */
+    const double* gamma;   /* QMC_CRIT_WCE2: device double[d], finite gamma_j >= 0 (caller's
+                              contract; read back and checked under QMC_VALIDATE) */
+    double beta;           /* QMC_CRIT_WCE2: finite beta >= 0 */
+} qmc_criterion;
+
+/* Workspace bytes of the criteria entry points (qmc_bernoulli_sum, qmc_p_alpha,
+ * qmc_shift_avg_wce2, qmc_korobov_search, qmc_cbc) at d, n. */
 qmc_status qmc_criteria_workspace_size(int32_t d, int64_t n, size_t* bytes);
+
+/* P_alpha(z) of eq. 2.4 for nz generating vectors (rows of z), two launches.
+ *   z      device int64[nz][d], 0 <= z_j < n;  nz in [1, 4096];  n in [2, 2^31)
+ *   alpha  2 or 4
+ *   p_out  device double[nz]
+ *   ws     device workspace of qmc_criteria_workspace_size(d, n) bytes
+ * Errors: QMC_ERR_INVALID_ARG (ranges, NULL pointers), QMC_ERR_WORKSPACE. */
+qmc_status qmc_p_alpha(int32_t d, int64_t n, const int64_t* z, int32_t nz, int32_t alpha, double* p_out,
+                       void* ws, size_t ws_bytes, void* stream);
+
+/* e^2(z) of eq. 2.12 (squared worst-case error averaged over shifts, product
+ * weights gamma_j, beta as above) for nz generating vectors, two launches.
+ *   gamma   device double[d];  beta finite, >= 0;  other arguments as qmc_p_alpha */
+qmc_status qmc_shift_avg_wce2(int32_t d, int64_t n, const int64_t* z, int32_t nz, const double* gamma,
+                              double beta, double* e2_out, void* ws, size_t ws_bytes, void* stream);
 
 /* S for nz generating vectors (rows of z) in one launch.
  *   z      device int64[nz][d], 0 <= z_j < n;  nz in [1, 4096];  n in [2, 2^31)
@@ -267,27 +300,29 @@ qmc_status qmc_bernoulli_sum(int32_t d, int64_t n, const int64_t* z, int32_t nz,
                              const double* a, double* s_out, void* ws, size_t ws_bytes,
                              void* stream);
 
-/* Korobov search (Sec. 2.2): S(z(a)) for the Korobov vectors
+/* Korobov search (Sec. 2.2): the criterion of the Korobov vectors
  * z(a) = (1, a, ..., a^{d-1}) mod n of a = a0 .. a0 + count - 1 (1 <= a0,
- * a0 + count <= n), and the best: best_out[0] = S, best_out[1] = a (as a double).
- * The search is O(count * n * d / 2) work; it is asynchronous like every launch.
- *   s_out     device double[count]
+ * a0 + count <= n), and the best: best_out[0] = its criterion, best_out[1] = a (as a
+ * double).  The search is O(count * n * d / 2) work; it is asynchronous like every launch.
+ *   crit      host descriptor (copied at the call; gamma stays a device array)
+ *   s_out     device double[count]: P_alpha or e^2 of each candidate
  *   best_out  device double[2]
  *   ws        device workspace of qmc_criteria_workspace_size(d, n) bytes */
-qmc_status qmc_korobov_search(int32_t d, int64_t n, int32_t alpha, const double* a, int64_t a0,
+qmc_status qmc_korobov_search(int32_t d, int64_t n, const qmc_criterion* crit, int64_t a0,
                               int32_t count, double* s_out, double* best_out, void* ws,
                               size_t ws_bytes, void* stream);
 
-/* CBC construction (Sec. 2.2, CBC lattice; product weights): z_1 = 1, then for
- * j = 2..d the z_j in {1 <= c <= n/2 : gcd(c, n) = 1} minimising S of (z_1..z_j)
- * with weights a_1..a_j (which minimises e^2 of eq. 2.12 when a_j = gamma_j /
- * (1 + gamma_j beta)).  s_out[j-1] is S of the chosen (z_1..z_j).  O(d n^2 / 4) work,
- * 3 launches per component, all on `stream`.
+/* CBC construction (Sec. 2.2, CBC lattice): z_1 = 1, then for j = 2..d the z_j in
+ * {1 <= c <= n/2 : gcd(c, n) = 1} minimising the criterion of (z_1..z_j) (e^2 of
+ * eq. 2.12 with the weights gamma_1..gamma_j, or P_alpha of eq. 2.4).
+ * s_out[j-1] is that criterion of the chosen (z_1..z_j).  O(d n^2 / 4) work,
+ * 3 launches per component plus one, all on `stream`.
+ *   crit    host descriptor, as qmc_korobov_search
  *   n       in [2, 2^26]
  *   z_out   device int64[d]
  *   s_out   device double[d]
  *   ws      device workspace of qmc_criteria_workspace_size(d, n) bytes */
-qmc_status qmc_cbc(int32_t d, int64_t n, int32_t alpha, const double* a, int64_t* z_out,
+qmc_status qmc_cbc(int32_t d, int64_t n, const qmc_criterion* crit, int64_t* z_out,
                    double* s_out, void* ws, size_t ws_bytes, void* stream);
 
 /* Launch configuration of the plain-sum kernel.  Zero fields mean "choose
@@ -319,8 +354,11 @@ qmc_status qmc_lattice_points(int32_t d, int64_t n, const int64_t* z, int64_t i0
  * the dimension sweep of a product-form integrand (the oscillatory family is the
  * real part of a complex product with the factor e^{2 pi i u}).  Each sweep step
  * sums one direction out of the symbolic product, as eq. 2.14c does.
- *   N       device int32[d], 1 <= N_k <= 2^20 (e.g. from qmc_mdi_lr_dims); values
- *           outside that range are clamped into it on the device
+ *   N       device int32[d] node counts (e.g. from qmc_mdi_lr_dims, copied to the
+ *           device).  1 <= N_k <= 2^20 is the caller's contract, like z_j in [0, n):
+ *           with QMC_VALIDATE=1 the call reads N back and returns QMC_ERR_INVALID_ARG
+ *           for an entry outside it; otherwise such an entry makes q_out NaN for
+ *           every set (it is never clamped to a valid count).
  *   nsets   1 .. 2^24 parameter sets (one launch; no workspace is used)
  *   params  device double[nsets][qmc_param_count(family, d)]
  *   q_out   device double[nsets] */

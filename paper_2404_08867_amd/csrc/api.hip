@@ -42,18 +42,18 @@ qmc_status from_hip(hipError_t e, const char* where) {
 // on the call's stream -- synchronously, after the work already queued there -- and
 // checked before anything is launched.  A stream that is being captured into a
 // graph cannot be synchronised, so there the check is skipped.
-static bool validate_mode() {
+bool validate_mode() {
     const char* v = getenv("QMC_VALIDATE");
     return v && v[0] == '1';
 }
 
-static bool capturing(hipStream_t stream) {
+bool capturing(hipStream_t stream) {
     hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
     return hipStreamIsCapturing(stream, &st) == hipSuccess && st != hipStreamCaptureStatusNone;
 }
 
 template <class T>
-static qmc_status read_back(const T* dev, size_t count, hipStream_t stream, std::vector<T>& host, const char* what) {
+qmc_status read_back(const T* dev, size_t count, hipStream_t stream, std::vector<T>& host, const char* what) {
     host.resize(count);
     hipError_t e = hipMemcpyAsync(host.data(), dev, count * sizeof(T), hipMemcpyDeviceToHost, stream);
     if (e == hipSuccess) e = hipStreamSynchronize(stream);
@@ -403,6 +403,57 @@ static qmc_status check_criteria(int32_t d, int64_t n, int32_t alpha, const doub
     return QMC_OK;
 }
 
+// gamma_j >= 0 (device) is the caller's contract, read back under QMC_VALIDATE.
+static qmc_status validate_gamma(const double* gamma, int32_t d, void* stream, const char* what) {
+    if (!qmc::validate_mode() || qmc::capturing((hipStream_t)stream)) return QMC_OK;
+    std::vector<double> h;
+    qmc_status s = qmc::read_back(gamma, (size_t)d, (hipStream_t)stream, h, what);
+    if (s != QMC_OK) return s;
+    for (int32_t j = 0; j < d; ++j)
+        if (!(h[j] >= 0.0 && h[j] < INFINITY))
+            return fail(QMC_ERR_INVALID_ARG, "%s: gamma[%d] = %g is not a finite weight >= 0 (QMC_VALIDATE)",
+                        what, j, h[j]);
+    return QMC_OK;
+}
+
+// A criterion descriptor: P_alpha (alpha 2 or 4) or e^2 (gamma non-NULL, beta >= 0).
+static qmc_status check_criterion(int32_t d, int64_t n, const qmc_criterion* c, void* stream, const char* what,
+                                  qmc::CriterionSpec* out) {
+    if (d < 1 || d > kMaxD) return fail(QMC_ERR_INVALID_ARG, "d = %d outside [1, %d]", d, kMaxD);
+    if (n < 2 || n >= kMaxN) return fail(QMC_ERR_INVALID_ARG, "n = %lld outside [2, 2^31)", (long long)n);
+    if (!c) return fail(QMC_ERR_INVALID_ARG, "criterion must be non-NULL");
+    if (c->kind == QMC_CRIT_P_ALPHA) {
+        if (c->alpha != 2 && c->alpha != 4)
+            return fail(QMC_ERR_INVALID_ARG, "alpha = %d is not 2 or 4", c->alpha);
+        *out = qmc::CriterionSpec{qmc::kCritPAlpha, c->alpha, nullptr, 0.0};
+        return QMC_OK;
+    }
+    if (c->kind == QMC_CRIT_WCE2) {
+        if (!c->gamma) return fail(QMC_ERR_INVALID_ARG, "gamma must be non-NULL for QMC_CRIT_WCE2");
+        if (!(c->beta >= 0.0 && c->beta < INFINITY))
+            return fail(QMC_ERR_INVALID_ARG, "beta = %g is not finite and >= 0", c->beta);
+        qmc_status s = validate_gamma(c->gamma, d, stream, what);
+        if (s != QMC_OK) return s;
+        *out = qmc::CriterionSpec{qmc::kCritWce2, 2, c->gamma, c->beta};
+        return QMC_OK;
+    }
+    return fail(QMC_ERR_INVALID_ARG, "unknown criterion kind %d", c->kind);
+}
+
+static qmc_status criterion_values(int32_t d, int64_t n, const int64_t* z, int32_t nz, const qmc_criterion* crit,
+                                   double* out, void* ws, size_t ws_bytes, void* stream, const char* what) {
+    qmc::CriterionSpec spec{};
+    qmc_status s = check_criterion(d, n, crit, stream, what, &spec);
+    if (s != QMC_OK) return s;
+    if (nz < 1 || nz > kMaxSets) return fail(QMC_ERR_INVALID_ARG, "nz = %d outside [1, %d]", nz, kMaxSets);
+    if (!z || !out) return fail(QMC_ERR_INVALID_ARG, "z and the output must be non-NULL");
+    s = check_workspace(ws, ws_bytes, qmc::criteria_workspace_bytes(d, n));
+    if (s != QMC_OK) return s;
+    if ((s = validate_z(z, (size_t)nz * (size_t)d, n, stream, what)) != QMC_OK) return s;
+    qmc::CriterionLaunch L{d, (uint32_t)n, z, nz, spec, out, ws};
+    return from_hip(qmc::launch_criterion(L, (hipStream_t)stream), what);
+}
+
 qmc_status qmc_bernoulli_sum(int32_t d, int64_t n, const int64_t* z, int32_t nz, int32_t alpha,
                              const double* a, double* s_out, void* ws, size_t ws_bytes,
                              void* stream) {
@@ -417,10 +468,23 @@ qmc_status qmc_bernoulli_sum(int32_t d, int64_t n, const int64_t* z, int32_t nz,
     return from_hip(qmc::launch_bernoulli_sum(L, (hipStream_t)stream), "qmc_bernoulli_sum");
 }
 
-qmc_status qmc_korobov_search(int32_t d, int64_t n, int32_t alpha, const double* a, int64_t a0,
+qmc_status qmc_p_alpha(int32_t d, int64_t n, const int64_t* z, int32_t nz, int32_t alpha, double* p_out,
+                       void* ws, size_t ws_bytes, void* stream) {
+    const qmc_criterion c{QMC_CRIT_P_ALPHA, alpha, nullptr, 0.0};
+    return criterion_values(d, n, z, nz, &c, p_out, ws, ws_bytes, stream, "qmc_p_alpha");
+}
+
+qmc_status qmc_shift_avg_wce2(int32_t d, int64_t n, const int64_t* z, int32_t nz, const double* gamma,
+                              double beta, double* e2_out, void* ws, size_t ws_bytes, void* stream) {
+    const qmc_criterion c{QMC_CRIT_WCE2, 2, gamma, beta};
+    return criterion_values(d, n, z, nz, &c, e2_out, ws, ws_bytes, stream, "qmc_shift_avg_wce2");
+}
+
+qmc_status qmc_korobov_search(int32_t d, int64_t n, const qmc_criterion* crit, int64_t a0,
                               int32_t count, double* s_out, double* best_out, void* ws,
                               size_t ws_bytes, void* stream) {
-    qmc_status s = check_criteria(d, n, alpha, a);
+    qmc::CriterionSpec spec{};
+    qmc_status s = check_criterion(d, n, crit, stream, "qmc_korobov_search", &spec);
     if (s != QMC_OK) return s;
     if (a0 < 1 || count < 1 || a0 + (int64_t)count > n)
         return fail(QMC_ERR_INVALID_ARG, "candidates [%lld, %lld) outside [1, n)", (long long)a0,
@@ -428,19 +492,20 @@ qmc_status qmc_korobov_search(int32_t d, int64_t n, int32_t alpha, const double*
     if (!s_out || !best_out) return fail(QMC_ERR_INVALID_ARG, "s_out and best_out must be non-NULL");
     s = check_workspace(ws, ws_bytes, qmc::criteria_workspace_bytes(d, n));
     if (s != QMC_OK) return s;
-    qmc::SearchLaunch L{d, (uint32_t)n, alpha, a, a0, count, s_out, best_out, ws};
+    qmc::SearchLaunch L{d, (uint32_t)n, spec, a0, count, s_out, best_out, ws};
     return from_hip(qmc::launch_korobov_search(L, (hipStream_t)stream), "qmc_korobov_search");
 }
 
-qmc_status qmc_cbc(int32_t d, int64_t n, int32_t alpha, const double* a, int64_t* z_out,
+qmc_status qmc_cbc(int32_t d, int64_t n, const qmc_criterion* crit, int64_t* z_out,
                    double* s_out, void* ws, size_t ws_bytes, void* stream) {
-    qmc_status s = check_criteria(d, n, alpha, a);
+    qmc::CriterionSpec spec{};
+    qmc_status s = check_criterion(d, n, crit, stream, "qmc_cbc", &spec);
     if (s != QMC_OK) return s;
     if (n > kMaxCbcN) return fail(QMC_ERR_INVALID_ARG, "n = %lld above the CBC limit 2^26", (long long)n);
     if (!z_out || !s_out) return fail(QMC_ERR_INVALID_ARG, "z_out and s_out must be non-NULL");
     s = check_workspace(ws, ws_bytes, qmc::criteria_workspace_bytes(d, n));
     if (s != QMC_OK) return s;
-    qmc::CbcLaunch L{d, (uint32_t)n, alpha, a, z_out, s_out, ws};
+    qmc::CbcLaunch L{d, (uint32_t)n, spec, z_out, s_out, ws};
     return from_hip(qmc::launch_cbc(L, (hipStream_t)stream), "qmc_cbc");
 }
 
@@ -567,6 +632,15 @@ qmc_status qmc_mdi_lr(int32_t d, const int32_t* N, int32_t family, const double*
     qmc_status s = check_common(d, family, nsets, precision, kMaxMdiSets);
     if (s != QMC_OK) return s;
     if (!N || !params || !q_out) return fail(QMC_ERR_INVALID_ARG, "N, params and q_out must be non-NULL");
+    if (qmc::validate_mode() && !qmc::capturing((hipStream_t)stream)) {
+        std::vector<int32_t> h;
+        s = qmc::read_back(N, (size_t)d, (hipStream_t)stream, h, "qmc_mdi_lr");
+        if (s != QMC_OK) return s;
+        for (int32_t k = 0; k < d; ++k)
+            if (h[k] < 1 || h[k] > kMaxNodes)
+                return fail(QMC_ERR_INVALID_ARG, "qmc_mdi_lr: N[%d] = %d outside [1, 2^20] (QMC_VALIDATE)", k,
+                            h[k]);
+    }
     qmc::MdiLaunch L{};
     L.d = d;
     L.N = N;

@@ -50,7 +50,8 @@ __global__ __launch_bounds__(256) void korobov_table_kernel(int d, uint32_t n, d
 // --------------------------------------------------------------------------
 // Selection over v[0..count) for candidates c = c_first + i.  One workgroup.
 // If `coprime` is not null, writes +infinity over the entries it marks 0; then
-//   *best_value = v[i*],  *best_cand_f64 = c_first + i*  (if not null),
+//   *best_value = v[i*] (times *value_scale if that is not null),
+//   *best_cand_f64 = c_first + i*                        (if not null),
 //   *best_cand_i64 = c_first + i*                        (if not null),
 // i* the smallest index within kTieRel of the minimum (i* = 0 and +infinity when
 // no candidate is coprime to n).  The coprimality test itself runs where the
@@ -62,7 +63,8 @@ __global__ __launch_bounds__(kSelectBlock) void select_kernel(double* v, int cou
                                                              const uint8_t* coprime,
                                                              double* best_value,
                                                              double* best_cand_f64,
-                                                             int64_t* best_cand_i64) {
+                                                             int64_t* best_cand_i64,
+                                                             const double* value_scale) {
     __shared__ double s_min[kSelectBlock / kWave];
     __shared__ int s_idx[kSelectBlock / kWave];
     const int tid = threadIdx.x, lane = tid & (kWave - 1), wv = tid / kWave;
@@ -106,9 +108,36 @@ __global__ __launch_bounds__(kSelectBlock) void select_kernel(double* v, int cou
         int f = s_idx[0];
         for (int w = 1; w < W; ++w) f = min(f, s_idx[w]);
         if (f >= count) f = 0;
-        *best_value = v[f];
+        *best_value = value_scale ? v[f] * *value_scale : v[f];
         if (best_cand_f64) *best_cand_f64 = (double)(c_first + f);
         if (best_cand_i64) *best_cand_i64 = c_first + f;
+    }
+}
+
+// --------------------------------------------------------------------------
+// Criterion weights.  Both criteria are S of the Bernoulli product sum with weights
+//   P_alpha (eq. 2.4):  a_j = (-1)^{alpha/2+1} (2 pi)^alpha / alpha!  (2 pi^2 for
+//                       alpha = 2, -2 pi^4 / 3 for alpha = 4), and P_alpha = S;
+//   e^2 (eq. 2.12, product weights gamma_j, beta = c^2 - c + 1/3 for the anchored
+//        space with anchor c, 0 unanchored, alpha = 2):  a_j = gamma_j / (1 + gamma_j beta)
+//                       and e^2 = prod_j (1 + gamma_j beta) * S.
+// One workgroup writes a[0..d) and a[d] = C_d, and cum[j] = C_{j+1} = prod_{i<=j}
+// (1 + gamma_i beta) (all 1 for P_alpha), the products taken in index order.
+// --------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void criterion_weights_kernel(int d, int kind, int alpha,
+                                                               const double* gamma, double beta,
+                                                               double* a, double* cum) {
+    const double tp = 2.0 * 3.14159265358979323846;
+    const double c_pa = alpha == 2 ? 0.5 * tp * tp : -(tp * tp) * (tp * tp) / 24.0;
+    for (int j = threadIdx.x; j < d; j += blockDim.x)
+        a[j] = kind == kCritPAlpha ? c_pa : gamma[j] / fma(gamma[j], beta, 1.0);
+    if (threadIdx.x == 0) {
+        double c = 1.0;
+        for (int j = 0; j < d; ++j) {
+            if (kind != kCritPAlpha) c *= fma(gamma[j], beta, 1.0);
+            cum[j] = c;
+        }
+        a[d] = c;
     }
 }
 
@@ -223,12 +252,53 @@ __global__ __launch_bounds__(256) void cbc_update_kernel(uint32_t n, double inv_
 // --------------------------------------------------------------------------
 // Launchers
 // --------------------------------------------------------------------------
+// Criteria workspace: the zero region, the weights a[d + 1] and the cumulative
+// scales cum[d] (criterion_weights_kernel), then either the search's table of
+// kMaxSumSets vectors and one coprimality byte per candidate (< n), or CBC's
+// running product and the candidates' values.
+static size_t weights_bytes(int d) { return ((size_t)(2 * d + 1) * sizeof(double) + 255) / 256 * 256; }
+
 size_t criteria_workspace_bytes(int d, int64_t n) {
-    // search: a table of kMaxSumSets vectors and one coprimality byte per
-    // candidate (< n); CBC: the running product and the candidates' values
     const size_t table = (size_t)kMaxSumSets * (size_t)d * sizeof(int64_t) + (size_t)n;
     const size_t cbc = ((size_t)n + (size_t)n / 2 + 2) * sizeof(double);
-    return kZeroBytes + ((table > cbc ? table : cbc) + 255) / 256 * 256;
+    return kZeroBytes + weights_bytes(d) + ((table > cbc ? table : cbc) + 255) / 256 * 256;
+}
+
+static double* weights_of(void* ws) { return (double*)((char*)ws + kZeroBytes); }
+static void* after_weights(void* ws, int d) { return (char*)ws + kZeroBytes + weights_bytes(d); }
+
+static hipError_t launch_weights(const CriterionSpec& c, int d, void* ws, hipStream_t stream) {
+    double* a = weights_of(ws);
+    hipLaunchKernelGGL(criterion_weights_kernel, dim3(1), dim3(256), 0, stream, d, c.kind, c.alpha,
+                       c.gamma, c.beta, a, a + d + 1);
+    return hipGetLastError();
+}
+
+// Bernoulli sums whose weights (and the scale a[d]) are in the workspace.
+static hipError_t launch_scaled_sums(int d, uint32_t n, const int64_t* z, int nz, int alpha,
+                                     const double* a, double* out, void* ws, hipStream_t stream) {
+    PlainLaunch P{};
+    P.d = d;
+    P.n = n;
+    P.z = z;
+    P.shift = nullptr;
+    P.family = alpha == 2 ? kBernoulli2S : kBernoulli4S;
+    P.params = a;
+    P.P = d + 1;
+    P.nsets = nz;
+    P.param_stride = 0;
+    P.shift_stride = 0;
+    P.z_stride = d;
+    P.fp32 = false;
+    P.q_out = out;
+    P.ws = ws;
+    return launch_lattice_sum(P, stream);
+}
+
+hipError_t launch_criterion(const CriterionLaunch& L, hipStream_t stream) {
+    hipError_t e = launch_weights(L.crit, L.d, L.ws, stream);
+    if (e != hipSuccess) return e;
+    return launch_scaled_sums(L.d, L.n, L.z, L.nz, L.crit.alpha, weights_of(L.ws), L.out, L.ws, stream);
 }
 
 hipError_t launch_bernoulli_sum(const BernoulliLaunch& L, hipStream_t stream) {
@@ -252,49 +322,57 @@ hipError_t launch_bernoulli_sum(const BernoulliLaunch& L, hipStream_t stream) {
 
 hipError_t launch_korobov_search(const SearchLaunch& L, hipStream_t stream) {
     const double inv_n = 1.0 / (double)L.n;
-    int64_t* table = (int64_t*)((char*)L.ws + kZeroBytes);
+    hipError_t e = launch_weights(L.crit, L.d, L.ws, stream);
+    if (e != hipSuccess) return e;
+    const double* a = weights_of(L.ws);
+    int64_t* table = (int64_t*)after_weights(L.ws, L.d);
     uint8_t* coprime = (uint8_t*)(table + (size_t)kMaxSumSets * L.d);
     for (int64_t c0 = 0; c0 < L.count; c0 += kMaxSumSets) {
         const int cnt = (int)((L.count - c0) < kMaxSumSets ? (L.count - c0) : kMaxSumSets);
         hipLaunchKernelGGL(korobov_table_kernel, dim3((cnt + 255) / 256), dim3(256), 0, stream, L.d,
                            L.n, inv_n, L.a0 + c0, cnt, table, coprime + c0);
-        hipError_t e = hipGetLastError();
+        e = hipGetLastError();
         if (e != hipSuccess) return e;
-        BernoulliLaunch B{L.d, L.n, table, cnt, L.alpha, L.a, L.s_out + c0, L.ws};
-        e = launch_bernoulli_sum(B, stream);
+        e = launch_scaled_sums(L.d, L.n, table, cnt, L.crit.alpha, a, L.s_out + c0, L.ws, stream);
         if (e != hipSuccess) return e;
     }
     hipLaunchKernelGGL(select_kernel, dim3(1), dim3(kSelectBlock), 0, stream, L.s_out, L.count,
-                       L.a0, (const uint8_t*)coprime, L.best_out, L.best_out + 1, (int64_t*)nullptr);
+                       L.a0, (const uint8_t*)coprime, L.best_out, L.best_out + 1, (int64_t*)nullptr,
+                       (const double*)nullptr);
     return hipGetLastError();
 }
 
 template <int ALPHA>
 static hipError_t launch_cbc_a(const CbcLaunch& L, hipStream_t stream) {
     const double inv_n = 1.0 / (double)L.n;
-    double* p = (double*)((char*)L.ws + kZeroBytes);
+    hipError_t e = launch_weights(L.crit, L.d, L.ws, stream);
+    if (e != hipSuccess) return e;
+    const double* a = weights_of(L.ws);
+    const double* cum = a + L.d + 1;
+    double* p = (double*)after_weights(L.ws, L.d);
     double* cand = p + L.n;
     const unsigned half_blocks = (unsigned)((L.n / 2 + 1 + 255) / 256);
     hipLaunchKernelGGL(cbc_init_kernel, dim3(half_blocks), dim3(256), 0, stream, L.n, p);
-    hipError_t e = hipGetLastError();
+    e = hipGetLastError();
     for (int j = 0; j < L.d && e == hipSuccess; ++j) {
-        // z_1 = 1; later components range over 1 <= c <= n/2 (c and n - c tie).
+        // z_1 = 1; later components range over 1 <= c <= n/2 (c and n - c tie).  The
+        // candidates are compared by S; the chosen one's criterion is C_{j+1} S.
         const int ncand = j == 0 ? 1 : (int)(L.n / 2);
         hipLaunchKernelGGL((cbc_eval_kernel<ALPHA>), dim3((ncand + kCbcCand - 1) / kCbcCand),
-                           dim3(kCbcBlock), 0, stream, L.n, inv_n, L.a, j, p, (int64_t)1, ncand,
+                           dim3(kCbcBlock), 0, stream, L.n, inv_n, a, j, p, (int64_t)1, ncand,
                            cand);
         hipLaunchKernelGGL(select_kernel, dim3(1), dim3(kSelectBlock), 0, stream, cand, ncand,
                            (int64_t)1, (const uint8_t*)nullptr, L.s_out + j, (double*)nullptr,
-                           L.z_out + j);
+                           L.z_out + j, cum + j);
         hipLaunchKernelGGL((cbc_update_kernel<ALPHA>), dim3(half_blocks), dim3(256), 0, stream,
-                           L.n, inv_n, L.a, j, L.z_out, p);
+                           L.n, inv_n, a, j, L.z_out, p);
         e = hipGetLastError();
     }
     return e;
 }
 
 hipError_t launch_cbc(const CbcLaunch& L, hipStream_t stream) {
-    return L.alpha == 2 ? launch_cbc_a<2>(L, stream) : launch_cbc_a<4>(L, stream);
+    return L.crit.alpha == 2 ? launch_cbc_a<2>(L, stream) : launch_cbc_a<4>(L, stream);
 }
 
 }  // namespace qmc

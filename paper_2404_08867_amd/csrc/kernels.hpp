@@ -99,11 +99,33 @@ struct BernoulliLaunch {
 };
 hipError_t launch_bernoulli_sum(const BernoulliLaunch& L, hipStream_t stream);
 
+// A lattice-quality criterion: P_alpha of eq. 2.4, or e^2 of eq. 2.12 with
+// product weights gamma (device, d entries) and beta (alpha = 2).
+constexpr int kCritPAlpha = 0;
+constexpr int kCritWce2 = 1;
+struct CriterionSpec {
+    int kind;
+    int alpha;
+    const double* gamma;  // kCritWce2 only
+    double beta;
+};
+
+// The criterion of nz generating vectors (rows of z).
+struct CriterionLaunch {
+    int d;
+    uint32_t n;
+    const int64_t* z;  // [nz][d]
+    int nz;
+    CriterionSpec crit;
+    double* out;       // [nz]
+    void* ws;
+};
+hipError_t launch_criterion(const CriterionLaunch& L, hipStream_t stream);
+
 struct SearchLaunch {
     int d;
     uint32_t n;
-    int alpha;
-    const double* a;
+    CriterionSpec crit;
     int64_t a0;
     int count;
     double* s_out;     // [count]
@@ -115,16 +137,15 @@ hipError_t launch_korobov_search(const SearchLaunch& L, hipStream_t stream);
 struct CbcLaunch {
     int d;
     uint32_t n;
-    int alpha;
-    const double* a;
+    CriterionSpec crit;
     int64_t* z_out;  // [d]
     double* s_out;   // [d]
     void* ws;
 };
 hipError_t launch_cbc(const CbcLaunch& L, hipStream_t stream);
 
-// Workspace of the criteria entry points: the zero region, then the larger of a
-// table of kMaxSumSets generating vectors and the CBC vectors (n + n/2 doubles).
+// Workspace of the criteria entry points: the zero region, the weights, then the
+// larger of a table of kMaxSumSets generating vectors and the CBC vectors.
 size_t criteria_workspace_bytes(int d, int64_t n);
 
 // MDI-LR for integrands of the coordinate sum (mdi_sum.hip).

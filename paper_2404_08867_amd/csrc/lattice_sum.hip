@@ -92,8 +92,11 @@ __global__ __launch_bounds__(B) void lattice_sum_kernel(
     const GridSlots slots =
         set_slots(scratch, scratch_stride, slot_stride, tickets, set, (int)gridDim.x);
     double total;
-    if (grid_sum_wave0(bsum, (int)blockIdx.x, (int)gridDim.x, slots, total) && threadIdx.x == 0)
-        q_out[set] = (total / v.dn) * F::scale(ds1, ie);
+    if (grid_sum_wave0(bsum, (int)blockIdx.x, (int)gridDim.x, slots, total) && threadIdx.x == 0) {
+        double q = (total / v.dn) * F::scale(ds1, ie);
+        if constexpr (param_scaled<F>::value) q *= v.p[v.d];
+        q_out[set] = q;
+    }
 }
 
 static_assert((kMaxSumBlocksPerSet + kReduceGroups - 1) / kReduceGroups <= kWave &&
@@ -264,6 +267,8 @@ hipError_t launch_lattice_sum(const PlainLaunch& L, hipStream_t stream) {
     // The Bernoulli products behind the criteria run in FP64 in both precisions.
     if (L.family == kBernoulli2) return launch_f<BernoulliProduct<2>>(L, stream);
     if (L.family == kBernoulli4) return launch_f<BernoulliProduct<4>>(L, stream);
+    if (L.family == kBernoulli2S) return launch_f<BernoulliProduct<2, true>>(L, stream);
+    if (L.family == kBernoulli4S) return launch_f<BernoulliProduct<4, true>>(L, stream);
     if (L.fp32) {
         switch (L.family) {
             case kExpSum: return launch_f<ExpSum<true>>(L, stream);

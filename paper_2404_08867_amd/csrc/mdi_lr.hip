@@ -7,11 +7,12 @@
 //   M_k = (1/N_k) sum_{t=0}^{N_k-1} phi_k((t + 1/2) / N_k),
 // so Qhat = C_0 prod_k M_k (C_0 = 1, or e^{2 pi i u} for the oscillatory family,
 // whose factors e^{i c_k y} are complex).  The d sweeps are independent of one
-// another, so a workgroup evaluates the M_k of G parameter sets in parallel --
-// one (set, direction) pair per thread, N_k nodes each -- keeps them in LDS, and
-// then multiplies each set's d factors in direction order with exact
-// power-of-two renormalisation (no overflow or underflow of the running product
-// for d in the thousands).
+// another: L lanes of a wave serve one parameter set (L a power of two chosen so
+// that the grid fills the GPU), lane l takes directions k = l, l + L, l + 2L, ...,
+// multiplies their M_k into a running product kept as mantissa times 2^E (exact
+// power-of-two renormalisation, so d in the thousands cannot overflow or
+// underflow), and the L partial products are combined by a fixed butterfly of
+// lane exchanges (every lane of the group ends with the same bits).
 #include "common.hpp"
 #include "families.hpp"
 #include "kernels.hpp"
@@ -24,40 +25,46 @@ struct MdiArgs {
     const double* params;
     int P;
     int nsets;
-    int G;  // sets per workgroup
+    int lanes_log2;  // L = 2^lanes_log2 lanes per set, L <= kWave
     double* q_out;
 };
 
+constexpr int kMdiBlock = 256;
+constexpr int kMaxNodesPerDim = 1 << 20;
+
 // Sum over t = 0..Nk-1 of 2^{s y_t^2}, y_t = A t + B, s = -1 (a Gaussian) or +1 (a
-// growing factor of the signed quadratic), by the exact recurrence on equispaced
-// nodes: phi_{t+1} = phi_t r_t and r_{t+1} = r_t q with r_t = 2^{s A (2 y_t + A)},
-// q = 2^{2 s A^2} -- two FP64 multiplies and one add per node.  phi and r are
-// recomputed with exp2 at every S-th node, which bounds the compounded rounding of a
-// run to S^2/2 units in the last place: S = 8 for QMC_FP64 (< 1e-15 per factor, so
-// that a thousand identical directions stay within 1e-12), 64 for
-// QMC_FP32_COMPENSATED (one run for N = 64).  The recurrence is used only while
-// every node value, every ratio and q stay within 2^-1000..2^1000 (max y^2 over the
-// nodes, taken at an end point, and 2 A^2 at most 1000), so no intermediate value
-// underflows or overflows; otherwise each node is evaluated directly (FP32: FP64
-// argument, split FP32 exp2).
+// growing factor of the signed quadratic).  Consecutive nodes differ by the ratio
+// r_t = phi_{t+1} / phi_t = 2^{s A (2 y_t + A)}, and r_{t-1} = r_t / q with
+// q = 2^{2 s A^2}, so a run of nodes t0 .. t0 + m - 1 sums in Horner form,
+//   phi_{t0} (1 + r_{t0} (1 + r_{t0+1} (1 + ... (1 + r_{t0+m-2})))),
+// from its last ratio down: one FP64 multiply (the ratio) and one FP64 FMA (the
+// partial sum) per node.  phi_{t0} and the run's last ratio come from exp2: every
+// S-th node (S = 8 for QMC_FP64, which keeps the compounded rounding of a run below
+// ~1e-15 so that a thousand identical directions stay within 1e-12; 64 for
+// QMC_FP32_COMPENSATED).  The recurrence is used only while every node value, ratio
+// and q stay within 2^-1000..2^1000 (max y^2 over the nodes, taken at an end point,
+// and 2 A^2 at most 1000), so no partial sum or ratio leaves the FP64 range;
+// otherwise each node is evaluated directly (FP32: FP64 argument, split FP32 exp2).
 template <bool FP32>
 __device__ __forceinline__ double quad_node_sum(double A, double B, int Nk, double s) {
     constexpr int kSeed = FP32 ? 64 : 8;
     const double y_last = fma((double)(Nk - 1), A, B);
     double sr = 0.0;
     if (fmax(fmax(B * B, y_last * y_last), 2.0 * A * A) <= 1000.0) {
-        const double q = exp2(2.0 * s * A * A);
+        const double qinv = exp2(-2.0 * s * A * A);
         for (int t0 = 0; t0 < Nk; t0 += kSeed) {
-            const double y = fma((double)t0, A, B);
-            double f = exp2(s * y * y), r = exp2(s * A * fma(2.0, y, A));
-            const int n1 = min(kSeed, Nk - t0);
-            sr += f;
+            const int m = min(kSeed, Nk - t0);
+            const double y0 = fma((double)t0, A, B);
+            const double phi0 = exp2(s * y0 * y0);
+            const double yl = fma((double)(t0 + m - 2), A, B);  // the run's last ratio r_{t0+m-2}
+            double r = exp2(s * A * fma(2.0, yl, A));
+            double h = 1.0;
 #pragma unroll 4
-            for (int t = 1; t < n1; ++t) {
-                f *= r;
-                r *= q;
-                sr += f;
+            for (int t = m - 2; t >= 0; --t) {
+                h = fma(r, h, 1.0);
+                r *= qinv;
             }
+            sr = fma(phi0, h, sr);
         }
     } else if constexpr (FP32) {
         for (int t = 0; t < Nk; ++t) {
@@ -73,30 +80,23 @@ __device__ __forceinline__ double quad_node_sum(double A, double B, int Nk, doub
     return sr;
 }
 
-// One direction's weighted node sum.  FP32 evaluates the factor in single
-// precision (argument, exp2 / reciprocal / cos-sin) and accumulates in double.
+// One direction's factor M_k = (1/N_k) sum_t phi_k((t + 1/2)/N_k) (real and
+// imaginary parts).  An N_k outside [1, 2^20] (the caller's contract) gives NaN.
 template <int FAM, bool FP32>
 __device__ __forceinline__ void direction_sum(const double* p, int d, int k, int Nk, double& re,
                                               double& im) {
+    if (Nk < 1 || Nk > kMaxNodesPerDim) {
+        re = im = __builtin_nan("");
+        return;
+    }
     const double invN = 1.0 / (double)Nk;
     double sr = 0.0, si = 0.0;
     if constexpr (FAM == kExpSum) {
-        // phi = 2^{c log2e (t + 1/2)/N} = 2^{A t + B}: a geometric sequence, phi_{t+1} =
-        // phi_t 2^A, one FP64 multiply and one add per node in both precisions; phi is
-        // reseeded with exp2 every 64 nodes (the rounding of a run grows linearly).
-        const double c = p[k] * kLog2e;
-        const double A = c * invN, B = 0.5 * c * invN;
-        const double R = exp2(A);
-        for (int t0 = 0; t0 < Nk; t0 += 64) {
-            double f = exp2(fma((double)t0, A, B));
-            const int n1 = min(64, Nk - t0);
-            sr += f;
-#pragma unroll 4
-            for (int t = 1; t < n1; ++t) {
-                f *= R;
-                sr += f;
-            }
-        }
+        // phi = e^{c (t + 1/2)/N}: a geometric sequence, whose sum over the N nodes is
+        // e^{c/(2N)} (e^c - 1) / (e^{c/N} - 1) = expm1(c) / (2 sinh(c / (2N)))  (c != 0;
+        // every term 1 for c = 0), evaluated in FP64 in both precisions.
+        const double c = p[k];
+        sr = c == 0.0 ? (double)Nk : expm1(c) / (2.0 * sinh(0.5 * c * invN));
     } else if constexpr (FAM == kGaussian) {
         // phi = 2^{-y^2}, y = c sqrt(log2 e) ((t + 1/2)/N - w) = A t + B
         const double c = p[k] * kSqrtLog2e, w = p[d + k];
@@ -142,19 +142,19 @@ __device__ __forceinline__ void direction_sum(const double* p, int d, int k, int
             for (int t = 0; t < Nk; ++t) {
                 const double a = fma((double)t, A, B);
                 const float fr = (float)(a - rint(a));
-                float s, co;
-                sincospif(2.0f * fr, &s, &co);
+                float sn, co;
+                sincospif(2.0f * fr, &sn, &co);
                 sr += (double)co;
-                si += (double)s;
+                si += (double)sn;
             }
         } else {
             for (int t = 0; t < Nk; ++t) {
                 const double a = fma((double)t, A, B);
                 const double fr = a - rint(a);
-                double s, co;
-                sincospi(2.0 * fr, &s, &co);
+                double sn, co;
+                sincospi(2.0 * fr, &sn, &co);
                 sr += co;
-                si += s;
+                si += sn;
             }
         }
     }
@@ -162,57 +162,76 @@ __device__ __forceinline__ void direction_sum(const double* p, int d, int k, int
     im = si * invN;
 }
 
+// (cr + i ci) 2^E times (mr + i mi), renormalised to a largest part in [1/2, 1).
+template <bool COMPLEX>
+__device__ __forceinline__ void mul_renorm(double& cr, double& ci, int& E, double mr, double mi) {
+    double nr, ni = 0.0;
+    if constexpr (COMPLEX) {
+        nr = fma(cr, mr, -ci * mi);
+        ni = fma(cr, mi, ci * mr);
+    } else {
+        nr = cr * mr;
+    }
+    const double big = COMPLEX ? fmax(fabs(nr), fabs(ni)) : fabs(nr);
+    if (big > 0.0 && big < INFINITY) {
+        const int e = __builtin_amdgcn_frexp_exp(big);
+        nr = ldexp(nr, -e);
+        if constexpr (COMPLEX) ni = ldexp(ni, -e);
+        E += e;
+    }
+    cr = nr;
+    ci = ni;
+}
+
 template <int FAM, bool FP32>
-__global__ __launch_bounds__(kBlock) void mdi_lr_kernel(const MdiArgs a) {
-    extern __shared__ double s_m[];  // [G*d] real parts, then [G*d] imaginary parts (oscillatory)
+__global__ __launch_bounds__(kMdiBlock) void mdi_lr_kernel(const MdiArgs a) {
     constexpr bool kComplex = FAM == kOscillatory;
-    const int set0 = blockIdx.x * a.G;
-    const int g_here = min(a.G, a.nsets - set0);
-    const int pairs = g_here * a.d;
-    double* s_im = s_m + (size_t)a.G * a.d;
+    const int L = 1 << a.lanes_log2;
+    const int gid = blockIdx.x * kMdiBlock + threadIdx.x;
+    const int set = gid >> a.lanes_log2, li = gid & (L - 1);
+    const bool active = set < a.nsets;
 
-    for (int q = threadIdx.x; q < pairs; q += kBlock) {
-        const int sl = q / a.d, k = q % a.d;
-        const double* p = a.params + (size_t)(set0 + sl) * a.P;
-        double re, im;
-        // N_k in [1, 2^20] is the caller's contract; clamp so that a bad value
-        // cannot turn into an unbounded loop.
-        const int Nk = min(max(a.N[k], 1), 1 << 20);
-        direction_sum<FAM, FP32>(p, a.d, k, Nk, re, im);
-        s_m[q] = re;
-        if constexpr (kComplex) s_im[q] = im;
-    }
-    __syncthreads();
-
-    // Product over directions in order: the coefficient of the symbolic function
-    // after each sweep step, kept as mantissa pair times 2^E.
-    for (int sl = threadIdx.x; sl < g_here; sl += kBlock) {
-        const double* p = a.params + (size_t)(set0 + sl) * a.P;
-        double cr = 1.0, ci = 0.0;
-        int E = 0;
-        if constexpr (kComplex) sincospi(2.0 * p[0], &ci, &cr);
-        for (int k = 0; k < a.d; ++k) {
-            const double mr = s_m[sl * a.d + k];
-            double nr, ni = 0.0;
-            if constexpr (kComplex) {
-                const double mi = s_im[sl * a.d + k];
-                nr = cr * mr - ci * mi;
-                ni = cr * mi + ci * mr;
-            } else {
-                nr = cr * mr;
-            }
-            const double big = kComplex ? fmax(fabs(nr), fabs(ni)) : fabs(nr);
-            if (big > 0.0 && big < INFINITY) {
-                const int e = __builtin_amdgcn_frexp_exp(big);
-                nr = ldexp(nr, -e);
-                ni = ldexp(ni, -e);
-                E += e;
-            }
-            cr = nr;
-            ci = ni;
+    // This lane's directions k = li, li + L, ... in increasing order.
+    double cr = 1.0, ci = 0.0;
+    int E = 0;
+    if (active) {
+        const double* p = a.params + (size_t)set * a.P;
+        for (int k = li; k < a.d; k += L) {
+            double re, im;
+            direction_sum<FAM, FP32>(p, a.d, k, a.N[k], re, im);
+            mul_renorm<kComplex>(cr, ci, E, re, im);
         }
-        a.q_out[set0 + sl] = ldexp(cr, E);
     }
+    // Partial products of the set's L lanes, combined by a butterfly over lane
+    // distances 1, 2, 4, ...: products commute exactly, so both partners of every
+    // exchange compute the same bits and the order is fixed by the lane structure.
+    for (int off = 1; off < L; off <<= 1) {
+        const double pr = __shfl_xor(cr, off, kWave);
+        const double pi = kComplex ? __shfl_xor(ci, off, kWave) : 0.0;
+        const int pe = __shfl_xor(E, off, kWave);
+        E += pe;
+        mul_renorm<kComplex>(cr, ci, E, pr, pi);
+    }
+    if (active && li == 0) {
+        if constexpr (kComplex) {
+            // the coefficient e^{2 pi i u} of the symbolic function before the sweeps
+            double su, cu;
+            sincospi(2.0 * a.params[(size_t)set * a.P], &su, &cu);
+            double r = cr, i = ci;
+            mul_renorm<true>(r, i, E, cu, su);
+            cr = r;
+        }
+        a.q_out[set] = ldexp(cr, E);
+    }
+}
+
+// Lanes per set: enough (set, lane) pairs for about four waves per SIMD of the
+// whole GPU, at most one wave per set and at most one lane per direction.
+static int mdi_lanes_log2(int d, int nsets) {
+    const int64_t want = (int64_t)device_cu_count() * 4 * 4 * kWave;
+    int lg = 0;
+    while (lg < 6 && (int64_t)nsets << lg < want && (2 << lg) <= d) ++lg;
+    return lg;
 }
 
 template <int FAM, bool FP32>
@@ -223,15 +242,11 @@ static hipError_t launch_mdi_t(const MdiLaunch& L, hipStream_t stream) {
     a.params = L.params;
     a.P = L.P;
     a.nsets = L.nsets;
-    // About 4096 (set, direction) pairs per workgroup (16 per thread); 32 KB of LDS.
-    int G = (FAM == kOscillatory ? 2048 : 4096) / L.d;
-    if (G < 1) G = 1;
-    if (G > L.nsets) G = L.nsets;
-    a.G = G;
+    a.lanes_log2 = mdi_lanes_log2(L.d, L.nsets);
     a.q_out = L.q_out;
-    const size_t lds = (size_t)G * L.d * sizeof(double) * (FAM == kOscillatory ? 2 : 1);
-    const unsigned grid = (unsigned)((L.nsets + G - 1) / G);
-    hipLaunchKernelGGL((mdi_lr_kernel<FAM, FP32>), dim3(grid), dim3(kBlock), lds, stream, a);
+    const int64_t threads = (int64_t)L.nsets << a.lanes_log2;
+    const unsigned grid = (unsigned)((threads + kMdiBlock - 1) / kMdiBlock);
+    hipLaunchKernelGGL((mdi_lr_kernel<FAM, FP32>), dim3(grid), dim3(kMdiBlock), 0, stream, a);
     return hipGetLastError();
 }
 

@@ -8,7 +8,6 @@ fallback.
 from __future__ import annotations
 
 import ctypes
-import math
 import os
 import threading
 
@@ -25,6 +24,8 @@ FP64, FP32_COMPENSATED = 0, 1
 N_A_POW_D, N_ONE_PLUS_A_POW_D, N_EXPLICIT = 0, 1, 2
 # qmc_implr_method
 IMPLR_AUTO, IMPLR_BITMAP = 0, 1
+# qmc_criterion_kind
+CRIT_P_ALPHA, CRIT_WCE2 = 0, 1
 # qmc_status
 OK, ERR_INVALID_ARG, ERR_UNSUPPORTED, ERR_WORKSPACE, ERR_OUT_OF_MEMORY, ERR_DEVICE = range(6)
 
@@ -68,8 +69,10 @@ def lib() -> ctypes.CDLL:
         L.qmc_mdi_lr_sum_workspace_size.argtypes = [i32, i32, vp]
         L.qmc_mdi_lr_sum.argtypes = [i32, i32, i32, i32, dp, i32, i32, dp, vp, sz, vp]
         L.qmc_bernoulli_sum.argtypes = [i32, i64, dp, i32, i32, dp, dp, vp, sz, vp]
-        L.qmc_korobov_search.argtypes = [i32, i64, i32, dp, i64, i32, dp, dp, vp, sz, vp]
-        L.qmc_cbc.argtypes = [i32, i64, i32, dp, dp, dp, vp, sz, vp]
+        L.qmc_p_alpha.argtypes = [i32, i64, dp, i32, i32, dp, vp, sz, vp]
+        L.qmc_shift_avg_wce2.argtypes = [i32, i64, dp, i32, dp, ctypes.c_double, dp, vp, sz, vp]
+        L.qmc_korobov_search.argtypes = [i32, i64, vp, i64, i32, dp, dp, vp, sz, vp]
+        L.qmc_cbc.argtypes = [i32, i64, vp, dp, dp, vp, sz, vp]
         L.qmc_implr_workspace_size.argtypes = [i32, i64, i64, vp]
         L.qmc_implr_grid.argtypes = [i32, i64, i64, i32, vp, dp, vp, sz, vp]
         L.qmc_implr_points.argtypes = [i32, i64, i64, i64, i64, dp, i64, vp]
@@ -329,15 +332,20 @@ def _criteria_workspace(d, n, device, ws):
     return cur
 
 
-def p_alpha_weight(alpha: int) -> float:
-    """(-1)^{alpha/2+1} (2 pi)^alpha / alpha!: the weight a_j that makes S equal P_alpha (eq. 2.4)."""
-    return (1.0 if (alpha // 2) % 2 == 1 else -1.0) * (2.0 * math.pi) ** alpha / math.factorial(alpha)
+class Criterion(ctypes.Structure):
+    """qmc_criterion: P_alpha of eq. 2.4, or e^2 of eq. 2.12 with product weights."""
+    _fields_ = [("kind", ctypes.c_int32), ("alpha", ctypes.c_int32), ("gamma", ctypes.c_void_p),
+                ("beta", ctypes.c_double)]
 
 
-def wce2_weights(gamma, beta: float):
-    """(a_j, C) with e^2 = C * S(a) for product weights gamma_j (eq. 2.12)."""
-    g = np.asarray(gamma, dtype=np.float64)
-    return g / (1.0 + g * beta), float(np.prod(1.0 + g * beta))
+def _criterion(d, alpha, gamma, beta, device):
+    """(qmc_criterion, the device tensor of gamma it points to or None)."""
+    if gamma is None:
+        return Criterion(CRIT_P_ALPHA, alpha, None, 0.0), None
+    gt = _dev(gamma, _torch().float64, device)
+    if gt.numel() != d:
+        raise QmcError(ERR_INVALID_ARG, "gamma must hold d weights")
+    return Criterion(CRIT_WCE2, 2, _ptr(gt), float(beta)), gt
 
 
 def bernoulli_sum(z, n: int, alpha: int, a, ws: Workspace | None = None, device="cuda"):
@@ -358,55 +366,73 @@ def bernoulli_sum(z, n: int, alpha: int, a, ws: Workspace | None = None, device=
     return s
 
 
-def p_alpha(z, n: int, alpha: int, device="cuda"):
-    """P_alpha(z) of eq. 2.4 for each row of z (device tensor)."""
-    d = int(np.asarray(z).shape[-1]) if not hasattr(z, "shape") else int(z.shape[-1])
-    return bernoulli_sum(z, n, alpha, np.full(d, p_alpha_weight(alpha)), device=device)
+def _rows(z, device):
+    zt = _dev(z, _torch().int64, device)
+    return zt.unsqueeze(0) if zt.dim() == 1 else zt
 
 
-def shift_avg_wce2(z, n: int, gamma, beta: float, device="cuda"):
-    """Squared shift-averaged worst-case error of eq. 2.12 (product weights) per row of z."""
-    a, c = wce2_weights(gamma, beta)
-    return c * bernoulli_sum(z, n, 2, a, device=device)
+def p_alpha(z, n: int, alpha: int, ws: Workspace | None = None, device="cuda"):
+    """P_alpha(z) of eq. 2.4 for each row of z (qmc_p_alpha); a device tensor [nz]."""
+    torch = _torch()
+    zt = _rows(z, device)
+    nz, d = int(zt.shape[0]), int(zt.shape[1])
+    out = torch.empty(nz, dtype=torch.float64, device=device)
+    w = _criteria_workspace(d, n, device, ws)
+    with _on(out):
+        _check(lib().qmc_p_alpha(d, n, _ptr(zt), nz, alpha, _ptr(out), w.ptr, w.nbytes, _stream()),
+               "qmc_p_alpha")
+    return out
 
 
-def korobov_search(d: int, n: int, alpha: int = 2, a=None, a0: int = 1, count: int | None = None,
-                   ws: Workspace | None = None, device="cuda"):
-    """S(z(a)) for a = a0 .. a0+count-1 (qmc_korobov_search; a_j = P_alpha weights by default).
+def shift_avg_wce2(z, n: int, gamma, beta: float, ws: Workspace | None = None, device="cuda"):
+    """e^2(z) of eq. 2.12 (product weights gamma_j, beta) for each row of z
+    (qmc_shift_avg_wce2); a device tensor [nz]."""
+    torch = _torch()
+    zt = _rows(z, device)
+    nz, d = int(zt.shape[0]), int(zt.shape[1])
+    gt = _dev(gamma, torch.float64, device)
+    if gt.numel() != d:
+        raise QmcError(ERR_INVALID_ARG, "gamma must hold d weights")
+    out = torch.empty(nz, dtype=torch.float64, device=device)
+    w = _criteria_workspace(d, n, device, ws)
+    with _on(out):
+        _check(lib().qmc_shift_avg_wce2(d, n, _ptr(zt), nz, _ptr(gt), float(beta), _ptr(out), w.ptr,
+                                        w.nbytes, _stream()), "qmc_shift_avg_wce2")
+    return out
+
+
+def korobov_search(d: int, n: int, alpha: int = 2, gamma=None, beta: float = 0.0, a0: int = 1,
+                   count: int | None = None, ws: Workspace | None = None, device="cuda"):
+    """The criterion of z(a) for a = a0 .. a0+count-1 (qmc_korobov_search): P_alpha of
+    eq. 2.4 when gamma is None, else e^2 of eq. 2.12 with weights gamma and beta.
     Returns (values [count] device tensor, best [2] device tensor: value, a)."""
     torch = _torch()
     count = (n - a0) if count is None else count
-    weights = np.full(d, p_alpha_weight(alpha)) if a is None else a
-    at = _dev(weights, torch.float64, device)
+    crit, keep = _criterion(d, alpha, gamma, beta, device)
     vals = torch.empty(count, dtype=torch.float64, device=device)
     best = torch.empty(2, dtype=torch.float64, device=device)
     w = _criteria_workspace(d, n, device, ws)
     with _on(vals):
-        _check(lib().qmc_korobov_search(d, n, alpha, _ptr(at), a0, count, _ptr(vals), _ptr(best), w.ptr,
+        _check(lib().qmc_korobov_search(d, n, ctypes.byref(crit), a0, count, _ptr(vals), _ptr(best), w.ptr,
                                         w.nbytes, _stream()), "qmc_korobov_search")
+    del keep
     return vals, best
 
 
-def cbc(d: int, n: int, gamma, beta: float, alpha: int = 2, ws: Workspace | None = None,
+def cbc(d: int, n: int, gamma=None, beta: float = 0.0, alpha: int = 2, ws: Workspace | None = None,
         device="cuda"):
-    """CBC generating vector (qmc_cbc) for product weights gamma_j and beta.
-    Returns (z [d] int64 device tensor, criterion after each component [d]:
-    e^2 of eq. 2.12 for alpha = 2, S for alpha = 4)."""
+    """CBC generating vector (qmc_cbc) minimising e^2 of eq. 2.12 (weights gamma, beta),
+    or P_alpha of eq. 2.4 when gamma is None.  Returns (z [d] int64 device tensor,
+    the criterion of (z_1..z_j) for each j [d])."""
     torch = _torch()
-    g = np.asarray(gamma, dtype=np.float64)
-    if g.size != d:
-        raise QmcError(ERR_INVALID_ARG, "gamma must hold d weights")
-    a, _ = wce2_weights(g, beta) if alpha == 2 else (g, 1.0)
-    at = _dev(a, torch.float64, device)
+    crit, keep = _criterion(d, alpha, gamma, beta, device)
     z = torch.empty(d, dtype=torch.int64, device=device)
     sv = torch.empty(d, dtype=torch.float64, device=device)
     w = _criteria_workspace(d, n, device, ws)
     with _on(z):
-        _check(lib().qmc_cbc(d, n, alpha, _ptr(at), _ptr(z), _ptr(sv), w.ptr, w.nbytes, _stream()),
+        _check(lib().qmc_cbc(d, n, ctypes.byref(crit), _ptr(z), _ptr(sv), w.ptr, w.nbytes, _stream()),
                "qmc_cbc")
-    if alpha == 2:
-        cj = torch.tensor(np.cumprod(1.0 + g * beta), dtype=torch.float64, device=device)
-        sv = sv * cj
+    del keep
     return z, sv
 
 

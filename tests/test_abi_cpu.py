@@ -99,11 +99,27 @@ def test_invalid_arguments_fail_before_launch():
     assert L.qmc_bernoulli_sum(4, 1, fake, 1, 2, fake, fake, ws, big, None) == qmc.ERR_INVALID_ARG
     assert L.qmc_bernoulli_sum(4, 100, fake, 0, 2, fake, fake, ws, big, None) == qmc.ERR_INVALID_ARG
     assert L.qmc_bernoulli_sum(4, 100, fake, 1, 2, None, fake, ws, big, None) == qmc.ERR_INVALID_ARG
-    assert L.qmc_korobov_search(4, 100, 2, fake, 0, 10, fake, fake, ws, big, None) == qmc.ERR_INVALID_ARG
-    assert L.qmc_korobov_search(4, 100, 2, fake, 95, 10, fake, fake, ws, big, None) == qmc.ERR_INVALID_ARG
-    assert L.qmc_korobov_search(4, 100, 2, fake, 1, 10, fake, fake, ws, 16, None) == qmc.ERR_WORKSPACE
-    assert L.qmc_cbc(4, (1 << 26) + 1, 2, fake, fake, fake, ws, big, None) == qmc.ERR_INVALID_ARG
-    assert L.qmc_cbc(4, 100, 2, fake, None, fake, ws, big, None) == qmc.ERR_INVALID_ARG
+    p2 = ctypes.byref(qmc.Criterion(qmc.CRIT_P_ALPHA, 2, None, 0.0))
+    assert L.qmc_korobov_search(4, 100, p2, 0, 10, fake, fake, ws, big, None) == qmc.ERR_INVALID_ARG
+    assert L.qmc_korobov_search(4, 100, p2, 95, 10, fake, fake, ws, big, None) == qmc.ERR_INVALID_ARG
+    assert L.qmc_korobov_search(4, 100, p2, 1, 10, fake, fake, ws, 16, None) == qmc.ERR_WORKSPACE
+    assert L.qmc_korobov_search(4, 100, None, 1, 10, fake, fake, ws, big, None) == qmc.ERR_INVALID_ARG
+    assert L.qmc_cbc(4, (1 << 26) + 1, p2, fake, fake, ws, big, None) == qmc.ERR_INVALID_ARG
+    assert L.qmc_cbc(4, 100, p2, None, fake, ws, big, None) == qmc.ERR_INVALID_ARG
+    # criterion descriptors: unknown kind, alpha, missing gamma, negative or infinite beta
+    for crit in (qmc.Criterion(7, 2, None, 0.0), qmc.Criterion(qmc.CRIT_P_ALPHA, 3, None, 0.0),
+                 qmc.Criterion(qmc.CRIT_WCE2, 2, None, 0.0), qmc.Criterion(qmc.CRIT_WCE2, 2, fake.value, -1.0),
+                 qmc.Criterion(qmc.CRIT_WCE2, 2, fake.value, float("inf"))):
+        assert L.qmc_cbc(4, 100, ctypes.byref(crit), fake, fake, ws, big, None) == qmc.ERR_INVALID_ARG
+        assert L.qmc_korobov_search(4, 100, ctypes.byref(crit), 1, 10, fake, fake, ws, big,
+                                    None) == qmc.ERR_INVALID_ARG
+    assert L.qmc_p_alpha(4, 100, fake, 1, 3, fake, ws, big, None) == qmc.ERR_INVALID_ARG
+    assert L.qmc_p_alpha(4, 100, fake, 0, 2, fake, ws, big, None) == qmc.ERR_INVALID_ARG
+    assert L.qmc_p_alpha(4, 100, fake, 1, 2, None, ws, big, None) == qmc.ERR_INVALID_ARG
+    assert L.qmc_p_alpha(4, 100, fake, 1, 2, fake, ws, 16, None) == qmc.ERR_WORKSPACE
+    assert L.qmc_shift_avg_wce2(4, 100, fake, 1, None, 0.0, fake, ws, big, None) == qmc.ERR_INVALID_ARG
+    assert L.qmc_shift_avg_wce2(4, 100, fake, 1, fake, -0.1, fake, ws, big, None) == qmc.ERR_INVALID_ARG
+    assert L.qmc_shift_avg_wce2(4, 1, fake, 1, fake, 0.0, fake, ws, big, None) == qmc.ERR_INVALID_ARG
     # the improved rule's grid: d, a, a^{d-1} < n, null output, workspace
     assert L.qmc_implr_grid(0, 101, 3, 0, None, fake, ws, big, None) == qmc.ERR_INVALID_ARG
     assert L.qmc_implr_grid(3, 101, 0, 0, None, fake, ws, big, None) == qmc.ERR_INVALID_ARG
@@ -136,9 +152,11 @@ def test_invalid_arguments_fail_before_launch():
 
 
 def test_criteria_workspace_size():
-    # zero region, then the larger of (4096 generating vectors + n mask bytes) and n + n/2 doubles
+    # zero region, the weights (2 d + 1 doubles), then the larger of (4096 generating
+    # vectors + n mask bytes) and n + n/2 doubles, each part 256-byte aligned
     def expect(d, n):
-        return (4 << 20) + (max(4096 * d * 8 + n, (n + n // 2 + 2) * 8) + 255) // 256 * 256
+        weights = ((2 * d + 1) * 8 + 255) // 256 * 256
+        return (4 << 20) + weights + (max(4096 * d * 8 + n, (n + n // 2 + 2) * 8) + 255) // 256 * 256
     for d, n in [(20, 65521), (200, 1009), (2, 1 << 24), (1024, 3)]:
         assert qmc.criteria_workspace_size(d, n) == expect(d, n)
 

@@ -1,5 +1,5 @@
 """Parity of the lattice-quality criteria and constructions (qmc_bernoulli_sum,
-qmc_korobov_search, qmc_cbc) with the FP64 oracle.
+qmc_p_alpha, qmc_shift_avg_wce2, qmc_korobov_search, qmc_cbc) with the FP64 oracle.
 
 Tolerance: criteria are FP64 sums of O(1) terms of both signs whose result is
 small, so |S - S_oracle| <= 1e-12 * max(|S_oracle|, A), A the oracle's mean |term|
@@ -8,6 +8,7 @@ integers decided by floating point: both sides apply the same rule (smallest
 candidate within 1e-10 relative of the minimum), so they are compared exactly,
 and the GPU's choice is also checked to attain the oracle's minimum.
 """
+import ctypes
 import math
 
 import numpy as np
@@ -55,14 +56,45 @@ def test_bernoulli_sum_mirrored_half_for_any_z(n):
             assert _close(s[r], so, ao), (n, alpha, r, s[r], so)
 
 
-@pytest.mark.parametrize("z,n", [([1, 3, 9, 27, 81], 1009), ([1, 40, 33, 19], 97)])
-def test_criterion_helpers(z, n):
+# The weights that make the Bernoulli sum S equal each criterion (eq. 2.4; eq. 2.12 with
+# product weights): used here only to take the oracle's mean |term| as the scale of
+# the mixed-sign sums.
+P_ALPHA_WEIGHT = {2: 2 * math.pi ** 2, 4: -2 * math.pi ** 4 / 3}
+
+
+def _p_alpha_scale(z, n, alpha):
+    return O.lattice_kernel_sum(z, n, alpha, np.full(len(z), P_ALPHA_WEIGHT[alpha]))[1]
+
+
+def _wce2_scale(z, n, gamma, beta):
+    g = np.asarray(gamma, dtype=np.float64)[: len(z)]
+    return float(np.prod(1 + g * beta)) * O.lattice_kernel_sum(z, n, 2, g / (1 + g * beta))[1]
+
+
+@pytest.mark.parametrize("z,n", [([1, 3, 9, 27, 81], 1009), ([1, 40, 33, 19], 97), ([1, 1], 2)])
+def test_criteria_entry_points(z, n):
+    """qmc_p_alpha and qmc_shift_avg_wce2 return eq. 2.4's and eq. 2.12's values."""
+    rows = np.stack([np.array(z), (np.array(z) * 7) % n])
     for alpha in (2, 4):
-        p = float(qmc.p_alpha(np.array(z), n, alpha)[0].item())
-        assert p == pytest.approx(O.p_alpha(z, n, alpha), rel=1e-10)
-    gamma, beta = [1.0, 0.5, 0.25, 0.125, 0.0625][: len(z)], 0.3
-    e2 = float(qmc.shift_avg_wce2(np.array(z), n, gamma, beta)[0].item())
-    assert e2 == pytest.approx(O.shift_avg_wce2(z, n, gamma, beta), rel=1e-10)
+        p = qmc.p_alpha(rows, n, alpha).cpu().numpy()
+        for r in range(2):
+            assert _close(p[r], O.p_alpha(rows[r], n, alpha), _p_alpha_scale(rows[r], n, alpha)), (alpha, r)
+    for gamma, beta in (([1.0, 0.5, 0.25, 0.125, 0.0625][: len(z)], 0.3), ([2.0] * len(z), 0.0),
+                        ([0.7] * len(z), 1.0 / 12.0)):
+        e2 = qmc.shift_avg_wce2(rows, n, gamma, beta).cpu().numpy()
+        for r in range(2):
+            eo = O.shift_avg_wce2(rows[r], n, gamma, beta)
+            assert _close(e2[r], eo, _wce2_scale(rows[r], n, gamma, beta)), (gamma, beta, r)
+
+
+def test_criteria_reject_bad_descriptors():
+    z = np.array([[1, 3, 9]])
+    with pytest.raises(qmc.QmcError):
+        qmc.p_alpha(z, 101, 3)
+    with pytest.raises(qmc.QmcError):
+        qmc.shift_avg_wce2(z, 101, [1.0, 1.0, 1.0], -0.5)
+    with pytest.raises(qmc.QmcError):
+        qmc.shift_avg_wce2(z, 101, [1.0, 1.0], 0.0)
 
 
 @pytest.mark.parametrize("d,n,alpha", [(8, 1009, 2), (5, 2003, 4), (4, 1000, 2), (4, 8191, 2)])
@@ -72,13 +104,33 @@ def test_korobov_search_matches_oracle(d, n, alpha):
     best = best.cpu().numpy()
     ov, ob = O.korobov_search(d, n, alpha)
     assert np.array_equal(np.isinf(vals), np.isinf(ov))
-    c = qmc.p_alpha_weight(alpha)
     for a in range(1, n):
         if np.isfinite(ov[a - 1]):
-            _, ao = O.lattice_kernel_sum(O.korobov(d, n, a), n, alpha, np.full(d, c))
+            ao = _p_alpha_scale(O.korobov(d, n, a), n, alpha)
             assert _close(vals[a - 1], ov[a - 1], ao), (a, vals[a - 1], ov[a - 1])
     assert int(best[1]) == ob
     assert best[0] == vals[ob - 1]
+
+
+@pytest.mark.parametrize("d,n,gamma,beta", [(5, 1009, [1.0, 0.5, 0.3, 0.2, 0.1], 0.0),
+                                            (3, 997, [0.9, 0.9, 0.9], 0.25)])
+def test_korobov_search_wce2_matches_oracle(d, n, gamma, beta):
+    """The search minimising e^2 of eq. 2.12: every candidate's e^2 against the oracle's
+    and the chosen a against the same selection rule on the oracle's values."""
+    vals, best = qmc.korobov_search(d, n, gamma=gamma, beta=beta)
+    vals = vals.cpu().numpy()
+    best = best.cpu().numpy()
+    ov = np.full(n - 1, np.inf)
+    for a in range(1, n):
+        if math.gcd(a, n) == 1:
+            z = O.korobov(d, n, a)
+            ov[a - 1] = O.shift_avg_wce2(z, n, gamma, beta)
+            assert _close(vals[a - 1], ov[a - 1], _wce2_scale(z, n, gamma, beta)), a
+        else:
+            assert np.isinf(vals[a - 1])
+    m = np.min(ov)
+    pick = 1 + int(np.argmax(ov <= m + 1e-10 * abs(m)))
+    assert int(best[1]) == pick and best[0] == vals[pick - 1]
 
 
 @pytest.mark.parametrize("d,n,gamma,beta", [
@@ -93,7 +145,22 @@ def test_cbc_matches_oracle(d, n, gamma, beta):
     e2 = e2.cpu().numpy()
     oz, oe2 = O.cbc(d, n, gamma, beta)
     assert np.array_equal(z, oz), (z, oz)
-    assert np.allclose(e2, oe2, rtol=1e-9, atol=1e-13)
+    for j in range(d):
+        assert _close(e2[j], oe2[j], _wce2_scale(oz[: j + 1], n, gamma, beta)), j
+
+
+def _greedy_p_alpha_cbc(d, n, alpha):
+    """CBC for P_alpha from oracle values: z_1 = 1, then the smallest coprime
+    c <= n/2 within 1e-10 relative of the minimum of P_alpha(z_1..z_{j-1}, c)."""
+    prefix, crit = [1], [O.p_alpha([1], n, alpha)]
+    for _ in range(1, d):
+        cand = [c for c in range(1, n // 2 + 1) if math.gcd(c, n) == 1]
+        vals = [O.p_alpha(prefix + [c], n, alpha) for c in cand]
+        m = min(vals)
+        pick = next(c for c, v in zip(cand, vals) if v <= m + 1e-10 * abs(m))
+        prefix.append(pick)
+        crit.append(vals[cand.index(pick)])
+    return np.array(prefix), np.array(crit)
 
 
 @pytest.mark.parametrize("n", [2, 3, 4, 6, 8, 30, 1024, 1025])
@@ -101,41 +168,31 @@ def test_cbc_matches_oracle(d, n, gamma, beta):
 def test_cbc_small_and_even_n(n, alpha):
     """The device sums each criterion over the mirrored half of the indices (k and
     n - k give mirrored points); odd and even n, down to n = 2, against the oracle's
-    full sums."""
+    full sums: e^2 (alpha = 2) and P_4."""
     d = 3
     if alpha == 2:
         gamma = np.array([1.0, 0.7, 0.3])
         z, e2 = qmc.cbc(d, n, gamma, 0.2)
         oz, oe2 = O.cbc(d, n, gamma, 0.2)
         assert np.array_equal(z.cpu().numpy(), oz)
-        assert np.allclose(e2.cpu().numpy(), oe2, rtol=1e-9, atol=1e-13)
-    else:
-        a = np.array([-1.5, -1.0, -0.5])
-        z, s = qmc.cbc(d, n, a, 0.0, alpha=4)
-        z = z.cpu().numpy()
-        s = s.cpu().numpy()
         for j in range(d):
-            so, _ = O.lattice_kernel_sum(list(z[: j + 1]), n, 4, a[: j + 1])
-            assert s[j] == pytest.approx(so, rel=1e-9, abs=1e-14), (n, j)
+            assert _close(e2.cpu().numpy()[j], oe2[j], _wce2_scale(oz[: j + 1], n, gamma, 0.2)), j
+    else:
+        z, s = qmc.cbc(d, n, alpha=4)
+        oz, os_ = _greedy_p_alpha_cbc(d, n, 4)
+        assert np.array_equal(z.cpu().numpy(), oz)
+        for j in range(d):
+            assert _close(s.cpu().numpy()[j], os_[j], _p_alpha_scale(oz[: j + 1], n, 4)), (n, j)
 
 
-def test_cbc_alpha4_against_exhaustive_oracle_search():
+@pytest.mark.parametrize("alpha", [2, 4])
+def test_cbc_p_alpha_against_exhaustive_oracle_search(alpha):
     d, n = 3, 101
-    a = np.array([-1.5, -1.0, -0.5])
-    z, s = qmc.cbc(d, n, a, 0.0, alpha=4)  # alpha = 4 takes the weights as they are
-    z = z.cpu().numpy()
-    s = s.cpu().numpy()
-    prefix = [1]
-    so, _ = O.lattice_kernel_sum(prefix, n, 4, a[:1])
-    assert s[0] == pytest.approx(so, rel=1e-9, abs=1e-14)
-    for j in range(1, d):
-        cand = [c for c in range(1, n // 2 + 1) if math.gcd(c, n) == 1]
-        vals = [O.lattice_kernel_sum(prefix + [c], n, 4, a[: j + 1])[0] for c in cand]
-        m = min(vals)
-        pick = next(c for c, v in zip(cand, vals) if v <= m + 1e-10 * abs(m))
-        assert z[j] == pick
-        assert s[j] == pytest.approx(m, rel=1e-9, abs=1e-14)
-        prefix.append(pick)
+    z, s = qmc.cbc(d, n, alpha=alpha)
+    oz, os_ = _greedy_p_alpha_cbc(d, n, alpha)
+    assert np.array_equal(z.cpu().numpy(), oz)
+    for j in range(d):
+        assert _close(s.cpu().numpy()[j], os_[j], _p_alpha_scale(oz[: j + 1], n, alpha)), j
 
 
 def test_korobov_search_d20_full_size_sampled():
@@ -143,16 +200,14 @@ def test_korobov_search_d20_full_size_sampled():
     [1, n/2]): sampled candidates against the oracle, the chosen a's value, and the
     selection rule on the GPU's own values."""
     w = W.korobov_search_d20()
-    a, c = qmc.wce2_weights(w.gamma, w.beta)
-    vals, best = qmc.korobov_search(w.d, w.n, w.alpha, a=a, a0=w.a0, count=w.count)
+    vals, best = qmc.korobov_search(w.d, w.n, gamma=w.gamma, beta=w.beta, a0=w.a0, count=w.count)
     vals = vals.cpu().numpy()
     best = best.cpu().numpy()
     assert np.all(np.isfinite(vals)) and vals.size == w.count
     for cand in (1, 2, 17, 4099, w.a0 + w.count - 1, int(best[1])):
         z = O.korobov(w.d, w.n, cand)
         eo = O.shift_avg_wce2(z, w.n, w.gamma, w.beta)
-        _, ao = O.lattice_kernel_sum(z, w.n, 2, a)
-        assert _close(c * vals[cand - w.a0], eo, c * ao), cand
+        assert _close(vals[cand - w.a0], eo, _wce2_scale(z, w.n, w.gamma, w.beta)), cand
     m = np.min(vals)
     assert best[0] <= m * (1 + 1e-10) and np.all(vals[: int(best[1]) - w.a0] > m * (1 + 1e-10))
 
@@ -165,27 +220,25 @@ def test_cbc_d20_full_size_components():
     z = z.cpu().numpy()
     e2 = e2.cpu().numpy()
     assert z[0] == 1 and np.all((z >= 1) & (z <= w.n // 2))
-    a, _ = qmc.wce2_weights(w.gamma, w.beta)
     for j in (0, 1, 2, 9, 19):
         eo = O.shift_avg_wce2(z[: j + 1], w.n, w.gamma[: j + 1], w.beta)
-        _, ao = O.lattice_kernel_sum(z[: j + 1], w.n, 2, a[: j + 1])
-        assert _close(e2[j], eo, ao), j
+        assert _close(e2[j], eo, _wce2_scale(z[: j + 1], w.n, w.gamma, w.beta)), j
     for c in (1, 2, 1000, 20000, w.n // 2):
         alt = O.shift_avg_wce2(np.concatenate([z[:1], [c]]), w.n, w.gamma[:2], w.beta)
         assert e2[1] <= alt * (1 + 1e-10)
 
 
 def test_criteria_graph_replays_match_eager():
-    """The Korobov search (table, mirrored Bernoulli sums, selection) and CBC (init,
-    then evaluation, selection and product update per component) captured in one
-    graph through the C ABI: every replay reproduces the eager results bit for bit,
-    with eager calls of other sizes on the same workspace in between."""
+    """The Korobov search (weights, table, mirrored Bernoulli sums, selection) and CBC
+    (weights, init, then evaluation, selection and product update per component)
+    captured in one graph through the C ABI: every replay reproduces the eager results
+    bit for bit, with eager calls of other sizes on the same workspace in between."""
     import torch
     L = qmc.lib()
     d, n, count = 6, 1031, 515
-    gamma = np.array([1.0, 0.8, 0.6, 0.4, 0.3, 0.2])
-    a_np, _ = qmc.wce2_weights(gamma, 0.1)
-    a = torch.tensor(a_np, dtype=torch.float64, device="cuda")
+    gamma_np = np.array([1.0, 0.8, 0.6, 0.4, 0.3, 0.2])
+    gamma = torch.tensor(gamma_np, dtype=torch.float64, device="cuda")
+    crit = qmc.Criterion(qmc.CRIT_WCE2, 2, qmc._ptr(gamma), 0.1)
     ws = qmc.Workspace(qmc.criteria_workspace_size(d, 4099))
     vals = torch.zeros(count, dtype=torch.float64, device="cuda")
     best = torch.zeros(2, dtype=torch.float64, device="cuda")
@@ -193,9 +246,9 @@ def test_criteria_graph_replays_match_eager():
     s = torch.zeros(d, dtype=torch.float64, device="cuda")
 
     def calls():
-        qmc._check(L.qmc_korobov_search(d, n, 2, qmc._ptr(a), 1, count, qmc._ptr(vals), qmc._ptr(best),
+        qmc._check(L.qmc_korobov_search(d, n, ctypes.byref(crit), 1, count, qmc._ptr(vals), qmc._ptr(best),
                                         ws.ptr, ws.nbytes, qmc._stream()), "qmc_korobov_search")
-        qmc._check(L.qmc_cbc(d, n, 2, qmc._ptr(a), qmc._ptr(z), qmc._ptr(s), ws.ptr, ws.nbytes,
+        qmc._check(L.qmc_cbc(d, n, ctypes.byref(crit), qmc._ptr(z), qmc._ptr(s), ws.ptr, ws.nbytes,
                              qmc._stream()), "qmc_cbc")
 
     calls()
@@ -215,9 +268,9 @@ def test_criteria_graph_replays_match_eager():
         torch.cuda.synchronize()
         for t, r in zip((vals, best, z, s), ref):
             assert torch.equal(t, r), rep
-        qmc.cbc(4, 4099, gamma[:4], 0.0, ws=ws)  # other sizes on the same workspace
-        qmc.korobov_search(3, 2048, 2, a=a_np[:3], a0=1, count=100, ws=ws)
+        qmc.cbc(4, 4099, gamma_np[:4], 0.0, ws=ws)  # other sizes on the same workspace
+        qmc.korobov_search(3, 2048, 2, a0=1, count=100, ws=ws)
         torch.cuda.synchronize()
     # the eager results themselves against the oracle
-    oz, oe2 = O.cbc(d, n, gamma, 0.1)
+    oz, oe2 = O.cbc(d, n, gamma_np, 0.1)
     assert np.array_equal(z.cpu().numpy(), oz)

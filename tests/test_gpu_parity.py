@@ -110,6 +110,63 @@ def test_plain_sum_float_index_boundary(n, shift):
             assert _rel(q, qo, ao) <= TOL[precision], (n, precision, ppt, q, qo)
 
 
+def _peak(seed, d, n, c, w, shift=False):
+    rng = np.random.default_rng(seed)
+    s = rng.uniform(0, 1, d) if shift else None
+    return W.Plain(f"peak{seed}", d, n, W.draw_coprime(rng, n), 1,
+                   np.concatenate([np.asarray(c, float), np.asarray(w, float)]), s)
+
+
+@pytest.mark.parametrize("case", ["narrow_at_0", "narrow_random", "one_narrow", "w_outside",
+                                  "c_at_limit", "d32", "d33"])
+def test_plain_sum_product_peak_guard(case):
+    """FP32 product-peak factors run only where every direction passes the guard
+    (|c_j| <= 4, factor range within 2^+-7); narrow peaks (c_j = 50..100, which would
+    underflow an FP32 run of 16 factors), centres far outside [0, 1], and d above
+    the FP32 limit take the FP64 factors.  Every case at both precisions' bars."""
+    rng = np.random.default_rng(len(case))
+    d, n = 20, 65537
+    if case == "narrow_at_0":      # point i = 0 sits on every peak
+        prob = _peak(1, d, n, rng.uniform(50, 100, d), np.zeros(d))
+    elif case == "narrow_random":
+        prob = _peak(2, d, n, rng.uniform(50, 100, d), rng.uniform(0, 1, d), shift=True)
+    elif case == "one_narrow":     # a single direction fails the guard
+        c = rng.uniform(0.5, 2, d)
+        c[7] = 60.0
+        prob = _peak(3, d, n, c, rng.uniform(0, 1, d))
+    elif case == "w_outside":
+        w = rng.uniform(0, 1, d)
+        w[3] = 40.0
+        prob = _peak(4, d, n, rng.uniform(0.5, 2, d), w, shift=True)
+    elif case == "c_at_limit":     # the widest range the FP32 form accepts
+        prob = _peak(5, d, n, np.full(d, 4.0), rng.uniform(0, 1, d), shift=True)
+    else:
+        dd = int(case[1:])
+        prob = _peak(6 + dd, dd, 30011, rng.uniform(0.5, 2, dd), rng.uniform(0, 1, dd))
+    qo, ao = _oracle_sum(prob)
+    assert np.isfinite(qo)
+    for precision in PRECS:
+        for ppt in (4, 16):
+            q = _gpu_sum(prob, precision, points_per_thread=ppt)
+            assert np.isfinite(q) and _rel(q, qo, ao) <= TOL[precision], (case, precision, ppt, q, qo)
+
+
+def test_batched_product_peak_guard():
+    """The same guard in the batched kernel: narrow, wide and in-range product peaks in
+    one launch, each against the oracle."""
+    rng = np.random.default_rng(21)
+    probs = [_peak(31, 20, 40009, rng.uniform(50, 100, 20), np.zeros(20)),
+             _peak(32, 12, 20011, rng.uniform(0.5, 2, 12), rng.uniform(0, 1, 12)),
+             _peak(33, 30, 30011, np.r_[rng.uniform(0.5, 2, 29), 70.0], rng.uniform(0, 1, 30), shift=True),
+             _peak(34, 8, 10007, np.full(8, 4.0), rng.uniform(0, 1, 8))]
+    descs = [(p.family, qmc.korobov(p.d, p.n, p.a), p.n, p.params, p.shift) for p in probs]
+    for precision in PRECS:
+        q = qmc.BatchPlan(descs, precision).run().cpu().numpy()
+        for i, p in enumerate(probs):
+            qo, ao = _oracle_sum(p)
+            assert np.isfinite(q[i]) and _rel(q[i], qo, ao) <= TOL[precision], (i, precision, q[i], qo)
+
+
 def test_plain_sum_max_dimension():
     for family in range(5):
         prob = W.random_plain(5 + family, family, 1024, 257, shift=True)
@@ -158,7 +215,7 @@ def test_character_identity_on_device():
         params = np.concatenate([[u], 2 * math.pi * h.astype(float)])
         expect = math.cos(2 * math.pi * u + 2 * math.pi * float(np.dot(h, shift))) if in_dual else 0.0
         q = float(qmc.lattice_sum(z, n, qmc.OSCILLATORY, params, qmc.FP64, shift=shift).item())
-        assert abs(q - expect) < 1e-9, (h, q, expect)
+        assert abs(q - expect) < 1e-12, (h, q, expect)
 
 
 @pytest.mark.parametrize("shifted", [False, True])
@@ -175,7 +232,7 @@ def test_character_identity_at_largest_n(shifted):
         h = np.array(h, dtype=float)
         params = np.concatenate([[u], 2 * math.pi * h])
         expect = math.cos(2 * math.pi * u + 2 * math.pi * float(np.dot(h, shift))) if in_dual else 0.0
-        for precision, tol in ((qmc.FP64, 1e-9), (qmc.FP32_COMPENSATED, 1e-6)):
+        for precision, tol in ((qmc.FP64, 1e-12), (qmc.FP32_COMPENSATED, 1e-6)):
             for ppt in (4, 8, 16):
                 q = float(qmc.lattice_sum(z, n, qmc.OSCILLATORY, params, precision,
                                           shift=shift if shifted else None,
@@ -491,3 +548,56 @@ def test_validate_mode_rejects_out_of_range_z_and_shift(monkeypatch):
     g.replay()
     torch.cuda.synchronize()
     assert float(out[0]) == q_plain
+
+
+@pytest.mark.parametrize("precision", PRECS)
+def test_mdi_lr_exp_sum_d1000_identical_directions(precision):
+    """exp of the alternating sum at d = 1000 with N = 64 nodes: two kinds of identical
+    directions, so any rounding of one factor repeats 500 times; held to the usual bars."""
+    d = 1000
+    p = np.array([(-1.0) ** j for j in range(d)])
+    for N in (8, 64, 1000):
+        q = float(qmc.mdi_lr(np.full(d, N, np.int32), qmc.EXP_SUM, p, precision).item())
+        qo = O.mdi_lr(np.full(d, N), O.EXP_SUM, p)
+        assert abs(q - qo) <= TOL[precision] * abs(qo), (N, q, qo)
+
+
+@pytest.mark.parametrize("precision", PRECS)
+@pytest.mark.parametrize("family", [0, 1, 2, 3, 4])
+@pytest.mark.parametrize("d,nsets", [(1, 5), (3, 1), (7, 300), (64, 2), (65, 70), (130, 3)])
+def test_mdi_lr_lane_groups(precision, family, d, nsets):
+    """Sets spread over 1 to 64 lanes (a power of two no larger than d, chosen by the
+    number of sets), with ragged node counts: every set against the oracle."""
+    rng = np.random.default_rng(1000 * d + nsets + family)
+    N = rng.integers(1, 40, d).astype(np.int32)
+    params = np.stack([W.draw_params(rng, family, d) for _ in range(nsets)])
+    q = qmc.mdi_lr(N, family, params, precision).cpu().numpy()
+    for s in range(nsets):
+        qo = O.mdi_lr(N.astype(np.int64), family, params[s])
+        if family == 3:
+            re, im = O.mdi_lr_factors(N.astype(np.int64), family, params[s])
+            scale = float(np.prod(np.hypot(re, im)))
+        else:
+            scale = abs(qo)
+        assert abs(q[s] - qo) <= TOL[precision] * scale, (s, q[s], qo)
+
+
+def test_mdi_lr_node_counts_out_of_range(monkeypatch):
+    """N_k outside [1, 2^20] is the caller's contract: QMC_VALIDATE=1 rejects it before
+    any launch; without the check the results are NaN (never a clamped count)."""
+    d = 6
+    p = W.draw_params(np.random.default_rng(3), qmc.GAUSSIAN, d)
+    good = np.full(d, 16, np.int32)
+    ref = float(qmc.mdi_lr(good, qmc.GAUSSIAN, p, qmc.FP64).item())
+    for bad in (0, -5, (1 << 20) + 1):
+        N = good.copy()
+        N[4] = bad
+        for precision in PRECS:
+            q = qmc.mdi_lr(N, qmc.GAUSSIAN, np.stack([p, p]), precision).cpu().numpy()
+            assert np.all(np.isnan(q)), (bad, precision, q)
+        monkeypatch.setenv("QMC_VALIDATE", "1")
+        with pytest.raises(qmc.QmcError) as e:
+            qmc.mdi_lr(N, qmc.GAUSSIAN, p, qmc.FP64)
+        assert e.value.status == qmc.ERR_INVALID_ARG and "N[4]" in str(e.value)
+        assert float(qmc.mdi_lr(good, qmc.GAUSSIAN, p, qmc.FP64).item()) == ref
+        monkeypatch.delenv("QMC_VALIDATE")
