@@ -4,9 +4,11 @@ qmc_p_alpha, qmc_shift_avg_wce2, qmc_korobov_search, qmc_cbc) with the FP64 orac
 Tolerance: criteria are FP64 sums of O(1) terms of both signs whose result is
 small, so |S - S_oracle| <= 1e-12 * max(|S_oracle|, A), A the oracle's mean |term|
 (the measure used for every mixed-sign sum).  The chosen generating vectors are
-integers decided by floating point: both sides apply the same rule (smallest
-candidate within 1e-10 relative of the minimum), so they are compared exactly,
-and the GPU's choice is also checked to attain the oracle's minimum.
+integers decided by floating point: for e^2 both sides apply the same rule
+(smallest candidate within 1e-10 relative of the minimum) and are compared
+exactly; for P_alpha, whose minimum can sit many orders of magnitude below its
+terms and tie exactly between candidates, the GPU's choice is checked to attain
+the oracle's minimum within the tolerance above.
 """
 import ctypes
 import math
@@ -149,18 +151,26 @@ def test_cbc_matches_oracle(d, n, gamma, beta):
         assert _close(e2[j], oe2[j], _wce2_scale(oz[: j + 1], n, gamma, beta)), j
 
 
-def _greedy_p_alpha_cbc(d, n, alpha):
-    """CBC for P_alpha from oracle values: z_1 = 1, then the smallest coprime
-    c <= n/2 within 1e-10 relative of the minimum of P_alpha(z_1..z_{j-1}, c)."""
-    prefix, crit = [1], [O.p_alpha([1], n, alpha)]
-    for _ in range(1, d):
-        cand = [c for c in range(1, n // 2 + 1) if math.gcd(c, n) == 1]
-        vals = [O.p_alpha(prefix + [c], n, alpha) for c in cand]
-        m = min(vals)
-        pick = next(c for c, v in zip(cand, vals) if v <= m + 1e-10 * abs(m))
-        prefix.append(pick)
-        crit.append(vals[cand.index(pick)])
-    return np.array(prefix), np.array(crit)
+def _check_p_alpha_cbc(z, s, n, alpha):
+    """A P_alpha CBC result is valid when, at every component j, the chosen z_j is
+    coprime to n, lies in [1, n/2], and its oracle P_alpha(z_1..z_j) attains the oracle's
+    minimum over all such candidates given the same z_1..z_{j-1}, within the
+    tolerance of the mixed-sign sums; and s_j is the oracle's P_alpha of z_1..z_j.
+    Where the minimum is isolated this fixes z_j; exact ties (c and its inverse
+    mod n at d = 2, where P_alpha sits many orders of magnitude below its terms)
+    leave either choice valid."""
+    assert z[0] == 1
+    for j in range(len(z)):
+        if j > 0:
+            assert 1 <= z[j] <= n // 2 and math.gcd(int(z[j]), n) == 1, (j, z[j])
+            prefix = [int(c) for c in z[:j]]
+            m = min(O.p_alpha(prefix + [c], n, alpha)
+                    for c in range(1, n // 2 + 1) if math.gcd(c, n) == 1)
+        got = O.p_alpha(z[: j + 1], n, alpha)
+        scale = _p_alpha_scale(z[: j + 1], n, alpha)
+        if j > 0:
+            assert got - m <= TOL * max(abs(m), scale), (n, j, z[j], got, m)
+        assert _close(s[j], got, scale), (n, j, s[j], got)
 
 
 @pytest.mark.parametrize("n", [2, 3, 4, 6, 8, 30, 1024, 1025])
@@ -179,20 +189,14 @@ def test_cbc_small_and_even_n(n, alpha):
             assert _close(e2.cpu().numpy()[j], oe2[j], _wce2_scale(oz[: j + 1], n, gamma, 0.2)), j
     else:
         z, s = qmc.cbc(d, n, alpha=4)
-        oz, os_ = _greedy_p_alpha_cbc(d, n, 4)
-        assert np.array_equal(z.cpu().numpy(), oz)
-        for j in range(d):
-            assert _close(s.cpu().numpy()[j], os_[j], _p_alpha_scale(oz[: j + 1], n, 4)), (n, j)
+        _check_p_alpha_cbc(z.cpu().numpy(), s.cpu().numpy(), n, 4)
 
 
 @pytest.mark.parametrize("alpha", [2, 4])
 def test_cbc_p_alpha_against_exhaustive_oracle_search(alpha):
     d, n = 3, 101
     z, s = qmc.cbc(d, n, alpha=alpha)
-    oz, os_ = _greedy_p_alpha_cbc(d, n, alpha)
-    assert np.array_equal(z.cpu().numpy(), oz)
-    for j in range(d):
-        assert _close(s.cpu().numpy()[j], os_[j], _p_alpha_scale(oz[: j + 1], n, alpha)), j
+    _check_p_alpha_cbc(z.cpu().numpy(), s.cpu().numpy(), n, alpha)
 
 
 def test_korobov_search_d20_full_size_sampled():
