@@ -31,7 +31,7 @@
  *   - Launches are asynchronous on `stream` (a hipStream_t; NULL = the default
  *     stream).  Results are valid once the stream has been synchronised.
  *   - No entry point that launches work allocates memory.  Scratch space comes
- *     from the caller's workspace `ws` (device, 256-byte aligned, at least the
+ *     (except for qmc_lattice_sum_noalloc) from the caller's workspace `ws` (device, 256-byte aligned, at least the
  *     size reported by the matching *_workspace_size query).  Its first 4 MiB
  *     hold completion counters and reduction slots: a workspace must be
  *     zero-filled once before its first use, and every call leaves that region at
@@ -144,6 +144,23 @@ qmc_status qmc_lattice_sum(int32_t d, int64_t n, const int64_t* z, const double*
                            int32_t family, const double* params, int32_t nsets,
                            int32_t precision, double* q_out, void* ws, size_t ws_bytes,
                            void* stream);
+
+/* qmc_lattice_sum without a workspace argument, for callers that cannot allocate
+ * device memory (code under graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc): the same kernels and the same result, bit for bit, with
+ * their counters and reduction slots in a static device array of 4 MiB inside the
+ * library (one per device, set up and cleared by the first call on that device
+ * with the device current, held until the process ends).  The call allocates
+ * nothing, on the device or the host.
+ *   Arguments as qmc_lattice_sum (limits too: nsets <= 4096 fits the static
+ *   scratch; a larger need returns QMC_ERR_WORKSPACE).
+ * Every call on a device shares that device's array; a completed call leaves it
+ * zero for the next one.  Calls that overlap on one device (other streams, other
+ * threads) race and give wrong results: serialise them, or use qmc_lattice_sum
+ * with distinct workspaces. */
+qmc_status qmc_lattice_sum_noalloc(int32_t d, int64_t n, const int64_t* z, const double* shift,
+                                   int32_t family, const double* params, int32_t nsets,
+                                   int32_t precision, double* q_out, void* stream);
 
 /* Randomly shifted lattice rule (Sec. 2.1: the shifted lattice P + Delta, whose
  * error averaged over a shift drawn uniformly from [0,1]^d is the quality measure

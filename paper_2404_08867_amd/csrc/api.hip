@@ -4,31 +4,31 @@
 #include <stdio.h>
 #include <stdlib.h>
 
-#include <string>
-#include <vector>
+#include <mutex>
 
 #include "qmc.h"
+#include "common.hpp"
 #include "kernels.hpp"
 #include "status.hpp"
 
 namespace {
-thread_local std::string g_last_error;
+// Message of the last failing call on this thread; a fixed buffer, so that no call
+// allocates host memory either, on any path.
+thread_local char g_last_error[512];
 }
 
 namespace qmc {
 
 qmc_status fail(qmc_status s, const char* fmt, ...) {
-    char buf[512];
     va_list ap;
     va_start(ap, fmt);
-    vsnprintf(buf, sizeof(buf), fmt, ap);
+    vsnprintf(g_last_error, sizeof(g_last_error), fmt, ap);
     va_end(ap);
-    g_last_error = buf;
     return s;
 }
 
 qmc_status ok() {
-    g_last_error.clear();
+    g_last_error[0] = '\0';
     return QMC_OK;
 }
 
@@ -52,37 +52,54 @@ bool capturing(hipStream_t stream) {
     return hipStreamIsCapturing(stream, &st) == hipSuccess && st != hipStreamCaptureStatusNone;
 }
 
-template <class T>
-qmc_status read_back(const T* dev, size_t count, hipStream_t stream, std::vector<T>& host, const char* what) {
-    host.resize(count);
-    hipError_t e = hipMemcpyAsync(host.data(), dev, count * sizeof(T), hipMemcpyDeviceToHost, stream);
-    if (e == hipSuccess) e = hipStreamSynchronize(stream);
-    if (e != hipSuccess) return from_hip(e, what);
+// Reads the `count` entries of device array `dev` back on `stream` in chunks of 4 KiB
+// through a buffer on the stack (no allocation) and sets *bad to the index of the
+// first entry x with !good(x) (count if there is none) and *bad_value to that entry.
+template <class T, class Good>
+qmc_status scan_back(const T* dev, size_t count, hipStream_t stream, const char* what, Good good,
+                     size_t* bad, T* bad_value) {
+    constexpr size_t kChunk = 4096 / sizeof(T);
+    T h[kChunk];
+    for (size_t i0 = 0; i0 < count; i0 += kChunk) {
+        const size_t m = count - i0 < kChunk ? count - i0 : kChunk;
+        hipError_t e = hipMemcpyAsync(h, dev + i0, m * sizeof(T), hipMemcpyDeviceToHost, stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(stream);
+        if (e != hipSuccess) return from_hip(e, what);
+        for (size_t i = 0; i < m; ++i)
+            if (!good(h[i])) {
+                *bad = i0 + i;
+                *bad_value = h[i];
+                return QMC_OK;
+            }
+    }
+    *bad = count;
     return QMC_OK;
 }
 
 // z: `count` int64 entries, each in [0, n).
 qmc_status validate_z(const int64_t* z, size_t count, int64_t n, void* stream, const char* what) {
     if (!validate_mode() || !z || capturing((hipStream_t)stream)) return QMC_OK;
-    std::vector<int64_t> h;
-    qmc_status s = read_back(z, count, (hipStream_t)stream, h, what);
+    size_t i = 0;
+    int64_t x = 0;
+    qmc_status s = scan_back(z, count, (hipStream_t)stream, what,
+                             [n](int64_t v) { return v >= 0 && v < n; }, &i, &x);
     if (s != QMC_OK) return s;
-    for (size_t i = 0; i < count; ++i)
-        if (h[i] < 0 || h[i] >= n)
-            return fail(QMC_ERR_INVALID_ARG, "%s: z[%zu] = %lld outside [0, %lld) (QMC_VALIDATE)", what, i,
-                        (long long)h[i], (long long)n);
+    if (i < count)
+        return fail(QMC_ERR_INVALID_ARG, "%s: z[%zu] = %lld outside [0, %lld) (QMC_VALIDATE)", what, i,
+                    (long long)x, (long long)n);
     return QMC_OK;
 }
 
 // shift: `count` doubles, each in [0, 1).
 qmc_status validate_shift(const double* sh, size_t count, void* stream, const char* what) {
     if (!validate_mode() || !sh || capturing((hipStream_t)stream)) return QMC_OK;
-    std::vector<double> h;
-    qmc_status s = read_back(sh, count, (hipStream_t)stream, h, what);
+    size_t i = 0;
+    double x = 0.0;
+    qmc_status s = scan_back(sh, count, (hipStream_t)stream, what,
+                             [](double v) { return v >= 0.0 && v < 1.0; }, &i, &x);
     if (s != QMC_OK) return s;
-    for (size_t i = 0; i < count; ++i)
-        if (!(h[i] >= 0.0 && h[i] < 1.0))
-            return fail(QMC_ERR_INVALID_ARG, "%s: shift[%zu] = %g outside [0, 1) (QMC_VALIDATE)", what, i, h[i]);
+    if (i < count)
+        return fail(QMC_ERR_INVALID_ARG, "%s: shift[%zu] = %g outside [0, 1) (QMC_VALIDATE)", what, i, x);
     return QMC_OK;
 }
 
@@ -148,6 +165,58 @@ int64_t gcd64(int64_t a, int64_t b) {
 
 }  // namespace
 
+// ---------------------------------------------------------------------------
+// Scratch of qmc_lattice_sum_noalloc: the plain sum's counter and tagged-slot region
+// (qmc::kZeroBytes = 4 MiB), one copy per device in the library's code object, held
+// until the process ends.  Its name stands for a host-side shadow in host code; the
+// device address comes from hipGetSymbolAddress, once per device, and only that
+// address is ever passed on.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) unsigned char scratch[qmc::kZeroBytes];
+
+namespace {
+
+constexpr size_t kNoallocScratchBytes = qmc::kZeroBytes;
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mutex;
+void* g_scratch_addr[kMaxDevices];  // device address of `scratch` per device, null until set up
+
+__global__ __launch_bounds__(256) void scratch_clear_kernel(uint4* p, size_t count) {
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += stride)
+        p[i] = make_uint4(0u, 0u, 0u, 0u);
+}
+
+// This device's scratch address.  The first call on a device (with the device
+// current) looks the address up and clears the array with a kernel on `stream`
+// (the plain sum needs its counters and slots zero, and leaves them zero when it
+// completes).
+qmc_status scratch_address(hipStream_t stream, void** addr) {
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return from_hip(e, "qmc_lattice_sum_noalloc: hipGetDevice");
+    if (dev < 0 || dev >= kMaxDevices)
+        return fail(QMC_ERR_UNSUPPORTED, "qmc_lattice_sum_noalloc: device %d beyond the %d supported", dev,
+                    kMaxDevices);
+    std::lock_guard<std::mutex> lock(g_scratch_mutex);
+    if (!g_scratch_addr[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return from_hip(e, "qmc_lattice_sum_noalloc: hipGetSymbolAddress(scratch)");
+        if (!p || ((uintptr_t)p) % 256 != 0)
+            return fail(QMC_ERR_DEVICE, "qmc_lattice_sum_noalloc: scratch address %p unusable", p);
+        hipLaunchKernelGGL(scratch_clear_kernel, dim3(256), dim3(256), 0, stream, (uint4*)p,
+                           kNoallocScratchBytes / sizeof(uint4));
+        e = hipGetLastError();
+        if (e != hipSuccess) return from_hip(e, "qmc_lattice_sum_noalloc: clearing the scratch");
+        g_scratch_addr[dev] = p;
+    }
+    *addr = g_scratch_addr[dev];
+    return QMC_OK;
+}
+
+}  // namespace
+
 extern "C" {
 
 const char* qmc_version(void) { return "qmc-mi355x 0.1.0 (gfx950)"; }
@@ -164,7 +233,7 @@ const char* qmc_status_string(qmc_status s) {
     return "unknown status";
 }
 
-const char* qmc_last_error(void) { return g_last_error.c_str(); }
+const char* qmc_last_error(void) { return g_last_error; }
 
 qmc_status qmc_korobov(int32_t d, int64_t n, int64_t a, int64_t* z_out) {
     if (d < 1 || d > kMaxD) return fail(QMC_ERR_INVALID_ARG, "d = %d outside [1, %d]", d, kMaxD);
@@ -353,6 +422,42 @@ qmc_status qmc_lattice_sum_ex(int32_t d, int64_t n, const int64_t* z, const doub
     return from_hip(qmc::launch_lattice_sum(L, (hipStream_t)stream), "qmc_lattice_sum");
 }
 
+qmc_status qmc_lattice_sum_noalloc(int32_t d, int64_t n, const int64_t* z, const double* shift,
+                                   int32_t family, const double* params, int32_t nsets,
+                                   int32_t precision, double* q_out, void* stream) {
+    qmc_status s = check_common(d, family, nsets, precision);
+    if (s != QMC_OK) return s;
+    if (n < 1 || n >= kMaxN) return fail(QMC_ERR_INVALID_ARG, "n = %lld outside [1, 2^31)", (long long)n);
+    if (!z || !params || !q_out) return fail(QMC_ERR_INVALID_ARG, "z, params and q_out must be non-NULL");
+    const size_t need = qmc::plain_workspace_bytes(nsets);
+    if (need > kNoallocScratchBytes)
+        return fail(QMC_ERR_WORKSPACE,
+                    "qmc_lattice_sum_noalloc: nsets = %d needs %zu bytes of scratch, the static scratch holds %zu",
+                    nsets, need, kNoallocScratchBytes);
+    if ((s = validate_z(z, (size_t)d, n, stream, "qmc_lattice_sum_noalloc")) != QMC_OK) return s;
+    if ((s = validate_shift(shift, (size_t)d, stream, "qmc_lattice_sum_noalloc")) != QMC_OK) return s;
+    void* ws = nullptr;
+    if ((s = scratch_address((hipStream_t)stream, &ws)) != QMC_OK) return s;
+    qmc::PlainLaunch L{};
+    L.d = d;
+    L.n = (uint32_t)n;
+    L.z = z;
+    L.shift = shift;
+    L.family = family;
+    L.params = params;
+    L.P = param_count(family, d);
+    L.nsets = nsets;
+    L.param_stride = L.P;
+    L.shift_stride = 0;
+    L.z_stride = 0;
+    L.fp32 = precision == QMC_FP32_COMPENSATED;
+    L.q_out = q_out;
+    L.ws = ws;
+    L.points_per_thread = 0;
+    L.max_blocks = 0;
+    return from_hip(qmc::launch_lattice_sum(L, (hipStream_t)stream), "qmc_lattice_sum_noalloc");
+}
+
 qmc_status qmc_lattice_sum_shifts(int32_t d, int64_t n, const int64_t* z, const double* shifts,
                                   int32_t nshifts, int32_t family, const double* params,
                                   int32_t precision, double* q_out, double* stats_out, void* ws,
@@ -406,13 +511,14 @@ static qmc_status check_criteria(int32_t d, int64_t n, int32_t alpha, const doub
 // gamma_j >= 0 (device) is the caller's contract, read back under QMC_VALIDATE.
 static qmc_status validate_gamma(const double* gamma, int32_t d, void* stream, const char* what) {
     if (!qmc::validate_mode() || qmc::capturing((hipStream_t)stream)) return QMC_OK;
-    std::vector<double> h;
-    qmc_status s = qmc::read_back(gamma, (size_t)d, (hipStream_t)stream, h, what);
+    size_t j = 0;
+    double x = 0.0;
+    qmc_status s = qmc::scan_back(gamma, (size_t)d, (hipStream_t)stream, what,
+                                  [](double v) { return v >= 0.0 && v < INFINITY; }, &j, &x);
     if (s != QMC_OK) return s;
-    for (int32_t j = 0; j < d; ++j)
-        if (!(h[j] >= 0.0 && h[j] < INFINITY))
-            return fail(QMC_ERR_INVALID_ARG, "%s: gamma[%d] = %g is not a finite weight >= 0 (QMC_VALIDATE)",
-                        what, j, h[j]);
+    if (j < (size_t)d)
+        return fail(QMC_ERR_INVALID_ARG, "%s: gamma[%zu] = %g is not a finite weight >= 0 (QMC_VALIDATE)",
+                    what, j, x);
     return QMC_OK;
 }
 
@@ -633,13 +739,13 @@ qmc_status qmc_mdi_lr(int32_t d, const int32_t* N, int32_t family, const double*
     if (s != QMC_OK) return s;
     if (!N || !params || !q_out) return fail(QMC_ERR_INVALID_ARG, "N, params and q_out must be non-NULL");
     if (qmc::validate_mode() && !qmc::capturing((hipStream_t)stream)) {
-        std::vector<int32_t> h;
-        s = qmc::read_back(N, (size_t)d, (hipStream_t)stream, h, "qmc_mdi_lr");
+        size_t k = 0;
+        int32_t x = 0;
+        s = qmc::scan_back(N, (size_t)d, (hipStream_t)stream, "qmc_mdi_lr",
+                           [](int32_t v) { return v >= 1 && v <= kMaxNodes; }, &k, &x);
         if (s != QMC_OK) return s;
-        for (int32_t k = 0; k < d; ++k)
-            if (h[k] < 1 || h[k] > kMaxNodes)
-                return fail(QMC_ERR_INVALID_ARG, "qmc_mdi_lr: N[%d] = %d outside [1, 2^20] (QMC_VALIDATE)", k,
-                            h[k]);
+        if (k < (size_t)d)
+            return fail(QMC_ERR_INVALID_ARG, "qmc_mdi_lr: N[%zu] = %d outside [1, 2^20] (QMC_VALIDATE)", k, x);
     }
     qmc::MdiLaunch L{};
     L.d = d;

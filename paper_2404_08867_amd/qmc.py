@@ -63,6 +63,7 @@ def lib() -> ctypes.CDLL:
         L.qmc_workspace_size.argtypes = [i32, i64, i32, vp]
         L.qmc_lattice_sum.argtypes = [i32, i64, dp, dp, i32, dp, i32, i32, dp, vp, sz, vp]
         L.qmc_lattice_sum_ex.argtypes = [i32, i64, dp, dp, i32, dp, i32, i32, dp, vp, sz, vp, vp]
+        L.qmc_lattice_sum_noalloc.argtypes = [i32, i64, dp, dp, i32, dp, i32, i32, dp, vp]
         L.qmc_lattice_sum_shifts.argtypes = [i32, i64, dp, dp, i32, i32, dp, i32, dp, dp, vp, sz, vp]
         L.qmc_lattice_points.argtypes = [i32, i64, dp, i64, i64, dp, vp]
         L.qmc_criteria_workspace_size.argtypes = [i32, i64, vp]
@@ -89,7 +90,8 @@ def lib() -> ctypes.CDLL:
         L.qmc_graph_launch.argtypes = [vp, vp]
         L.qmc_graph_destroy.argtypes = [vp]
         for name in ("qmc_korobov", "qmc_mdi_lr_dims", "qmc_param_count", "qmc_workspace_size",
-                     "qmc_lattice_sum", "qmc_lattice_sum_ex", "qmc_lattice_points", "qmc_mdi_lr",
+                     "qmc_lattice_sum", "qmc_lattice_sum_ex", "qmc_lattice_sum_noalloc",
+                     "qmc_lattice_points", "qmc_mdi_lr",
                      "qmc_lattice_sum_adjoint",
                      "qmc_batch_plan_create", "qmc_batch_plan_destroy", "qmc_batch_plan_config",
                      "qmc_batch_plan_set_config", "qmc_batch_workspace_size",
@@ -244,6 +246,34 @@ def lattice_sum(z, n: int, family: int, params, precision: int = FP64, shift=Non
         _check(lib().qmc_lattice_sum_ex(d, n, _ptr(zt), _ptr(st), family, _ptr(pt), nsets, precision,
                                         _ptr(q), w.ptr, w.nbytes, _stream(), ctypes.byref(cfg)),
                "qmc_lattice_sum")
+    if out is not None:
+        return out
+    return q[0] if squeeze else q
+
+
+def lattice_sum_noalloc(z, n: int, family: int, params, precision: int = FP64, shift=None,
+                        device="cuda", out=None):
+    """qmc_lattice_sum_noalloc: lattice_sum with the library's static per-device
+    scratch instead of a workspace (the library allocates nothing; calls that
+    overlap on one device race).  Same arguments and result as lattice_sum."""
+    torch = _torch()
+    zt = _dev(z, torch.int64, device)
+    pt = _dev(params, torch.float64, device)
+    squeeze = pt.dim() == 1
+    if squeeze:
+        pt = pt.unsqueeze(0)
+    d = int(zt.numel())
+    nsets = int(pt.shape[0])
+    st = None if shift is None else _dev(shift, torch.float64, device)
+    if out is not None:
+        if out.dtype != torch.float64 or out.numel() < nsets or not out.is_contiguous():
+            raise QmcError(ERR_INVALID_ARG, "out must be a contiguous float64 tensor of >= nsets values")
+        q = out
+    else:
+        q = torch.empty(nsets, dtype=torch.float64, device=device)
+    with _on(q):
+        _check(lib().qmc_lattice_sum_noalloc(d, n, _ptr(zt), _ptr(st), family, _ptr(pt), nsets, precision,
+                                             _ptr(q), _stream()), "qmc_lattice_sum_noalloc")
     if out is not None:
         return out
     return q[0] if squeeze else q
