@@ -155,7 +155,7 @@ def parse():
     ap.add_argument("--workload", default="batched_4096",
                     choices=["plain_d20_peak", "plain_d4_expsum", "plain_d20_f5", "mdi_d100_gauss", "batched_4096",
                              "adjoint_d50_osc", "shifts_d20_peak", "korobov_search_d20",
-                             "cbc_d20", "mdi_sum_d100", "implr_d3"])
+                             "cbc_d20", "mdi_sum_d100", "implr_d3", "rates"])
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
                     help="one core's worth of oracle work in the CPU-baseline sample of a plain workload")
     ap.add_argument("--batched-stride", type=int, default=64,
@@ -800,6 +800,67 @@ def oracle_adjoint_baseline(w, r32, r64):
     return w.n / dt, errs[0], errs[1]
 
 
+# ---------------------------------------------------------------- issue-rate probe
+# paper_2404_08867_amd/probe/issue_rates.hip (libqmc_probe.so): lane-operations per second
+# of each instruction type on the lattice path, alone and mixed, over 8 workgroups of 256
+# threads per CU with 8 independent chains per thread.  The ceiling the ALU rooflines use,
+# 256 CUs x 64 lanes x 2.4 GHz, and the transcendental costs rest on these figures.
+PROBE_KINDS = ["u32_add", "index_step(add,add,min)", "f32_fma", "f64_fma", "f64_add", "cvt_f64_u32",
+               "cvt_f32_u32", "exp2_f32", "rcp_f32", "cos_f32", "log2_f32", "f64_fma x4 + exp2_f32",
+               "u32_add + f64_fma", "point_dim(index step, cvt_f64_u32, f64_fma)", "u32_min", "u32_sub",
+               "sub + cmp + cndmask", "f32_add", "f32_mul", "float_step(f32 add x2, u32 min)",
+               "u32_add + f32_fma", "f32_fma + f64_fma", "f32_fma x4 + exp2_f32",
+               "peak_dim(float step, f32 fma x2, f32 mul)", "cvt_f64_f32",
+               "point_dim_float(float step, cvt_f64_f32, f64_fma)",
+               "gauss_dim(index step, cvt_f64_u32, f64_fma x2)",
+               "gauss_dim_float(float step, cvt_f64_f32, f64_fma x2)"]
+PROBE_MAIN = "point_dim(index step, cvt_f64_u32, f64_fma)"
+LANE_RATE = 256 * 64 * 2.4e9  # one VALU lane-operation per lane per clock
+
+
+def bench_rates(args, torch):
+    import ctypes
+    lib = ctypes.CDLL(os.path.join(ROOT, "paper_2404_08867_amd", "libqmc_probe.so"))
+    lib.qmc_probe_lane_ops.restype = ctypes.c_double
+    lib.qmc_probe_lane_ops.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int]
+    lib.qmc_probe_launch.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p]
+    assert lib.qmc_probe_kinds() == len(PROBE_KINDS)
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    blocks, iters = 8 * cus, 256
+    out = torch.empty(blocks * 256, dtype=torch.float64, device="cuda")
+    stream = torch.cuda.current_stream()
+    rates = {}
+    for k, name in enumerate(PROBE_KINDS):
+        def launch(k=k):
+            rc = lib.qmc_probe_launch(k, blocks, iters, ctypes.c_void_p(out.data_ptr()),
+                                      ctypes.c_void_p(stream.cuda_stream))
+            if rc != 0:
+                raise RuntimeError(f"qmc_probe_launch({k}) returned {rc}")
+        for _ in range(max(1, args.warmup)):
+            launch()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(args.steps):
+            launch()
+        e1.record()
+        torch.cuda.synchronize()
+        t = e0.elapsed_time(e1) * 1e-3 / args.steps
+        ops = lib.qmc_probe_lane_ops(k, blocks, iters)
+        rates[name] = {"lane_ops_per_s": ops / t, "vs_lane_rate": ops / t / LANE_RATE, "launch_us": t * 1e6}
+    main = rates[PROBE_MAIN]
+    line = {"metric": "VALU lane-operation issue rate of the point-and-direction loop (probe)",
+            "value": main["lane_ops_per_s"], "unit": "lane-ops/s", "n_gpus": 1, "steps": args.steps,
+            "warmup": args.warmup, "ms_per_step": main["launch_us"] * 1e-3, "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None, "dtype": "u32/f64", "data": "synthetic",
+            "config": {"workload": "rates", "workgroups": blocks, "threads": 256, "chains_per_thread": 8,
+                       "cus": cus},
+            "roofline": {"bound": "alu", "achieved": main["lane_ops_per_s"] / 1e12, "peak": LANE_RATE / 1e12,
+                         "unit": "T VALU lane-ops/s", "frac": main["vs_lane_rate"], "traffic": None},
+            "rates": rates}
+    print(json.dumps(line), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -816,6 +877,9 @@ def main():
         print("bench.py: no GPU visible", file=sys.stderr)
         sys.exit(1)
     torch.cuda.set_device(0)
+    if args.workload == "rates":
+        bench_rates(args, torch)
+        return
     qmc.lib()  # fail loudly if the HIP library is missing
     if args.copy_probe_mib > 0:
         copy_probe(torch, args.copy_probe_mib)

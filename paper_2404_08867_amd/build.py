@@ -16,6 +16,10 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libqmc.so")
+# The issue-rate probe behind the benchmark's ALU roofline (bench.py --workload rates):
+# a library of its own, not part of the C ABI.
+PROBE_SRC = os.path.join(PKG, "probe", "issue_rates.hip")
+PROBE_LIB = os.path.join(PKG, "libqmc_probe.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
@@ -57,12 +61,28 @@ def _compile(src: str, verbose: bool) -> str:
     return obj
 
 
+def build_probe(verbose: bool = False) -> str:
+    """Compile the issue-rate probe into libqmc_probe.so; returns its path."""
+    tmp = PROBE_LIB + ".tmp"
+    cmd = [HIPCC, "-shared", *DEVICE_FLAGS, PROBE_SRC, "-o", tmp]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"hipcc failed on {PROBE_SRC}:\n{r.stdout}\n{r.stderr}")
+    os.replace(tmp, PROBE_LIB)
+    return PROBE_LIB
+
+
 def build(verbose: bool = False) -> str:
-    """Compile every csrc/*.hip and link libqmc.so; returns the library path."""
+    """Compile every csrc/*.hip and link libqmc.so (and the probe library); returns the
+    path of libqmc.so."""
     os.makedirs(BUILD, exist_ok=True)
     srcs = sources()
-    with cf.ThreadPoolExecutor(max_workers=min(8, len(srcs))) as ex:
+    with cf.ThreadPoolExecutor(max_workers=min(8, len(srcs) + 1)) as ex:
+        probe = ex.submit(build_probe, verbose)
         objs = list(ex.map(lambda s: _compile(s, verbose), srcs))
+        probe.result()
     tmp = LIB + ".tmp"
     cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs]
     if verbose:

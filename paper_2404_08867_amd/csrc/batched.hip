@@ -10,7 +10,8 @@
 // partials in tile order and writes its Q -- a fixed order, so the results are
 // bit-reproducible whatever the schedule was.  The last workgroup to leave resets
 // the queue, so the launch can be replayed (e.g. from a captured graph) without
-// any memset.
+// any memset.  When every problem has n <= 2^24 the indices are stepped as exact
+// floats (tile.hpp).
 #include "batched.hpp"
 #include "tile.hpp"
 
@@ -45,7 +46,7 @@ union BatchShared {
     TileShared<typename BatchFamilies<FP32>::Q> q;
 };
 
-template <class F, int M>
+template <class F, int M, bool FI>
 __device__ __forceinline__ void run_tile(const BatchArgs& a, int pi, const DevProblem& pr,
                                          uint32_t local_tile, TileShared<F>& s, double* red,
                                          int* flag) {
@@ -56,10 +57,10 @@ __device__ __forceinline__ void run_tile(const BatchArgs& a, int pi, const DevPr
     double t;
     if (v.d <= kDimChunk) {
         setup_one_chunk<F, M>(v, s, red, local_tile * kTile, init0, ds1, ie);
-        t = tile_points_one_chunk<F, M>(v, s, local_tile * kTile, init0, true);
+        t = tile_points_one_chunk<F, M, kBlock, FI>(v, s, local_tile * kTile, init0, true);
     } else {
         block_constants<F>(v, red, init0, ds1, ie);
-        t = tile_points<F, M>(v, s, local_tile * kTile, init0);
+        t = tile_points<F, M, kBlock, FI>(v, s, local_tile * kTile, init0);
     }
     const double bsum = block_sum(t, red);
     if (threadIdx.x == 0) {
@@ -76,7 +77,7 @@ __device__ __forceinline__ void run_tile(const BatchArgs& a, int pi, const DevPr
     }
 }
 
-template <bool FP32, int M>
+template <bool FP32, int M, bool FI>
 __global__ __launch_bounds__(kBlock) void batched_kernel(const BatchArgs a) {
     using Fam = BatchFamilies<FP32>;
     __shared__ BatchShared<FP32> s;
@@ -102,16 +103,16 @@ __global__ __launch_bounds__(kBlock) void batched_kernel(const BatchArgs a) {
         const DevProblem pr = a.probs[lo];
         const uint32_t local = tile - pr.tile_begin;
         switch (pr.family) {
-            case kExpSum: run_tile<typename Fam::E, M>(a, lo, pr, local, s.e, red, &flag); break;
+            case kExpSum: run_tile<typename Fam::E, M, FI>(a, lo, pr, local, s.e, red, &flag); break;
             case kProductPeak:
                 if (!FP32 || pr.d <= kPeakF32MaxDims)
-                    run_tile<typename Fam::PS, M>(a, lo, pr, local, s.ps, red, &flag);
+                    run_tile<typename Fam::PS, M, FI>(a, lo, pr, local, s.ps, red, &flag);
                 else
-                    run_tile<typename Fam::PD, M>(a, lo, pr, local, s.pd, red, &flag);
+                    run_tile<typename Fam::PD, M, FI>(a, lo, pr, local, s.pd, red, &flag);
                 break;
-            case kGaussian: run_tile<typename Fam::G, M>(a, lo, pr, local, s.g, red, &flag); break;
-            case kExpQuadratic: run_tile<typename Fam::Q, M>(a, lo, pr, local, s.q, red, &flag); break;
-            default: run_tile<typename Fam::O, M>(a, lo, pr, local, s.o, red, &flag); break;
+            case kGaussian: run_tile<typename Fam::G, M, FI>(a, lo, pr, local, s.g, red, &flag); break;
+            case kExpQuadratic: run_tile<typename Fam::Q, M, FI>(a, lo, pr, local, s.q, red, &flag); break;
+            default: run_tile<typename Fam::O, M, FI>(a, lo, pr, local, s.o, red, &flag); break;
         }
         __syncthreads();  // shared tables and flag are free for the next tile
     }
@@ -120,7 +121,7 @@ __global__ __launch_bounds__(kBlock) void batched_kernel(const BatchArgs a) {
         __hip_atomic_store(&a.counters[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-template <bool FP32, int M>
+template <bool FP32, int M, bool FI>
 static hipError_t launch_batched_m(const BatchLaunch& L, hipStream_t stream) {
     BatchArgs a;
     a.probs = L.probs;
@@ -129,18 +130,25 @@ static hipError_t launch_batched_m(const BatchLaunch& L, hipStream_t stream) {
     a.q_out = L.q_out;
     a.counters = (uint32_t*)L.ws;
     a.partials = (double*)((char*)L.ws + kZeroBytes);
-    hipLaunchKernelGGL((batched_kernel<FP32, M>), dim3((unsigned)L.grid), dim3(kBlock), 0, stream, a);
+    hipLaunchKernelGGL((batched_kernel<FP32, M, FI>), dim3((unsigned)L.grid), dim3(kBlock), 0, stream, a);
     return hipGetLastError();
 }
 
+template <int M, bool FI>
+static hipError_t launch_batched_mf(const BatchLaunch& L, hipStream_t stream) {
+    return L.fp32 ? launch_batched_m<true, M, FI>(L, stream) : launch_batched_m<false, M, FI>(L, stream);
+}
+
+template <int M>
+static hipError_t launch_batched_mm(const BatchLaunch& L, hipStream_t stream) {
+    return L.float_index ? launch_batched_mf<M, true>(L, stream) : launch_batched_mf<M, false>(L, stream);
+}
+
 hipError_t launch_batched(const BatchLaunch& L, hipStream_t stream) {
-    switch (L.points_per_thread * 2 + (L.fp32 ? 1 : 0)) {
-        case 8: return launch_batched_m<false, 4>(L, stream);
-        case 9: return launch_batched_m<true, 4>(L, stream);
-        case 16: return launch_batched_m<false, 8>(L, stream);
-        case 17: return launch_batched_m<true, 8>(L, stream);
-        case 32: return launch_batched_m<false, 16>(L, stream);
-        case 33: return launch_batched_m<true, 16>(L, stream);
+    switch (L.points_per_thread) {
+        case 4: return launch_batched_mm<4>(L, stream);
+        case 8: return launch_batched_mm<8>(L, stream);
+        case 16: return launch_batched_mm<16>(L, stream);
     }
     return hipErrorInvalidValue;
 }

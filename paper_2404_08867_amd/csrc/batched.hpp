@@ -28,6 +28,7 @@ struct BatchLaunch {
     int points_per_thread;  // 4, 8 or 16
     int grid;               // persistent workgroups
     bool fp32;
+    bool float_index;       // every problem has n <= kFloatIndexMaxN: exact-float index step
     double* q_out;
     void* ws;
 };

@@ -2,7 +2,10 @@
 // loop of the sum kernels.  Each family is split into
 //   Dim      constants of one direction j (computed once per workgroup, kept in LDS),
 //   Acc      the running per-point state over directions (registers),
-//   step     one direction's contribution for lattice index k in [0, n),
+//   step     one direction's contribution for lattice index k in [0, n), given as
+//            a 32-bit integer or, for n <= 2^24, as the same integer held exactly in
+//            a float (the exact-float index step of common.hpp; (double)k is then a
+//            conversion from float, and the FP32 factors take k with none),
 //   finish   the per-point transcendental, returning f(x) / scale,
 // and three workgroup-wide sums over directions (block_terms) that give the
 // initial state and the final scale.  Coordinates are x_j = (k + sfrac_j) / n
@@ -78,7 +81,8 @@ struct ExpSum {
         return Dim{p[j] * kLog2e * inv_n};
     }
     __device__ static Acc init(double s0) { return Acc{s0}; }
-    __device__ static void step(Acc& acc, uint32_t k, const Dim& c) {
+    template <class K>
+    __device__ static void step(Acc& acc, K k, const Dim& c) {
         acc.s = fma((double)k, c.a, acc.s);
     }
     __device__ static void renorm(Acc&) {}
@@ -116,7 +120,8 @@ struct Gaussian {
         return Dim{b, fma(b, sfrac, -c * w)};
     }
     __device__ static Acc init(double) { return Acc{0.0}; }
-    __device__ static void step(Acc& acc, uint32_t k, const Dim& c) {
+    template <class K>
+    __device__ static void step(Acc& acc, K k, const Dim& c) {
         const double y = fma((double)k, c.b, c.g);
         acc.s = fma(y, y, acc.s);
     }
@@ -157,7 +162,8 @@ struct ExpQuadratic {
         return Dim{b, g, sg * b, sg * g};
     }
     __device__ static Acc init(double) { return Acc{0.0}; }
-    __device__ static void step(Acc& acc, uint32_t k, const Dim& c) {
+    template <class K>
+    __device__ static void step(Acc& acc, K k, const Dim& c) {
         const double kd = (double)k;
         const double y = fma(kd, c.b, c.g), ys = fma(kd, c.sb, c.sg);
         acc.s = fma(ys, y, acc.s);
@@ -196,7 +202,8 @@ struct Oscillatory {
         return Dim{p[1 + j] * kInv2Pi * inv_n};
     }
     __device__ static Acc init(double s0) { return Acc{s0}; }
-    __device__ static void step(Acc& acc, uint32_t k, const Dim& c) {
+    template <class K>
+    __device__ static void step(Acc& acc, K k, const Dim& c) {
         acc.s = fma((double)k, c.a, acc.s);
     }
     __device__ static void renorm(Acc&) {}
@@ -276,14 +283,8 @@ struct ProductPeak {
         return Dim{(T)(s * inv_n), (T)(s * fma(sfrac, inv_n, -w)), (T)(s * s / (c * c))};
     }
     __device__ static Acc init(double) { return Acc{(T)1, 0}; }
-    __device__ static void step(Acc& acc, uint32_t k, const Dim& c) {
-        const T y = fma((T)k, c.a, c.b);
-        acc.D *= fma(y, y, c.g);
-    }
-    // FP32 factors can take the index as an exact float (stepmod_f): the same y
-    // as step() without the conversion.
-    static constexpr bool kFloatIndex = FP32_DIMS;
-    __device__ static void step_f(Acc& acc, float k, const Dim& c) {
+    template <class K>
+    __device__ static void step(Acc& acc, K k, const Dim& c) {
         const T y = fma((T)k, c.a, c.b);
         acc.D *= fma(y, y, c.g);
     }
@@ -340,7 +341,8 @@ struct BernoulliProduct {
         return Dim{inv_n, sfrac * inv_n, a, ALPHA == 2 ? 1.0 + a / 6.0 : 1.0 - a / 30.0};
     }
     __device__ static Acc init(double) { return Acc{1.0}; }
-    __device__ static void step(Acc& acc, uint32_t k, const Dim& c) {
+    template <class K>
+    __device__ static void step(Acc& acc, K k, const Dim& c) {
         const double x = fma((double)k, c.inv_n, c.off);
         const double y = fma(-x, x, x);
         double f;

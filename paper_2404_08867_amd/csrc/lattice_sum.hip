@@ -229,17 +229,15 @@ static hipError_t launch_fm(const PlainLaunch& L, hipStream_t stream) {
     return hipGetLastError();
 }
 
-// Families with an exact-float index step use it whenever n allows; mirror-
-// symmetric families on an unshifted lattice sum half of the points.
+// The exact-float index step whenever n allows; mirror-symmetric families on an
+// unshifted lattice sum half of the points.
 template <class F, int M>
 static hipError_t launch_fi(const PlainLaunch& L, hipStream_t stream) {
-    if constexpr (float_index<F>::value) {
-        if (L.n <= kFloatIndexMaxN) return launch_fm<F, M, true, false>(L, stream);
-    }
+    const bool fi = L.n <= kFloatIndexMaxN;
     if constexpr (mirror_family<F>::value) {
-        if (!L.shift) return launch_fm<F, M, false, true>(L, stream);
+        if (!L.shift) return fi ? launch_fm<F, M, true, true>(L, stream) : launch_fm<F, M, false, true>(L, stream);
     }
-    return launch_fm<F, M, false, false>(L, stream);
+    return fi ? launch_fm<F, M, true, false>(L, stream) : launch_fm<F, M, false, false>(L, stream);
 }
 
 template <class F>

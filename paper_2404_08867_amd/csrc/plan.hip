@@ -169,6 +169,9 @@ void store_cache_file(const std::string& key, const qmc_batch_config& c) {
 
 qmc_status launch(const qmc_batch_plan* p, double* q_out, void* ws, hipStream_t stream) {
     qmc::BatchLaunch L;
+    bool fi = true;  // the exact-float index step when every problem's n allows it
+    for (const auto& q : p->probs) fi = fi && q.n <= (int64_t)qmc::kFloatIndexMaxN;
+    L.float_index = fi;
     L.probs = p->d_probs;
     L.count = p->count;
     L.total_tiles = p->total_tiles;

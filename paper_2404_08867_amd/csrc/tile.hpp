@@ -19,12 +19,6 @@
 
 namespace qmc {
 
-// Families whose step can take the index as an exact float (F::kFloatIndex).
-template <class F, class = void>
-struct float_index : std::false_type {};
-template <class F>
-struct float_index<F, std::void_t<decltype(F::kFloatIndex)>> : std::bool_constant<F::kFloatIndex> {};
-
 // Families with f(x) = f(1 - x) in every coordinate (F::kMirror): on an unshifted
 // lattice their sum needs only the points i <= n/2 (finish_points).
 template <class F, class = void>
@@ -98,7 +92,7 @@ struct TileShared {
     uint32_t lz[kDimChunk * kWave];   // [j][lane]
     uint32_t kw[kDimChunk * (B / kWave)];  // [j][wave]
     uint2 st[kDimChunk];              // (D_j, D_j - n)
-    float2 stf[kDimChunk];            // the same as exact floats (n <= kFloatIndexMaxN)
+    float2 stf[kDimChunk];            // the same as exact floats (used when n <= kFloatIndexMaxN)
     uint32_t sh[kDimChunk];           // whole part of the shift
     typename F::Dim c[kDimChunk];     // family constants
     // guarded families: the fallback's constants and whether the problem needs them
@@ -173,7 +167,7 @@ __device__ __forceinline__ void fill_dims(const ProblemView& v, TileShared<F, B>
         split_shift(v.shift, j, v.n, whole, frac);
         const uint32_t st = mulmod_small((uint32_t)kWave, (uint32_t)v.z[j], v.dn, v.inv_n);
         s.st[e] = make_uint2(st, st - v.n);
-        if constexpr (float_index<F>::value) s.stf[e] = make_float2((float)st, (float)st - (float)v.n);
+        s.stf[e] = make_float2((float)st, (float)st - (float)v.n);
         s.sh[e] = whole;
         s.c[e] = F::dim(v.p, v.d, j, v.inv_n, frac);
     }
@@ -192,11 +186,15 @@ __device__ __forceinline__ void fill_tile(const ProblemView& v, TileShared<F, B>
 
 // Accumulates directions [j0, j0 + dc) into the thread's M point states, from
 // the direction tables (fill_dims) and the tile's start residues (fill_tile) in s.
-// FI (families with kFloatIndex, n <= kFloatIndexMaxN): the thread's M indices
-// of a direction are stepped as exact floats (stepmod_f), converted once.
+// FI (n <= kFloatIndexMaxN): the thread's M indices of a direction are stepped as
+// exact floats (stepmod_f: two FP32 adds and a minimum, which gfx950 issues at
+// about twice the rate of the integer step's two 32-bit adds and minimum), and the
+// family takes the float (a float-to-double conversion where it needs a double).
 // `dims` holds F's constants of the chunk's directions (the tables' own c, or the
 // fallback constants c2 of a guarded family).
-template <class F, int M, int B, bool FI = false, class S>
+// M0 > 0: the accumulators hold the thread's points M0 .. M0 + M - 1 (each index
+// is first stepped M0 times).
+template <class F, int M, int B, bool FI = false, int M0 = 0, class S>
 __device__ __forceinline__ void chunk_points(typename F::Acc (&acc)[M], const S& s,
                                              const typename F::Dim* dims, int j0, int dc, uint32_t n) {
     using Dim = typename F::Dim;
@@ -204,12 +202,17 @@ __device__ __forceinline__ void chunk_points(typename F::Acc (&acc)[M], const S&
     for (int jj = 0; jj < dc; ++jj) {
         uint32_t k = addmod(s.kw[jj * (B / kWave) + wv], s.lz[jj * kWave + lane], n);
         const Dim c = dims[jj];
+        if constexpr (M0 > 0) {
+            const uint2 stp = s.st[jj];
+#pragma unroll
+            for (int m = 0; m < M0; ++m) k = stepmod(k, stp.x, stp.y);
+        }
         if constexpr (FI) {
             const float2 stp = s.stf[jj];
             float kf = (float)k;
 #pragma unroll
             for (int m = 0; m < M; ++m) {
-                F::step_f(acc[m], kf, c);
+                F::step(acc[m], kf, c);
                 kf = stepmod_f(kf, stp.x, stp.y);
             }
         } else {
@@ -233,11 +236,13 @@ __device__ __forceinline__ void chunk_points(typename F::Acc (&acc)[M], const S&
 // MIRROR (unshifted lattices, integrands with f(x) = f(1 - x) in every coordinate):
 // point n - i is the mirror image of point i, so only i <= n/2 is evaluated, with
 // weight 2 except for i = 0 and, for even n, i = n/2 (their own mirrors).
-template <class F, int M, bool MIRROR = false>
+// MT is the thread's number of points in the tile and M0 the first of them that acc
+// holds (chunk_points with the same M0).
+template <class F, int M, bool MIRROR = false, int MT = M, int M0 = 0>
 __device__ __forceinline__ double finish_points(const typename F::Acc (&acc)[M], uint32_t tile_base,
                                                 uint32_t n) {
     const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
-    const uint32_t i0 = tile_base + (uint32_t)wv * (kWave * M) + (uint32_t)lane;
+    const uint32_t i0 = tile_base + (uint32_t)wv * (kWave * MT) + (uint32_t)(kWave * M0) + (uint32_t)lane;
     double t = 0.0;
 #pragma unroll
     for (int m = 0; m < M; ++m) {
@@ -300,8 +305,7 @@ __device__ __forceinline__ void setup_one_chunk(const ProblemView& v, TileShared
             if constexpr (F::kBlockTerms) F::block_terms(v.p, d, j, v.inv_n, frac, t0, t1, te);
             const uint32_t st = mulmod_small((uint32_t)kWave, (uint32_t)v.z[j], v.dn, v.inv_n);
             s.st[j] = make_uint2(st, st - v.n);
-            if constexpr (float_index<F>::value)
-                s.stf[j] = make_float2((float)st, (float)st - (float)v.n);
+            s.stf[j] = make_float2((float)st, (float)st - (float)v.n);
             s.sh[j] = whole;
             s.c[j] = F::dim(v.p, d, j, v.inv_n, frac);
             if constexpr (guarded_family<F>::value) {
@@ -343,6 +347,18 @@ __device__ __forceinline__ void setup_one_chunk(const ProblemView& v, TileShared
     init0 = ds0 + F::extra(v.p);
 }
 
+// Points M0 .. M0 + M - 1 of the thread's MT points of a tile, with the fallback
+// constants c2 of a guarded family (F is the fallback).
+template <class F, int M, int MT, int M0, int B, bool FI, bool MIRROR, class S>
+__device__ __forceinline__ double fallback_points(const ProblemView& v, const S& s, uint32_t tile_base,
+                                                  double init0) {
+    typename F::Acc acc[M];
+#pragma unroll
+    for (int m = 0; m < M; ++m) acc[m] = F::init(init0);
+    chunk_points<F, M, B, FI, M0>(acc, s, s.c2, 0, v.d, v.n);
+    return finish_points<F, M, MIRROR, MT, M0>(acc, tile_base, v.n);
+}
+
 // One tile of a problem set up by setup_one_chunk.  With `kw_ready` the start
 // residues of this tile are already in s; otherwise they are rebuilt between two
 // barriers.  The caller may overwrite s afterwards only after a barrier.
@@ -357,12 +373,17 @@ __device__ __forceinline__ double tile_points_one_chunk(const ProblemView& v, Ti
     }
     if constexpr (guarded_family<F>::value) {
         if (s.use_fallback) {
+            // The double-precision factors take twice the registers of the single-
+            // precision ones; for M >= 8 they run over the thread's points in two
+            // halves, so that this rarely taken branch does not set the register
+            // count (and the occupancy) of the whole kernel.
             using FB = typename F::Fallback;
-            typename FB::Acc acc[M];
-#pragma unroll
-            for (int m = 0; m < M; ++m) acc[m] = FB::init(init0);
-            chunk_points<FB, M, B, false>(acc, s, s.c2, 0, v.d, v.n);
-            return finish_points<FB, M, MIRROR>(acc, tile_base, v.n);
+            if constexpr (M >= 8) {
+                return fallback_points<FB, M / 2, M, 0, B, FI, MIRROR>(v, s, tile_base, init0) +
+                       fallback_points<FB, M / 2, M, M / 2, B, FI, MIRROR>(v, s, tile_base, init0);
+            } else {
+                return fallback_points<FB, M, M, 0, B, FI, MIRROR>(v, s, tile_base, init0);
+            }
         }
     }
     typename F::Acc acc[M];
