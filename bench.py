@@ -99,10 +99,10 @@ def uses_adjoint_sets(d: int, family: int, nsets: int) -> bool:
     return family in (0, 3) and d <= 64 and nsets >= 16
 
 
-# MDI-LR factor evaluation (Gaussian): the node recurrence phi_{t+1} = phi_t r_t,
-# r_{t+1} = r_t q and the accumulation, two FP64 multiplies and one FP64 add per
+# MDI-LR factor evaluation (Gaussian): a run of nodes summed in Horner form from its
+# last ratio down, h <- 1 + r h and r <- r / q: one FP64 FMA and one FP64 multiply per
 # node (the exp2 seeds of each run of nodes are not counted).
-WORK_PER_MDI_FACTOR = 3 * C64
+WORK_PER_MDI_FACTOR = 2 * C64
 
 # MDI-LR of g(sum x), power g, QMC_FP32_COMPENSATED, per merged-state evaluation of
 # g (FP64 operations): the node and b + c s (2); log2 by the atanh series (22: the

@@ -14,6 +14,7 @@
 // underflow), and the L partial products are combined by a fixed butterfly of
 // lane exchanges (every lane of the group ends with the same bits).
 #include "common.hpp"
+#include "exp2_f64.hpp"
 #include "families.hpp"
 #include "kernels.hpp"
 
@@ -43,23 +44,27 @@ constexpr int kMaxNodesPerDim = 1 << 20;
 // ~1e-15 so that a thousand identical directions stay within 1e-12; 64 for
 // QMC_FP32_COMPENSATED).  The recurrence is used only while every node value, ratio
 // and q stay within 2^-1000..2^1000 (max y^2 over the nodes, taken at an end point,
-// and 2 A^2 at most 1000), so no partial sum or ratio leaves the FP64 range;
-// otherwise each node is evaluated directly (FP32: FP64 argument, split FP32 exp2).
-template <bool FP32>
+// and 2 A^2 at most 1000; a ratio's exponent is a difference of two node exponents),
+// so every exp2 argument lies in [-1000, 1000] (exp2_f64) and no partial sum or
+// ratio leaves the FP64 range; otherwise each node is evaluated directly (FP32: FP64
+// argument, split FP32 exp2).  NK is the number of nodes when it is the same for
+// every lane of the wave (the loops then run on the scalar unit), else 0 and Nk
+// holds each lane's count.
+template <bool FP32, int NK = 0>
 __device__ __forceinline__ double quad_node_sum(double A, double B, int Nk, double s) {
     constexpr int kSeed = FP32 ? 64 : 8;
     const double y_last = fma((double)(Nk - 1), A, B);
     double sr = 0.0;
     if (fmax(fmax(B * B, y_last * y_last), 2.0 * A * A) <= 1000.0) {
-        const double qinv = exp2(-2.0 * s * A * A);
+        const double qinv = exp2_f64(-2.0 * s * A * A);
         for (int t0 = 0; t0 < Nk; t0 += kSeed) {
             const int m = min(kSeed, Nk - t0);
             const double y0 = fma((double)t0, A, B);
-            const double phi0 = exp2(s * y0 * y0);
+            const double phi0 = exp2_f64(s * y0 * y0);
             const double yl = fma((double)(t0 + m - 2), A, B);  // the run's last ratio r_{t0+m-2}
-            double r = exp2(s * A * fma(2.0, yl, A));
+            double r = exp2_f64(s * A * fma(2.0, yl, A));
             double h = 1.0;
-#pragma unroll 4
+#pragma unroll 8
             for (int t = m - 2; t >= 0; --t) {
                 h = fma(r, h, 1.0);
                 r *= qinv;
@@ -80,11 +85,36 @@ __device__ __forceinline__ double quad_node_sum(double A, double B, int Nk, doub
     return sr;
 }
 
+// The inputs of one direction's factor: its node count and the family's one or two
+// parameters (c, w), read one direction ahead of their use so that the loads'
+// latency overlaps the previous direction's sum.
+struct DirIn {
+    double c, w;
+    int Nk;
+};
+
+template <int FAM>
+__device__ __forceinline__ DirIn load_dir(const double* p, int d, const int32_t* N, int k) {
+    DirIn in;
+    in.Nk = N[k];
+    if constexpr (FAM == kOscillatory) {
+        in.c = p[1 + k];
+        in.w = 0.0;
+    } else if constexpr (FAM == kExpSum) {
+        in.c = p[k];
+        in.w = 0.0;
+    } else {
+        in.c = p[k];
+        in.w = p[d + k];
+    }
+    return in;
+}
+
 // One direction's factor M_k = (1/N_k) sum_t phi_k((t + 1/2)/N_k) (real and
-// imaginary parts).  An N_k outside [1, 2^20] (the caller's contract) gives NaN.
-template <int FAM, bool FP32>
-__device__ __forceinline__ void direction_sum(const double* p, int d, int k, int Nk, double& re,
-                                              double& im) {
+// imaginary parts), Nk = in.Nk (NK: see quad_node_sum).  An N_k outside [1, 2^20]
+// (the caller's contract) gives NaN.
+template <int FAM, bool FP32, int NK = 0>
+__device__ __forceinline__ void direction_sum(const DirIn& in, int Nk, double& re, double& im) {
     if (Nk < 1 || Nk > kMaxNodesPerDim) {
         re = im = __builtin_nan("");
         return;
@@ -95,22 +125,22 @@ __device__ __forceinline__ void direction_sum(const double* p, int d, int k, int
         // phi = e^{c (t + 1/2)/N}: a geometric sequence, whose sum over the N nodes is
         // e^{c/(2N)} (e^c - 1) / (e^{c/N} - 1) = expm1(c) / (2 sinh(c / (2N)))  (c != 0;
         // every term 1 for c = 0), evaluated in FP64 in both precisions.
-        const double c = p[k];
+        const double c = in.c;
         sr = c == 0.0 ? (double)Nk : expm1(c) / (2.0 * sinh(0.5 * c * invN));
     } else if constexpr (FAM == kGaussian) {
         // phi = 2^{-y^2}, y = c sqrt(log2 e) ((t + 1/2)/N - w) = A t + B
-        const double c = p[k] * kSqrtLog2e, w = p[d + k];
+        const double c = in.c * kSqrtLog2e, w = in.w;
         const double A = c * invN, B = c * fma(0.5, invN, -w);
-        sr = quad_node_sum<FP32>(A, B, Nk, -1.0);
+        sr = quad_node_sum<FP32, NK>(A, B, Nk, -1.0);
     } else if constexpr (FAM == kExpQuadratic) {
         // phi = 2^{s y^2}, y = sqrt(|c| log2 e) ((t + 1/2)/N - w) = A t + B, s = sign(c)
-        const double cq = p[k], w = p[d + k];
+        const double cq = in.c, w = in.w;
         const double m = sqrt(fabs(cq) * kLog2e);
         const double A = m * invN, B = m * fma(0.5, invN, -w);
-        sr = quad_node_sum<FP32>(A, B, Nk, cq < 0.0 ? -1.0 : 1.0);
+        sr = quad_node_sum<FP32, NK>(A, B, Nk, cq < 0.0 ? -1.0 : 1.0);
     } else if constexpr (FAM == kProductPeak) {
         // phi = 1 / (c^-2 + y^2), y = (t + 1/2)/N - w = A t + B
-        const double c = p[k], w = p[d + k];
+        const double c = in.c, w = in.w;
         const double g = 1.0 / (c * c), A = invN, B = fma(0.5, invN, -w);
         // v = g + y^2 lies in [g, g + max(B^2, y_last^2)] (y^2 is largest at an end node)
         const double y_last = fma((double)(Nk - 1), A, B);
@@ -134,7 +164,7 @@ __device__ __forceinline__ void direction_sum(const double* p, int d, int k, int
             }
         }
     } else {  // kOscillatory: phi = e^{i c y}, angle in turns a = c/(2 pi) y = A t + B
-        const double c = p[1 + k] * kInv2Pi;
+        const double c = in.c * kInv2Pi;
         const double A = c * invN, B = 0.5 * c * invN;
         if constexpr (FP32) {
             // The few nodes per direction do not average the hardware sin/cos error
@@ -191,14 +221,24 @@ __global__ __launch_bounds__(kMdiBlock) void mdi_lr_kernel(const MdiArgs a) {
     const int set = gid >> a.lanes_log2, li = gid & (L - 1);
     const bool active = set < a.nsets;
 
-    // This lane's directions k = li, li + L, ... in increasing order.
+    // This lane's directions k = li, li + L, ... in increasing order, each one's
+    // inputs loaded while the previous one is summed.  Where every lane of the wave
+    // has the same node count (every N_k equal, the usual case) the node loops take
+    // it from a scalar register.
     double cr = 1.0, ci = 0.0;
     int E = 0;
-    if (active) {
+    if (active && li < a.d) {
         const double* p = a.params + (size_t)set * a.P;
+        DirIn cur = load_dir<FAM>(p, a.d, a.N, li);
         for (int k = li; k < a.d; k += L) {
+            const DirIn in = cur;
+            if (k + L < a.d) cur = load_dir<FAM>(p, a.d, a.N, k + L);
             double re, im;
-            direction_sum<FAM, FP32>(p, a.d, k, a.N[k], re, im);
+            const int n0 = __builtin_amdgcn_readfirstlane(in.Nk);
+            if (__builtin_amdgcn_ballot_w64(in.Nk != n0) == 0)
+                direction_sum<FAM, FP32, 1>(in, n0, re, im);
+            else
+                direction_sum<FAM, FP32, 0>(in, in.Nk, re, im);
             mul_renorm<kComplex>(cr, ci, E, re, im);
         }
     }

@@ -1,0 +1,43 @@
+"""The double-precision exp2 of the MDI-LR node recurrences (csrc/exp2_f64.hpp),
+compiled for the host with g++ and checked against the C library's long-double
+exp2l: within one unit in the last place over its range |x| <= 1000, exact at
+integers (powers of two) and at 0."""
+import os
+import shutil
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def checker(tmp_path_factory):
+    if shutil.which("g++") is None:
+        pytest.skip("g++ not available")
+    out = tmp_path_factory.mktemp("exp2") / "exp2_check"
+    subprocess.run(["g++", "-O2", "-std=c++17", "-I", os.path.join(ROOT, "paper_2404_08867_amd", "csrc"),
+                    os.path.join(ROOT, "tests", "host", "exp2_check.cpp"), "-o", str(out), "-lm"],
+                   check=True)
+    return str(out)
+
+
+def _max_ulp(checker, n, lo, hi):
+    r = subprocess.run([checker, str(n), repr(lo), repr(hi)], capture_output=True, text=True, check=True)
+    ulp, x = r.stdout.split()
+    return float(ulp), float(x)
+
+
+@pytest.mark.parametrize("lo,hi,n", [(-1000.0, 1000.0, 2_000_000), (-1.0, 1.0, 1_000_000),
+                                     (-0.5, 0.5, 1_000_000), (-64.0, -63.0, 200_000),
+                                     (999.0, 1000.0, 100_000), (-1000.0, -999.0, 100_000)])
+def test_within_one_ulp(checker, lo, hi, n):
+    ulp, x = _max_ulp(checker, n, lo, hi)
+    assert ulp <= 1.0, (ulp, x)
+
+
+@pytest.mark.parametrize("x", [0.0, 1.0, -1.0, 7.0, -300.0, 1000.0, -1000.0])
+def test_exact_at_integers(checker, x):
+    # one point, the end points lo = hi = x: a power of two is exact
+    ulp, _ = _max_ulp(checker, 0, x, x)
+    assert ulp == 0.0
