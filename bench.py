@@ -167,26 +167,33 @@ def parse():
     return ap.parse_args()
 
 
-# HBM traffic of the plain-sum kernel as measured with rocprofv3 counters and
-# recorded in the profile summary, together with a SHA-256 of the kernel's
-# sources at the time: reported only while the sources still match.
-TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "lattice_sum_plain_d20_peak.md")
-KERNEL_SOURCES = ["lattice_sum.hip", "tile.hpp", "common.hpp", "families.hpp", "kernels.hpp"]
+# HBM traffic of a workload's dominant kernel as measured with rocprofv3 counters and
+# recorded in its profile summary, together with a SHA-256 of the kernel's sources at
+# the time: reported only while the sources still match.
+TRAFFIC = {
+    "plain_d20_peak": ("lattice_sum_plain_d20_peak.md",
+                       ["lattice_sum.hip", "tile.hpp", "common.hpp", "families.hpp", "exp2_f64.hpp", "kernels.hpp"]),
+    "batched_4096": ("batched_kernel_batched_4096.md",
+                     ["batched.hip", "batched.hpp", "plan.hip", "tile.hpp", "common.hpp", "families.hpp", "exp2_f64.hpp"]),
+}
 
 
-def kernel_sources_sha256() -> str:
+def kernel_sources_sha256(names) -> str:
     import hashlib
     h = hashlib.sha256()
-    for name in KERNEL_SOURCES:
+    for name in names:
         with open(os.path.join(ROOT, "paper_2404_08867_amd", "csrc", name), "rb") as f:
             h.update(f.read())
     return h.hexdigest()
 
 
-def measured_traffic():
-    """Bytes per launch from the profile summary, or None if absent or stale."""
+def measured_traffic(workload):
+    """Bytes per launch from the workload's profile summary, or None if absent or stale."""
+    if workload not in TRAFFIC:
+        return None
+    profile, names = TRAFFIC[workload]
     try:
-        with open(TRAFFIC_PROFILE) as f:
+        with open(os.path.join(ROOT, "profiles", profile)) as f:
             text = f.read()
     except OSError:
         return None
@@ -195,7 +202,7 @@ def measured_traffic():
         if ln.startswith("traffic_bytes_per_launch:") or ln.startswith("kernel_sources_sha256:"):
             k, v = ln.split(":", 1)
             fields[k.strip()] = v.strip().strip("`")
-    if fields.get("kernel_sources_sha256") != kernel_sources_sha256():
+    if fields.get("kernel_sources_sha256") != kernel_sources_sha256(names):
         return None
     try:
         return float(fields["traffic_bytes_per_launch"])
@@ -265,31 +272,43 @@ def cpu_baseline(unit, calls, units, single_calls, single_units, sample):
             "host": info}, res
 
 
-def plain_partial_calls(z, prob, pieces):
-    """The oracle's sum over [0, n) as `pieces` index ranges (oracle.lattice_partial)."""
+def plain_partial_tasks(z, prob, reps, tasks):
+    """`reps` full oracle sums over [0, n) as `tasks` callables: the sums are split into
+    index ranges (oracle.lattice_partial) only when they are long, and each task runs
+    its share of (range, repetition) items in a loop, so that tiny sums do not turn
+    into millions of pool tasks."""
     import oracle as O
+    pieces = tasks if prob.n >= (1 << 16) else 1
     edges = [prob.n * k // pieces for k in range(pieces + 1)]
-    return [(lambda lo=lo, hi=hi: O.lattice_partial(z, prob.n, prob.family, prob.params, lo, hi - lo,
-                                                    prob.shift))
-            for lo, hi in zip(edges[:-1], edges[1:]) if hi > lo]
+    items = [(lo, hi) for _ in range(reps) for lo, hi in zip(edges[:-1], edges[1:]) if hi > lo]
+    shares = [items[t::tasks] for t in range(tasks)]
+
+    def run(share):
+        for lo, hi in share:
+            O.lattice_partial(z, prob.n, prob.family, prob.params, lo, hi - lo, prob.shift)
+    return [(lambda sh=sh: run(sh)) for sh in shares if sh], pieces
 
 
 def oracle_baseline(prob, seconds):
-    """CPU-baseline leg of a plain workload: the whole sum, split into index ranges over
-    the host cores and repeated for about `seconds` of one core's work, and once on one
-    core.  Returns (cpu_baseline dict, Q, A) with Q and A from the single-core run."""
+    """CPU-baseline leg of a plain workload: the whole sum repeated for about `seconds`
+    of one core's work, spread over the host cores (index ranges of one sum for long
+    sums, whole sums for short ones), and once on one core.  Returns (cpu_baseline
+    dict, Q, A) with Q and A from the single-core run."""
     import oracle as O
     z = O.korobov(prob.d, prob.n, prob.a)
     t0 = time.perf_counter()
     q, a = O.lattice_sum(z, prob.n, prob.family, prob.params, prob.shift)
     t1 = time.perf_counter() - t0
     reps = max(1, int(seconds / max(t1, 1e-9)))
-    pieces = 4 * max(1, min(cpu_info()["usable"], MAX_POOL))
-    calls = plain_partial_calls(z, prob, pieces) * reps
+    cores = max(1, min(cpu_info()["usable"], MAX_POOL))
+    calls, pieces = plain_partial_tasks(z, prob, reps, 4 * cores)
+    single_reps = max(1, reps // 8)
     base, _ = cpu_baseline("lattice-point evals/s", calls, prob.n * reps,
-                           [lambda: O.lattice_sum(z, prob.n, prob.family, prob.params, prob.shift)], prob.n,
-                           f"the full sum (n={prob.n}) repeated {reps} times, each split into {pieces} "
-                           "index ranges (oracle.lattice_partial) over the cores; single core: one full sum")
+                           [lambda: [O.lattice_sum(z, prob.n, prob.family, prob.params, prob.shift)
+                                     for _ in range(single_reps)]], prob.n * single_reps,
+                           f"the full sum (n={prob.n}) repeated {reps} times"
+                           + (f", each split into {pieces} index ranges (oracle.lattice_partial)" if pieces > 1 else "")
+                           + f", over the cores; single core: {single_reps} full sums")
     return base, q, a
 
 
@@ -935,7 +954,7 @@ def main():
             "peak": PEAK_SLOTS / 1e12,
             "unit": "T 32-bit VALU lane-op slots/s",
             "frac": achieved / PEAK_SLOTS,
-            "traffic": measured_traffic() if args.workload == "plain_d20_peak" else None,
+            "traffic": measured_traffic(args.workload),
             "work_per_unit": wpp,
             "kernel_us": main_r["kern_s"] * 1e6,
         },

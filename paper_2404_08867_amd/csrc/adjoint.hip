@@ -507,7 +507,7 @@ __global__ __launch_bounds__(kBlock) void adjoint_sets_kernel(const AdjSetsArgs 
                         wt = -sn;
                     }
                 } else {
-                    val = FP32 ? exp2_split_f32(tt) : exp2(tt);
+                    val = FP32 ? exp2_split_f32(tt) : exp2_double(tt);
                     wt = val;
                 }
                 val = live ? val : 0.0;

@@ -1,6 +1,7 @@
 // 2^x in double precision for |x| <= 1000, written out so that it compiles both for
 // the device and, with a plain C++ compiler, for the host check of its accuracy
-// (tests/test_exp2_f64.py).
+// (tests/test_exp2_f64.py).  Used for the MDI-LR node-recurrence seeds and the
+// per-point exponentials of the QMC_FP64 sums.
 //
 // x = i + f with i = rint(x) and |f| <= 1/2 (x - i is exact); 2^f = e^t with
 // t = f ln 2, |t| <= 0.3466, by the Taylor series of e^t to degree 13 in Horner

@@ -24,6 +24,8 @@
 
 #include <type_traits>
 
+#include "exp2_f64.hpp"
+
 namespace qmc {
 
 constexpr double kLog2e = 1.4426950408889634074;
@@ -50,6 +52,12 @@ __device__ __forceinline__ double exp2_split_f32(double s) {
     const double r = rint(s);
     const float fr = (float)(s - r);
     return ldexp((double)__builtin_amdgcn_exp2f(fr), (int)r);
+}
+
+// exp2 in double precision: the local series (exp2_f64.hpp, within 1 ulp, about 20
+// instructions) over its range, the library exp2 (overflow, underflow) beyond it.
+__device__ __forceinline__ double exp2_double(double s) {
+    return fabs(s) <= 1000.0 ? exp2_f64(s) : exp2(s);
 }
 
 // ------------------------------------------------------------------ exp-sum
@@ -90,7 +98,7 @@ struct ExpSum {
         if constexpr (FP32)
             return exp2_split_f32(acc.s);
         else
-            return exp2(acc.s);
+            return exp2_double(acc.s);
     }
     __device__ static double scale(double ds1, int ie) {
         (void)ie;
@@ -130,7 +138,7 @@ struct Gaussian {
         if constexpr (FP32)
             return exp2_split_f32(-acc.s);
         else
-            return exp2(-acc.s);
+            return exp2_double(-acc.s);
     }
     __device__ static double scale(double, int) { return 1.0; }
 };
@@ -173,7 +181,7 @@ struct ExpQuadratic {
         if constexpr (FP32)
             return exp2_split_f32(acc.s);
         else
-            return exp2(acc.s);
+            return exp2_double(acc.s);
     }
     __device__ static double scale(double, int) { return 1.0; }
 };
