@@ -52,13 +52,15 @@ CT = 4    # v_exp_f32 / v_rcp_f32 / v_cos_f32 (a quarter of the 32-bit rate, mea
 PEAK_SLOTS = 256 * 128 * 2.4e9
 
 # Algorithmic work per lattice point of the QMC_FP32_COMPENSATED path, in slots:
-# per direction, the index step (two adds and a min) and the conversion of the
-# index, plus the family's operations once the coordinate's scale and offset are
-# folded into its first FMA; per point, one transcendental and the FP64
-# accumulation (convert, add).
-#   exp-sum, oscillatory: FP64 argument FMA;
-#   Gaussian:             FP64 y = b k + g, FP64 y^2 accumulated;
-#   product peak:         FP32 y, y^2 + g, product (FP64 for d > 64).
+# per direction, the exact-float index step (two FP32 adds and an unsigned minimum, or
+# the integer step's two adds and a minimum: 3) plus the family's operations once the
+# coordinate's scale and offset are folded into its first FMA; per point, one
+# transcendental and the FP64 accumulation (convert, add).
+#   exp-sum, oscillatory: conversion to FP64, FP64 argument FMA;
+#   Gaussian:             conversion, FP64 y = b k + g, FP64 y^2 accumulated;
+#   product peak:         FP32 y, y^2 + g, product (d <= 32, the exact float taken
+#                         as it is); FP64 factors above 32 directions (conversion, three
+#                         FP64 operations).
 INDEX = 3 * C32
 ACCUM = 2 * C64
 PEAK_F32_MAX_DIMS = 32
@@ -67,7 +69,7 @@ PEAK_F32_MAX_DIMS = 32
 def work_per_point(d: int, family: int) -> int:
     if family == 1:  # product peak
         if d <= PEAK_F32_MAX_DIMS:
-            per_dim = INDEX + C32 + 3 * C32
+            per_dim = INDEX + 3 * C32
         else:
             per_dim = INDEX + C64 + 3 * C64
     elif family in (2, 4):  # Gaussian, exp of a signed quadratic (y, then s y^2 added)
@@ -75,6 +77,23 @@ def work_per_point(d: int, family: int) -> int:
     else:  # exp-sum, oscillatory
         per_dim = INDEX + C64 + C64
     return d * per_dim + CT + ACCUM
+
+
+# The count the roofline's `achieved` uses: the minimal work per point of the plain
+# rule counted one operation per lane, W = d (3 index + 2 coordinate + c_f) + 1
+# transcendental + 6 (accumulation and scaling), c_f = 1 (exp-sum, oscillatory),
+# 2 (Gaussian, exp of a signed quadratic), 3 (product peak); per MDI-LR factor
+# evaluation 2 FMAs + 1 exp = 3.  work_per_point() above weights the same operations by
+# their measured issue cost (an FP64 operation two 32-bit slots) and is reported beside
+# it as `measured_costs`.
+LANE_OPS_FAMILY = {0: 1, 3: 1, 2: 2, 4: 2, 1: 3}
+
+
+def lane_ops_per_point(d: int, family: int) -> int:
+    return d * (3 + 2 + LANE_OPS_FAMILY[family]) + 1 + 6
+
+
+LANE_OPS_PER_MDI_FACTOR = 3
 
 
 # The adjoint's second sweep regenerates each direction's indices and accumulates
@@ -382,6 +401,7 @@ def bench_plain(args, torch, qmc, W):
         del g
     units = prob.n
     wpp = work_per_point(prob.d, prob.family)
+    results["fp32c"]["lane_ops"] = lane_ops_per_point(prob.d, prob.family)
     config = {"workload": prob.name, "d": prob.d, "n": prob.n, "a": prob.a,
               "family": W.FAMILY_NAMES[prob.family], "precision": "fp32_compensated",
               "lattice": "korobov", "shift": None}
@@ -412,6 +432,7 @@ def bench_shifts(args, torch, qmc, W):
         del g
     units = w.n * R
     wpp = work_per_point(w.d, w.family)
+    results["fp32c"]["lane_ops"] = lane_ops_per_point(w.d, w.family)
     config = {"workload": w.name, "d": w.d, "n": w.n, "a": w.a, "shifts": R,
               "family": W.FAMILY_NAMES[w.family], "precision": "fp32_compensated",
               "lattice": "korobov", "unit_of_work": "one point of one shifted lattice"}
@@ -686,6 +707,7 @@ def bench_mdi(args, torch, qmc, W):
         del g
     units = int(w.N.sum()) * nsets  # one-dimensional factor evaluations per launch
     wpp = WORK_PER_MDI_FACTOR
+    results["fp32c"]["lane_ops"] = LANE_OPS_PER_MDI_FACTOR
     results["vs_plain_rule"] = mdi_beside_plain_rule(torch, qmc, W, w, results)
     config = {"workload": w.name, "d": w.d, "N": int(w.N[0]), "nsets": nsets,
               "family": W.FAMILY_NAMES[w.family], "precision": "fp32_compensated",
@@ -725,6 +747,7 @@ def bench_batched(args, torch, qmc, W):
         step_s, kern_s = time_eager(torch, lambda: plan.run(out=out), args.steps, args.warmup)
         results[name] = dict(step_s=step_s, kern_s=kern_s, lat_s=step_s, q=out.cpu().numpy())
         del plan
+    results["fp32c"]["lane_ops"] = sum(p.n * lane_ops_per_point(p.d, p.family) for p in batch.problems) / units
     config = {"workload": batch.name, "integrands": len(batch.problems), "points": units,
               "point_dims": int(sum(p.n * p.d for p in batch.problems)),
               "families": "exp_sum/product_peak/gaussian", "precision": "fp32_compensated",
@@ -927,7 +950,21 @@ def main():
     if args.no_cpu_baseline:
         main_r.pop("pts", None)  # the f4 point set is kept only for the oracle's spot checks
     value = units / main_r["step_s"]
-    achieved = wpp * units / main_r["kern_s"]  # slots per second
+    achieved = wpp * units / main_r["kern_s"]  # slots per second, measured costs
+    lane_ops = main_r.get("lane_ops")
+    if lane_ops is not None:
+        roofline = {"bound": "alu", "achieved": lane_ops * units / main_r["kern_s"] / 1e12,
+                    "peak": PEAK_SLOTS / 1e12, "unit": "T 32-bit VALU lane-op slots/s",
+                    "frac": lane_ops * units / main_r["kern_s"] / PEAK_SLOTS,
+                    "traffic": measured_traffic(args.workload), "work_per_unit": lane_ops,
+                    "kernel_us": main_r["kern_s"] * 1e6,
+                    "measured_costs": {"work_per_unit": wpp, "achieved": achieved / 1e12,
+                                       "frac": achieved / PEAK_SLOTS}}
+    else:
+        roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_SLOTS / 1e12,
+                    "unit": "T 32-bit VALU lane-op slots/s", "frac": achieved / PEAK_SLOTS,
+                    "traffic": measured_traffic(args.workload), "work_per_unit": wpp,
+                    "kernel_us": main_r["kern_s"] * 1e6}
     line.update({
         "value": value,
         "unit": {"mdi_d100_gauss": "factor evals/s",
@@ -948,16 +985,7 @@ def main():
         "dtype": {"korobov_search_d20": "f64", "cbc_d20": "f64", "implr_d3": "u32"}.get(args.workload, "f32"),
         "data": "synthetic",
         "config": config,
-        "roofline": main_r.get("roofline") or {
-            "bound": "alu",
-            "achieved": achieved / 1e12,
-            "peak": PEAK_SLOTS / 1e12,
-            "unit": "T 32-bit VALU lane-op slots/s",
-            "frac": achieved / PEAK_SLOTS,
-            "traffic": measured_traffic(args.workload),
-            "work_per_unit": wpp,
-            "kernel_us": main_r["kern_s"] * 1e6,
-        },
+        "roofline": main_r.get("roofline") or roofline,
         "eager_latency_us": main_r["lat_s"] * 1e6,
         "fp64": {"value": units / res["fp64"]["step_s"], "ms_per_step": res["fp64"]["step_s"] * 1e3,
                  "kernel_us": res["fp64"]["kern_s"] * 1e6},

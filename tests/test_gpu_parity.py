@@ -118,14 +118,19 @@ def _peak(seed, d, n, c, w, shift=False):
 
 
 @pytest.mark.parametrize("case", ["narrow_at_0", "narrow_random", "one_narrow", "w_outside",
-                                  "c_at_limit", "d32", "d33"])
+                                  "c_at_limit", "d32", "d33", "narrow_at_0_d48", "one_narrow_d40",
+                                  "c_at_limit_d64"])
 def test_plain_sum_product_peak_guard(case):
-    """FP32 product-peak factors run only where every direction passes the guard
-    (|c_j| <= 4, factor range within 2^+-7); narrow peaks (c_j = 50..100, which would
-    underflow an FP32 run of 16 factors), centres far outside [0, 1], and d above
-    the FP32 limit take the FP64 factors.  Every case at both precisions' bars."""
+    """FP32 product-peak factors (up to 32 directions) run only where every direction
+    passes the guard (|c_j| <= 4, factor range within 2^+-7); narrow peaks (c_j = 50..100,
+    which would underflow an FP32 run of 16 factors), centres far outside [0, 1] and d
+    above the FP32 limit (the same cases at 40, 48 and 64 directions) take the FP64
+    factors.  Every case at both precisions' bars."""
     rng = np.random.default_rng(len(case))
     d, n = 20, 65537
+    if case.endswith(("_d48", "_d40", "_d64")):
+        d = int(case[-2:])
+        case = case[:-4]
     if case == "narrow_at_0":      # point i = 0 sits on every peak
         prob = _peak(1, d, n, rng.uniform(50, 100, d), np.zeros(d))
     elif case == "narrow_random":
@@ -153,12 +158,15 @@ def test_plain_sum_product_peak_guard(case):
 
 def test_batched_product_peak_guard():
     """The same guard in the batched kernel: narrow, wide and in-range product peaks in
-    one launch, each against the oracle."""
+    one launch, below and above 32 directions, each against the oracle."""
     rng = np.random.default_rng(21)
     probs = [_peak(31, 20, 40009, rng.uniform(50, 100, 20), np.zeros(20)),
              _peak(32, 12, 20011, rng.uniform(0.5, 2, 12), rng.uniform(0, 1, 12)),
              _peak(33, 30, 30011, np.r_[rng.uniform(0.5, 2, 29), 70.0], rng.uniform(0, 1, 30), shift=True),
-             _peak(34, 8, 10007, np.full(8, 4.0), rng.uniform(0, 1, 8))]
+             _peak(34, 8, 10007, np.full(8, 4.0), rng.uniform(0, 1, 8)),
+             _peak(35, 48, 20011, rng.uniform(50, 100, 48), np.zeros(48)),
+             _peak(36, 40, 30011, np.r_[rng.uniform(0.5, 2, 39), 70.0], rng.uniform(0, 1, 40), shift=True),
+             _peak(37, 64, 10007, np.full(64, 4.0), rng.uniform(0, 1, 64))]
     descs = [(p.family, qmc.korobov(p.d, p.n, p.a), p.n, p.params, p.shift) for p in probs]
     for precision in PRECS:
         q = qmc.BatchPlan(descs, precision).run().cpu().numpy()
