@@ -9,6 +9,8 @@ Q_r (recomputed here in FP64) to rounding.
 """
 import math
 
+import os
+
 import numpy as np
 import pytest
 
@@ -76,21 +78,44 @@ def test_single_shift_equals_shifted_plain_sum(precision, family):
     assert st[0] == float(q2.item()) and st[1] == 0.0
 
 
+_SHIFT_ORACLE = {}
+
+
+def _oracle_shift_sums(w):
+    """The oracle's (Q_r, A_r) of every shift of w, the shifts spread over host threads;
+    computed once for both precisions' tests."""
+    import concurrent.futures as cf
+    if w.name not in _SHIFT_ORACLE:
+        zo = O.korobov(w.d, w.n, w.a)
+        with cf.ThreadPoolExecutor(max_workers=min(16, os.cpu_count() or 1)) as ex:
+            _SHIFT_ORACLE[w.name] = list(ex.map(
+                lambda r: O.lattice_sum(zo, w.n, w.family, w.params, w.shifts[r]), range(w.shifts.shape[0])))
+    return _SHIFT_ORACLE[w.name]
+
+
 @pytest.mark.parametrize("precision", PRECS)
 def test_shifts_d20_peak_full_size(precision):
-    """The benchmark's workload (n = 1048573, R = 64): sampled shifts against the
-    oracle, the statistics against the GPU's own values, the spread across shifts
-    against the oracle's."""
+    """The benchmark's workload (n = 1048573, R = 64): every shifted sum against the
+    oracle, the statistics against the GPU's own values and against the oracle's."""
     w = W.shifts_d20_peak()
     z = qmc.korobov(w.d, w.n, w.a)
     q, stats = qmc.lattice_sum_shifts(z, w.n, w.family, w.params, w.shifts, precision)
     q = q.cpu().numpy()
     stats = stats.cpu().numpy()
-    zo = O.korobov(w.d, w.n, w.a)
-    for r in (0, 37, 63):
-        qo, ao = O.lattice_sum(zo, w.n, w.family, w.params, w.shifts[r])
+    ref = _oracle_shift_sums(w)
+    for r, (qo, ao) in enumerate(ref):
         assert abs(q[r] - qo) <= TOL[precision] * max(abs(qo), ao), (r, q[r], qo)
     _check_stats_against_own_q(q, stats)
+    # The mean and the standard error are a mean and a seminorm of the R values, so the
+    # GPU's differ from the oracle's by at most max_r |q_r - qo_r| and that over
+    # sqrt(R - 1) (triangle inequality), plus their own rounding.
+    qo = np.array([v for v, _ in ref])
+    R = len(qo)
+    mean = qo.mean()
+    se = np.sqrt(np.sum((qo - mean) ** 2) / (R * (R - 1)))
+    dmax = float(np.max(np.abs(q - qo)))
+    assert abs(stats[0] - mean) <= dmax + 1e-15 * abs(mean)
+    assert abs(stats[1] - se) <= dmax / math.sqrt(R - 1) + 1e-12 * se
     assert stats[1] > 0 and np.all(np.isfinite(q))
 
 
