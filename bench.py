@@ -758,11 +758,49 @@ def bench_batched(args, torch, qmc, W):
         results[name] = dict(step_s=step_s, kern_s=kern_s, lat_s=step_s, q=out.cpu().numpy())
         del plan
     results["fp32c"]["lane_ops"] = sum(p.n * lane_ops_per_point(p.d, p.family) for p in batch.problems) / units
+    results["plain_per_integrand"] = plain_per_integrand(torch, qmc, batch, results)
     config = {"workload": batch.name, "integrands": len(batch.problems), "points": units,
               "point_dims": int(sum(p.n * p.d for p in batch.problems)),
               "families": "exp_sum/product_peak/gaussian", "precision": "fp32_compensated",
               "schedule": dict(tuned)}
     return batch, results, units, wpp, config
+
+
+def plain_per_integrand(torch, qmc, batch, results):
+    """The same integrands as one plain-rule launch each (qmc_lattice_sum), the 4096
+    launches captured in one HIP graph and replayed (the plain form's best case: no host
+    work between launches), in FP64 and FP32c: the time per pass over the whole batch,
+    and the batched launch's speed-up over it."""
+    probs = batch.problems
+    zs = [torch.tensor(qmc.korobov(p.d, p.n, p.a), device="cuda") for p in probs]
+    ps = [torch.tensor(p.params, dtype=torch.float64, device="cuda") for p in probs]
+    ws = qmc.Workspace(qmc.workspace_size(max(p.d for p in probs), max(p.n for p in probs), 1))
+    out = torch.zeros(len(probs), dtype=torch.float64, device="cuda")
+    res = {}
+    for prec, name in ((qmc.FP64, "fp64"), (qmc.FP32_COMPENSATED, "fp32c")):
+        def one_pass(prec=prec):
+            for b, p in enumerate(probs):
+                qmc.lattice_sum(zs[b], p.n, p.family, ps[b], prec, ws=ws, out=out[b:b + 1])
+        one_pass()  # eager warm-up
+        torch.cuda.synchronize()
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g, stream=side):
+            one_pass()
+        g.replay()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        g.replay()
+        e1.record()
+        torch.cuda.synchronize()
+        res[name + "_ms"] = e0.elapsed_time(e1)
+        del g
+    res["launches"] = len(probs)
+    res["batched_fp32c_speedup_over_plain_fp64"] = res["fp64_ms"] / (results["fp32c"]["kern_s"] * 1e3)
+    res["batched_fp32c_speedup_over_plain_fp32c"] = res["fp32c_ms"] / (results["fp32c"]["kern_s"] * 1e3)
+    return res
 
 
 def bench_adjoint(args, torch, qmc, W):
@@ -1023,6 +1061,8 @@ def main():
     })
     if "vs_plain_rule" in res:
         line["vs_plain_rule"] = res["vs_plain_rule"]
+    if "plain_per_integrand" in res:
+        line["plain_per_integrand"] = res["plain_per_integrand"]
 
     if not args.no_cpu_baseline:
         base = None
