@@ -921,7 +921,8 @@ PROBE_KINDS = ["u32_add", "index_step(add,add,min)", "f32_fma", "f64_fma", "f64_
                "peak_dim(float step, f32 fma x2, f32 mul)", "cvt_f64_f32",
                "point_dim_float(float step, cvt_f64_f32, f64_fma)",
                "gauss_dim(index step, cvt_f64_u32, f64_fma x2)",
-               "gauss_dim_float(float step, cvt_f64_f32, f64_fma x2)"]
+               "gauss_dim_float(float step, cvt_f64_f32, f64_fma x2)", "f64_mul",
+               "horner(f64 fma + mul)", "horner, 2 chains per thread(f64 fma + mul)"]
 PROBE_MAIN = "point_dim(index step, cvt_f64_u32, f64_fma)"
 LANE_RATE = 256 * 64 * 2.4e9  # one VALU lane-operation per lane per clock
 

@@ -14,7 +14,7 @@
 // underflow), and the L partial products are combined by a fixed butterfly of
 // lane exchanges (every lane of the group ends with the same bits).
 #include "common.hpp"
-#include "exp2_f64.hpp"
+#include "exp2_seed.hpp"
 #include "families.hpp"
 #include "kernels.hpp"
 
@@ -33,10 +33,27 @@ struct MdiArgs {
 constexpr int kMdiBlock = 256;
 constexpr int kMaxNodesPerDim = 1 << 20;
 
-// Sum over t = 0..Nk-1 of 2^{s y_t^2}, y_t = A t + B, s = -1 (a Gaussian) or +1 (a
-// growing factor of the signed quadratic).  Consecutive nodes differ by the ratio
-// r_t = phi_{t+1} / phi_t = 2^{s A (2 y_t + A)}, and r_{t-1} = r_t / q with
-// q = 2^{2 s A^2}, so a run of nodes t0 .. t0 + m - 1 sums in Horner form,
+// Sum over t = 0..Nk-1 of 2^{s y_t^2} by direct evaluation of every node (the
+// fallback of quad_node_sums; FP32: FP64 argument, split FP32 exp2).
+template <bool FP32>
+__device__ __forceinline__ double quad_node_direct(double A, double B, int Nk, double s) {
+    double sr = 0.0;
+    for (int t = 0; t < Nk; ++t) {
+        const double y = fma((double)t, A, B);
+        if constexpr (FP32)
+            sr += exp2_split_f32(s * y * y);
+        else
+            sr += exp2(s * y * y);
+    }
+    return sr;
+}
+
+// For each of J directions (J = 1 or 2, summed together so that their two dependent
+// chains interleave): the sum over t = 0..Nk-1 of 2^{s y_t^2}, y_t = A t + B, s = -1
+// (a Gaussian) or +1 (a growing factor of the signed quadratic).  Consecutive nodes
+// differ by the ratio r_t = phi_{t+1} / phi_t = 2^{s A (2 y_t + A)}, and
+// r_{t-1} = r_t / q with q = 2^{2 s A^2}, so a run of nodes t0 .. t0 + m - 1 sums in
+// Horner form,
 //   phi_{t0} (1 + r_{t0} (1 + r_{t0+1} (1 + ... (1 + r_{t0+m-2})))),
 // from its last ratio down: one FP64 multiply (the ratio) and one FP64 FMA (the
 // partial sum) per node.  phi_{t0} and the run's last ratio come from exp2: every
@@ -45,44 +62,65 @@ constexpr int kMaxNodesPerDim = 1 << 20;
 // QMC_FP32_COMPENSATED).  The recurrence is used only while every node value, ratio
 // and q stay within 2^-1000..2^1000 (max y^2 over the nodes, taken at an end point,
 // and 2 A^2 at most 1000; a ratio's exponent is a difference of two node exponents),
-// so every exp2 argument lies in [-1000, 1000] (exp2_f64) and no partial sum or
-// ratio leaves the FP64 range; otherwise each node is evaluated directly (FP32: FP64
-// argument, split FP32 exp2).  NK is the number of nodes when it is the same for
-// every lane of the wave (the loops then run on the scalar unit), else 0 and Nk
-// holds each lane's count.
-template <bool FP32, int NK = 0>
-__device__ __forceinline__ double quad_node_sum(double A, double B, int Nk, double s) {
+// so every exp2 argument lies in [-1000, 1000] and no partial sum or ratio leaves the
+// FP64 range; otherwise the nodes are evaluated directly.  A direction's sum does
+// not depend on J or on the other direction: where one of two directions fails the
+// range test, each is summed on its own.  The loops' trip counts depend only on Nk,
+// which is the same in every lane where the caller has checked that (the loops then
+// run on the scalar unit).
+template <bool FP32, int J>
+__device__ __forceinline__ void quad_node_sums(const double (&A)[J], const double (&B)[J],
+                                               const double (&s)[J], int Nk, double (&out)[J]) {
     constexpr int kSeed = FP32 ? 64 : 8;
-    const double y_last = fma((double)(Nk - 1), A, B);
-    double sr = 0.0;
-    if (fmax(fmax(B * B, y_last * y_last), 2.0 * A * A) <= 1000.0) {
-        const double qinv = exp2_f64(-2.0 * s * A * A);
+    bool ok[J], all = true;
+#pragma unroll
+    for (int j = 0; j < J; ++j) {
+        const double y_last = fma((double)(Nk - 1), A[j], B[j]);
+        ok[j] = fmax(fmax(B[j] * B[j], y_last * y_last), 2.0 * A[j] * A[j]) <= 1000.0;
+        all = all && ok[j];
+    }
+    if (all) {
+        double qinv[J], sr[J];
+#pragma unroll
+        for (int j = 0; j < J; ++j) {
+            qinv[j] = exp2_seed(-2.0 * s[j] * A[j] * A[j]);
+            sr[j] = 0.0;
+        }
         for (int t0 = 0; t0 < Nk; t0 += kSeed) {
             const int m = min(kSeed, Nk - t0);
-            const double y0 = fma((double)t0, A, B);
-            const double phi0 = exp2_f64(s * y0 * y0);
-            const double yl = fma((double)(t0 + m - 2), A, B);  // the run's last ratio r_{t0+m-2}
-            double r = exp2_f64(s * A * fma(2.0, yl, A));
-            double h = 1.0;
+            double phi0[J], r[J], h[J];
+#pragma unroll
+            for (int j = 0; j < J; ++j) {
+                const double y0 = fma((double)t0, A[j], B[j]);
+                phi0[j] = exp2_seed_reduced(s[j] * y0 * y0);
+                const double yl = fma((double)(t0 + m - 2), A[j], B[j]);  // the run's last ratio r_{t0+m-2}
+                r[j] = exp2_seed(s[j] * A[j] * fma(2.0, yl, A[j]));
+                h[j] = 1.0;
+            }
 #pragma unroll 8
             for (int t = m - 2; t >= 0; --t) {
-                h = fma(r, h, 1.0);
-                r *= qinv;
+#pragma unroll
+                for (int j = 0; j < J; ++j) {
+                    h[j] = fma(r[j], h[j], 1.0);
+                    r[j] *= qinv[j];
+                }
             }
-            sr = fma(phi0, h, sr);
+#pragma unroll
+            for (int j = 0; j < J; ++j) sr[j] = fma(phi0[j], h[j], sr[j]);
         }
-    } else if constexpr (FP32) {
-        for (int t = 0; t < Nk; ++t) {
-            const double y = fma((double)t, A, B);
-            sr += exp2_split_f32(s * y * y);
-        }
+#pragma unroll
+        for (int j = 0; j < J; ++j) out[j] = sr[j];
+    } else if constexpr (J == 1) {
+        out[0] = quad_node_direct<FP32>(A[0], B[0], Nk, s[0]);
     } else {
-        for (int t = 0; t < Nk; ++t) {
-            const double y = fma((double)t, A, B);
-            sr += exp2(s * y * y);
+#pragma unroll
+        for (int j = 0; j < J; ++j) {
+            const double Aj[1] = {A[j]}, Bj[1] = {B[j]}, sj[1] = {s[j]};
+            double oj[1];
+            quad_node_sums<FP32, 1>(Aj, Bj, sj, Nk, oj);
+            out[j] = oj[0];
         }
     }
-    return sr;
 }
 
 // The inputs of one direction's factor: its node count and the family's one or two
@@ -110,86 +148,98 @@ __device__ __forceinline__ DirIn load_dir(const double* p, int d, const int32_t*
     return in;
 }
 
-// One direction's factor M_k = (1/N_k) sum_t phi_k((t + 1/2)/N_k) (real and
-// imaginary parts), Nk = in.Nk (NK: see quad_node_sum).  An N_k outside [1, 2^20]
-// (the caller's contract) gives NaN.
-template <int FAM, bool FP32, int NK = 0>
-__device__ __forceinline__ void direction_sum(const DirIn& in, int Nk, double& re, double& im) {
-    if (Nk < 1 || Nk > kMaxNodesPerDim) {
-        re = im = __builtin_nan("");
-        return;
-    }
-    const double invN = 1.0 / (double)Nk;
-    double sr = 0.0, si = 0.0;
-    if constexpr (FAM == kExpSum) {
-        // phi = e^{c (t + 1/2)/N}: a geometric sequence, whose sum over the N nodes is
-        // e^{c/(2N)} (e^c - 1) / (e^{c/N} - 1) = expm1(c) / (2 sinh(c / (2N)))  (c != 0;
-        // every term 1 for c = 0), evaluated in FP64 in both precisions.
-        const double c = in.c;
-        sr = c == 0.0 ? (double)Nk : expm1(c) / (2.0 * sinh(0.5 * c * invN));
-    } else if constexpr (FAM == kGaussian) {
-        // phi = 2^{-y^2}, y = c sqrt(log2 e) ((t + 1/2)/N - w) = A t + B
-        const double c = in.c * kSqrtLog2e, w = in.w;
-        const double A = c * invN, B = c * fma(0.5, invN, -w);
-        sr = quad_node_sum<FP32, NK>(A, B, Nk, -1.0);
-    } else if constexpr (FAM == kExpQuadratic) {
-        // phi = 2^{s y^2}, y = sqrt(|c| log2 e) ((t + 1/2)/N - w) = A t + B, s = sign(c)
-        const double cq = in.c, w = in.w;
-        const double m = sqrt(fabs(cq) * kLog2e);
-        const double A = m * invN, B = m * fma(0.5, invN, -w);
-        sr = quad_node_sum<FP32, NK>(A, B, Nk, cq < 0.0 ? -1.0 : 1.0);
-    } else if constexpr (FAM == kProductPeak) {
-        // phi = 1 / (c^-2 + y^2), y = (t + 1/2)/N - w = A t + B
-        const double c = in.c, w = in.w;
-        const double g = 1.0 / (c * c), A = invN, B = fma(0.5, invN, -w);
-        // v = g + y^2 lies in [g, g + max(B^2, y_last^2)] (y^2 is largest at an end node)
-        const double y_last = fma((double)(Nk - 1), A, B);
-        const bool f32_range = g >= 1e-36 && g + fmax(B * B, y_last * y_last) <= 1e36;
-        if (FP32 && f32_range) {
-            // FP32 reciprocal refined by one Newton step in FP64 (relative error ~1e-15):
-            // an FP32 factor's rounding would repeat in every direction with the same
-            // parameters and grow linearly in d (3.4e-6 at d = 1000 for Table 2-3).  Only
-            // where every denominator is a normal FP32 number.
-            double td = 0.0;
+// The factors M_k = (1/N_k) sum_t phi_k((t + 1/2)/N_k) (real and imaginary parts) of
+// J directions with the same node count Nk, 1 <= Nk <= 2^20, invN = 1/Nk.
+template <int FAM, bool FP32, int J>
+__device__ __forceinline__ void direction_sums(const DirIn (&in)[J], int Nk, double invN,
+                                               double (&re)[J], double (&im)[J]) {
+    double sr[J], si[J];
+#pragma unroll
+    for (int j = 0; j < J; ++j) sr[j] = si[j] = 0.0;
+    if constexpr (FAM == kGaussian || FAM == kExpQuadratic) {
+        // Gaussian: phi = 2^{-y^2}, y = c sqrt(log2 e) ((t + 1/2)/N - w) = A t + B.
+        // Signed quadratic: phi = 2^{s y^2}, y = sqrt(|c| log2 e) ((t + 1/2)/N - w),
+        // s = sign(c).
+        double A[J], B[J], sg[J];
+#pragma unroll
+        for (int j = 0; j < J; ++j) {
+            const double m = FAM == kGaussian ? in[j].c * kSqrtLog2e : sqrt(fabs(in[j].c) * kLog2e);
+            A[j] = m * invN;
+            B[j] = m * fma(0.5, invN, -in[j].w);
+            sg[j] = FAM == kGaussian || in[j].c < 0.0 ? -1.0 : 1.0;
+        }
+        quad_node_sums<FP32, J>(A, B, sg, Nk, sr);
+    } else {
+#pragma unroll
+        for (int j = 0; j < J; ++j) {
+            if constexpr (FAM == kExpSum) {
+                // phi = e^{c (t + 1/2)/N}: a geometric sequence, whose sum over the N nodes
+                // is e^{c/(2N)} (e^c - 1) / (e^{c/N} - 1) = expm1(c) / (2 sinh(c / (2N)))
+                // (c != 0; every term 1 for c = 0), evaluated in FP64 in both precisions.
+                const double c = in[j].c;
+                sr[j] = c == 0.0 ? (double)Nk : expm1(c) / (2.0 * sinh(0.5 * c * invN));
+            } else if constexpr (FAM == kProductPeak) {
+                // phi = 1 / (c^-2 + y^2), y = (t + 1/2)/N - w = A t + B
+                const double c = in[j].c, w = in[j].w;
+                const double g = 1.0 / (c * c), A = invN, B = fma(0.5, invN, -w);
+                // v = g + y^2 lies in [g, g + max(B^2, y_last^2)] (y^2 is largest at an end node)
+                const double y_last = fma((double)(Nk - 1), A, B);
+                const bool f32_range = g >= 1e-36 && g + fmax(B * B, y_last * y_last) <= 1e36;
+                double acc = 0.0;
+                if (FP32 && f32_range) {
+                    // FP32 reciprocal refined by one Newton step in FP64 (relative error
+                    // ~1e-15): an FP32 factor's rounding would repeat in every direction
+                    // with the same parameters and grow linearly in d (3.4e-6 at d = 1000
+                    // for Table 2-3).  Only where every denominator is a normal FP32 number.
+                    double td = 0.0;
 #pragma unroll 4
-            for (int t = 0; t < Nk; ++t, td += 1.0) {
-                const double y = fma(td, A, B), v = fma(y, y, g);
-                const double r = (double)__builtin_amdgcn_rcpf((float)v);
-                sr += fma(r, fma(-v, r, 1.0), r);
-            }
-        } else {
-            for (int t = 0; t < Nk; ++t) {
-                const double y = fma((double)t, A, B);
-                sr += 1.0 / fma(y, y, g);
-            }
-        }
-    } else {  // kOscillatory: phi = e^{i c y}, angle in turns a = c/(2 pi) y = A t + B
-        const double c = in.c * kInv2Pi;
-        const double A = c * invN, B = 0.5 * c * invN;
-        if constexpr (FP32) {
-            // The few nodes per direction do not average the hardware sin/cos error
-            // away, so the factor uses the correctly reduced single-precision sincospi.
-            for (int t = 0; t < Nk; ++t) {
-                const double a = fma((double)t, A, B);
-                const float fr = (float)(a - rint(a));
-                float sn, co;
-                sincospif(2.0f * fr, &sn, &co);
-                sr += (double)co;
-                si += (double)sn;
-            }
-        } else {
-            for (int t = 0; t < Nk; ++t) {
-                const double a = fma((double)t, A, B);
-                const double fr = a - rint(a);
-                double sn, co;
-                sincospi(2.0 * fr, &sn, &co);
-                sr += co;
-                si += sn;
+                    for (int t = 0; t < Nk; ++t, td += 1.0) {
+                        const double y = fma(td, A, B), v = fma(y, y, g);
+                        const double r = (double)__builtin_amdgcn_rcpf((float)v);
+                        acc += fma(r, fma(-v, r, 1.0), r);
+                    }
+                } else {
+                    for (int t = 0; t < Nk; ++t) {
+                        const double y = fma((double)t, A, B);
+                        acc += 1.0 / fma(y, y, g);
+                    }
+                }
+                sr[j] = acc;
+            } else {  // kOscillatory: phi = e^{i c y}, angle in turns a = c/(2 pi) y = A t + B
+                const double c = in[j].c * kInv2Pi;
+                const double A = c * invN, B = 0.5 * c * invN;
+                double ar = 0.0, ai = 0.0;
+                if constexpr (FP32) {
+                    // The few nodes per direction do not average the hardware sin/cos error
+                    // away, so the factor uses the correctly reduced single-precision sincospi.
+                    for (int t = 0; t < Nk; ++t) {
+                        const double a = fma((double)t, A, B);
+                        const float fr = (float)(a - rint(a));
+                        float sn, co;
+                        sincospif(2.0f * fr, &sn, &co);
+                        ar += (double)co;
+                        ai += (double)sn;
+                    }
+                } else {
+                    for (int t = 0; t < Nk; ++t) {
+                        const double a = fma((double)t, A, B);
+                        const double fr = a - rint(a);
+                        double sn, co;
+                        sincospi(2.0 * fr, &sn, &co);
+                        ar += co;
+                        ai += sn;
+                    }
+                }
+                sr[j] = ar;
+                si[j] = ai;
             }
         }
     }
-    re = sr * invN;
-    im = si * invN;
+#pragma unroll
+    for (int j = 0; j < J; ++j) {
+        re[j] = sr[j] * invN;
+        im[j] = si[j] * invN;
+    }
 }
 
 // (cr + i ci) 2^E times (mr + i mi), renormalised to a largest part in [1/2, 1).
@@ -221,25 +271,61 @@ __global__ __launch_bounds__(kMdiBlock) void mdi_lr_kernel(const MdiArgs a) {
     const int set = gid >> a.lanes_log2, li = gid & (L - 1);
     const bool active = set < a.nsets;
 
-    // This lane's directions k = li, li + L, ... in increasing order, each one's
-    // inputs loaded while the previous one is summed.  Where every lane of the wave
-    // has the same node count (every N_k equal, the usual case) the node loops take
-    // it from a scalar register.
+    // This lane's directions k = li, li + L, ... in increasing order, two at a time,
+    // each pair's inputs loaded while the previous pair is summed.  Where every lane of
+    // the wave has the same node count (every N_k equal, the usual case) the node loops
+    // take it from a scalar register and 1/N_k is computed once per count; otherwise
+    // each direction is summed on its own with its lane's count.  An N_k outside
+    // [1, 2^20] (the caller's contract) gives NaN.
     double cr = 1.0, ci = 0.0;
     int E = 0;
     if (active && li < a.d) {
         const double* p = a.params + (size_t)set * a.P;
-        DirIn cur = load_dir<FAM>(p, a.d, a.N, li);
-        for (int k = li; k < a.d; k += L) {
-            const DirIn in = cur;
-            if (k + L < a.d) cur = load_dir<FAM>(p, a.d, a.N, k + L);
-            double re, im;
-            const int n0 = __builtin_amdgcn_readfirstlane(in.Nk);
-            if (__builtin_amdgcn_ballot_w64(in.Nk != n0) == 0)
-                direction_sum<FAM, FP32, 1>(in, n0, re, im);
-            else
-                direction_sum<FAM, FP32, 0>(in, in.Nk, re, im);
-            mul_renorm<kComplex>(cr, ci, E, re, im);
+        DirIn n1 = load_dir<FAM>(p, a.d, a.N, li);
+        DirIn n2 = li + L < a.d ? load_dir<FAM>(p, a.d, a.N, li + L) : n1;
+        int n_inv = 0;  // the count whose reciprocal invN holds (0: none yet)
+        double invN = 0.0;
+        for (int k = li; k < a.d; k += 2 * L) {
+            const bool two = k + L < a.d;
+            const DirIn in[2] = {n1, n2};
+            if (k + 2 * L < a.d) n1 = load_dir<FAM>(p, a.d, a.N, k + 2 * L);
+            if (k + 3 * L < a.d) n2 = load_dir<FAM>(p, a.d, a.N, k + 3 * L);
+            double re[2] = {1.0, 1.0}, im[2] = {0.0, 0.0};
+            const int n0 = __builtin_amdgcn_readfirstlane(in[0].Nk);
+            const bool bad0 = in[0].Nk < 1 || in[0].Nk > kMaxNodesPerDim;
+            const bool bad1 = two && (in[1].Nk < 1 || in[1].Nk > kMaxNodesPerDim);
+            if (__builtin_amdgcn_ballot_w64(in[0].Nk != n0 || (two && in[1].Nk != n0)) == 0 &&
+                n0 >= 1 && n0 <= kMaxNodesPerDim) {
+                if (n0 != n_inv) {
+                    invN = 1.0 / (double)n0;
+                    n_inv = n0;
+                }
+                if (two) {
+                    direction_sums<FAM, FP32, 2>(in, n0, invN, re, im);
+                } else {
+                    const DirIn in1[1] = {in[0]};
+                    double re1[1], im1[1];
+                    direction_sums<FAM, FP32, 1>(in1, n0, invN, re1, im1);
+                    re[0] = re1[0];
+                    im[0] = im1[0];
+                }
+            } else {
+#pragma unroll
+                for (int j = 0; j < 2; ++j) {
+                    if (j == 1 && !two) break;
+                    if (j == 0 ? bad0 : bad1) {
+                        re[j] = im[j] = __builtin_nan("");
+                        continue;
+                    }
+                    const DirIn inj[1] = {in[j]};
+                    double rej[1], imj[1];
+                    direction_sums<FAM, FP32, 1>(inj, in[j].Nk, 1.0 / (double)in[j].Nk, rej, imj);
+                    re[j] = rej[0];
+                    im[j] = imj[0];
+                }
+            }
+            mul_renorm<kComplex>(cr, ci, E, re[0], im[0]);
+            if (two) mul_renorm<kComplex>(cr, ci, E, re[1], im[1]);
         }
     }
     // Partial products of the set's L lanes, combined by a butterfly over lane
@@ -265,10 +351,11 @@ __global__ __launch_bounds__(kMdiBlock) void mdi_lr_kernel(const MdiArgs a) {
     }
 }
 
-// Lanes per set: enough (set, lane) pairs for about four waves per SIMD of the
-// whole GPU, at most one wave per set and at most one lane per direction.
+// Lanes per set: enough (set, lane) pairs for about eight waves per SIMD of the
+// whole GPU (the kernel's FP64 chains need that many to keep the SIMD issuing), at
+// most one wave per set and at most one lane per direction.
 static int mdi_lanes_log2(int d, int nsets) {
-    const int64_t want = (int64_t)device_cu_count() * 4 * 4 * kWave;
+    const int64_t want = (int64_t)device_cu_count() * 4 * 8 * kWave;
     int lg = 0;
     while (lg < 6 && (int64_t)nsets << lg < want && (2 << lg) <= d) ++lg;
     return lg;

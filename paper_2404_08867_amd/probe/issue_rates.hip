@@ -57,12 +57,18 @@ enum Kind : int {
     kGaussDim = 26,    // Gaussian (FP64) work of one point and direction (6 ops): integer
                        // step, v_cvt_f64_u32, y = k b + g, s += y y
     kGaussDimF = 27,   // the same with the exact-float step and v_cvt_f64_f32 (6 ops)
-    kNumKinds = 28
+    kF64Mul = 28,      // v_mul_f64
+    kHorner = 29,      // the MDI-LR node step h = r h + 1, r = r q (v_fma_f64, v_mul_f64)
+    kHorner2 = 30,     // the same step in only two of the chains (two directions' sums, as
+                       // the MDI-LR kernel runs them per lane): latency exposed
+    kNumKinds = 31
 };
 
-// Lane-operations one step of one chain performs.
-__host__ __device__ constexpr int ops_per_step(int kind) {
+// Lane-operations one step of one chain performs (on average over the chains).
+__host__ __device__ constexpr double ops_per_step(int kind) {
     switch (kind) {
+        case kHorner: return 2;
+        case kHorner2: return 2.0 * 2 / kChains;
         case kIndexStep: case kFloatStep: return 3;
         case kF64FmaExp: case kPointDim: case kF32FmaExp: case kPointDimF: return 5;
         case kGaussDim: case kGaussDimF: return 6;
@@ -82,12 +88,13 @@ __global__ __launch_bounds__(kBlock) void rate_kernel(int iters, uint32_t seed, 
     const double ad = 0.999 + (double)(s & 15) * 1e-9, bd = 1e-3;
     uint32_t r[kChains];
     float x[kChains];
-    double y[kChains];
+    double y[kChains], h[kChains];
 #pragma unroll
     for (int c = 0; c < kChains; ++c) {
         r[c] = (s >> (c & 15)) % n;
         x[c] = (float)r[c];  // an exact integer below 2^24 for the float step
         y[c] = 0.25 + (double)c * 0.01 + (double)(s & 7) * 1e-3;
+        h[c] = 1.0;
     }
     const float stf = (float)dlt, stmf = (float)dlt - (float)n;
     for (int it = 0; it < iters; ++it) {
@@ -189,13 +196,20 @@ __global__ __launch_bounds__(kBlock) void rate_kernel(int iters, uint32_t seed, 
                     x[c] = __uint_as_float(p1 < p2 ? p1 : p2);
                     const double g = __builtin_fma((double)x[c], bd, -0.5);
                     y[c] = __builtin_fma(g, g, y[c]);
+                } else if constexpr (K == kF64Mul) {
+                    y[c] = y[c] * ad;
+                } else if constexpr (K == kHorner || K == kHorner2) {
+                    if (K == kHorner || c < 2) {
+                        h[c] = __builtin_fma(y[c], h[c], 1.0);
+                        y[c] = y[c] * ad;
+                    }
                 }
             }
         }
     }
     double acc = 0.0;
 #pragma unroll
-    for (int c = 0; c < kChains; ++c) acc += (double)r[c] + (double)x[c] + y[c];
+    for (int c = 0; c < kChains; ++c) acc += (double)r[c] + (double)x[c] + y[c] + h[c];
     out[tid] = acc;
 }
 

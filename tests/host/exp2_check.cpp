@@ -1,12 +1,15 @@
-// Host check of qmc::exp2_f64 (paper_2404_08867_amd/csrc/exp2_f64.hpp): the largest
-// error, in units in the last place, against exp2l over n pseudo-random points of
-// [lo, hi] and the two end points; prints "<max ulp> <x at the max>".
+// Host check of qmc::exp2_f64 (paper_2404_08867_amd/csrc/exp2_f64.hpp) and, with a
+// fourth argument "small", "reduced" or "seed", of the MDI-LR seed forms
+// qmc::exp2_seed_small, qmc::exp2_seed_reduced and qmc::exp2_seed (exp2_seed.hpp): the
+// largest error, in units in the last place, against exp2l over n pseudo-random points
+// of [lo, hi] and the two end points; prints "<max ulp> <x at the max>".
 #include <math.h>
 #include <stdint.h>
 #include <stdio.h>
 #include <stdlib.h>
+#include <string.h>
 
-#include "exp2_f64.hpp"
+#include "exp2_seed.hpp"
 
 static double ulp_error(double got, long double ref) {
     const double r = fabs((double)ref);
@@ -14,8 +17,24 @@ static double ulp_error(double got, long double ref) {
     return (double)(fabsl((long double)got - ref) / ulp);
 }
 
+static double eval(char which, double x) {
+    switch (which) {
+        case 's': return qmc::exp2_seed_small(x);
+        case 'r': return qmc::exp2_seed_reduced(x);
+        case 'e': return qmc::exp2_seed(x);
+        default: return qmc::exp2_f64(x);
+    }
+}
+
 int main(int argc, char** argv) {
-    if (argc != 4) return 2;
+    if (argc != 4 && argc != 5) return 2;
+    char which = 'f';  // exp2_f64
+    if (argc == 5) {
+        if (!strcmp(argv[4], "small")) which = 's';
+        else if (!strcmp(argv[4], "reduced")) which = 'r';
+        else if (!strcmp(argv[4], "seed")) which = 'e';
+        else return 2;
+    }
     const long n = atol(argv[1]);
     const double lo = atof(argv[2]), hi = atof(argv[3]);
     double worst = 0.0, worst_x = lo;
@@ -30,7 +49,7 @@ int main(int argc, char** argv) {
             s ^= s << 17;
             x = lo + (hi - lo) * ((double)(s >> 11) * 0x1p-53);
         }
-        const double e = ulp_error(qmc::exp2_f64(x), exp2l((long double)x));
+        const double e = ulp_error(eval(which, x), exp2l((long double)x));
         if (e > worst) {
             worst = e;
             worst_x = x;

@@ -1,7 +1,9 @@
-"""The double-precision exp2 of the MDI-LR node recurrences (csrc/exp2_f64.hpp),
-compiled for the host with g++ and checked against the C library's long-double
-exp2l: within one unit in the last place over its range |x| <= 1000, exact at
-integers (powers of two) and at 0."""
+"""The double-precision exp2 of the QMC_FP64 per-point exponentials (csrc/exp2_f64.hpp)
+and of the MDI-LR recurrence seeds (csrc/exp2_seed.hpp), compiled for the host with
+g++ and checked against the C library's long-double exp2l: within one unit in the last
+place over the range |x| <= 1000, exact at integers (powers of two) and at 0; the
+seeds' short form within one unit in the last place over |x| <= 1/16, and the seeds'
+dispatch between the two forms over the whole range."""
 import os
 import shutil
 import subprocess
@@ -22,8 +24,9 @@ def checker(tmp_path_factory):
     return str(out)
 
 
-def _max_ulp(checker, n, lo, hi):
-    r = subprocess.run([checker, str(n), repr(lo), repr(hi)], capture_output=True, text=True, check=True)
+def _max_ulp(checker, n, lo, hi, form=None):
+    r = subprocess.run([checker, str(n), repr(lo), repr(hi)] + ([form] if form else []),
+                       capture_output=True, text=True, check=True)
     ulp, x = r.stdout.split()
     return float(ulp), float(x)
 
@@ -40,4 +43,32 @@ def test_within_one_ulp(checker, lo, hi, n):
 def test_exact_at_integers(checker, x):
     # one point, the end points lo = hi = x: a power of two is exact
     ulp, _ = _max_ulp(checker, 0, x, x)
+    assert ulp == 0.0
+
+
+@pytest.mark.parametrize("lo,hi,n", [(-0.0625, 0.0625, 2_000_000), (-1e-3, 1e-3, 500_000),
+                                     (0.06, 0.0625, 200_000), (-0.0625, -0.06, 200_000)])
+def test_seed_small_within_one_ulp(checker, lo, hi, n):
+    ulp, x = _max_ulp(checker, n, lo, hi, form="small")
+    assert ulp <= 1.0, (ulp, x)
+
+
+@pytest.mark.parametrize("form", ["reduced", "seed"])
+@pytest.mark.parametrize("lo,hi,n", [(-1000.0, 1000.0, 1_000_000), (-1.0, 1.0, 1_000_000),
+                                     (-0.07, 0.07, 500_000), (999.0, 1000.0, 100_000),
+                                     (-1000.0, -999.0, 100_000)])
+def test_seed_within_one_ulp(checker, form, lo, hi, n):
+    ulp, x = _max_ulp(checker, n, lo, hi, form=form)
+    assert ulp <= 1.0, (ulp, x)
+
+
+@pytest.mark.parametrize("form", ["small", "reduced", "seed"])
+def test_seed_exact_at_zero(checker, form):
+    ulp, _ = _max_ulp(checker, 0, 0.0, 0.0, form=form)
+    assert ulp == 0.0
+
+
+@pytest.mark.parametrize("x", [1.0, -1.0, 7.0, -300.0, 1000.0, -1000.0])
+def test_seed_reduced_exact_at_integers(checker, x):
+    ulp, _ = _max_ulp(checker, 0, x, x, form="reduced")
     assert ulp == 0.0

@@ -402,6 +402,28 @@ def test_mdi_lr_gaussian_wide_and_narrow_in_one_launch(precision):
 
 
 @pytest.mark.parametrize("precision", PRECS)
+@pytest.mark.parametrize("d", [12, 15])
+def test_mdi_lr_gaussian_pairs_mixed_branches(precision, d):
+    """Every N_k equal, so a lane sums its directions two at a time (with 200 sets the
+    library gives each set eight lanes: lanes 0..d-9 hold a pair, the others one
+    direction); the widths are drawn so that many pairs mix a direction of the node
+    recurrence with one summed node by node (each of the two is then summed on its own)."""
+    rng = np.random.default_rng(22 + d)
+    nsets = 200
+    N = np.full(d, 64, np.int32)
+    c = np.exp(rng.uniform(math.log(0.1), math.log(80.0), (nsets, d)))
+    w = rng.uniform(-0.2, 1.2, (nsets, d))
+    params = np.concatenate([c, w], axis=1)
+    q = qmc.mdi_lr(N, qmc.GAUSSIAN, params, precision).cpu().numpy()
+    for s in range(nsets):
+        qo = O.mdi_lr(N.astype(np.int64), O.GAUSSIAN, params[s])
+        if qo == 0.0:
+            assert q[s] == 0.0, s
+        else:
+            assert abs(q[s] - qo) <= TOL[precision] * abs(qo), (s, q[s], qo)
+
+
+@pytest.mark.parametrize("precision", PRECS)
 def test_mdi_lr_product_peak_extreme_widths(precision):
     """Product-peak factors whose denominators c^-2 + y^2 leave the normal FP32 range
     (c = 1e-25: about 1e50; c = 1e25 with w on a node: down to 1e-50) are summed with FP64
