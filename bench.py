@@ -180,6 +180,9 @@ def parse():
     ap.add_argument("--batched-stride", type=int, default=64,
                     help="the batched workload's CPU-baseline sample: every k-th integrand")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-plain-form", action="store_true",
+                    help="batched workload: leave out the comparison with the plain form (its 8192 "
+                         "single-integrand launches); used for the rocprofv3 counter runs")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="first run a plain device-to-device copy of this many MiB three times "
                          "(the reference for scaling rocprofv3 FETCH_SIZE / WRITE_SIZE)")
@@ -758,7 +761,8 @@ def bench_batched(args, torch, qmc, W):
         results[name] = dict(step_s=step_s, kern_s=kern_s, lat_s=step_s, q=out.cpu().numpy())
         del plan
     results["fp32c"]["lane_ops"] = sum(p.n * lane_ops_per_point(p.d, p.family) for p in batch.problems) / units
-    results["plain_per_integrand"] = plain_per_integrand(torch, qmc, batch, results)
+    if not args.no_plain_form:
+        results["plain_per_integrand"] = plain_per_integrand(torch, qmc, batch, results)
     config = {"workload": batch.name, "integrands": len(batch.problems), "points": units,
               "point_dims": int(sum(p.n * p.d for p in batch.problems)),
               "families": "exp_sum/product_peak/gaussian", "precision": "fp32_compensated",
