@@ -174,7 +174,7 @@ def parse():
     ap.add_argument("--workload", default="batched_4096",
                     choices=["plain_d20_peak", "plain_d4_expsum", "plain_d20_f5", "mdi_d100_gauss", "batched_4096",
                              "adjoint_d50_osc", "shifts_d20_peak", "korobov_search_d20",
-                             "cbc_d20", "mdi_sum_d100", "implr_d3", "rates"])
+                             "cbc_d20", "mdi_sum_d100", "implr_d3", "rates", "timeline_d20_peak"])
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
                     help="one core's worth of oracle work in the CPU-baseline sample of a plain workload")
     ap.add_argument("--batched-stride", type=int, default=64,
@@ -931,6 +931,87 @@ PROBE_MAIN = "point_dim(index step, cvt_f64_u32, f64_fma)"
 LANE_RATE = 256 * 64 * 2.4e9  # one VALU lane-operation per lane per clock
 
 
+TIMELINE_MODES = {0: "whole kernel", 1: "empty kernel on the same grid",
+                  2: "setup, workgroup total and grid sum, no tiles"}
+CLOCK_HZ = 100e6  # the constant clock that wall_clock64() (s_memrealtime) reads on gfx950
+
+
+def bench_timeline(args, torch, qmc, W):
+    """Phase timeline of the plain_d20_peak launch (FP32c) from the probe copy of the
+    plain-sum kernel (probe/plain_timeline.hip), beside the library's own launch: when
+    the last workgroup starts, how long the setup, the tiles and the grid sum take, and
+    the launch time of the empty kernel and of the fixed part without the tiles."""
+    import ctypes
+    import numpy as np
+    lib = ctypes.CDLL(os.path.join(ROOT, "paper_2404_08867_amd", "libqmc_probe.so"))
+    lib.qmc_probe_plain_timeline.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_uint32, ctypes.c_void_p,
+                                             ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                             ctypes.c_void_p, ctypes.c_void_p]
+    lib.qmc_probe_timeline_workgroups.argtypes = [ctypes.c_uint32]
+    w = W.plain_d20_peak()
+    z = torch.tensor(qmc.korobov(w.d, w.n, w.a), device="cuda")
+    params = torch.tensor(w.params, dtype=torch.float64, device="cuda")
+    ws = qmc.Workspace(qmc.workspace_size(w.d, w.n, 1))
+    q_lib = torch.zeros(1, dtype=torch.float64, device="cuda")
+    q_probe = torch.zeros(1, dtype=torch.float64, device="cuda")
+    G = lib.qmc_probe_timeline_workgroups(w.n)
+    KM = lib.qmc_probe_timeline_marks()
+    marks = torch.zeros(G * KM, dtype=torch.int64, device="cuda")
+
+    def lib_launch():
+        qmc.lattice_sum(z, w.n, w.family, params, qmc.FP32_COMPENSATED, ws=ws, out=q_lib)
+
+    _, lib_kern, _, g = time_graph(torch, lib_launch, args.steps, args.warmup)
+    del g
+    line = {"metric": "phases of the plain-sum launch (probe copy of the kernel)",
+            "value": lib_kern * 1e6, "unit": "us per launch (library kernel)", "n_gpus": 1,
+            "steps": args.steps, "warmup": args.warmup, "ms_per_step": lib_kern * 1e3,
+            "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+            "data": "synthetic",
+            "config": {"workload": "timeline_d20_peak", "d": w.d, "n": w.n, "family": "product_peak",
+                       "precision": "fp32_compensated", "workgroups": G, "threads": 1024,
+                       "points_per_thread": 4, "clock_hz": CLOCK_HZ},
+            "modes": {}}
+    for mode, name in TIMELINE_MODES.items():
+        def launch(mode=mode):
+            rc = lib.qmc_probe_plain_timeline(mode, w.d, w.n, ctypes.c_void_p(z.data_ptr()),
+                                              ctypes.c_void_p(params.data_ptr()),
+                                              ctypes.c_void_p(q_probe.data_ptr()),
+                                              ctypes.c_void_p(marks.data_ptr()), ctypes.c_void_p(ws.ptr),
+                                              ctypes.c_void_p(torch.cuda.current_stream().cuda_stream))
+            if rc != G:
+                raise RuntimeError(f"qmc_probe_plain_timeline(mode {mode}) returned {rc}")
+        _, kern, _, g = time_graph(torch, launch, args.steps, args.warmup)
+        del g
+        # phases of single launches (the medians over `reps` launches of each figure)
+        reps = 9
+        figs = []
+        for _ in range(reps):
+            marks.zero_()
+            torch.cuda.synchronize()
+            launch()
+            torch.cuda.synchronize()
+            a = marks.view(G, KM).cpu().numpy().astype(np.float64)
+            us = (a - a[:, 0].min()) / CLOCK_HZ * 1e6
+            f = {"last_workgroup_start_us": us[:, 0].max(), "kernel_end_us": us[:, 19].max()}
+            if mode != 1:
+                tile_end = us[:, 2:18].max(axis=1)
+                f.update({"setup_us_median": float(np.median(us[:, 1] - us[:, 0])),
+                          "setup_end_us_max": us[:, 1].max(),
+                          "wave0_tiles_end_us_median": float(np.median(us[:, 2])),
+                          "tiles_end_us_median": float(np.median(tile_end)),
+                          "tiles_end_us_max": tile_end.max(),
+                          "workgroup_total_us_max": us[:, 18].max(),
+                          "grid_sum_after_last_total_us": us[:, 19].max() - us[:, 18].max()})
+                assert int(a[:, 20].sum()) == 1, "exactly one workgroup produces the total"
+            figs.append(f)
+        med = {k: round(float(np.median([f[k] for f in figs])), 3) for k in figs[0]}
+        line["modes"][name] = {"us_per_launch": round(kern * 1e6, 3), "phases": med}
+        if mode == 0:
+            line["bits_equal_to_library"] = bool(torch.equal(q_probe, q_lib))
+    print(json.dumps(line), flush=True)
+
+
 def bench_rates(args, torch):
     import ctypes
     lib = ctypes.CDLL(os.path.join(ROOT, "paper_2404_08867_amd", "libqmc_probe.so"))
@@ -992,6 +1073,9 @@ def main():
     torch.cuda.set_device(0)
     if args.workload == "rates":
         bench_rates(args, torch)
+        return
+    if args.workload == "timeline_d20_peak":
+        bench_timeline(args, torch, qmc, W)
         return
     qmc.lib()  # fail loudly if the HIP library is missing
     if args.copy_probe_mib > 0:

@@ -16,9 +16,11 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libqmc.so")
-# The issue-rate probe behind the benchmark's ALU roofline (bench.py --workload rates):
-# a library of its own, not part of the C ABI.
-PROBE_SRC = os.path.join(PKG, "probe", "issue_rates.hip")
+# The probes behind the benchmark's measurements, a library of their own, not part of
+# the C ABI: the issue-rate probe behind the ALU roofline (bench.py --workload rates)
+# and the phase timeline of the plain-sum launch (--workload timeline_d20_peak).
+PROBE_DIR = os.path.join(PKG, "probe")
+PROBE_SRCS = ["issue_rates.hip", "plain_timeline.hip"]
 PROBE_LIB = os.path.join(PKG, "libqmc_probe.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
@@ -37,6 +39,8 @@ DEVICE_FLAGS = [
 # prologue that loads them for firmware without it).
 SOURCE_FLAGS = {
     "lattice_sum.hip": ["-mllvm", "-amdgpu-kernarg-preload-count=10"],
+    # the timeline copy of the plain-sum kernel is built as the kernel itself is
+    "plain_timeline.hip": ["-mllvm", "-amdgpu-kernarg-preload-count=10"],
     # The set-batched adjoint keeps its FP64 matrix accumulators in ordinary
     # VGPRs: in the AGPR form the compiler moved them between the two register
     # files every block of points.
@@ -48,9 +52,9 @@ def sources():
     return sorted(f for f in os.listdir(CSRC) if f.endswith(".hip"))
 
 
-def _compile(src: str, verbose: bool) -> str:
-    obj = os.path.join(BUILD, src.replace(".hip", ".o"))
-    cmd = [HIPCC, "-c", *DEVICE_FLAGS, *SOURCE_FLAGS.get(src, []), os.path.join(CSRC, src), "-o", obj]
+def _compile(src: str, verbose: bool, src_dir: str = CSRC, prefix: str = "") -> str:
+    obj = os.path.join(BUILD, prefix + src.replace(".hip", ".o"))
+    cmd = [HIPCC, "-c", *DEVICE_FLAGS, *SOURCE_FLAGS.get(src, []), os.path.join(src_dir, src), "-o", obj]
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)
@@ -62,14 +66,14 @@ def _compile(src: str, verbose: bool) -> str:
 
 
 def build_probe(verbose: bool = False) -> str:
-    """Compile the issue-rate probe into libqmc_probe.so; returns its path."""
+    """Compile the probes into libqmc_probe.so; returns its path."""
+    os.makedirs(BUILD, exist_ok=True)
+    objs = [_compile(src, verbose, PROBE_DIR, "probe_") for src in PROBE_SRCS]
     tmp = PROBE_LIB + ".tmp"
-    cmd = [HIPCC, "-shared", *DEVICE_FLAGS, PROBE_SRC, "-o", tmp]
+    cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs]
     if verbose:
         print(" ".join(cmd), flush=True)
-    r = subprocess.run(cmd, capture_output=True, text=True)
-    if r.returncode != 0:
-        raise RuntimeError(f"hipcc failed on {PROBE_SRC}:\n{r.stdout}\n{r.stderr}")
+    subprocess.run(cmd, check=True)
     os.replace(tmp, PROBE_LIB)
     return PROBE_LIB
 

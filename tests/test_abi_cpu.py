@@ -211,3 +211,31 @@ def test_batch_plan_rejects_invalid_problems():
     assert L.qmc_lattice_sum_batched(None, fake, fake, 0, None) == qmc.ERR_INVALID_ARG
     assert L.qmc_graph_launch(None, None) == qmc.ERR_INVALID_ARG
     assert L.qmc_batch_plan_destroy(None) == qmc.OK
+
+
+def test_probe_library_host_side():
+    """The measurement probes (libqmc_probe.so, not part of the C ABI) load without a GPU:
+    the issue-rate kinds and the timeline's layout are host arithmetic, and the timeline
+    entry point rejects bad arguments before any HIP call."""
+    path = os.path.join(ROOT, "paper_2404_08867_amd", "libqmc_probe.so")
+    if not os.path.exists(path):
+        pytest.skip("libqmc_probe.so not built")
+    P = ctypes.CDLL(path)
+    P.qmc_probe_lane_ops.restype = ctypes.c_double
+    P.qmc_probe_lane_ops.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int]
+    kinds = P.qmc_probe_kinds()
+    assert kinds == 31
+    # two chains of two operations per step out of eight chains: half an operation each
+    assert P.qmc_probe_lane_ops(30, 2, 3) == 2 * 256 * 3 * 16 * 8 * 0.5
+    assert P.qmc_probe_lane_ops(kinds, 2, 3) == -1.0
+    P.qmc_probe_timeline_workgroups.argtypes = [ctypes.c_uint32]
+    assert P.qmc_probe_timeline_marks() == 24
+    # 1024 threads x 4 points per tile, one workgroup per tile up to 512
+    assert P.qmc_probe_timeline_workgroups(1048573) == 256
+    assert P.qmc_probe_timeline_workgroups(4096) == 1
+    assert P.qmc_probe_timeline_workgroups(1 << 24) == 512
+    P.qmc_probe_plain_timeline.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_uint32] + [ctypes.c_void_p] * 6
+    fake = ctypes.c_void_p(256)  # never dereferenced: every call below fails its argument check
+    for mode, d, n in [(3, 20, 1000), (0, 0, 1000), (0, 33, 1000), (0, 20, 0), (0, 20, (1 << 24) + 1)]:
+        assert P.qmc_probe_plain_timeline(mode, d, n, fake, fake, fake, fake, fake, None) == -1
+    assert P.qmc_probe_plain_timeline(0, 20, 1000, None, fake, fake, fake, fake, None) == -1
