@@ -190,13 +190,16 @@ def parse():
 
 
 # HBM traffic of a workload's dominant kernel as measured with rocprofv3 counters and
-# recorded in its profile summary, together with a SHA-256 of the kernel's sources at
-# the time: reported only while the sources still match.
+# recorded in its profile summary, together with a SHA-256 of the kernel's sources and
+# of the build script (its compiler flags) at the time: reported only while they still
+# match.
 TRAFFIC = {
     "plain_d20_peak": ("lattice_sum_plain_d20_peak.md",
-                       ["lattice_sum.hip", "tile.hpp", "common.hpp", "families.hpp", "exp2_f64.hpp", "kernels.hpp"]),
+                       ["lattice_sum.hip", "tile.hpp", "common.hpp", "families.hpp", "exp2_f64.hpp", "kernels.hpp",
+                        "../build.py"]),
     "batched_4096": ("batched_kernel_batched_4096.md",
-                     ["batched.hip", "batched.hpp", "plan.hip", "tile.hpp", "common.hpp", "families.hpp", "exp2_f64.hpp"]),
+                     ["batched.hip", "batched.hpp", "plan.hip", "tile.hpp", "common.hpp", "families.hpp", "exp2_f64.hpp",
+                      "../build.py"]),
 }
 
 

@@ -45,6 +45,12 @@ SOURCE_FLAGS = {
     # VGPRs: in the AGPR form the compiler moved them between the two register
     # files every block of points.
     "adjoint.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form=1"],
+    # The batched kernel's persistent loop: machine-level loop-invariant code motion
+    # hoisted constants and per-thread addresses of every family's tile code out of it
+    # and kept them live across the whole loop, which set the register count (150
+    # vector registers in single precision, three waves per SIMD).  Without it: 125 and
+    # 117, four waves per SIMD, no spills; the direction loops are unchanged.
+    "batched.hip": ["-mllvm", "-disable-machine-licm"],
 }
 
 
