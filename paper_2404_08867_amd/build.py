@@ -51,6 +51,9 @@ SOURCE_FLAGS = {
     # vector registers in single precision, three waves per SIMD).  Without it: 125 and
     # 117, four waves per SIMD, no spills; the direction loops are unchanged.
     "batched.hip": ["-mllvm", "-disable-machine-licm"],
+    # The same for the MDI-LR sum evaluation: the hoisted series constants of its log2
+    # and exp2 held 85 registers in FP64 (63 without), and the step takes 2.5 % less.
+    "mdi_sum.hip": ["-mllvm", "-disable-machine-licm"],
 }
 
 
