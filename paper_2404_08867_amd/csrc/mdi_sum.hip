@@ -24,7 +24,8 @@ namespace qmc {
 // N-point window (each direction averages the previous weights over N states).
 // Rather than k sequential window steps -- one short, serial pass per direction,
 // a poor fit for 256 CUs -- the launcher forms them by repeated squaring:
-// O(log k) convolutions, each parallel over its outputs.  Each output adds
+// O(log k) convolutions, each parallel over its outputs, starting from powers of
+// up to eight directions counted exactly (window_powers_kernel).  Each output adds
 // positive terms in ascending order, so every state keeps full relative accuracy
 // and the result does not depend on the schedule.
 // A convolution out = a * b is split over (output tiles) x (segments of i):
@@ -188,6 +189,78 @@ static hipError_t launch_eval(const MdiSumLaunch& L, int states, int nl, double 
     return hipGetLastError();
 }
 
+// The k-fold self-convolution of the N-point window for small k, exactly.  The number
+// of k-tuples of nodes in [0, N) with index sum T is, by inclusion and exclusion over
+// the coordinates that exceed N - 1,
+//   c_k[T] = sum_{i >= 0, i N <= T} (-1)^i C(k, i) C(T - i N + k - 1, k - 1),
+// computed here in 64-bit integers (direct_k checks that every term and every partial
+// product of the binomials fits), and w_k[T] = c_k[T] / N^k with one rounding.  It
+// stands for the first log2 k squarings of the window, and it is exact where they
+// round.
+constexpr int kDirectMaxK = 8;
+
+template <int K>
+__device__ __forceinline__ uint64_t window_count(uint64_t N, uint64_t T) {
+    int64_t total = 0;
+    uint64_t cki = 1;  // C(K, i)
+#pragma unroll
+    for (int i = 0; i <= K; ++i) {
+        if ((uint64_t)i * N > T) break;
+        const uint64_t m = T - (uint64_t)i * N + (K - 1);
+        uint64_t c = 1;  // C(m, r), r = 0 .. K - 1: C(m, r) = C(m, r - 1) (m - r + 1) / r exactly
+#pragma unroll
+        for (int r = 1; r < K; ++r) c = c * (m - r + 1) / r;
+        const int64_t term = (int64_t)(cki * c);
+        total += (i & 1) ? -term : term;
+        cki = cki * (K - i) / (i + 1);
+    }
+    return (uint64_t)total;
+}
+
+template <int K>
+__device__ __forceinline__ void window_power(int N, double NK, int T, double* w) {
+    if (T <= K * (N - 1)) w[T] = (double)window_count<K>((uint64_t)N, (uint64_t)T) / NK;
+}
+
+__device__ __forceinline__ void window_power_k(int k, int N, double NK, int T, double* w) {
+    switch (k) {
+        case 1: window_power<1>(N, NK, T, w); break;
+        case 2: window_power<2>(N, NK, T, w); break;
+        case 3: window_power<3>(N, NK, T, w); break;
+        case 4: window_power<4>(N, NK, T, w); break;
+        case 5: window_power<5>(N, NK, T, w); break;
+        case 6: window_power<6>(N, NK, T, w); break;
+        case 7: window_power<7>(N, NK, T, w); break;
+        case 8: window_power<8>(N, NK, T, w); break;
+        default: break;  // k = 0: nothing to write
+    }
+}
+
+// w1 = w_{k1} (if k1 > 0) and w2 = w_{k2}, N^k as doubles in nk1 and nk2.
+__global__ __launch_bounds__(kConvBlock) void window_powers_kernel(int N, int k1, double nk1, double* w1,
+                                                                  int k2, double nk2, double* w2) {
+    const int T = blockIdx.x * kConvBlock + threadIdx.x;
+    window_power_k(k1, N, nk1, T, w1);
+    window_power_k(k2, N, nk2, T, w2);
+}
+
+// The largest power of two k <= min(kDirectMaxK, steps) for which window_count stays in
+// 64-bit integers at every T: N^k, every term C(k, i) C(m, k - 1) (m <= k N - 1, and
+// C(k, i) <= 2^k) with the sum of their magnitudes, and every partial product
+// r C(m, r) <= (k - 1) C(k N - 1, k - 1) below 2^62.  1 if none is.
+static int direct_k(int N, int steps) {
+    int best = 1;
+    for (int k = 2; k <= kDirectMaxK && k <= steps; k *= 2) {
+        long double c = 1.0L;  // C(k N - 1, k - 1)
+        for (int r = 1; r < k; ++r) c = c * (long double)((int64_t)k * N - r) / (long double)r;
+        const long double nk = powl((long double)N, (long double)k);
+        const long double lim = 0x1p62L;
+        if (nk > lim || c * (long double)(1 << k) > lim || c * (long double)(k - 1) > lim) break;
+        best = k;
+    }
+    return best;
+}
+
 // out = a * b through `partial` (kConvMaxSeg * (La + Lb - 1) doubles).  An operand a
 // of at most kConvOneSeg states is one segment: its partial sums are the output and
 // no reduction launch follows.  (Longer single segments make each thread's FMA chain
@@ -220,34 +293,65 @@ hipError_t launch_mdi_sum(const MdiSumLaunch& L, hipStream_t stream) {
     const int nl = merge ? 1 : L.N_last;
     const double off = merge ? 0.5 * (double)L.d / (double)L.N
                              : 0.5 * (double)(L.d - 1) / (double)L.N + 0.5 / (double)L.N_last;
-    // Three buffers of d (N - 1) + 1 doubles rotate between the running result R,
-    // the running square B and the output of each convolution.
+    // Three buffers of d (N - 1) + 1 doubles hold the running result R, the running
+    // square B and the output of each convolution; R and B may share one (R = B after
+    // the first factor).
     const size_t cap = (size_t)L.d * (size_t)(L.N - 1) + 1;
     double* buf[3] = {(double*)L.ws, (double*)L.ws + cap, (double*)L.ws + 2 * cap};
     double* partial = (double*)L.ws + 3 * cap;
-    double *R = buf[0], *B = buf[1], *T = buf[2];
-    int LR = 1, LB = L.N;
-    hipLaunchKernelGGL(states_init_kernel, dim3((L.N + kConvBlock - 1) / kConvBlock), dim3(kConvBlock),
-                       0, stream, L.N, R, B);
-    hipError_t e = hipGetLastError();
-    for (int bits = steps; bits > 0 && e == hipSuccess; bits >>= 1) {
+    int iR = 0, iB = 1;
+    auto free_buf = [&]() {
+        for (int i = 0; i < 3; ++i)
+            if (i != iR && i != iB) return i;
+        return 2;
+    };
+    // R = w_r0 and B = w_kd from the exact counts, then R * B^(steps / kd) by repeated
+    // squaring; without them (kd = 1) R = (1), B = the window and R * B^steps.
+    const int kd = direct_k(L.N, steps);
+    int LR, LB, bits;
+    bool r_one;  // R is the empty product (1)
+    hipError_t e;
+    if (kd >= 2) {
+        const int r0 = steps % kd;
+        LB = kd * (L.N - 1) + 1;
+        LR = r0 * (L.N - 1) + 1;
+        r_one = r0 == 0;
+        bits = steps / kd;
+        const double nk0 = pow((double)L.N, (double)r0), nkd = pow((double)L.N, (double)kd);
+        hipLaunchKernelGGL(window_powers_kernel, dim3((LB + kConvBlock - 1) / kConvBlock), dim3(kConvBlock), 0,
+                           stream, L.N, r0, nk0, buf[iR], kd, nkd, buf[iB]);
+    } else {
+        LR = 1;
+        LB = L.N;
+        r_one = true;
+        bits = steps;
+        hipLaunchKernelGGL(states_init_kernel, dim3((L.N + kConvBlock - 1) / kConvBlock), dim3(kConvBlock),
+                           0, stream, L.N, buf[iR], buf[iB]);
+    }
+    e = hipGetLastError();
+    for (; bits > 0 && e == hipSuccess; bits >>= 1) {
         if (bits & 1) {
-            // the shorter operand is staged as a (the convolution is symmetric)
-            e = LR <= LB ? launch_conv(R, LR, B, LB, T, partial, stream)
-                         : launch_conv(B, LB, R, LR, T, partial, stream);
-            double* t = R;
-            R = T;
-            T = t;
-            LR += LB - 1;
+            if (r_one) {
+                iR = iB;  // R = 1 * B: share B's buffer
+                LR = LB;
+                r_one = false;
+            } else {
+                // the shorter operand is staged as a (the convolution is symmetric)
+                const int iT = free_buf();
+                e = LR <= LB ? launch_conv(buf[iR], LR, buf[iB], LB, buf[iT], partial, stream)
+                             : launch_conv(buf[iB], LB, buf[iR], LR, buf[iT], partial, stream);
+                iR = iT;
+                LR += LB - 1;
+            }
         }
         if ((bits >> 1) > 0 && e == hipSuccess) {
-            e = launch_conv(B, LB, B, LB, T, partial, stream);
-            double* t = B;
-            B = T;
-            T = t;
+            const int iT = free_buf();
+            e = launch_conv(buf[iB], LB, buf[iB], LB, buf[iT], partial, stream);
+            iB = iT;
             LB = 2 * LB - 1;
         }
     }
+    double* R = buf[iR];
     if (e != hipSuccess) return e;
     // LR = steps (N - 1) + 1 states.
     if (L.gfamily == 0)

@@ -17,9 +17,14 @@ PRECS = [qmc.FP64, qmc.FP32_COMPENSATED]
 # (d, N, N_last): one direction; N = 1 (every state merges); a last count of
 # a + 1 (eq. 3.5 with n = 1 + a^d); states past one pass of the window loop;
 # Test 7's shape; more states than LDS holds (workspace buffers); long windows
-# (N = 128, 600, 1500) with few directions, odd and even step counts.
+# (N = 128, 600, 1500) with few directions, odd and even step counts.  The launcher
+# counts the powers of up to 8 directions exactly (fewer where N^k or the binomials
+# would leave 64-bit integers: 4 for N = 128 and 300, 2 for N = 1500 at two steps)
+# and squares on from there: (64, 8, 8) is a pure power (no remainder), (2, 1500, 1500)
+# needs no convolution at all, (5, 1500, 1500) counts four directions with N^4 near 5e12.
 SHAPES = [(1, 1, 17), (5, 1, 3), (4, 10, 11), (12, 9, 9), (100, 64, 64), (300, 64, 65),
-          (9, 128, 128), (3, 600, 600), (2, 1500, 1500), (2, 1500, 7)]
+          (9, 128, 128), (3, 600, 600), (2, 1500, 1500), (2, 1500, 7),
+          (64, 8, 8), (40, 2, 2), (5, 1500, 1500), (20, 300, 300)]
 PARAMS = {qmc.SUM_POWER: [[1.0, 1.0, 5.0], [0.7, 1.3, 2.5], [2.0, 0.4, 0.5]],
           qmc.SUM_GAUSS: [[0.9, 0.3], [0.2, 1.7], [1.5, 4.0]]}
 
