@@ -23,13 +23,16 @@ namespace qmc {
 
 constexpr double kLn2 = 0.69314718055994530942;
 
-// p t + c.  On the device one v_fma_f64 with all three operands in registers: left
-// to itself the compiler may emit the two-address v_fmac_f64 and a copy of the
-// constant c before each of them.
+// p t + c for a series coefficient c (a compile-time constant, the same in every
+// lane).  On the device one v_fma_f64 that reads c from a scalar register pair: left
+// to itself the compiler may emit the two-address v_fmac_f64 with a copy of c into
+// vector registers before each of them, and with c in vector registers a kernel keeps
+// the thirteen coefficients in 26 of them (the plain sums' FP64 exp-sum and Gaussian
+// kernels held 96 vector registers that way, 75 with the coefficients in scalar ones).
 QMC_HD inline double horner_step(double p, double t, double c) {
 #if defined(__HIP_DEVICE_COMPILE__)
     double r;
-    asm("v_fma_f64 %0, %1, %2, %3" : "=v"(r) : "v"(p), "v"(t), "v"(c));
+    asm("v_fma_f64 %0, %1, %2, %3" : "=v"(r) : "v"(p), "v"(t), "s"(c));
     return r;
 #else
     return fma(p, t, c);

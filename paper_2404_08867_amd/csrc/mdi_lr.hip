@@ -92,7 +92,7 @@ __device__ __forceinline__ void quad_node_sums(const double (&A)[J], const doubl
 #pragma unroll
             for (int j = 0; j < J; ++j) {
                 const double y0 = fma((double)t0, A[j], B[j]);
-                phi0[j] = exp2_seed_reduced(s[j] * y0 * y0);
+                phi0[j] = exp2_f64(s[j] * y0 * y0);
                 const double yl = fma((double)(t0 + m - 2), A[j], B[j]);  // the run's last ratio r_{t0+m-2}
                 r[j] = exp2_seed(s[j] * A[j] * fma(2.0, yl, A[j]));
                 h[j] = 1.0;

@@ -1,8 +1,8 @@
 // Host check of qmc::exp2_f64 (paper_2404_08867_amd/csrc/exp2_f64.hpp) and, with a
-// fourth argument "small", "reduced" or "seed", of the MDI-LR seed forms
-// qmc::exp2_seed_small, qmc::exp2_seed_reduced and qmc::exp2_seed (exp2_seed.hpp): the
-// largest error, in units in the last place, against exp2l over n pseudo-random points
-// of [lo, hi] and the two end points; prints "<max ulp> <x at the max>".
+// fourth argument "small" or "seed", of the MDI-LR seed forms qmc::exp2_seed_small and
+// qmc::exp2_seed (exp2_seed.hpp): the largest error, in units in the last place,
+// against exp2l over n pseudo-random points of [lo, hi] and the two end points; prints
+// "<max ulp> <x at the max>".
 #include <math.h>
 #include <stdint.h>
 #include <stdio.h>
@@ -20,7 +20,6 @@ static double ulp_error(double got, long double ref) {
 static double eval(char which, double x) {
     switch (which) {
         case 's': return qmc::exp2_seed_small(x);
-        case 'r': return qmc::exp2_seed_reduced(x);
         case 'e': return qmc::exp2_seed(x);
         default: return qmc::exp2_f64(x);
     }
@@ -31,7 +30,6 @@ int main(int argc, char** argv) {
     char which = 'f';  // exp2_f64
     if (argc == 5) {
         if (!strcmp(argv[4], "small")) which = 's';
-        else if (!strcmp(argv[4], "reduced")) which = 'r';
         else if (!strcmp(argv[4], "seed")) which = 'e';
         else return 2;
     }
