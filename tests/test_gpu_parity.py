@@ -402,6 +402,30 @@ def test_mdi_lr_gaussian_wide_and_narrow_in_one_launch(precision):
 
 
 @pytest.mark.parametrize("precision", PRECS)
+@pytest.mark.parametrize("seed", range(8))
+def test_mdi_lr_random_shapes_every_set(precision, seed):
+    """Seeded random launches: d in [1, 70], 1 to 300 sets (so the library's lanes per set
+    and the split of each lane's directions into pairs and a last single vary), node counts
+    all equal or drawn per direction, the five families in turn; every set against the
+    oracle."""
+    rng = np.random.default_rng(900 + seed)
+    family = seed % 5
+    d = int(rng.integers(1, 71))
+    nsets = int(rng.integers(1, 301))
+    N = (np.full(d, int(rng.integers(1, 41))) if seed % 2 == 0 else rng.integers(1, 41, d)).astype(np.int32)
+    params = np.stack([W.draw_params(rng, family, d) for _ in range(nsets)])
+    q = qmc.mdi_lr(N, family, params, precision).cpu().numpy()
+    for s in range(nsets):
+        qo = O.mdi_lr(N.astype(np.int64), family, params[s])
+        if family == 3:
+            re, im = O.mdi_lr_factors(N.astype(np.int64), family, params[s])
+            scale = float(np.prod(np.hypot(re, im)))
+        else:
+            scale = abs(qo)
+        assert abs(q[s] - qo) <= TOL[precision] * max(scale, 1e-300), (family, d, nsets, s, q[s], qo)
+
+
+@pytest.mark.parametrize("precision", PRECS)
 @pytest.mark.parametrize("d", [12, 15])
 def test_mdi_lr_gaussian_pairs_mixed_branches(precision, d):
     """Every N_k equal, so a lane sums its directions two at a time (with 200 sets the
