@@ -244,13 +244,14 @@ template <class F>
 static hipError_t launch_f(const PlainLaunch& L, hipStream_t stream) {
     int M = L.points_per_thread;
     if (M == 0) {
-        // As many points per thread as still leaves >= 1.5 tiles per CU (the
-        // per-direction setup is amortised over M points, the latency over the
-        // workgroups resident on a CU).
+        // As many points per thread as still leaves >= 1.5 tiles per CU over all the
+        // launch's sets (the per-direction setup is amortised over M points, the
+        // latency over the workgroups resident on a CU).
         const uint64_t want_tiles = 3ull * device_cu_count() / 2;
         const uint64_t pts = evaluated_points(L, mirror_family<F>::value && !L.shift);
         M = 16;
-        while (M > 4 && (pts + kSumBlock * M - 1) / ((uint64_t)kSumBlock * M) < want_tiles)
+        while (M > 4 &&
+               (uint64_t)L.nsets * ((pts + kSumBlock * M - 1) / ((uint64_t)kSumBlock * M)) < want_tiles)
             M /= 2;
     }
     switch (M) {
