@@ -169,7 +169,10 @@ __device__ __forceinline__ double bernoulli_factor(double aj, double c0, double 
         return fma(aj * y, y, c0);  // 1 + a (y^2 - 1/30) = 1 + a B_4(x)
 }
 
-template <int ALPHA>
+// FI: the residues stepped as exact floats (stepmod_f, n <= kFloatIndexMaxN), three
+// FP32 operations per point in place of addmod's integer add, compare and select
+// followed by a conversion; the same residues, so the same bits.
+template <int ALPHA, bool FI>
 __global__ __launch_bounds__(kCbcBlock) void cbc_eval_kernel(uint32_t n, double inv_n,
                                                             const double* a, int j,
                                                             const double* p, int64_t c_first,
@@ -199,14 +202,26 @@ __global__ __launch_bounds__(kCbcBlock) void cbc_eval_kernel(uint32_t n, double 
             bias += ok ? 0.0 : 1.0;
             r[m] = ok ? mulmod((uint64_t)k, cbeg, n, inv_n) : 0u;
         }
+        float rf[kCbcM], kf[kCbcM], kmf[kCbcM];
+        if constexpr (FI) {
+#pragma unroll
+            for (int m = 0; m < kCbcM; ++m) {
+                rf[m] = (float)r[m];
+                kf[m] = (float)kk[m];
+                kmf[m] = (float)kk[m] - (float)n;
+            }
+        }
         for (int c = 0; c < gc; ++c) {
             double acc = bias;
 #pragma unroll
             for (int m = 0; m < kCbcM; ++m) {
-                const double x = (double)r[m] * inv_n;
+                const double x = (FI ? (double)rf[m] : (double)r[m]) * inv_n;
                 const double y = fma(-x, x, x);  // x (1 - x)
                 acc += fma(pk[m], bernoulli_factor<ALPHA>(aj, c0, y), -1.0);
-                r[m] = addmod(r[m], kk[m], n);
+                if constexpr (FI)
+                    rf[m] = stepmod_f(rf[m], kf[m], kmf[m]);
+                else
+                    r[m] = addmod(r[m], kk[m], n);
             }
             const double w = wave_total(acc);
             if (lane == kWaveTotalLane) s_acc[c * W + wv] += w;
@@ -358,9 +373,13 @@ static hipError_t launch_cbc_a(const CbcLaunch& L, hipStream_t stream) {
         // z_1 = 1; later components range over 1 <= c <= n/2 (c and n - c tie).  The
         // candidates are compared by S; the chosen one's criterion is C_{j+1} S.
         const int ncand = j == 0 ? 1 : (int)(L.n / 2);
-        hipLaunchKernelGGL((cbc_eval_kernel<ALPHA>), dim3((ncand + kCbcCand - 1) / kCbcCand),
-                           dim3(kCbcBlock), 0, stream, L.n, inv_n, a, j, p, (int64_t)1, ncand,
-                           cand);
+        const dim3 eval_grid((ncand + kCbcCand - 1) / kCbcCand);
+        if (L.n <= kFloatIndexMaxN)
+            hipLaunchKernelGGL((cbc_eval_kernel<ALPHA, true>), eval_grid, dim3(kCbcBlock), 0, stream,
+                               L.n, inv_n, a, j, p, (int64_t)1, ncand, cand);
+        else
+            hipLaunchKernelGGL((cbc_eval_kernel<ALPHA, false>), eval_grid, dim3(kCbcBlock), 0, stream,
+                               L.n, inv_n, a, j, p, (int64_t)1, ncand, cand);
         hipLaunchKernelGGL(select_kernel, dim3(1), dim3(kSelectBlock), 0, stream, cand, ncand,
                            (int64_t)1, (const uint8_t*)nullptr, L.s_out + j, (double*)nullptr,
                            L.z_out + j, cum + j);

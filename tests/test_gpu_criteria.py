@@ -199,6 +199,18 @@ def test_cbc_p_alpha_against_exhaustive_oracle_search(alpha):
     _check_p_alpha_cbc(z.cpu().numpy(), s.cpu().numpy(), n, alpha)
 
 
+@pytest.mark.parametrize("n", [(1 << 24) - 3, 1 << 24, (1 << 24) + 1, (1 << 24) + 43])
+def test_cbc_either_side_of_the_float_index_limit(n):
+    """Up to n = 2^24 the candidate sums step their residues as exact floats, above it
+    as integers.  At d = 1 the one candidate z_1 = 1 is summed over all n/2 paired
+    indices: its criterion against the oracle on either side of the limit."""
+    gamma = np.array([0.8])
+    z, e2 = qmc.cbc(1, n, gamma, 0.3)
+    assert z.cpu().numpy().tolist() == [1]
+    eo = O.shift_avg_wce2([1], n, gamma, 0.3)
+    assert _close(e2.cpu().numpy()[0], eo, _wce2_scale([1], n, gamma, 0.3)), (n, e2, eo)
+
+
 def test_korobov_search_d20_full_size_sampled():
     """The benchmark's search (n = 65521, d = 20, e^2 with gamma_j = j^-2, a in
     [1, n/2]): sampled candidates against the oracle, the chosen a's value, and the
