@@ -111,6 +111,18 @@ def test_plain_sum_float_index_boundary(n, shift):
             assert _rel(q, qo, ao) <= TOL[precision], (n, precision, ppt, q, qo)
 
 
+@pytest.mark.parametrize("d,n", [(40, 16777213), (65, 16777259)])
+def test_plain_sum_exact_slope_peak_index_bound(d, n):
+    """Above 32 directions the FP32 product-peak factors need exact float indices: up to
+    n = 2^24 they run (one table chunk at d = 40), above it the problem takes the FP64
+    factors (d = 65, chunked tables)."""
+    rng = np.random.default_rng(d + n)
+    prob = _peak(d + n, d, n, rng.uniform(0.5, 2, d), rng.uniform(0, 1, d), shift=True)
+    qo, ao = _oracle_sum(prob)
+    q = _gpu_sum(prob, qmc.FP32_COMPENSATED, points_per_thread=16)
+    assert _rel(q, qo, ao) <= TOL[qmc.FP32_COMPENSATED], (d, n, q, qo)
+
+
 def _peak(seed, d, n, c, w, shift=False):
     rng = np.random.default_rng(seed)
     s = rng.uniform(0, 1, d) if shift else None
@@ -120,18 +132,22 @@ def _peak(seed, d, n, c, w, shift=False):
 
 @pytest.mark.parametrize("case", ["narrow_at_0", "narrow_random", "one_narrow", "w_outside",
                                   "c_at_limit", "d32", "d33", "narrow_at_0_d48", "one_narrow_d40",
-                                  "c_at_limit_d64"])
+                                  "c_at_limit_d64", "d65", "d100", "d200",
+                                  "one_narrow_d130", "w_outside_d100", "c_at_limit_d100",
+                                  "c_at_limit_d200", "narrow_random_d70"])
 def test_plain_sum_product_peak_guard(case):
-    """FP32 product-peak factors (up to 32 directions) run only where every direction
-    passes the guard (|c_j| <= 4, factor range within 2^+-7); narrow peaks (c_j = 50..100,
-    which would underflow an FP32 run of 16 factors), centres far outside [0, 1] and d
-    above the FP32 limit (the same cases at 40, 48 and 64 directions) take the FP64
-    factors.  Every case at both precisions' bars."""
+    """FP32 product-peak factors run only where every direction passes the guard
+    (|c_j| <= 4, centre in [0, 1], factor range within 2^+-7): up to 32 directions the
+    six-operation form, above it the exact-slope form, whose check runs per tile when
+    the tables come in chunks (d > 64).  Narrow peaks (c_j = 50..100, which would
+    underflow an FP32 run of 16 factors), a single failing direction and centres far
+    outside [0, 1] take the FP64 factors, at 20 to 130 directions.  Every case at both
+    precisions' bars."""
     rng = np.random.default_rng(len(case))
     d, n = 20, 65537
-    if case.endswith(("_d48", "_d40", "_d64")):
-        d = int(case[-2:])
-        case = case[:-4]
+    if "_d" in case:
+        case, dd = case.rsplit("_d", 1)
+        d = int(dd)
     if case == "narrow_at_0":      # point i = 0 sits on every peak
         prob = _peak(1, d, n, rng.uniform(50, 100, d), np.zeros(d))
     elif case == "narrow_random":
@@ -167,7 +183,12 @@ def test_batched_product_peak_guard():
              _peak(34, 8, 10007, np.full(8, 4.0), rng.uniform(0, 1, 8)),
              _peak(35, 48, 20011, rng.uniform(50, 100, 48), np.zeros(48)),
              _peak(36, 40, 30011, np.r_[rng.uniform(0.5, 2, 39), 70.0], rng.uniform(0, 1, 40), shift=True),
-             _peak(37, 64, 10007, np.full(64, 4.0), rng.uniform(0, 1, 64))]
+             _peak(37, 64, 10007, np.full(64, 4.0), rng.uniform(0, 1, 64)),
+             _peak(38, 100, 20011, rng.uniform(50, 100, 100), rng.uniform(0, 1, 100)),
+             _peak(39, 150, 30011, np.r_[rng.uniform(0.5, 2, 149), 70.0], rng.uniform(0, 1, 150), shift=True),
+             _peak(40, 90, 10007, rng.uniform(0.5, 2, 90), np.r_[rng.uniform(0, 1, 89), -3.0]),
+             _peak(41, 200, 40009, np.full(200, 4.0), rng.uniform(0, 1, 200), shift=True),
+             _peak(42, 120, 30011, rng.uniform(0.5, 2, 120), rng.uniform(0, 1, 120))]
     descs = [(p.family, qmc.korobov(p.d, p.n, p.a), p.n, p.params, p.shift) for p in probs]
     for precision in PRECS:
         q = qmc.BatchPlan(descs, precision).run().cpu().numpy()
