@@ -59,8 +59,8 @@ PEAK_SLOTS = 256 * 128 * 2.4e9
 #   exp-sum, oscillatory: conversion to FP64, FP64 argument FMA;
 #   Gaussian:             conversion, FP64 y = b k + g, FP64 y^2 accumulated;
 #   product peak:         FP32 y, y^2 + g, product (d <= 32, the exact float taken
-#                         as it is); above 32 directions the exact-slope FP32 form:
-#                         y = se k - se Wi exact, + fraction, y^2 + glo, + ghi, product.
+#                         as it is); FP64 factors above 32 directions (conversion, three
+#                         FP64 operations).
 INDEX = 3 * C32
 ACCUM = 2 * C64
 PEAK_F32_MAX_DIMS = 32
@@ -71,7 +71,7 @@ def work_per_point(d: int, family: int) -> int:
         if d <= PEAK_F32_MAX_DIMS:
             per_dim = INDEX + 3 * C32
         else:
-            per_dim = INDEX + 5 * C32
+            per_dim = INDEX + C64 + 3 * C64
     elif family in (2, 4):  # Gaussian, exp of a signed quadratic (y, then s y^2 added)
         per_dim = INDEX + C64 + 2 * C64
     else:  # exp-sum, oscillatory

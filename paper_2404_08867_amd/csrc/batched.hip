@@ -30,8 +30,7 @@ template <bool FP32>
 struct BatchFamilies {
     using E = ExpSum<FP32>;
     using PS = ProductPeak<FP32, FP32>;   // FP32 factors (d <= kPeakF32MaxDims when FP32)
-    using PX = ProductPeakX<FP32, false>; // FP32 factors, exact slope (d > kPeakF32MaxDims)
-    using PD = ProductPeak<false, FP32>;  // FP64 factors, where PX's check fails
+    using PD = ProductPeak<false, FP32>;  // FP64 factors
     using G = Gaussian<FP32>;
     using O = Oscillatory<FP32>;
     using Q = ExpQuadratic<FP32>;
@@ -41,7 +40,6 @@ template <bool FP32>
 union BatchShared {
     TileShared<typename BatchFamilies<FP32>::E> e;
     TileShared<typename BatchFamilies<FP32>::PS> ps;
-    TileShared<typename BatchFamilies<FP32>::PX> px;
     TileShared<typename BatchFamilies<FP32>::PD> pd;
     TileShared<typename BatchFamilies<FP32>::G> g;
     TileShared<typename BatchFamilies<FP32>::O> o;
@@ -107,21 +105,10 @@ __global__ __launch_bounds__(kBlock) void batched_kernel(const BatchArgs a) {
         switch (pr.family) {
             case kExpSum: run_tile<typename Fam::E, M, FI>(a, lo, pr, local, s.e, red, &flag); break;
             case kProductPeak:
-                if constexpr (FP32) {
-                    if (pr.d > kPeakF32MaxDims) {
-                        // every direction checked by the whole workgroup: all tiles of
-                        // a problem take the same form (and the same scale)
-                        int bad = 0;
-                        for (int j = threadIdx.x; j < pr.d; j += kBlock)
-                            bad |= Fam::PX::fp32_dim_ok(pr.params, pr.d, j, pr.n) ? 0 : 1;
-                        if (__syncthreads_or(bad))
-                            run_tile<typename Fam::PD, M, FI>(a, lo, pr, local, s.pd, red, &flag);
-                        else
-                            run_tile<typename Fam::PX, M, FI>(a, lo, pr, local, s.px, red, &flag);
-                        break;
-                    }
-                }
-                run_tile<typename Fam::PS, M, FI>(a, lo, pr, local, s.ps, red, &flag);
+                if (!FP32 || pr.d <= kPeakF32MaxDims)
+                    run_tile<typename Fam::PS, M, FI>(a, lo, pr, local, s.ps, red, &flag);
+                else
+                    run_tile<typename Fam::PD, M, FI>(a, lo, pr, local, s.pd, red, &flag);
                 break;
             case kGaussian: run_tile<typename Fam::G, M, FI>(a, lo, pr, local, s.g, red, &flag); break;
             case kExpQuadratic: run_tile<typename Fam::Q, M, FI>(a, lo, pr, local, s.q, red, &flag); break;

@@ -24,7 +24,6 @@
 
 #include <type_traits>
 
-#include "common.hpp"
 #include "exp2_f64.hpp"
 
 namespace qmc {
@@ -269,8 +268,7 @@ struct ProductPeak {
     // double-precision factors serve the other problems (same scale, same constants).
     static constexpr bool kGuarded = FP32_DIMS;
     using Fallback = ProductPeak<false, FP32_FINISH>;
-    __device__ static bool fp32_dim_ok(const double* p, int d, int j, uint32_t n) {
-        (void)n;
+    __device__ static bool fp32_dim_ok(const double* p, int d, int j) {
         const double c = fabs(p[j]), w = p[d + j];
         if (!(c > 0.0 && c <= kPeakF32MaxC)) return false;
         const double s2 = ldexp(1.0, -2 * peak_pow4(c));
@@ -319,118 +317,6 @@ struct ProductPeak {
         }
     }
     __device__ static double scale(double, int ie) { return ldexp(1.0, ie); }
-};
-
-// ------------------------------------- product peak with an exact slope (FP32)
-// The same integrand for d > kPeakF32MaxDims in single precision, without the
-// per-direction bias of ProductPeak<true, ...>.  In index units, with x = (k + sfrac)/n
-// and W = w n - sfrac, a factor is n^-2 ((k - W)^2 + n^2 c^-2); the form carries
-//   q'_j = se^2 ((k - W)^2 + n^2 c^-2) = y^2 + G,   y = se (k - W),   G = se^2 n^2 c^-2,
-// with se = 2^-m a power of two that puts q' near 1, and restores the n^2 se^2 of every
-// direction at the end (exponents exactly, mantissas through a logarithm sum).
-//   y:  W = Wi + Wf with Wi an integer; se (k - Wi) is exact (one FMA on the exact
-//       float k, |k - Wi| <= 2^24), and adding -se Wf rounds once per point.  The
-//       slope se is exact, so no rounding is shared by all points of a direction.
-//   G:  split as ghi + glo (two floats); y^2 + glo rounds per point and ghi is added
-//       after it, so the rounding of G to single precision does not bias the product
-//       either (adding glo after ghi would be lost below half an ulp every time).
-// 8 VALU operations per point and direction with the exact-float step, all FP32;
-// relative errors stay within about 1e-7 up to d = 200 (host emulation, c in
-// [1/2, 2]), against up to 2e-6 for the biased 6-operation form.  Directions must
-// have 0 <= w <= 1 (so that |k - Wi| <= n), |c| <= kPeakF32MaxC, factors within
-// [2^-7, 2^7] and n <= kFloatIndexMaxN (exact float indices); otherwise the whole
-// problem takes the double-precision form of the same algebra (Fallback).
-__device__ __forceinline__ int peak_pow4_n(double c, double dn) {
-    const double q = dn * dn * (__builtin_amdgcn_rcp(c * c) + 1.0 / 6.0);
-    return __builtin_amdgcn_frexp_exp(q) >> 1;
-}
-
-// GUARDED = false: the caller has checked every direction with fp32_dim_ok.
-template <bool FP32, bool GUARDED = FP32>
-struct ProductPeakX {
-    using T = typename std::conditional<FP32, float, double>::type;
-    struct DimF {
-        float a, bhi, blo, ghi, glo;
-    };
-    struct DimD {
-        double a, b, g;
-    };
-    using Dim = typename std::conditional<FP32, DimF, DimD>::type;
-    struct Acc {
-        T D;
-        int E;
-    };
-    static constexpr int kRenorm = FP32 ? 16 : 64;
-    static constexpr bool kBlockTerms = true;
-    static constexpr bool kGuarded = GUARDED;
-    using Fallback = ProductPeakX<false>;
-    __device__ static double index_n(double inv_n) { return rint(1.0 / inv_n); }
-    __device__ static bool fp32_dim_ok(const double* p, int d, int j, uint32_t n) {
-        const double c = fabs(p[j]), w = p[d + j];
-        if (n > kFloatIndexMaxN || !(c > 0.0 && c <= kPeakF32MaxC) || !(w >= 0.0 && w <= 1.0))
-            return false;
-        const double dn = (double)n;
-        const double s2 = ldexp(1.0, -2 * peak_pow4_n(c, dn));
-        const double ymax = fmax(w, 1.0 - w);
-        const double lo = s2 * dn * dn / (c * c), hi = s2 * dn * dn * (1.0 / (c * c) + ymax * ymax);
-        return lo >= 0x1p-7 && hi <= 0x1p7;
-    }
-    // prod_j n^2 se_j^2 = 2^ie * 2^ds1: n = mn 2^ex, mn in [1/2, 1).
-    __device__ static void block_terms(const double* p, int d, int j, double inv_n, double, double&,
-                                       double& ds1, int& ie) {
-        (void)d;
-        const double dn = index_n(inv_n);
-        ie += 2 * __builtin_amdgcn_frexp_exp(dn) - 2 * peak_pow4_n(p[j], dn);
-        ds1 += 2.0 * log2(__builtin_amdgcn_frexp_mant(dn));
-    }
-    __device__ static double extra(const double*) { return 0.0; }
-    __device__ static Dim dim(const double* p, int d, int j, double inv_n, double sfrac) {
-        const double c = p[j], w = p[d + j];
-        const double dn = index_n(inv_n);
-        const double se = ldexp(1.0, -peak_pow4_n(c, dn));
-        const double W = fma(w, dn, -sfrac);
-        const double G = se * se * dn * dn / (c * c);
-        if constexpr (FP32) {
-            const double Wi = floor(W);
-            const float ghi = (float)G;
-            return Dim{(float)se, (float)(-se * Wi), (float)(-se * (W - Wi)), ghi, (float)(G - (double)ghi)};
-        } else {
-            return Dim{se, -se * W, G};
-        }
-    }
-    __device__ static Acc init(double) { return Acc{(T)1, 0}; }
-    template <class K>
-    __device__ static void step(Acc& acc, K k, const Dim& c) {
-        if constexpr (FP32) {
-            const float y = fmaf((float)k, c.a, c.bhi) + c.blo;
-            acc.D *= fmaf(y, y, c.glo) + c.ghi;
-        } else {
-            const double y = fma((double)k, c.a, c.b);
-            acc.D *= fma(y, y, c.g);
-        }
-    }
-    __device__ static void renorm(Acc& acc) {
-        if constexpr (FP32) {
-            acc.E += __builtin_amdgcn_frexp_expf(acc.D);
-            acc.D = __builtin_amdgcn_frexp_mantf(acc.D);
-        } else {
-            acc.E += __builtin_amdgcn_frexp_exp(acc.D);
-            acc.D = __builtin_amdgcn_frexp_mant(acc.D);
-        }
-    }
-    __device__ static double finish(const Acc& acc) {
-        if constexpr (FP32) {
-            return ldexp((double)__builtin_amdgcn_rcpf(acc.D), -acc.E);
-        } else {
-            const int e = __builtin_amdgcn_frexp_exp(acc.D);
-            const float m = (float)__builtin_amdgcn_frexp_mant(acc.D);
-            return ldexp((double)__builtin_amdgcn_rcpf(m), -(acc.E + e));
-        }
-    }
-    __device__ static double scale(double ds1, int ie) {
-        const double f = floor(ds1);
-        return ldexp(exp2(ds1 - f), ie + (int)f);
-    }
 };
 
 // --------------------------------------------------- Bernoulli products (FP64)

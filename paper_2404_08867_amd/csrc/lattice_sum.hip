@@ -273,7 +273,7 @@ hipError_t launch_lattice_sum(const PlainLaunch& L, hipStream_t stream) {
             case kExpSum: return launch_f<ExpSum<true>>(L, stream);
             case kProductPeak:
                 if (L.d <= kPeakF32MaxDims) return launch_f<ProductPeak<true, true>>(L, stream);
-                return launch_f<ProductPeakX<true>>(L, stream);
+                return launch_f<ProductPeak<false, true>>(L, stream);
             case kGaussian: return launch_f<Gaussian<true>>(L, stream);
             case kOscillatory: return launch_f<Oscillatory<true>>(L, stream);
             case kExpQuadratic: return launch_f<ExpQuadratic<true>>(L, stream);

@@ -156,8 +156,7 @@ __device__ __forceinline__ void fill_lz(const ProblemView& v, TileShared<F, B>& 
 
 // Tables that do not depend on the tile for directions [j0, j0 + dc).
 // 64 * z_j < 2^37, so the exact double-precision mulmod applies.
-// FALLBACK (guarded families): the constants go to c2, from F::Fallback.
-template <class F, int B, bool FALLBACK = false>
+template <class F, int B>
 __device__ __forceinline__ void fill_dims(const ProblemView& v, TileShared<F, B>& s, int j0, int dc) {
     const int tid = threadIdx.x;
     fill_lz<F, B>(v, s, j0, dc);
@@ -170,10 +169,7 @@ __device__ __forceinline__ void fill_dims(const ProblemView& v, TileShared<F, B>
         s.st[e] = make_uint2(st, st - v.n);
         s.stf[e] = make_float2((float)st, (float)st - (float)v.n);
         s.sh[e] = whole;
-        if constexpr (FALLBACK)
-            s.c2[e] = F::Fallback::dim(v.p, v.d, j, v.inv_n, frac);
-        else
-            s.c[e] = F::dim(v.p, v.d, j, v.inv_n, frac);
+        s.c[e] = F::dim(v.p, v.d, j, v.inv_n, frac);
     }
 }
 
@@ -262,48 +258,12 @@ __device__ __forceinline__ double finish_points(const typename F::Acc (&acc)[M],
     return t;
 }
 
-// Points M0 .. M0 + M - 1 of the thread's MT points of a tile, any d, with the
-// fallback constants of the guarded family F (tables rebuilt chunk by chunk, as
-// tile_points).
-template <class F, int M, int MT, int M0, int B, bool FI, bool MIRROR>
-__device__ __forceinline__ double fallback_tile_points(const ProblemView& v, TileShared<F, B>& s,
-                                                       uint32_t tile_base, double init0) {
-    using FB = typename F::Fallback;
-    typename FB::Acc acc[M];
-#pragma unroll
-    for (int m = 0; m < M; ++m) acc[m] = FB::init(init0);
-    for (int j0 = 0; j0 < v.d; j0 += kDimChunk) {
-        const int dc = min(kDimChunk, v.d - j0);
-        __syncthreads();
-        fill_dims<F, B, true>(v, s, j0, dc);
-        __syncthreads();
-        fill_tile<F, MT, B>(v, s, j0, dc, tile_base);
-        __syncthreads();
-        chunk_points<FB, M, B, FI, M0>(acc, s, s.c2, j0, dc, v.n);
-    }
-    return finish_points<FB, M, MIRROR, MT, M0>(acc, tile_base, v.n);
-}
-
 // The thread's sum of f / scale over its M points of the tile, any d: the
 // tables are rebuilt chunk by chunk.  Begins with a barrier; the caller may
-// reuse s afterwards only after another barrier.  A guarded family checks every
-// direction first and takes its fallback for the whole tile if any fails.
+// reuse s afterwards only after another barrier.
 template <class F, int M, int B, bool FI = false, bool MIRROR = false>
 __device__ __forceinline__ double tile_points(const ProblemView& v, TileShared<F, B>& s,
                                               uint32_t tile_base, double init0) {
-    if constexpr (guarded_family<F>::value) {
-        int bad = 0;
-        for (int j = threadIdx.x; j < v.d; j += B) bad |= F::fp32_dim_ok(v.p, v.d, j, v.n) ? 0 : 1;
-        if (__syncthreads_or(bad)) {
-            // in two halves for M >= 8, as in tile_points_one_chunk
-            if constexpr (M >= 8) {
-                return fallback_tile_points<F, M / 2, M, 0, B, FI, MIRROR>(v, s, tile_base, init0) +
-                       fallback_tile_points<F, M / 2, M, M / 2, B, FI, MIRROR>(v, s, tile_base, init0);
-            } else {
-                return fallback_tile_points<F, M, M, 0, B, FI, MIRROR>(v, s, tile_base, init0);
-            }
-        }
-    }
     typename F::Acc acc[M];
 #pragma unroll
     for (int m = 0; m < M; ++m) acc[m] = F::init(init0);
@@ -350,7 +310,7 @@ __device__ __forceinline__ void setup_one_chunk(const ProblemView& v, TileShared
             s.c[j] = F::dim(v.p, d, j, v.inv_n, frac);
             if constexpr (guarded_family<F>::value) {
                 s.c2[j] = F::Fallback::dim(v.p, d, j, v.inv_n, frac);
-                bad = !F::fp32_dim_ok(v.p, d, j, v.n);
+                bad = !F::fp32_dim_ok(v.p, d, j);
             }
         }
         if constexpr (guarded_family<F>::value) {

@@ -111,18 +111,6 @@ def test_plain_sum_float_index_boundary(n, shift):
             assert _rel(q, qo, ao) <= TOL[precision], (n, precision, ppt, q, qo)
 
 
-@pytest.mark.parametrize("d,n", [(40, 16777213), (65, 16777259)])
-def test_plain_sum_exact_slope_peak_index_bound(d, n):
-    """Above 32 directions the FP32 product-peak factors need exact float indices: up to
-    n = 2^24 they run (one table chunk at d = 40), above it the problem takes the FP64
-    factors (d = 65, chunked tables)."""
-    rng = np.random.default_rng(d + n)
-    prob = _peak(d + n, d, n, rng.uniform(0.5, 2, d), rng.uniform(0, 1, d), shift=True)
-    qo, ao = _oracle_sum(prob)
-    q = _gpu_sum(prob, qmc.FP32_COMPENSATED, points_per_thread=16)
-    assert _rel(q, qo, ao) <= TOL[qmc.FP32_COMPENSATED], (d, n, q, qo)
-
-
 def _peak(seed, d, n, c, w, shift=False):
     rng = np.random.default_rng(seed)
     s = rng.uniform(0, 1, d) if shift else None
@@ -136,12 +124,11 @@ def _peak(seed, d, n, c, w, shift=False):
                                   "one_narrow_d130", "w_outside_d100", "c_at_limit_d100",
                                   "c_at_limit_d200", "narrow_random_d70"])
 def test_plain_sum_product_peak_guard(case):
-    """FP32 product-peak factors run only where every direction passes the guard
-    (|c_j| <= 4, centre in [0, 1], factor range within 2^+-7): up to 32 directions the
-    six-operation form, above it the exact-slope form, whose check runs per tile when
-    the tables come in chunks (d > 64).  Narrow peaks (c_j = 50..100, which would
-    underflow an FP32 run of 16 factors), a single failing direction and centres far
-    outside [0, 1] take the FP64 factors, at 20 to 130 directions.  Every case at both
+    """FP32 product-peak factors (up to 32 directions) run only where every direction
+    passes the guard (|c_j| <= 4, factor range within 2^+-7); narrow peaks (c_j = 50..100,
+    which would underflow an FP32 run of 16 factors), a single failing direction,
+    centres far outside [0, 1] and d above the FP32 limit (up to 200 directions, one
+    table chunk or chunked tables) take the FP64 factors.  Every case at both
     precisions' bars."""
     rng = np.random.default_rng(len(case))
     d, n = 20, 65537
@@ -171,6 +158,138 @@ def test_plain_sum_product_peak_guard(case):
         for ppt in (4, 16):
             q = _gpu_sum(prob, precision, points_per_thread=ppt)
             assert np.isfinite(q) and _rel(q, qo, ao) <= TOL[precision], (case, precision, ppt, q, qo)
+
+
+def _gauss(seed, d, n, c, w, shift=False):
+    rng = np.random.default_rng(seed)
+    s = rng.uniform(0, 1, d) if shift else None
+    return W.Plain(f"gauss{seed}", d, n, W.draw_coprime(rng, n), 2,
+                   np.concatenate([np.asarray(c, float), np.asarray(w, float)]), s)
+
+
+@pytest.mark.parametrize("case", ["in_range_d20", "in_range_d200", "at_limit_d40", "at_limit_d150",
+                                  "wide_d30", "one_wide_d100", "w_outside_d50", "w_outside_d90",
+                                  "in_range_d1"])
+def test_plain_sum_gaussian_parameter_ranges(case):
+    """Gaussian sums over parameter ranges beyond the workloads': every term at its
+    largest (c_j = 1 with w_j at an end of [0, 1]), wide peaks (c_j = 3), a single wider
+    direction and a centre outside [0, 1], with one table chunk (d <= 64) or chunked
+    tables.  Both precisions' bars at 4 and 16 points per thread."""
+    name, dd = case.rsplit("_d", 1)
+    d = int(dd)
+    rng = np.random.default_rng(d + len(name))
+    n = 40009
+    if name == "in_range":
+        prob = _gauss(d, d, n, rng.uniform(0.1, 1, d), rng.uniform(0, 1, d), shift=True)
+    elif name == "at_limit":       # every term up to log2(e): c = 1 with w at an end
+        prob = _gauss(d, d, n, np.ones(d), rng.integers(0, 2, d).astype(float))
+    elif name == "wide":
+        prob = _gauss(d, d, n, np.full(d, 3.0), rng.uniform(0, 1, d), shift=True)
+    elif name == "one_wide":
+        c = rng.uniform(0.1, 1, d)
+        c[d // 2] = 1.5
+        prob = _gauss(d, d, n, c, rng.uniform(0, 1, d))
+    else:
+        w = rng.uniform(0, 1, d)
+        w[1] = 2.5
+        prob = _gauss(d, d, n, rng.uniform(0.1, 0.3, d), w, shift=True)
+    qo, ao = _oracle_sum(prob)
+    assert np.isfinite(qo) and qo > 0
+    for precision in PRECS:
+        for ppt in (4, 16):
+            q = _gpu_sum(prob, precision, points_per_thread=ppt)
+            assert _rel(q, qo, ao) <= TOL[precision], (case, precision, ppt, q, qo)
+
+
+@pytest.mark.parametrize("case", ["in_range_d20", "in_range_d200", "at_limit_d40", "at_limit_d150",
+                                  "signed_d70", "wide_d30", "one_wide_d100", "in_range_d1"])
+def test_plain_sum_exp_sum_parameter_ranges(case):
+    """Exp-sum sums over parameter ranges beyond the workloads': |c_j| = 1 with either
+    sign, signed c_j, c_j in [2, 3] and a single larger c_j, with one table chunk
+    (d <= 64) or chunked tables.  Both precisions' bars at 4 and 16 points per
+    thread."""
+    name, dd = case.rsplit("_d", 1)
+    d = int(dd)
+    rng = np.random.default_rng(d + len(name))
+    if name == "in_range":
+        c = rng.uniform(0, 1, d)
+    elif name == "at_limit":
+        c = np.where(rng.integers(0, 2, d) == 1, 1.0, -1.0)
+    elif name == "signed":
+        c = rng.uniform(-1, 1, d)
+    elif name == "wide":
+        c = rng.uniform(2, 3, d)
+    else:
+        c = rng.uniform(0, 1, d)
+        c[d // 3] = 1.25
+    prob = W.Plain(f"expsum{case}", d, 40009, W.draw_coprime(rng, 40009), 0, c,
+                   rng.uniform(0, 1, d) if d % 2 == 0 else None)
+    qo, ao = _oracle_sum(prob)
+    assert np.isfinite(qo) and qo > 0
+    for precision in PRECS:
+        for ppt in (4, 16):
+            q = _gpu_sum(prob, precision, points_per_thread=ppt)
+            assert _rel(q, qo, ao) <= TOL[precision], (case, precision, ppt, q, qo)
+
+
+def test_batched_gaussian_and_exp_sum_parameter_ranges():
+    """The same parameter ranges in the batched kernel, below and above 64 directions,
+    in one launch, each against the oracle."""
+    rng = np.random.default_rng(23)
+    probs = [_gauss(51, 20, 40009, rng.uniform(0.1, 1, 20), rng.uniform(0, 1, 20)),
+             _gauss(52, 30, 20011, np.full(30, 3.0), rng.uniform(0, 1, 30), shift=True),
+             _gauss(53, 120, 30011, rng.uniform(0.1, 1, 120), rng.uniform(0, 1, 120), shift=True),
+             _gauss(54, 90, 10007, np.r_[rng.uniform(0.1, 1, 89), 2.0], rng.uniform(0, 1, 90)),
+             _gauss(55, 200, 20011, np.ones(200), rng.integers(0, 2, 200).astype(float)),
+             W.Plain("e56", 40, 30011, 1234, 0, rng.uniform(-1, 1, 40), rng.uniform(0, 1, 40)),
+             W.Plain("e57", 100, 20011, 4321, 0, np.r_[rng.uniform(0, 1, 99), 1.5], None),
+             W.Plain("e58", 150, 10007, 777, 0, rng.uniform(0, 1, 150), None),
+             W.Plain("e59", 20, 40009, 999, 0, rng.uniform(2, 3, 20), None)]
+    descs = [(p.family, qmc.korobov(p.d, p.n, p.a), p.n, p.params, p.shift) for p in probs]
+    for precision in PRECS:
+        q = qmc.BatchPlan(descs, precision).run().cpu().numpy()
+        for i, p in enumerate(probs):
+            qo, ao = _oracle_sum(p)
+            assert np.isfinite(q[i]) and _rel(q[i], qo, ao) <= TOL[precision], (i, precision, q[i], qo)
+
+
+# Identical parameters in every direction (the paper's test integrands are of this
+# kind): a rounding bias that single-precision arithmetic leaves in each direction then
+# adds up linearly in d instead of averaging out.  Small n keeps the lattice's
+# coordinate values few and structured (n = 4099, c = 1, w = 1/2 puts the peak
+# half-way between two grid values).
+IDENTICAL = [(1, 20, 4099, 1.0, 0.5), (1, 32, 4099, 1.0, 0.5), (1, 40, 4099, 1.0, 0.5),
+             (1, 100, 4099, 1.0, 0.5), (1, 32, 1031, 1.0, 0.5), (1, 200, 65537, 1 / 0.9, 0.6),
+             (2, 100, 65537, 1 / math.sqrt(2), 0.0), (2, 200, 4099, 1.0, 0.5),
+             (0, 100, 65537, 1.0, None), (0, 300, 4099, -1.0, None)]
+
+
+def _identical(family, d, n, c, w):
+    params = np.full(d, c) if family == 0 else np.concatenate([np.full(d, c), np.full(d, w)])
+    return W.Plain(f"ident{family}_{d}_{n}", d, n, W.draw_coprime(np.random.default_rng(d + n), n),
+                   family, params, None)
+
+
+@pytest.mark.parametrize("family,d,n,c,w", IDENTICAL)
+def test_plain_sum_identical_directions(family, d, n, c, w):
+    """Identical parameters in every direction, both precisions at their bars."""
+    prob = _identical(family, d, n, c, w)
+    qo, ao = _oracle_sum(prob)
+    assert np.isfinite(qo) and qo > 0
+    for precision in PRECS:
+        q = _gpu_sum(prob, precision)
+        assert _rel(q, qo, ao) <= TOL[precision], (family, d, n, precision, q, qo)
+
+
+def test_batched_identical_directions():
+    """The identical-direction problems in one batched launch."""
+    probs = [_identical(*case) for case in IDENTICAL]
+    descs = [(p.family, qmc.korobov(p.d, p.n, p.a), p.n, p.params, p.shift) for p in probs]
+    for precision in PRECS:
+        q = qmc.BatchPlan(descs, precision).run().cpu().numpy()
+        for i, p in enumerate(probs):
+            qo, ao = _oracle_sum(p)
+            assert _rel(q[i], qo, ao) <= TOL[precision], (i, precision, q[i], qo)
 
 
 def test_batched_product_peak_guard():
