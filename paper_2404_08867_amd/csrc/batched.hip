@@ -57,12 +57,15 @@ __device__ __forceinline__ void run_tile(const BatchArgs& a, int pi, const DevPr
     double t;
     if (v.d <= kDimChunk) {
         setup_one_chunk<F, M>(v, s, red, local_tile * kTile, init0, ds1, ie);
+        guard_check<F, kBlock>(v, s);
         t = tile_points_one_chunk<F, M, kBlock, FI>(v, s, local_tile * kTile, init0, true);
     } else {
         block_constants<F>(v, red, init0, ds1, ie);
         t = tile_points<F, M, kBlock, FI>(v, s, local_tile * kTile, init0);
     }
-    const double bsum = block_sum(t, red);
+    double bsum = block_sum(t, red);
+    if (v.d <= kDimChunk && guard_redo(s, ds1))
+        bsum = block_sum(redo_tiles<F, M, kBlock, FI, false>(v, s, local_tile, 1, local_tile + 1, init0), red);
     if (threadIdx.x == 0) {
         publish_partial(&a.partials[pr.tile_begin + local_tile], bsum);
         *flag = take_ticket(&a.counters[2 + pi], pr.tiles) ? 1 : 0;

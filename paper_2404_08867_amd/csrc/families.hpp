@@ -240,17 +240,61 @@ __device__ __forceinline__ int peak_pow4(double c) {
 
 // FP32_DIMS: per-direction factors in single precision (6 VALU ops per point and
 // direction with the exact-float index step).  Their constants a, b, g are rounded to
-// FP32 once per direction: a bias that is the same for every point of the direction,
-// so over the product it does not average out but grows like sqrt(d) * 2^-24 (up to
-// ~5e-7 at d = 64 for c_j in [1/2, 2]).  The launchers therefore take single-precision
-// factors only for d <= kPeakF32MaxDims, and the kernels themselves fall back to the
-// double-precision factors for the whole problem unless every direction passes
-// fp32_dim_ok: |c_j| <= kPeakF32MaxC (the rounding of the coordinate's offset moves a
-// factor by up to 2^-23 |c_j| of itself near its peak) and a factor range that keeps a
-// run of kRenorm = 16 factors well inside the FP32 exponent range.
+// FP32 once per direction: a bias that is the same for every point of the direction.
+// Its first-order effect on the sum is computed in closed form from the three rounding
+// errors (peak_fp32_bias) and divided out of the result; the per-point roundings of y,
+// the factor and the product remain, up to a few 2^-24 per factor.  The single-
+// precision factors are taken only where that leaves a result within the 1e-6 target:
+// d <= kPeakF32MaxDims (launchers); every direction passes fp32_dim_ok, |c_j| <=
+// kPeakF32MaxC and a factor range that keeps a run of kRenorm = 16 factors well inside
+// the FP32 exponent range; the first-order bias is at most kPeakF32MaxBias; and the
+// integrand is flat enough that the sum is not carried by a handful of points
+// (n / prod_j (max f_j / mean f_j) >= kPeakF32MinPoints), where the per-point errors,
+// which do not average out there, would show.  Other problems take the double-precision
+// factors (same scale without the bias term).
 // FP32_FINISH: the per-point reciprocal by v_rcp_f32 instead of an IEEE divide.
 constexpr int kPeakF32MaxDims = 32;
 constexpr double kPeakF32MaxC = 4.0;
+constexpr double kPeakF32MaxBias = 1e-6;
+constexpr double kPeakF32MinPoints = 16.0;
+
+// Direction j of the single-precision product peak: the first-order relative change of
+// the sum that rounding its constants a = s/n, b = s(sfrac/n - w), g = s^2/c^2 to FP32
+// causes, and log(max f_j / mean f_j).  With u = x - w on [-w', 1 - w'] (w' = w -
+// sfrac/n), q = c^-2 and the factor's denominator s^2 (u^2 + q), the rounding errors
+// da, db, dg (relative) change the denominator by s^2 (2u(u + w') da - 2u w' db + q dg);
+// weighted by f_j = 1/(u^2 + q) its mean relative effect on f_j is
+//   -(2 da (Iu2 + w' Iu1) - 2 w' db Iu1 + q dg I1) / I0,
+// I0 = int du/D, I1 = int du/D^2, Iu1 = int u du/D^2, Iu2 = int u^2 du/D^2, D = u^2 + q.
+// The rounding errors are exact differences in double precision; the rest runs in
+// single precision (a relative accuracy of 1e-6 is far more than a correction of a
+// few 1e-8 needs), so that the setup that waits for it stays short.  a, b, g are the
+// double-precision constants that are rounded to FP32 (ProductPeak::dim).
+__device__ inline void peak_fp32_bias(double c, double w, double inv_n, double sfrac, double a, double b,
+                                      double g, double& bias, double& log_ratio) {
+    const float da = (float)((double)(float)a - a) * __builtin_amdgcn_rcpf((float)a);
+    const float db = b != 0.0 ? (float)((double)(float)b - b) * __builtin_amdgcn_rcpf((float)b) : 0.0f;
+    const float dg = (float)((double)(float)g - g) * __builtin_amdgcn_rcpf((float)g);
+    const float ac = (float)fabs(c), q = __builtin_amdgcn_rcpf(ac * ac);
+    const float wp = (float)fma(-sfrac, inv_n, w);
+    const float lo = -wp, hi = 1.0f - wp;
+    const float dlo = lo * lo + q, dhi = hi * hi + q;
+    // atan(hi ac) - atan(lo ac) as one arctangent: (x - y) / (1 + x y) with x = hi ac,
+    // y = lo ac; x > y, so the difference lies in (0, pi) and takes pi when 1 + x y < 0
+    // (1 + x y = 0 gives atan(+inf) = pi / 2)
+    const float x = hi * ac, y = lo * ac, den = fmaf(x, y, 1.0f);
+    const float t = atanf((x - y) * __builtin_amdgcn_rcpf(den));
+    const float dt = den >= 0.0f ? t : t + 3.14159265f;
+    const float rlo = __builtin_amdgcn_rcpf(dlo), rhi = __builtin_amdgcn_rcpf(dhi);
+    const float I0 = ac * dt, c2 = ac * ac;  // c^2 = 1 / q
+    const float I1 = 0.5f * c2 * (hi * rhi - lo * rlo) + 0.5f * c2 * ac * dt;
+    const float Iu1 = 0.5f * (rlo - rhi);
+    const float Iu2 = I0 - q * I1;
+    bias = (double)(-(2.0f * da * (Iu2 + wp * Iu1) - 2.0f * wp * db * Iu1 + q * dg * I1) *
+                    __builtin_amdgcn_rcpf(I0));
+    const float umin = lo > 0.0f ? lo : (hi < 0.0f ? -hi : 0.0f);  // closest |u| to the peak
+    log_ratio = (double)(-__logf((umin * umin + q) * I0));
+}
 
 template <bool FP32_DIMS, bool FP32_FINISH>
 struct ProductPeak {
@@ -282,6 +326,20 @@ struct ProductPeak {
                                        double&, int& ie) {
         (void)d;
         ie += -2 * peak_pow4(p[j]);
+    }
+    // The problem-wide part of the guard: per direction log(max f_j / mean f_j) and the
+    // first-order bias (summed over the directions by the setup), and the test on the
+    // sums (NaN fails it).  The bias sum becomes ds1 of scale() when the test passes.
+    __device__ static void guard_terms(const double* p, int d, int j, double inv_n, double sfrac,
+                                       double& log_ratio, double& bias) {
+        const double c = p[j], w = p[d + j];
+        const double s = ldexp(1.0, -peak_pow4(c));
+        peak_fp32_bias(c, w, inv_n, sfrac, s * inv_n, s * fma(sfrac, inv_n, -w), s * s / (c * c), bias,
+                       log_ratio);
+    }
+    __device__ static bool block_ok(double log_ratio, double bias, uint32_t n) {
+        return log_ratio <= (double)__logf((float)n * (float)(1.0 / kPeakF32MinPoints)) &&
+               fabs(bias) <= kPeakF32MaxBias;
     }
     __device__ static double extra(const double*) { return 0.0; }
     __device__ static Dim dim(const double* p, int d, int j, double inv_n, double sfrac) {
@@ -316,7 +374,12 @@ struct ProductPeak {
             return ldexp(1.0 / acc.D, -acc.E);
         }
     }
-    __device__ static double scale(double, int ie) { return ldexp(1.0, ie); }
+    __device__ static double scale(double ds1, int ie) {
+        if constexpr (FP32_DIMS)
+            return ldexp(1.0, ie) / (1.0 + ds1);
+        else
+            return ldexp(1.0, ie);
+    }
 };
 
 // --------------------------------------------------- Bernoulli products (FP64)

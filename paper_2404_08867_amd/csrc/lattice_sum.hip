@@ -77,6 +77,7 @@ __global__ __launch_bounds__(B) void lattice_sum_kernel(
         // One set of direction tables serves every tile; the first tile's start
         // residues are built with them.
         setup_one_chunk<F, M, B>(v, s, s_red, blockIdx.x * kTile, init0, ds1, ie);
+        guard_check<F, B>(v, s);
         for (uint32_t tile = blockIdx.x; tile < tiles; tile += gridDim.x)
             tacc += tile_points_one_chunk<F, M, B, FI, MIRROR>(v, s, tile * kTile, init0, tile == blockIdx.x);
     } else {
@@ -87,7 +88,9 @@ __global__ __launch_bounds__(B) void lattice_sum_kernel(
 
     // Workgroup total to wave 0 (red[B / kWave ..) is untouched by the setup), then
     // the grid sum by wave 0 alone; the other waves are done.
-    const double bsum = block_sum_wave0<B>(tacc, s_red);
+    double bsum = block_sum_wave0<B>(tacc, s_red);
+    if (v.d <= kDimChunk && guard_redo(s, ds1))
+        bsum = block_sum_wave0<B>(redo_tiles<F, M, B, FI, MIRROR>(v, s, blockIdx.x, gridDim.x, tiles, init0), s_red);
     if (threadIdx.x >= kWave) return;
     const GridSlots slots =
         set_slots(scratch, scratch_stride, slot_stride, tickets, set, (int)gridDim.x);

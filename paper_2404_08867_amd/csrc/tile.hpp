@@ -34,8 +34,9 @@ template <class F>
 struct param_scaled<F, std::void_t<decltype(F::kParamScale)>> : std::bool_constant<F::kParamScale> {};
 
 // Families whose single-precision form is valid only for some parameters
-// (F::kGuarded): F::fp32_dim_ok decides per direction, and a problem with any
-// direction that fails is evaluated by F::Fallback (same constants and scale).
+// (F::kGuarded): F::fp32_dim_ok decides per direction and F::block_ok on the sums of
+// the block terms; a problem that fails either is evaluated by F::Fallback (same
+// constants, and the same scale once the form's own block term ds1 is dropped).
 template <class F, class = void>
 struct guarded_family : std::false_type {
     using fallback_dim = char;
@@ -97,7 +98,9 @@ struct TileShared {
     typename F::Dim c[kDimChunk];     // family constants
     // guarded families: the fallback's constants and whether the problem needs them
     typename guarded_family<F>::fallback_dim c2[guarded_family<F>::value ? kDimChunk : 1];
-    int use_fallback;
+    int use_fallback;   // a direction fails the family's per-direction check
+    int guard_fail;     // the problem fails the family's problem-wide check (guard_check)
+    double guard_bias;  // the single-precision form's ds1 (guard_check)
 };
 
 // Workgroup constants of a problem: sums over all directions in a fixed order.
@@ -297,6 +300,7 @@ __device__ __forceinline__ void setup_one_chunk(const ProblemView& v, TileShared
         int te = 0;
         bool bad = false;  // a direction the guarded family's FP32 form cannot take
         (void)bad;
+
         if (tid < d) {
             const int j = tid;
             uint32_t whole;
@@ -347,6 +351,33 @@ __device__ __forceinline__ void setup_one_chunk(const ProblemView& v, TileShared
     init0 = ds0 + F::extra(v.p);
 }
 
+// Guarded families, problem-wide part of the test (F::guard_terms summed over the
+// directions, F::block_ok on the sums): run by wave 0 right after setup_one_chunk,
+// while the other waves start on their points, so that it adds nothing to the setup.
+// The tiles take the single-precision form unless a direction failed (use_fallback);
+// after the workgroup sum, guard_redo tells whether to redo them with the fallback
+// (redo_tiles) because the problem-wide test failed.
+template <class F, int B>
+__device__ __forceinline__ void guard_check(const ProblemView& v, TileShared<F, B>& s) {
+    if constexpr (guarded_family<F>::value) {
+        if (threadIdx.x < kWave) {
+            const int j = threadIdx.x;
+            double g0 = 0.0, g1 = 0.0;
+            if (j < v.d) {
+                uint32_t whole;
+                double frac;
+                split_shift(v.shift, j, v.n, whole, frac);
+                F::guard_terms(v.p, v.d, j, v.inv_n, frac, g0, g1);
+            }
+            const double x = wave_total(g0), y = wave_total(g1);
+            if (j == kWaveTotalLane) {
+                s.guard_fail = F::block_ok(x, y, v.n) ? 0 : 1;
+                s.guard_bias = y;
+            }
+        }
+    }
+}
+
 // Points M0 .. M0 + M - 1 of the thread's MT points of a tile, with the fallback
 // constants c2 of a guarded family (F is the fallback).
 template <class F, int M, int MT, int M0, int B, bool FI, bool MIRROR, class S>
@@ -365,14 +396,14 @@ __device__ __forceinline__ double fallback_points(const ProblemView& v, const S&
 template <class F, int M, int B, bool FI = false, bool MIRROR = false>
 __device__ __forceinline__ double tile_points_one_chunk(const ProblemView& v, TileShared<F, B>& s,
                                                         uint32_t tile_base, double init0,
-                                                        bool kw_ready) {
+                                                        bool kw_ready, bool force_fallback = false) {
     if (!kw_ready) {
         __syncthreads();  // every read of the previous tile's residues is done
         fill_tile<F, M, B>(v, s, 0, v.d, tile_base);
         __syncthreads();
     }
     if constexpr (guarded_family<F>::value) {
-        if (s.use_fallback) {
+        if (s.use_fallback || force_fallback) {
             // The double-precision factors take twice the registers of the single-
             // precision ones; for M >= 8 they run over the thread's points in two
             // halves, so that this rarely taken branch does not set the register
@@ -391,6 +422,36 @@ __device__ __forceinline__ double tile_points_one_chunk(const ProblemView& v, Ti
     for (int m = 0; m < M; ++m) acc[m] = F::init(init0);
     chunk_points<F, M, B, FI>(acc, s, s.c, 0, v.d, v.n);
     return finish_points<F, M, MIRROR>(acc, tile_base, v.n);
+}
+
+// After the workgroup sum of a problem's tiles (setup_one_chunk, guard_check): that
+// sum's barrier has made guard_check's results visible.  Sets ds1 for F::scale (the
+// single-precision form's bias correction, none for the fallback) and returns whether
+// the tiles must be redone with the fallback (the problem-wide test failed); the same
+// answer in every thread of the workgroup.
+template <class F, int B>
+__device__ __forceinline__ bool guard_redo(const TileShared<F, B>& s, double& ds1) {
+    if constexpr (guarded_family<F>::value) {
+        const bool fb = s.use_fallback != 0, redo = !fb && s.guard_fail != 0;
+        ds1 = (fb || redo) ? 0.0 : s.guard_bias;
+        return redo;
+    } else {
+        (void)s;
+        (void)ds1;
+        return false;
+    }
+}
+
+// The workgroup's tiles first, first + stride, ... < tiles with the fallback (after
+// guard_redo).  Begins with a barrier.
+template <class F, int M, int B, bool FI, bool MIRROR>
+__device__ __forceinline__ double redo_tiles(const ProblemView& v, TileShared<F, B>& s, uint32_t first,
+                                             uint32_t stride, uint32_t tiles, double init0) {
+    constexpr uint32_t kTile = B * M;
+    double t = 0.0;
+    for (uint32_t tile = first; tile < tiles; tile += stride)
+        t += tile_points_one_chunk<F, M, B, FI, MIRROR>(v, s, tile * kTile, init0, false, true);
+    return t;
 }
 
 }  // namespace qmc

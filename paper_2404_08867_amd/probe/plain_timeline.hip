@@ -53,12 +53,15 @@ __global__ __launch_bounds__(B) void plain_timeline_kernel(const int64_t* z, con
         double tacc = 0.0;
         setup_one_chunk<F, M, B>(v, s, s_red, blockIdx.x * kTile, init0, ds1, ie);
         if (lead) put_mark(marks, 1);
+        guard_check<F, B>(v, s);
         if constexpr (MODE == 0) {
             for (uint32_t tile = blockIdx.x; tile < tiles; tile += gridDim.x)
                 tacc += tile_points_one_chunk<F, M, B, FI, false>(v, s, tile * kTile, init0, tile == blockIdx.x);
         }
         if ((threadIdx.x & (kWave - 1)) == 0) put_mark(marks, 2 + (int)(threadIdx.x / kWave));
-        const double bsum = block_sum_wave0<B>(tacc, s_red);
+        double bsum = block_sum_wave0<B>(tacc, s_red);
+        if (guard_redo(s, ds1))
+            bsum = block_sum_wave0<B>(redo_tiles<F, M, B, FI, false>(v, s, blockIdx.x, gridDim.x, MODE == 0 ? tiles : 0u, init0), s_red);
         if (threadIdx.x >= kWave) return;
         if (lead) put_mark(marks, 18);
         GridSlots gs;

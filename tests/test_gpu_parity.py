@@ -255,10 +255,16 @@ def test_batched_gaussian_and_exp_sum_parameter_ranges():
 
 # Identical parameters in every direction (the paper's test integrands are of this
 # kind): a rounding bias that single-precision arithmetic leaves in each direction then
-# adds up linearly in d instead of averaging out.  Small n keeps the lattice's
-# coordinate values few and structured (n = 4099, c = 1, w = 1/2 puts the peak
-# half-way between two grid values).
-IDENTICAL = [(1, 20, 4099, 1.0, 0.5), (1, 32, 4099, 1.0, 0.5), (1, 40, 4099, 1.0, 0.5),
+# adds up linearly in d instead of averaging out, and strongly peaked integrands on
+# small lattices let a handful of points carry the sum, so their per-point rounding
+# shows.  The FP32 product-peak factors divide out the first-order bias of their
+# rounded constants and take FP64 factors where the bias or the peakedness is too large;
+# these cases cover both sides (n = 4099, c = 1, w = 1/2 puts the peak half-way between
+# two grid values).
+IDENTICAL = [(1, 32, 1031, 2.0, 0.1), (1, 32, 1031, 2.75, 0.9), (1, 32, 10007, 3.75, 0.85),
+             (1, 16, 65537, 2.0, 0.1), (1, 32, 65537, 1.5, 0.3), (1, 24, 16411, 2.75, 0.1),
+             (1, 8, 257, 4.0, 0.5), (1, 32, 1048573, 1.25, 0.7), (1, 20, 16777213, 3.0, 0.05),
+             (1, 20, 4099, 1.0, 0.5), (1, 32, 4099, 1.0, 0.5), (1, 40, 4099, 1.0, 0.5),
              (1, 100, 4099, 1.0, 0.5), (1, 32, 1031, 1.0, 0.5), (1, 200, 65537, 1 / 0.9, 0.6),
              (2, 100, 65537, 1 / math.sqrt(2), 0.0), (2, 200, 4099, 1.0, 0.5),
              (0, 100, 65537, 1.0, None), (0, 300, 4099, -1.0, None)]
@@ -411,7 +417,9 @@ def test_workload_plain_d4_expsum(precision):
 def test_workload_plain_d20_peak(precision):
     prob = W.plain_d20_peak()
     qo, ao = _oracle_sum(prob)
-    assert _rel(_gpu_sum(prob, precision), qo, ao) <= TOL[precision]
+    err = _rel(_gpu_sum(prob, precision), qo, ao)
+    print(f"plain_d20_peak precision={precision} rel err {err:.3e}")
+    assert err <= TOL[precision]
 
 
 # ------------------------------------------------------------------------ MDI-LR
