@@ -81,8 +81,10 @@ typedef enum {
 /* QMC_FP64: every arithmetic step in IEEE double precision.
  * QMC_FP32_COMPENSATED: exact integer indices; the index-to-coordinate map, the
  * argument sums and all accumulation in double; the per-point transcendental
- * (exp2, cos, reciprocal) and the product-peak factors in single precision.
- * Its relative error against the FP64 rule is reported by the tests and the
+ * (exp2, cos, reciprocal) and the product-peak factors in single precision
+ * (up to 32 directions, with the first-order bias of their rounded constants divided
+ * out; in double for a problem with |c_j| > 4, factors beyond [2^-7, 2^7], a bias
+ * above 1e-6 or fewer than 16 effective lattice points).  Its relative error against the FP64 rule is reported by the tests and the
  * benchmark for every workload (target <= 1e-6).  In the MDI-LR product the FP32
  * error of one factor repeats in every direction with the same parameters, so for
  * inputs with many identical directions it can grow linearly in d.  The exp-sum,
