@@ -56,8 +56,9 @@ __device__ __forceinline__ void run_tile(const BatchArgs& a, int pi, const DevPr
     int ie;
     double t;
     if (v.d <= kDimChunk) {
-        setup_one_chunk<F, M>(v, s, red, local_tile * kTile, init0, ds1, ie);
-        guard_check<F, kBlock>(v, s);
+        guard_in_t<F> gin{};
+        setup_one_chunk<F, M>(v, s, red, local_tile * kTile, init0, ds1, ie, gin);
+        guard_check<F, kBlock>(v, s, gin);
         t = tile_points_one_chunk<F, M, kBlock, FI>(v, s, local_tile * kTile, init0, true);
     } else {
         block_constants<F>(v, red, init0, ds1, ie);

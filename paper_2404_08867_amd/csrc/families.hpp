@@ -266,17 +266,29 @@ constexpr double kPeakF32MinPoints = 16.0;
 // weighted by f_j = 1/(u^2 + q) its mean relative effect on f_j is
 //   -(2 da (Iu2 + w' Iu1) - 2 w' db Iu1 + q dg I1) / I0,
 // I0 = int du/D, I1 = int du/D^2, Iu1 = int u du/D^2, Iu2 = int u^2 du/D^2, D = u^2 + q.
+// What the bias of direction j needs: c, w' = w - sfrac/n, and the double-precision
+// constants a, b, g that are rounded to FP32 (ProductPeak::dim computes the same).
+struct PeakGuardIn {
+    double c, wp, a, b, g;
+};
+
+__device__ __forceinline__ PeakGuardIn peak_guard_input(const double* p, int d, int j, double inv_n,
+                                                        double sfrac) {
+    const double c = p[j], w = p[d + j];
+    const double s = ldexp(1.0, -peak_pow4(c));
+    return PeakGuardIn{c, fma(-sfrac, inv_n, w), s * inv_n, s * fma(sfrac, inv_n, -w), s * s / (c * c)};
+}
+
 // The rounding errors are exact differences in double precision; the rest runs in
 // single precision (a relative accuracy of 1e-6 is far more than a correction of a
-// few 1e-8 needs), so that the setup that waits for it stays short.  a, b, g are the
-// double-precision constants that are rounded to FP32 (ProductPeak::dim).
-__device__ inline void peak_fp32_bias(double c, double w, double inv_n, double sfrac, double a, double b,
-                                      double g, double& bias, double& log_ratio) {
+// few 1e-8 needs), with no memory access.
+__device__ inline void peak_fp32_bias(const PeakGuardIn& in, double& bias, double& log_ratio) {
+    const double a = in.a, b = in.b, g = in.g;
     const float da = (float)((double)(float)a - a) * __builtin_amdgcn_rcpf((float)a);
     const float db = b != 0.0 ? (float)((double)(float)b - b) * __builtin_amdgcn_rcpf((float)b) : 0.0f;
     const float dg = (float)((double)(float)g - g) * __builtin_amdgcn_rcpf((float)g);
-    const float ac = (float)fabs(c), q = __builtin_amdgcn_rcpf(ac * ac);
-    const float wp = (float)fma(-sfrac, inv_n, w);
+    const float ac = (float)fabs(in.c), q = __builtin_amdgcn_rcpf(ac * ac);
+    const float wp = (float)in.wp;
     const float lo = -wp, hi = 1.0f - wp;
     const float dlo = lo * lo + q, dhi = hi * hi + q;
     // atan(hi ac) - atan(lo ac) as one arctangent: (x - y) / (1 + x y) with x = hi ac,
@@ -330,12 +342,12 @@ struct ProductPeak {
     // The problem-wide part of the guard: per direction log(max f_j / mean f_j) and the
     // first-order bias (summed over the directions by the setup), and the test on the
     // sums (NaN fails it).  The bias sum becomes ds1 of scale() when the test passes.
-    __device__ static void guard_terms(const double* p, int d, int j, double inv_n, double sfrac,
-                                       double& log_ratio, double& bias) {
-        const double c = p[j], w = p[d + j];
-        const double s = ldexp(1.0, -peak_pow4(c));
-        peak_fp32_bias(c, w, inv_n, sfrac, s * inv_n, s * fma(sfrac, inv_n, -w), s * s / (c * c), bias,
-                       log_ratio);
+    using GuardIn = PeakGuardIn;
+    __device__ static GuardIn guard_input(const double* p, int d, int j, double inv_n, double sfrac) {
+        return peak_guard_input(p, d, j, inv_n, sfrac);
+    }
+    __device__ static void guard_terms(const GuardIn& in, double& log_ratio, double& bias) {
+        peak_fp32_bias(in, bias, log_ratio);
     }
     __device__ static bool block_ok(double log_ratio, double bias, uint32_t n) {
         return log_ratio <= (double)__logf((float)n * (float)(1.0 / kPeakF32MinPoints)) &&
@@ -343,10 +355,8 @@ struct ProductPeak {
     }
     __device__ static double extra(const double*) { return 0.0; }
     __device__ static Dim dim(const double* p, int d, int j, double inv_n, double sfrac) {
-        const double c = p[j], w = p[d + j];
-        const int m = peak_pow4(c);
-        const double s = ldexp(1.0, -m);
-        return Dim{(T)(s * inv_n), (T)(s * fma(sfrac, inv_n, -w)), (T)(s * s / (c * c))};
+        const PeakGuardIn k = peak_guard_input(p, d, j, inv_n, sfrac);
+        return Dim{(T)k.a, (T)k.b, (T)k.g};
     }
     __device__ static Acc init(double) { return Acc{(T)1, 0}; }
     template <class K>

@@ -76,8 +76,9 @@ __global__ __launch_bounds__(B) void lattice_sum_kernel(
     if (v.d <= kDimChunk) {
         // One set of direction tables serves every tile; the first tile's start
         // residues are built with them.
-        setup_one_chunk<F, M, B>(v, s, s_red, blockIdx.x * kTile, init0, ds1, ie);
-        guard_check<F, B>(v, s);
+        guard_in_t<F> gin{};
+        setup_one_chunk<F, M, B>(v, s, s_red, blockIdx.x * kTile, init0, ds1, ie, gin);
+        guard_check<F, B>(v, s, gin);
         for (uint32_t tile = blockIdx.x; tile < tiles; tile += gridDim.x)
             tacc += tile_points_one_chunk<F, M, B, FI, MIRROR>(v, s, tile * kTile, init0, tile == blockIdx.x);
     } else {

@@ -46,6 +46,19 @@ struct guarded_family<F, std::void_t<decltype(F::kGuarded)>> : std::bool_constan
     using fallback_dim = typename F::Fallback::Dim;
 };
 
+// What a guarded family's problem-wide test needs from a direction (F::GuardIn), kept in
+// the registers of the wave-0 lane that loaded it during the setup.
+template <class F, class = void>
+struct guard_input_of {
+    using type = char;
+};
+template <class F>
+struct guard_input_of<F, std::void_t<typename F::GuardIn>> {
+    using type = typename F::GuardIn;
+};
+template <class F>
+using guard_in_t = typename guard_input_of<F>::type;
+
 // A problem as seen by the device: lattice, shift and one parameter row.
 struct ProblemView {
     int d;
@@ -292,7 +305,7 @@ __device__ __forceinline__ double tile_points(const ProblemView& v, TileShared<F
 template <class F, int M, int B>
 __device__ __forceinline__ void setup_one_chunk(const ProblemView& v, TileShared<F, B>& s, double* red,
                                                 uint32_t first_base, double& init0, double& ds1,
-                                                int& ie) {
+                                                int& ie, guard_in_t<F>& gin) {
     const int tid = threadIdx.x, d = v.d;
     fill_lz<F, B>(v, s, 0, d);
     if (tid < kWave) {
@@ -315,6 +328,7 @@ __device__ __forceinline__ void setup_one_chunk(const ProblemView& v, TileShared
             if constexpr (guarded_family<F>::value) {
                 s.c2[j] = F::Fallback::dim(v.p, d, j, v.inv_n, frac);
                 bad = !F::fp32_dim_ok(v.p, d, j);
+                gin = F::guard_input(v.p, d, j, v.inv_n, frac);
             }
         }
         if constexpr (guarded_family<F>::value) {
@@ -358,17 +372,13 @@ __device__ __forceinline__ void setup_one_chunk(const ProblemView& v, TileShared
 // after the workgroup sum, guard_redo tells whether to redo them with the fallback
 // (redo_tiles) because the problem-wide test failed.
 template <class F, int B>
-__device__ __forceinline__ void guard_check(const ProblemView& v, TileShared<F, B>& s) {
+__device__ __forceinline__ void guard_check(const ProblemView& v, TileShared<F, B>& s,
+                                            const guard_in_t<F>& gin) {
     if constexpr (guarded_family<F>::value) {
         if (threadIdx.x < kWave) {
             const int j = threadIdx.x;
             double g0 = 0.0, g1 = 0.0;
-            if (j < v.d) {
-                uint32_t whole;
-                double frac;
-                split_shift(v.shift, j, v.n, whole, frac);
-                F::guard_terms(v.p, v.d, j, v.inv_n, frac, g0, g1);
-            }
+            if (j < v.d) F::guard_terms(gin, g0, g1);
             const double x = wave_total(g0), y = wave_total(g1);
             if (j == kWaveTotalLane) {
                 s.guard_fail = F::block_ok(x, y, v.n) ? 0 : 1;

@@ -51,9 +51,10 @@ __global__ __launch_bounds__(B) void plain_timeline_kernel(const int64_t* z, con
         double init0, ds1;
         int ie;
         double tacc = 0.0;
-        setup_one_chunk<F, M, B>(v, s, s_red, blockIdx.x * kTile, init0, ds1, ie);
+        guard_in_t<F> gin{};
+        setup_one_chunk<F, M, B>(v, s, s_red, blockIdx.x * kTile, init0, ds1, ie, gin);
         if (lead) put_mark(marks, 1);
-        guard_check<F, B>(v, s);
+        guard_check<F, B>(v, s, gin);
         if constexpr (MODE == 0) {
             for (uint32_t tile = blockIdx.x; tile < tiles; tile += gridDim.x)
                 tacc += tile_points_one_chunk<F, M, B, FI, false>(v, s, tile * kTile, init0, tile == blockIdx.x);
