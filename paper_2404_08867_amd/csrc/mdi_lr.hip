@@ -59,7 +59,13 @@ __device__ __forceinline__ double quad_node_direct(double A, double B, int Nk, d
 // partial sum) per node.  phi_{t0} and the run's last ratio come from exp2: every
 // S-th node (S = 8 for QMC_FP64, which keeps the compounded rounding of a run below
 // ~1e-15 so that a thousand identical directions stay within 1e-12; 64 for
-// QMC_FP32_COMPENSATED).  The recurrence is used only while every node value, ratio
+// QMC_FP32_COMPENSATED).  In QMC_FP64 the ratio's step q^-1 is carried as an unevaluated
+// sum of two doubles where |2 s A^2| <= 1/16: q^-1 = 1 + u with u = expm1(-2 s A^2 ln 2)
+// from its series, the rounding of 1 + u kept as the low part, and r <- r q^-1 as
+// fma(r, hi, r lo).  Its rounding otherwise compounds along the run, the same in every
+// direction with the same parameters: a factor's error drops from up to 1.7e-15 to
+// 2.5e-16 (host emulation against a 50-digit sum; c = 1/sqrt(2), N = 64: 1.1e-15 to
+// 4e-17).  The recurrence is used only while every node value, ratio
 // and q stay within 2^-1000..2^1000 (max y^2 over the nodes, taken at an end point,
 // and 2 A^2 at most 1000; a ratio's exponent is a difference of two node exponents),
 // so every exp2 argument lies in [-1000, 1000] and no partial sum or ratio leaves the
@@ -80,10 +86,18 @@ __device__ __forceinline__ void quad_node_sums(const double (&A)[J], const doubl
         all = all && ok[j];
     }
     if (all) {
-        double qinv[J], sr[J];
+        double qinv[J], qlo[J], sr[J];
 #pragma unroll
         for (int j = 0; j < J; ++j) {
-            qinv[j] = exp2_seed(-2.0 * s[j] * A[j] * A[j]);
+            const double x = -2.0 * s[j] * A[j] * A[j];
+            qlo[j] = 0.0;
+            if (!FP32 && fabs(x) <= 0.0625) {
+                const double u = expm1_small(x * kLn2);
+                qinv[j] = 1.0 + u;
+                qlo[j] = u - (qinv[j] - 1.0);  // exact: qinv - 1 is exact near 1
+            } else {
+                qinv[j] = exp2_seed(x);
+            }
             sr[j] = 0.0;
         }
         for (int t0 = 0; t0 < Nk; t0 += kSeed) {
@@ -102,7 +116,10 @@ __device__ __forceinline__ void quad_node_sums(const double (&A)[J], const doubl
 #pragma unroll
                 for (int j = 0; j < J; ++j) {
                     h[j] = fma(r[j], h[j], 1.0);
-                    r[j] *= qinv[j];
+                    if constexpr (FP32)
+                        r[j] *= qinv[j];
+                    else
+                        r[j] = fma(r[j], qinv[j], r[j] * qlo[j]);
                 }
             }
 #pragma unroll
@@ -206,6 +223,26 @@ __device__ __forceinline__ void direction_sums(const DirIn (&in)[J], int Nk, dou
                 }
                 sr[j] = acc;
             } else {  // kOscillatory: phi = e^{i c y}, angle in turns a = c/(2 pi) y = A t + B
+                // Also a geometric sequence: with x = c / (2N), the node sum is
+                //   sum_t e^{i c (t + 1/2)/N} = e^{i c/2} sin(c/2) / sin(x),
+                // evaluated in FP64 in both precisions for 0 < |x| <= pi/2 (every term 1
+                // for c = 0).  One rounding of a factor would otherwise repeat in every
+                // direction with the same c; beyond pi/2 (more than a quarter turn between
+                // nodes) the node loop below sums the terms.
+                const double x = 0.5 * in[j].c * invN;
+                if (fabs(x) <= 1.5707963267948966) {
+                    if (x == 0.0) {
+                        sr[j] = (double)Nk;
+                        si[j] = 0.0;
+                    } else {
+                        double sh, ch;
+                        sincos(0.5 * in[j].c, &sh, &ch);
+                        const double m = sh / sin(x);
+                        sr[j] = m * ch;
+                        si[j] = m * sh;
+                    }
+                    continue;
+                }
                 const double c = in[j].c * kInv2Pi;
                 const double A = c * invN, B = 0.5 * c * invN;
                 double ar = 0.0, ai = 0.0;

@@ -1,8 +1,9 @@
 // Host check of qmc::exp2_f64 (paper_2404_08867_amd/csrc/exp2_f64.hpp) and, with a
-// fourth argument "small" or "seed", of the MDI-LR seed forms qmc::exp2_seed_small and
-// qmc::exp2_seed (exp2_seed.hpp): the largest error, in units in the last place,
-// against exp2l over n pseudo-random points of [lo, hi] and the two end points; prints
-// "<max ulp> <x at the max>".
+// fourth argument "small", "seed" or "expm1", of the MDI-LR seed forms
+// qmc::exp2_seed_small and qmc::exp2_seed and of qmc::expm1_small (exp2_seed.hpp): the
+// largest error, in units in the last place, against exp2l (expm1l for "expm1") over n
+// pseudo-random points of [lo, hi] and the two end points; prints "<max ulp> <x at the
+// max>".
 #include <math.h>
 #include <stdint.h>
 #include <stdio.h>
@@ -21,6 +22,7 @@ static double eval(char which, double x) {
     switch (which) {
         case 's': return qmc::exp2_seed_small(x);
         case 'e': return qmc::exp2_seed(x);
+        case 'm': return qmc::expm1_small(x);
         default: return qmc::exp2_f64(x);
     }
 }
@@ -31,6 +33,7 @@ int main(int argc, char** argv) {
     if (argc == 5) {
         if (!strcmp(argv[4], "small")) which = 's';
         else if (!strcmp(argv[4], "seed")) which = 'e';
+        else if (!strcmp(argv[4], "expm1")) which = 'm';
         else return 2;
     }
     const long n = atol(argv[1]);
@@ -47,7 +50,8 @@ int main(int argc, char** argv) {
             s ^= s << 17;
             x = lo + (hi - lo) * ((double)(s >> 11) * 0x1p-53);
         }
-        const double e = ulp_error(eval(which, x), exp2l((long double)x));
+        const long double ref = which == 'm' ? expm1l((long double)x) : exp2l((long double)x);
+        const double e = x == 0.0 && which == 'm' ? fabs(eval(which, x)) : ulp_error(eval(which, x), ref);
         if (e > worst) {
             worst = e;
             worst_x = x;

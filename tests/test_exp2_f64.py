@@ -65,3 +65,16 @@ def test_seed_within_one_ulp(checker, lo, hi, n):
 def test_seed_exact_at_zero(checker, form):
     ulp, _ = _max_ulp(checker, 0, 0.0, 0.0, form=form)
     assert ulp == 0.0
+
+
+@pytest.mark.parametrize("lo,hi,n", [(-0.0434, 0.0434, 200000), (-1e-6, 1e-6, 20000), (1e-12, 0.0434, 20000)])
+def test_expm1_small_within_two_ulp(checker, lo, hi, n):
+    """e^t - 1 for the double-double ratio step of the FP64 MDI-LR recurrence: relative to
+    its (small) result, within two units in the last place over |t| <= 0.0434."""
+    ulp, x = _max_ulp(checker, n, lo, hi, form="expm1")
+    assert ulp <= 2.0, (ulp, x)
+
+
+def test_expm1_small_exact_at_zero(checker):
+    ulp, _ = _max_ulp(checker, 0, 0.0, 0.0, form="expm1")
+    assert ulp == 0.0

@@ -788,6 +788,41 @@ def test_mdi_lr_exp_sum_d1000_identical_directions(precision):
         assert abs(q - qo) <= TOL[precision] * abs(qo), (N, q, qo)
 
 
+MDI_IDENTICAL = [(0, 0.7, None), (1, 1 / 0.9, 0.6), (1, 1.5, 0.1), (2, 1 / math.sqrt(2), 0.0),
+                 (2, 2.0, 0.5), (2, 1.0, 0.37), (3, 1.0, 0.3), (3, 2.5, 0.0), (4, -0.8, 0.3),
+                 (4, "alt", 0.0)]
+
+
+@pytest.mark.parametrize("precision", PRECS)
+@pytest.mark.parametrize("N", [8, 64, 200])
+@pytest.mark.parametrize("case", range(len(MDI_IDENTICAL)))
+def test_mdi_lr_d1000_identical_directions_every_family(precision, N, case):
+    """A thousand directions with the same parameters, so that one factor's rounding
+    repeats a thousand times: every family (the oscillatory one with its phase u
+    taken from the second number; the signed quadratic also with alternating signs)
+    at the usual bars, FP64 included."""
+    family, c, w = MDI_IDENTICAL[case]
+    d = 1000
+    if family == 0:
+        p = np.full(d, c)
+    elif family == 3:
+        p = np.r_[[w], np.full(d, c)]
+    elif c == "alt":
+        p = np.r_[np.where(np.arange(d) % 2 == 0, 1.0, -1.0), np.full(d, w)]
+    else:
+        p = np.r_[np.full(d, c), np.full(d, w)]
+    Nv = np.full(d, N, np.int32)
+    q = float(qmc.mdi_lr(Nv, family, p, precision).item())
+    qo = O.mdi_lr(Nv.astype(np.int64), family, p)
+    if family == 3:
+        re, im = O.mdi_lr_factors(Nv.astype(np.int64), family, p)
+        scale = float(np.prod(np.hypot(re, im)))
+    else:
+        scale = abs(qo)
+    assert np.isfinite(qo) and scale > 0
+    assert abs(q - qo) <= TOL[precision] * scale, (family, c, w, N, q, qo)
+
+
 @pytest.mark.parametrize("precision", PRECS)
 @pytest.mark.parametrize("family", [0, 1, 2, 3, 4])
 @pytest.mark.parametrize("d,nsets", [(1, 5), (3, 1), (7, 300), (64, 2), (65, 70), (130, 3)])
