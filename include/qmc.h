@@ -88,9 +88,11 @@ typedef enum {
  * benchmark for every workload (target <= 1e-6).  In the MDI-LR product the FP32
  * error of one factor repeats in every direction with the same parameters, so for
  * inputs with many identical directions it can grow linearly in d.  The exp-sum,
- * Gaussian and signed-quadratic factors are summed by FP64 node recurrences and the
- * product-peak reciprocals refined in FP64; the oscillatory family's FP32 sin/cos,
- * and Gaussian factors too narrow for the recurrence, keep FP32 node values. */
+ * Gaussian and signed-quadratic factors are summed by FP64 node recurrences, the
+ * exp-sum and oscillatory node sums taken in closed form in FP64 and the product-peak
+ * reciprocals refined in FP64; oscillatory factors with more than a quarter turn
+ * between nodes and Gaussian factors too narrow for the recurrence keep FP32 node
+ * values. */
 typedef enum { QMC_FP64 = 0, QMC_FP32_COMPENSATED = 1 } qmc_precision;
 
 /* How qmc_mdi_lr_dims obtains n for the Korobov lattice z(a) (Lemma 3.2, eq. 3.5). */
