@@ -313,6 +313,7 @@ __device__ __forceinline__ void setup_one_chunk(const ProblemView& v, TileShared
         int te = 0;
         bool bad = false;  // a direction the guarded family's FP32 form cannot take
         (void)bad;
+
         if (tid < d) {
             const int j = tid;
             uint32_t whole;
