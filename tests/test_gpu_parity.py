@@ -287,6 +287,20 @@ def test_plain_sum_identical_directions(family, d, n, c, w):
         assert _rel(q, qo, ao) <= TOL[precision], (family, d, n, precision, q, qo)
 
 
+@pytest.mark.parametrize("d,n,c,w", [(32, 65537, 1.5, 0.3), (16, 4099, 2.0, 0.1), (32, 1031, 1.0, 0.5),
+                                     (24, 262139, 0.5, 0.1)])
+def test_plain_sum_identical_directions_on_the_diagonal(d, n, c, w):
+    """The Korobov vector of a = 1 puts every point on the diagonal, so that each point's
+    factors are all the same computation: the product peak with identical parameters in
+    both precisions at their bars (FP32 factors only where the guard accepts them)."""
+    prob = W.Plain(f"diag{d}_{n}", d, n, 1, 1, np.concatenate([np.full(d, c), np.full(d, w)]), None)
+    qo, ao = _oracle_sum(prob)
+    assert np.isfinite(qo) and qo > 0
+    for precision in PRECS:
+        q = _gpu_sum(prob, precision)
+        assert _rel(q, qo, ao) <= TOL[precision], (d, n, c, w, precision, q, qo)
+
+
 def test_batched_identical_directions():
     """The identical-direction problems in one batched launch."""
     probs = [_identical(*case) for case in IDENTICAL]
