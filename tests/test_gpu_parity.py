@@ -267,11 +267,18 @@ IDENTICAL = [(1, 32, 1031, 2.0, 0.1), (1, 32, 1031, 2.75, 0.9), (1, 32, 10007, 3
              (1, 20, 4099, 1.0, 0.5), (1, 32, 4099, 1.0, 0.5), (1, 40, 4099, 1.0, 0.5),
              (1, 100, 4099, 1.0, 0.5), (1, 32, 1031, 1.0, 0.5), (1, 200, 65537, 1 / 0.9, 0.6),
              (2, 100, 65537, 1 / math.sqrt(2), 0.0), (2, 200, 4099, 1.0, 0.5),
-             (0, 100, 65537, 1.0, None), (0, 300, 4099, -1.0, None)]
+             (0, 100, 65537, 1.0, None), (0, 300, 4099, -1.0, None),
+             (3, 100, 65537, 1.0, 0.3), (3, 200, 4099, 2.5, 0.0), (4, 100, 65537, -0.8, 0.3),
+             (4, 200, 4099, 1.0, 0.0)]
 
 
 def _identical(family, d, n, c, w):
-    params = np.full(d, c) if family == 0 else np.concatenate([np.full(d, c), np.full(d, w)])
+    if family == 0:
+        params = np.full(d, c)
+    elif family == 3:  # oscillatory: the phase u, then c
+        params = np.concatenate([[w], np.full(d, c)])
+    else:
+        params = np.concatenate([np.full(d, c), np.full(d, w)])
     return W.Plain(f"ident{family}_{d}_{n}", d, n, W.draw_coprime(np.random.default_rng(d + n), n),
                    family, params, None)
 
@@ -281,7 +288,7 @@ def test_plain_sum_identical_directions(family, d, n, c, w):
     """Identical parameters in every direction, both precisions at their bars."""
     prob = _identical(family, d, n, c, w)
     qo, ao = _oracle_sum(prob)
-    assert np.isfinite(qo) and qo > 0
+    assert np.isfinite(qo) and (qo > 0 or family == 3)
     for precision in PRECS:
         q = _gpu_sum(prob, precision)
         assert _rel(q, qo, ao) <= TOL[precision], (family, d, n, precision, q, qo)
