@@ -203,9 +203,10 @@ qmc_status qmc_lattice_sum_shifts(int32_t d, int64_t n, const int64_t* z, const 
  * QMC_FP32_COMPENSATED takes the exponent in FP64 and its fractional power in FP32. */
 typedef enum { QMC_SUM_POWER = 0, QMC_SUM_GAUSS = 1 } qmc_sum_family;
 
-/* Workspace bytes of qmc_mdi_lr_sum at d, N: 35 vectors of d (N - 1) + 1 doubles
- * (weights and convolution partials; when N_last = N the last direction merges
- * into the states too). */
+/* Workspace bytes of qmc_mdi_lr_sum at d, N: the 4 MiB zero region shared by every
+ * entry point (left untouched), then 35 vectors of d (N - 1) + 1 doubles (weights
+ * and convolution partials; when N_last = N the last direction merges into the
+ * states too). */
 qmc_status qmc_mdi_lr_sum_workspace_size(int32_t d, int32_t N, size_t* bytes);
 
 /* Q for nsets parameter sets of g (two launches on `stream`).
@@ -237,8 +238,9 @@ qmc_status qmc_mdi_lr_sum(int32_t d, int32_t N, int32_t N_last, int32_t gfamily,
  *   points of eq. 3.5's grid, which contains every transformed point.
  *   counts_host_out  host int64[d]: the per-direction counts (eq. 3.5), or NULL
  *   nstar_out        device int64[1]
- *   ws               device workspace of qmc_implr_workspace_size(d, n, a) bytes
- *                    (no zero-fill needed)
+ *   ws               device workspace of qmc_implr_workspace_size(d, n, a) bytes: the
+ *                    4 MiB zero region shared by every entry point (left untouched),
+ *                    256 bytes of state and the grid's bitmap (no zero-fill needed)
  * Errors: QMC_ERR_INVALID_ARG for arguments outside these ranges, an unknown
  * method or a NULL nstar_out, QMC_ERR_WORKSPACE for a missing, misaligned or short
  * workspace; nothing is launched and counts_host_out is left untouched then. */

@@ -388,7 +388,7 @@ __global__ void implr_finish_kernel(const ImplrState* st, uint64_t grid, uint64_
 
 size_t implr_workspace_bytes(uint64_t grid) {
     const uint64_t words = (grid + 31) / 32;
-    return 256 + (words * 4 + 255) / 256 * 256;
+    return kZeroBytes + 256 + (words * 4 + 255) / 256 * 256;
 }
 
 static unsigned blocks_for(uint64_t count, uint64_t per_block) {
@@ -396,9 +396,10 @@ static unsigned blocks_for(uint64_t count, uint64_t per_block) {
 }
 
 hipError_t launch_implr(const ImplrLaunch& L, hipStream_t stream) {
-    // Workspace: [0, 256) the state, then the bitmap of the grid.
-    ImplrState* st = (ImplrState*)L.ws;
-    uint32_t* bits = (uint32_t*)((char*)L.ws + 256);
+    // Workspace: the shared zero region (untouched here), 256 bytes of state, then
+    // the bitmap of the grid.
+    ImplrState* st = (ImplrState*)((char*)L.ws + kZeroBytes);
+    uint32_t* bits = (uint32_t*)((char*)L.ws + kZeroBytes + 256);
     const uint64_t words = (L.grid + 31) / 32;
     const double inv_n = 1.0 / (double)L.n;
     const uint32_t Q = L.n / L.zd, R = L.n % L.zd;

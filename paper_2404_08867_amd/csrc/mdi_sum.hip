@@ -177,8 +177,9 @@ __global__ __launch_bounds__(kSumEvalBlock) void sum_eval_kernel(int states, int
 
 size_t mdi_sum_workspace_bytes(int d, int N) {
     const size_t L = (size_t)d * (size_t)(N - 1) + 1;  // enough for both forms
-    // three rotating weight vectors and the convolution's segment partials
-    return ((3 + kConvMaxSeg) * L * sizeof(double) + 255) / 256 * 256;
+    // the shared zero region, then three rotating weight vectors and the
+    // convolution's segment partials
+    return kZeroBytes + ((3 + kConvMaxSeg) * L * sizeof(double) + 255) / 256 * 256;
 }
 
 template <int GFAM, bool FP32>
@@ -297,8 +298,9 @@ hipError_t launch_mdi_sum(const MdiSumLaunch& L, hipStream_t stream) {
     // square B and the output of each convolution; R and B may share one (R = B after
     // the first factor).
     const size_t cap = (size_t)L.d * (size_t)(L.N - 1) + 1;
-    double* buf[3] = {(double*)L.ws, (double*)L.ws + cap, (double*)L.ws + 2 * cap};
-    double* partial = (double*)L.ws + 3 * cap;
+    double* const base = (double*)((char*)L.ws + kZeroBytes);  // past the shared zero region
+    double* buf[3] = {base, base + cap, base + 2 * cap};
+    double* partial = base + 3 * cap;
     int iR = 0, iB = 1;
     auto free_buf = [&]() {
         for (int i = 0; i < 3; ++i)

@@ -164,10 +164,18 @@ def test_criteria_workspace_size():
 @pytest.mark.parametrize("d,n,a", [(3, 101, 3), (3, 1290**3 + 1, 1290), (1, 97, 5), (5, 1 << 30, 181),
                                    (2, 2147483647, 16807)])
 def test_implr_workspace_size(d, n, a):
-    # counter, then one bit per point of the a^{d-1} ceil(n / a^{d-1}) grid (eq. 3.5)
+    # the shared 4 MiB zero region, a counter, then one bit per point of the
+    # a^{d-1} ceil(n / a^{d-1}) grid (eq. 3.5)
     zd = a ** (d - 1)
     grid = zd * -(-n // zd)
-    assert qmc.implr_workspace_size(d, n, a) == 256 + ((grid + 31) // 32 * 4 + 255) // 256 * 256
+    assert qmc.implr_workspace_size(d, n, a) == (4 << 20) + 256 + ((grid + 31) // 32 * 4 + 255) // 256 * 256
+
+
+@pytest.mark.parametrize("d,N", [(1, 1), (7, 2), (100, 64), (300, 64)])
+def test_mdi_lr_sum_workspace_size(d, N):
+    # the shared 4 MiB zero region, then 35 vectors of d (N - 1) + 1 doubles
+    L = d * (N - 1) + 1
+    assert qmc.mdi_lr_sum_workspace_size(d, N) == (4 << 20) + (35 * L * 8 + 255) // 256 * 256
 
 
 def test_last_error_is_cleared_by_success():
