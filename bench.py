@@ -969,7 +969,7 @@ def bench_timeline(args, torch, qmc, W):
     line = {"metric": "phases of the plain-sum launch (probe copy of the kernel)",
             "value": lib_kern * 1e6, "unit": "us per launch (library kernel)", "n_gpus": 1,
             "steps": args.steps, "warmup": args.warmup, "ms_per_step": lib_kern * 1e3,
-            "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+            "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "f64/f32",
             "data": "synthetic",
             "config": {"workload": "timeline_d20_peak", "d": w.d, "n": w.n, "family": "product_peak",
                        "precision": "fp32_compensated", "workgroups": G, "threads": 1024,
@@ -1140,7 +1140,9 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": {"korobov_search_d20": "f64", "cbc_d20": "f64", "implr_d3": "u32"}.get(args.workload, "f32"),
+        # QMC_FP32_COMPENSATED: FP64 arguments and sums, FP32 transcendentals (and
+        # product-peak factors where their error allows)
+        "dtype": {"korobov_search_d20": "f64", "cbc_d20": "f64", "implr_d3": "u32"}.get(args.workload, "f64/f32"),
         "data": "synthetic",
         "config": config,
         "roofline": main_r.get("roofline") or roofline,
