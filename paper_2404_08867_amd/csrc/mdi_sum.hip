@@ -17,6 +17,7 @@
 #include "common.hpp"
 #include "families.hpp"
 #include "kernels.hpp"
+#include "log2_tab.hpp"
 
 namespace qmc {
 
@@ -99,44 +100,23 @@ __global__ __launch_bounds__(kConvBlock) void states_init_kernel(int N, double* 
     if (t < N) w[t] = 1.0 / (double)N;
 }
 
-// log2(x) for finite x > 0 to about 1e-13 absolute: x = m 2^e with m in
-// [sqrt(1/2), sqrt(2)), and log2(m) = (2 / ln 2) atanh(s) with s = (m - 1) / (m + 1),
-// |s| <= 3 - 2 sqrt(2) < 0.172, atanh(s) = s sum_k s^{2k} / (2k + 1) (the first
-// eight terms; the ninth is below 2e-14 s).  The reciprocal of m + 1 in [1.7, 2.5]
-// is the hardware estimate refined by two Newton steps.  Other x take the
-// library log2.
-__device__ __forceinline__ double log2_atanh(double x) {
-    if (!(x > 0.0 && x < __builtin_huge_val())) return log2(x);
-    int e = __builtin_amdgcn_frexp_exp(x);
-    double m = __builtin_amdgcn_frexp_mant(x);  // [1/2, 1)
-    if (m < 0.70710678118654752440) {
-        m *= 2.0;
-        e -= 1;
-    }
-    const double den = m + 1.0;
-    double rc = __builtin_amdgcn_rcp(den);
-    rc = fma(rc, fma(-den, rc, 1.0), rc);
-    rc = fma(rc, fma(-den, rc, 1.0), rc);
-    const double sv = (m - 1.0) * rc;
-    const double s2 = sv * sv;
-    double poly = 1.0 / 15.0;
-    poly = fma(poly, s2, 1.0 / 13.0);
-    poly = fma(poly, s2, 1.0 / 11.0);
-    poly = fma(poly, s2, 1.0 / 9.0);
-    poly = fma(poly, s2, 1.0 / 7.0);
-    poly = fma(poly, s2, 1.0 / 5.0);
-    poly = fma(poly, s2, 1.0 / 3.0);
-    poly = fma(poly, s2, 1.0);
-    return fma(2.0 * kLog2e * sv, poly, (double)e);
+// The table of log2_tab (log2_tab.hpp), copied into LDS by the kernels that use it.
+__constant__ Log2Table kLog2TableDev = make_log2_table();
+
+// log2 x for x > 0 to about 3e-13 absolute: the table form for positive normal x,
+// the library log2 for anything else.
+__device__ __forceinline__ double log2_fast(double x, const Log2Entry* tab) {
+    if (!(x >= 0x1p-1022 && x < __builtin_huge_val())) return log2(x);
+    return log2_tab(x, tab);
 }
 
 // g of the sum: power (b + c s)^-p, or Gaussian exp(-c^2 (s - w)^2).
 template <int GFAM, bool FP32>
-__device__ __forceinline__ double sum_g(const double* gp, double s) {
+__device__ __forceinline__ double sum_g(const double* gp, double s, const Log2Entry* tab) {
     if constexpr (GFAM == 0) {
         if constexpr (FP32) {
             // 2^{-p log2(b + c s)}: the exponent in FP64, its fractional power in FP32
-            return exp2_split_f32(-gp[2] * log2_atanh(fma(gp[1], s, gp[0])));
+            return exp2_split_f32(-gp[2] * log2_fast(fma(gp[1], s, gp[0]), tab));
         } else {
             return pow(fma(gp[1], s, gp[0]), -gp[2]);
         }
@@ -162,13 +142,19 @@ __global__ __launch_bounds__(kSumEvalBlock) void sum_eval_kernel(int states, int
                                                                 const double* params, int P,
                                                                 double* q_out) {
     __shared__ double s_red[kSumEvalBlock / kWave];
+    __shared__ Log2Entry s_tab[kLog2Tab];
+    constexpr bool kTable = GFAM == 0 && FP32;  // the power's log2 in the table form
+    if constexpr (kTable) {
+        for (int k = threadIdx.x; k < kLog2Tab; k += kSumEvalBlock) s_tab[k] = kLog2TableDev.e[k];
+        __syncthreads();
+    }
     const double* gp = params + (size_t)blockIdx.x * P;
     const double invN = 1.0 / (double)N, invNl = 1.0 / (double)nl;
     double acc = 0.0;
     for (int T = threadIdx.x; T < states; T += kSumEvalBlock) {
         const double s0 = fma((double)T, invN, off);
         double inner = 0.0;
-        for (int u = 0; u < nl; ++u) inner += sum_g<GFAM, FP32>(gp, fma((double)u, invNl, s0));
+        for (int u = 0; u < nl; ++u) inner += sum_g<GFAM, FP32>(gp, fma((double)u, invNl, s0), s_tab);
         acc = fma(c[T], inner, acc);
     }
     const double t = block_sum(acc, s_red);

@@ -3,7 +3,8 @@ and of the MDI-LR recurrence seeds (csrc/exp2_seed.hpp), compiled for the host w
 g++ and checked against the C library's long-double exp2l: within one unit in the last
 place over the range |x| <= 1000, exact at integers (powers of two) and at 0; the
 seeds' short form within one unit in the last place over |x| <= 1/16, and the seeds'
-dispatch between the two forms over the whole range."""
+dispatch between the two forms over the whole range; and the table form of log2
+(csrc/log2_tab.hpp) against log2l in absolute error."""
 import os
 import shutil
 import subprocess
@@ -78,3 +79,27 @@ def test_expm1_small_within_two_ulp(checker, lo, hi, n):
 def test_expm1_small_exact_at_zero(checker):
     ulp, _ = _max_ulp(checker, 0, 0.0, 0.0, form="expm1")
     assert ulp == 0.0
+
+
+@pytest.fixture(scope="module")
+def log2_checker(tmp_path_factory):
+    if shutil.which("g++") is None:
+        pytest.skip("g++ not available")
+    out = tmp_path_factory.mktemp("log2") / "log2_check"
+    subprocess.run(["g++", "-O2", "-std=c++17", "-I", os.path.join(ROOT, "paper_2404_08867_amd", "csrc"),
+                    os.path.join(ROOT, "tests", "host", "log2_check.cpp"), "-o", str(out), "-lm"],
+                   check=True)
+    return str(out)
+
+
+@pytest.mark.parametrize("lo,hi,n,bound", [(2.2250738585072014e-308, 1.7e308, 2_000_000, 3.5e-13),
+                                           (0.25, 4.0, 1_000_000, 2.7e-13),
+                                           (1.0, 202.0, 1_000_000, 2.7e-13)])
+def test_log2_table_form_absolute_error(log2_checker, lo, hi, n, bound):
+    """The table form of log2 (csrc/log2_tab.hpp) that the FP32c power of the coordinate
+    sum takes: the series' first omitted term t^5 / (5 ln 2) <= 2.6e-13 at the table's
+    interval edges, plus the rounding of e + log2 T_j (half a unit of 1022 at the range's
+    ends), against log2l; (1, 202) spans b + c s of the power sets up to d = 200."""
+    r = subprocess.run([log2_checker, str(n), repr(lo), repr(hi)], capture_output=True, text=True, check=True)
+    err, x = (float(v) for v in r.stdout.split())
+    assert err <= bound, (err, x)
