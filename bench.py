@@ -124,11 +124,12 @@ def uses_adjoint_sets(d: int, family: int, nsets: int) -> bool:
 WORK_PER_MDI_FACTOR = 2 * C64
 
 # MDI-LR of g(sum x), power g, QMC_FP32_COMPENSATED, per merged-state evaluation of
-# g (FP64 operations): the node and b + c s (2); log2 by the atanh series (22: the
-# mantissa and exponent, the reduction to [sqrt(1/2), sqrt(2)), the reciprocal with
-# two Newton steps, the eight-term polynomial, the exponent added back); the
-# exponent -p log2 (1); the split exp2 (5, plus one v_exp_f32); the weighted add (1).
-WORK_PER_SUM_EVAL = 31 * C64 + CT
+# g (FP64 operations): the node and b + c s (2); the range test (1); log2 from the
+# table (9: mantissa and exponent, t = m / T_j - 1, the three-step polynomial, the
+# exponent converted and added, the last FMA; plus two 32-bit operations for the table
+# index); the exponent -p log2 (1); the split exp2 (6: rounding, fraction, three
+# conversions, ldexp; plus one v_exp_f32); the weighted add (1).
+WORK_PER_SUM_EVAL = 20 * C64 + 2 * C32 + CT
 
 # Lattice-quality criteria (FP64): per point and direction the index step, the
 # conversion, x = k/n, y = x (1 - x), the factor 1 + a B(x) and the product; per

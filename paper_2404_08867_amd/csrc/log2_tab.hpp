@@ -77,4 +77,34 @@ QMC_HD inline double log2_tab(double x, const Log2Entry* tab) {
     return fma(t, q, (double)e + E.lg);
 }
 
+// log2 x as an unevaluated sum hi + lo, for finite x >= 2^-1022, to about 3e-16
+// absolute: the same table, the series to t^6 (first omitted term below 3e-18), the
+// fraction r = log2 T_j + log2(1 + t) in one double, and e + r split exactly into
+// hi + lo (e is an integer with e = 0 or |e| >= 1 > |r| - 2^-7, so the
+// subtraction below recovers the rounding of e + r).
+QMC_HD inline void log2_tab_dd(double x, const Log2Entry* tab, double& hi, double& lo) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    const int e = __builtin_amdgcn_frexp_exp(x);
+    const double m = __builtin_amdgcn_frexp_mant(x);
+#else
+    int e = 0;
+    const double m = frexp(x, &e);
+#endif
+    uint64_t bits = 0;
+    memcpy(&bits, &x, sizeof bits);
+    const int j = (int)((bits >> (52 - kLog2TabBits)) & (uint64_t)(kLog2Tab - 1));
+    const Log2Entry E = tab[j];
+    const double t = fma(m, E.inv, -1.0);
+    constexpr double l2e = 1.44269504088896340736;  // 1 / ln 2
+    double q = fma(t, -l2e / 6.0, l2e / 5.0);
+    q = horner_step(q, t, -l2e / 4.0);
+    q = horner_step(q, t, l2e / 3.0);
+    q = horner_step(q, t, -l2e / 2.0);
+    q = horner_step(q, t, l2e);
+    const double r = fma(t, q, E.lg);
+    const double de = (double)e;
+    hi = de + r;
+    lo = r - (hi - de);
+}
+
 }  // namespace qmc

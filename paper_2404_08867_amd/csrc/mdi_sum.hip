@@ -118,7 +118,17 @@ __device__ __forceinline__ double sum_g(const double* gp, double s, const Log2En
             // 2^{-p log2(b + c s)}: the exponent in FP64, its fractional power in FP32
             return exp2_split_f32(-gp[2] * log2_fast(fma(gp[1], s, gp[0]), tab));
         } else {
-            return pow(fma(gp[1], s, gp[0]), -gp[2]);
+            // 2^{-p log2 x} with log2 x = hi + lo from the table (2.2e-16 absolute) and
+            // y = -p log2 x as yh + yl (the product's rounding by an FMA): the exp2 of
+            // yh within one unit in the last place, times 1 + yl ln 2.
+            const double x = fma(gp[1], s, gp[0]), p = gp[2];
+            if (!(x >= 0x1p-1022 && x < __builtin_huge_val())) return pow(x, -p);
+            double hi, lo;
+            log2_tab_dd(x, tab, hi, lo);
+            const double yh = -p * hi;
+            const double yl = fma(-p, lo, fma(-p, hi, -yh));
+            if (!(fabs(yh) <= 1000.0)) return pow(x, -p);
+            return exp2_f64(yh) * fma(yl, kLn2, 1.0);
         }
     } else {
         const double y = gp[0] * (s - gp[1]);
@@ -143,7 +153,7 @@ __global__ __launch_bounds__(kSumEvalBlock) void sum_eval_kernel(int states, int
                                                                 double* q_out) {
     __shared__ double s_red[kSumEvalBlock / kWave];
     __shared__ Log2Entry s_tab[kLog2Tab];
-    constexpr bool kTable = GFAM == 0 && FP32;  // the power's log2 in the table form
+    constexpr bool kTable = GFAM == 0;  // the power's log2 in the table form
     if constexpr (kTable) {
         for (int k = threadIdx.x; k < kLog2Tab; k += kSumEvalBlock) s_tab[k] = kLog2TableDev.e[k];
         __syncthreads();

@@ -1,4 +1,5 @@
-// Host check of qmc::log2_tab (paper_2404_08867_amd/csrc/log2_tab.hpp): the largest
+// Host check of qmc::log2_tab (paper_2404_08867_amd/csrc/log2_tab.hpp), or with a
+// fourth argument "dd" of qmc::log2_tab_dd (hi + lo in long double): the largest
 // absolute error against log2l over n points of [lo, hi] (uniform in log x) and the
 // two end points, plus every interval edge of the table in [1/2, 1) scaled by 2^k for
 // k in [-8, 8]; prints "<max abs error> <x at the max>".
@@ -18,9 +19,16 @@ int main(int argc, char** argv) {
     }
     const long n = atol(argv[1]);
     const double lo = atof(argv[2]), hi = atof(argv[3]);
+    const bool dd = argc > 4 && argv[4][0] == 'd';  // the two-part form log2_tab_dd
     double worst = 0.0, at = lo;
+    auto value = [&](double x) -> long double {
+        if (!dd) return (long double)qmc::log2_tab(x, kTab.e);
+        double h = 0.0, l = 0.0;
+        qmc::log2_tab_dd(x, kTab.e, h, l);
+        return (long double)h + (long double)l;
+    };
     auto check = [&](double x) {
-        const double err = fabs((double)((long double)qmc::log2_tab(x, kTab.e) - log2l((long double)x)));
+        const double err = fabs((double)(value(x) - log2l((long double)x)));
         if (err > worst || err != err) {
             worst = err;
             at = x;

@@ -103,3 +103,14 @@ def test_log2_table_form_absolute_error(log2_checker, lo, hi, n, bound):
     r = subprocess.run([log2_checker, str(n), repr(lo), repr(hi)], capture_output=True, text=True, check=True)
     err, x = (float(v) for v in r.stdout.split())
     assert err <= bound, (err, x)
+
+
+@pytest.mark.parametrize("lo,hi,n", [(2.2250738585072014e-308, 1.7e308, 2_000_000), (0.25, 4.0, 1_000_000),
+                                     (0.999, 1.001, 500_000), (1.0, 202.0, 1_000_000)])
+def test_log2_table_two_part_form(log2_checker, lo, hi, n):
+    """The two-part form hi + lo of the FP64 power: the series to t^6 and the exact split
+    of e + r leave only the roundings of the table entries and of r, below 2.5e-16."""
+    r = subprocess.run([log2_checker, str(n), repr(lo), repr(hi), "dd"], capture_output=True, text=True,
+                       check=True)
+    err, x = (float(v) for v in r.stdout.split())
+    assert err <= 2.5e-16, (err, x)
